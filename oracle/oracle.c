@@ -1,0 +1,753 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle of the plug-and-play Langevin sampler.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the CPU
+ * baseline leg of the benchmark, never by the product library, and sharing
+ * no code with it.  Readability over speed: every operator is a direct sum in
+ * a fixed order (no FFT, no blocking beyond the paper's own blocks), and the
+ * only parallelism is OpenMP over independent output rows/channels, which
+ * does not change any result.
+ *
+ * Paper references (arXiv 2511.00870):
+ *   - posterior and splitting: Sec. II-C, Eq. (general_posterior_l2_axda),
+ *     conditionals (sgs:marginal_x), (sgs:marginal_z);
+ *   - PnP-ULA x-transition: Eq. (sgs_pnp_ula_psgla:pnp_ula), Algorithm 1;
+ *   - Gaussian likelihood, mask and blur operators: Sec. IV-A1, IV-A2,
+ *     Eq. (likelihood:gaussian_inpainting), (potential_gaussian_likelihood);
+ *   - CNN denoiser: Sec. II-B1 Eqs. (feedforward_cnn), (cnn:convolution),
+ *     Example 2 (DnCNN: D = Id - G, ReLU except on the last layer);
+ *   - blocks and halos: Sec. II-A Defs. 1-2 (local selection operators,
+ *     localized operators), Sec. II-B2 (overlap-save: compute each block on
+ *     its extended window and discard the entries with wrong boundary).
+ *   - Philox4xW-10: Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ *     easy as 1, 2, 3", SC'11 (the paper does not name its generator).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ======================================================================
+ * Philox4xW-10 (Salmon et al. SC'11, Sec. 4).  One round maps the counter
+ * (X0, X1, X2, X3) with round key (K0, K1) to
+ *   (hi(M1*X2) ^ X1 ^ K0, lo(M1*X2), hi(M0*X0) ^ X3 ^ K1, lo(M0*X0));
+ * between rounds the key is bumped by the Weyl constants (W0, W1).
+ * ==================================================================== */
+#define PHILOX_ROUND_BODY(T, X, K, M0, M1, MULHI)            \
+  do {                                                       \
+    T hi0 = MULHI((M0), X[0]), lo0 = (T)((M0) * X[0]);       \
+    T hi1 = MULHI((M1), X[2]), lo1 = (T)((M1) * X[2]);       \
+    T n0 = hi1 ^ X[1] ^ K[0], n2 = hi0 ^ X[3] ^ K[1];        \
+    X[0] = n0; X[1] = lo1; X[2] = n2; X[3] = lo0;            \
+  } while (0)
+
+static inline uint32_t mulhi32(uint32_t a, uint32_t b) {
+  return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+}
+static inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+  return (uint64_t)(((unsigned __int128)a * (unsigned __int128)b) >> 64);
+}
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t X[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t K[2] = {key[0], key[1]};
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { K[0] += W0; K[1] += W1; }
+    PHILOX_ROUND_BODY(uint32_t, X, K, M0, M1, mulhi32);
+  }
+  memcpy(out, X, sizeof X);
+}
+
+void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t X[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint64_t K[2] = {key[0], key[1]};
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { K[0] += W0; K[1] += W1; }
+    PHILOX_ROUND_BODY(uint64_t, X, K, M0, M1, mulhi64);
+  }
+  memcpy(out, X, sizeof X);
+}
+
+/* Box-Muller on two 24-bit uniforms u1 in (0,1], u2 in [0,1):
+ * xi = sqrt(-2 ln u1) cos(2 pi u2), zeta = sqrt(-2 ln u1) sin(2 pi u2). */
+void oracle_gauss_pair(uint32_t w0, uint32_t w1, double *xi, double *zeta) {
+  const double two_m24 = 1.0 / 16777216.0;
+  double u1 = (double)((w0 >> 8) + 1u) * two_m24;
+  double u2 = (double)(w1 >> 8) * two_m24;
+  double rad = sqrt(-2.0 * log(u1));
+  double ang = 2.0 * M_PI * u2;
+  *xi = rad * cos(ang);
+  *zeta = rad * sin(ang);
+}
+
+/* The two Gaussian draws of pixel p at iteration t: xi^(t+1) (x-update,
+ * Algorithm 1, "sample xi") and zeta^(t) (draw of z^(t)). */
+static void draw_pixel(uint64_t seed, int64_t p, int64_t t, uint32_t chain,
+                       double *xi, double *zeta) {
+  uint32_t ctr[4] = {(uint32_t)p, (uint32_t)t, chain, (uint32_t)((uint64_t)p >> 32)};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  oracle_philox4x32_10(ctr, key, w);
+  oracle_gauss_pair(w[0], w[1], xi, zeta);
+}
+
+void oracle_noise(int32_t ny, int32_t nx, uint64_t seed, uint32_t t, uint32_t chain,
+                  double *xi, double *zeta) {
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < ny; ++i)
+    for (int32_t j = 0; j < nx; ++j) {
+      int64_t p = (int64_t)i * nx + j;
+      draw_pixel(seed, p, t, chain, &xi[p], &zeta[p]);
+    }
+}
+
+/* ======================================================================
+ * Quantisation (round to nearest even).
+ * bf16: 8 significant bits, exponent range of fp32 (subnormal step 2^-133).
+ * e4m3fn (OCP): 4 significant bits, bias 7, min normal 2^-6, subnormal
+ * step 2^-9, largest finite 448, no infinities: saturate to +-448.
+ * ==================================================================== */
+double oracle_quantize(double v, int32_t fmt) {
+  if (fmt == OR_FMT_EXACT || v == 0.0 || isnan(v)) return v;
+  if (fmt == OR_FMT_BF16) {
+    if (isinf(v)) return v;
+    int e;
+    frexp(v, &e);
+    int lead = e - 1;
+    if (lead < -126) lead = -126;
+    double ulp = ldexp(1.0, lead - 7);
+    double q = nearbyint(v / ulp) * ulp;
+    const double bmax = ldexp(255.0, 120); /* (2 - 2^-7) 2^127 */
+    if (fabs(q) > bmax) q = copysign(INFINITY, v);
+    return q;
+  }
+  /* e4m3fn */
+  if (isinf(v)) return copysign(448.0, v);
+  int e;
+  frexp(v, &e);
+  int lead = e - 1;
+  if (lead < -6) lead = -6;
+  double ulp = ldexp(1.0, lead - 3);
+  double q = nearbyint(v / ulp) * ulp;
+  if (q > 448.0) q = 448.0;
+  if (q < -448.0) q = -448.0;
+  return q;
+}
+
+/* smallest power of two s with amax / s <= 448 (1 when amax == 0) */
+static double pow2_scale(double amax) {
+  if (!(amax > 0.0)) return 1.0;
+  int e;
+  double f = frexp(amax / 448.0, &e);
+  return (f == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+}
+
+static int layer_fmt(const oracle_net *n, int k) {
+  return n->layer_fmt ? n->layer_fmt[k] : OR_FMT_EXACT;
+}
+
+static size_t weight_offset(const oracle_net *n, int k) {
+  size_t off = 0;
+  for (int i = 0; i < k; ++i) off += (size_t)n->channels[i] * n->channels[i + 1] * 9;
+  return off;
+}
+static size_t bias_offset(const oracle_net *n, int k) {
+  size_t off = 0;
+  for (int i = 0; i < k; ++i) off += (size_t)n->channels[i + 1];
+  return off;
+}
+
+/* per-output-channel weight scales of layer k (power of two for e4m3, else 1) */
+void oracle_weight_scales(const oracle_net *n, int32_t k, double *scales) {
+  int cin = n->channels[k], cout = n->channels[k + 1];
+  const double *w = n->weights + weight_offset(n, k);
+  for (int co = 0; co < cout; ++co) {
+    if (layer_fmt(n, k) != OR_FMT_E4M3) { scales[co] = 1.0; continue; }
+    double amax = 0.0;
+    for (int i = 0; i < cin * 9; ++i) amax = fmax(amax, fabs(w[(size_t)co * cin * 9 + i]));
+    scales[co] = pow2_scale(amax);
+  }
+}
+
+/* ======================================================================
+ * Valid-mode stencils on explicit arrays.  Zero boundaries are obtained by
+ * padding the input with zeros before the call; a block's extended window
+ * is obtained by copying the window (zeros outside the image).  Each output
+ * is one sum in a fixed order, so results do not depend on which array the
+ * stencil runs on.
+ * ==================================================================== */
+
+/* out[i][j] = sum_{a,c} k[a][c] in[i + L-1-a][j + L-1-c]: linear convolution
+ * (flip) restricted to outputs whose support lies inside `in`. */
+static void valid_conv(const double *in, int H, int W, const double *k, int L, double *out) {
+  int Ho = H - L + 1, Wo = W - L + 1;
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < Ho; ++i)
+    for (int j = 0; j < Wo; ++j) {
+      double acc = 0.0;
+      for (int a = 0; a < L; ++a)
+        for (int c = 0; c < L; ++c)
+          acc += k[a * L + c] * in[(size_t)(i + L - 1 - a) * W + (j + L - 1 - c)];
+      out[(size_t)i * Wo + j] = acc;
+    }
+}
+
+/* out[i][j] = sum_{a,c} k[a][c] in[i + a][j + c]: the adjoint of valid_conv's
+ * zero-boundary operator (correlation with the same kernel). */
+static void valid_xcorr(const double *in, int H, int W, const double *k, int L, double *out) {
+  int Ho = H - L + 1, Wo = W - L + 1;
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < Ho; ++i)
+    for (int j = 0; j < Wo; ++j) {
+      double acc = 0.0;
+      for (int a = 0; a < L; ++a)
+        for (int c = 0; c < L; ++c)
+          acc += k[a * L + c] * in[(size_t)(i + a) * W + (j + c)];
+      out[(size_t)i * Wo + j] = acc;
+    }
+}
+
+/* One CNN layer (Eq. (cnn:convolution)) on a valid region:
+ *   out[co][i][j] = eta( oscale[co] * sum_ci sum_{a,c} w[co][ci][a][c]
+ *                        in[ci][i+a][j+c]  +  b[co] )
+ * in: [cin][H][W] -> out: [cout][H-2][W-2]; eta = ReLU if relu else Id.
+ * Each output sums in the order (ci, a, c). */
+static void valid_layer(const double *in, int cin, int H, int W, const double *w,
+                        const double *b, const double *oscale, int cout, int relu,
+                        double *out) {
+  int Ho = H - 2, Wo = W - 2;
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int co = 0; co < cout; ++co)
+    for (int i = 0; i < Ho; ++i) {
+      double *orow = out + ((size_t)co * Ho + i) * Wo;
+      for (int j = 0; j < Wo; ++j) orow[j] = 0.0;
+      for (int ci = 0; ci < cin; ++ci) {
+        const double *wp = w + ((size_t)co * cin + ci) * 9;
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) {
+            const double wv = wp[a * 3 + c];
+            const double *irow = in + ((size_t)ci * H + i + a) * W + c;
+            for (int j = 0; j < Wo; ++j) orow[j] += wv * irow[j];
+          }
+      }
+      for (int j = 0; j < Wo; ++j) {
+        double v = orow[j] * oscale[co] + b[co];
+        if (relu && v < 0.0) v = 0.0;
+        orow[j] = v;
+      }
+    }
+}
+
+/* copy a window [oy, oy+H) x [ox, ox+W) of C planes of an ny x nx image,
+ * with zeros outside the image */
+static void extract_window(const double *img, int C, int ny, int nx, int oy, int ox,
+                           int H, int W, double *win) {
+  for (int c = 0; c < C; ++c)
+    for (int i = 0; i < H; ++i)
+      for (int j = 0; j < W; ++j) {
+        int gi = oy + i, gj = ox + j;
+        double v = 0.0;
+        if (gi >= 0 && gi < ny && gj >= 0 && gj < nx)
+          v = img[((size_t)c * ny + gi) * nx + gj];
+        win[((size_t)c * H + i) * W + j] = v;
+      }
+}
+
+/* zero the entries of a window that fall outside the image (half padding
+ * at every layer, Eq. (cnn:convolution)) */
+static void zero_outside(double *win, int C, int ny, int nx, int oy, int ox, int H, int W) {
+  for (int c = 0; c < C; ++c)
+    for (int i = 0; i < H; ++i)
+      for (int j = 0; j < W; ++j) {
+        int gi = oy + i, gj = ox + j;
+        if (gi < 0 || gi >= ny || gj < 0 || gj >= nx)
+          win[((size_t)c * H + i) * W + j] = 0.0;
+      }
+}
+
+static void *xmalloc(size_t n) {
+  void *p = malloc(n ? n : 1);
+  if (!p) { fprintf(stderr, "oracle: out of memory (%zu bytes)\n", n); abort(); }
+  return p;
+}
+
+/* ======================================================================
+ * Operators on whole images (zero boundary)
+ * ==================================================================== */
+void oracle_blur(const double *x, int32_t ny, int32_t nx, const double *k, int32_t L,
+                 double *out) {
+  int r = L / 2;
+  int H = ny + 2 * r, W = nx + 2 * r;
+  double *pad = xmalloc((size_t)H * W * sizeof(double));
+  extract_window(x, 1, ny, nx, -r, -r, H, W, pad);
+  valid_conv(pad, H, W, k, L, out);
+  free(pad);
+}
+
+void oracle_blur_adjoint(const double *rr, int32_t ny, int32_t nx, const double *k,
+                         int32_t L, double *out) {
+  int r = L / 2;
+  int H = ny + 2 * r, W = nx + 2 * r;
+  double *pad = xmalloc((size_t)H * W * sizeof(double));
+  extract_window(rr, 1, ny, nx, -r, -r, H, W, pad);
+  valid_xcorr(pad, H, W, k, L, out);
+  free(pad);
+}
+
+void oracle_conv3x3(const double *in, int32_t cin, int32_t ny, int32_t nx,
+                    const double *w, const double *b, int32_t cout, int32_t relu,
+                    double *out) {
+  int H = ny + 2, W = nx + 2;
+  double *pad = xmalloc((size_t)cin * H * W * sizeof(double));
+  double *one = xmalloc((size_t)cout * sizeof(double));
+  for (int c = 0; c < cout; ++c) one[c] = 1.0;
+  extract_window(in, cin, ny, nx, -1, -1, H, W, pad);
+  valid_layer(pad, cin, H, W, w, b, one, cout, relu, out);
+  free(pad);
+  free(one);
+}
+
+/* ======================================================================
+ * Denoiser G = T_K o ... o T_1 on a window (Sec. II-B1, Example 2).
+ * `win` holds channels[0] planes of size H x W whose global origin is
+ * (oy, ox); each layer shrinks the valid region by one pixel per side and
+ * re-zeroes what lies outside the image.  With quantisation, layer k rounds
+ * its input (scaled by act_scales[k] for e4m3) and its weights (scaled per
+ * output channel) to its format and rescales the exact sum.
+ * Returns the final plane of size (H - 2K) x (W - 2K) in *res (caller frees).
+ * ==================================================================== */
+typedef struct {
+  double *wq;      /* quantised weights, all layers */
+  double *oscale;  /* per layer per output channel: s_w * s_a */
+} prepared_net;
+
+static void prepare_net(const oracle_net *n, prepared_net *p) {
+  size_t nw = weight_offset(n, n->n_layers), nb = bias_offset(n, n->n_layers);
+  p->wq = xmalloc(nw * sizeof(double));
+  p->oscale = xmalloc(nb * sizeof(double));
+  for (int k = 0; k < n->n_layers; ++k) {
+    int cin = n->channels[k], cout = n->channels[k + 1], fmt = layer_fmt(n, k);
+    const double *w = n->weights + weight_offset(n, k);
+    double *wq = p->wq + weight_offset(n, k);
+    double *os = p->oscale + bias_offset(n, k);
+    oracle_weight_scales(n, k, os);
+    double sa = (fmt == OR_FMT_E4M3 && n->act_scales) ? n->act_scales[k] : 1.0;
+    for (int co = 0; co < cout; ++co) {
+      for (int i = 0; i < cin * 9; ++i) {
+        size_t idx = (size_t)co * cin * 9 + i;
+        wq[idx] = oracle_quantize(w[idx] / os[co], fmt);
+      }
+      os[co] *= sa;
+    }
+  }
+}
+
+static void free_net(prepared_net *p) {
+  free(p->wq);
+  free(p->oscale);
+}
+
+static double *denoise_window(const oracle_net *n, const prepared_net *p, double *win,
+                              int ny, int nx, int oy, int ox, int H, int W,
+                              int keep_acts, double *acts_out, double *amax) {
+  double *cur = win;
+  int own = 0;
+  for (int k = 0; k < n->n_layers; ++k) {
+    int cin = n->channels[k], cout = n->channels[k + 1], fmt = layer_fmt(n, k);
+    double sa = (fmt == OR_FMT_E4M3 && n->act_scales) ? n->act_scales[k] : 1.0;
+    size_t nin = (size_t)cin * H * W;
+    if (amax) {
+      double m = 0.0;
+      for (size_t i = 0; i < nin; ++i) m = fmax(m, fabs(cur[i]));
+      amax[k] = m;
+    }
+    if (fmt != OR_FMT_EXACT) {
+      if (!own) {  /* never modify the caller's window in place */
+        double *cp = xmalloc(nin * sizeof(double));
+        memcpy(cp, cur, nin * sizeof(double));
+        cur = cp;
+        own = 1;
+      }
+      for (size_t i = 0; i < nin; ++i) cur[i] = oracle_quantize(cur[i] / sa, fmt);
+    }
+    double *out = xmalloc((size_t)cout * (H - 2) * (W - 2) * sizeof(double));
+    valid_layer(cur, cin, H, W, p->wq + weight_offset(n, k), n->biases + bias_offset(n, k),
+                p->oscale + bias_offset(n, k), cout, k < n->n_layers - 1, out);
+    if (own) free(cur);
+    cur = out;
+    own = 1;
+    H -= 2; W -= 2; oy += 1; ox += 1;
+    zero_outside(cur, cout, ny, nx, oy, ox, H, W);
+    if (keep_acts) {  /* monolithic only: window == image after the layer */
+      memcpy(acts_out, cur, (size_t)cout * H * W * sizeof(double));
+      acts_out += (size_t)cout * H * W;
+    }
+  }
+  return cur;
+}
+
+/* G(x) for the whole image.  block_y/block_x smaller than the image: each
+ * block is computed from its own extended window of half-width `halo`
+ * (one exchange of the whole receptive field, Sec. II-B2 last paragraph). */
+int oracle_denoiser(const oracle_net *n, const double *x, int32_t ny, int32_t nx,
+                    int32_t block_y, int32_t block_x, int32_t halo, double *G) {
+  int K = n->n_layers;
+  prepared_net p;
+  prepare_net(n, &p);
+  if (block_y <= 0 || block_x <= 0 || (block_y >= ny && block_x >= nx)) {
+    int H = ny + 2 * K, W = nx + 2 * K;
+    double *win = xmalloc((size_t)H * W * sizeof(double));
+    extract_window(x, 1, ny, nx, -K, -K, H, W, win);
+    double *res = denoise_window(n, &p, win, ny, nx, -K, -K, H, W, 0, NULL, NULL);
+    memcpy(G, res, (size_t)ny * nx * sizeof(double));
+    free(res);
+    free(win);
+  } else {
+    if (halo < K) { free_net(&p); return -1; }
+    for (int by = 0; by < ny; by += block_y)
+      for (int bx = 0; bx < nx; bx += block_x) {
+        int cy = (by + block_y <= ny) ? block_y : ny - by;
+        int cx = (bx + block_x <= nx) ? block_x : nx - bx;
+        int H = cy + 2 * halo, W = cx + 2 * halo;
+        double *win = xmalloc((size_t)H * W * sizeof(double));
+        extract_window(x, 1, ny, nx, by - halo, bx - halo, H, W, win);
+        double *res = denoise_window(n, &p, win, ny, nx, by - halo, bx - halo, H, W, 0,
+                                     NULL, NULL);
+        int Hr = H - 2 * K, Wr = W - 2 * K, off = halo - K;
+        for (int i = 0; i < cy; ++i)
+          for (int j = 0; j < cx; ++j)
+            G[(size_t)(by + i) * nx + bx + j] = res[(size_t)(i + off) * Wr + j + off];
+        (void)Hr;
+        free(res);
+        free(win);
+      }
+  }
+  free_net(&p);
+  return 0;
+}
+
+/* all layer outputs of the monolithic denoiser (layer k: channels[k+1]
+ * planes), and the max |input| of every layer before its quantisation */
+int oracle_denoiser_layers(const oracle_net *n, const double *x, int32_t ny, int32_t nx,
+                           double *acts, double *amax) {
+  int K = n->n_layers;
+  prepared_net p;
+  prepare_net(n, &p);
+  const double *cur = x;
+  for (int k = 0; k < K; ++k) {
+    int cin = n->channels[k], cout = n->channels[k + 1], fmt = layer_fmt(n, k);
+    double sa = (fmt == OR_FMT_E4M3 && n->act_scales) ? n->act_scales[k] : 1.0;
+    int H = ny + 2, W = nx + 2;
+    size_t nin = (size_t)cin * H * W;
+    double *pad = xmalloc(nin * sizeof(double));
+    extract_window(cur, cin, ny, nx, -1, -1, H, W, pad);
+    if (amax) {
+      double m = 0.0;
+      for (size_t i = 0; i < nin; ++i) m = fmax(m, fabs(pad[i]));
+      amax[k] = m;
+    }
+    if (fmt != OR_FMT_EXACT)
+      for (size_t i = 0; i < nin; ++i) pad[i] = oracle_quantize(pad[i] / sa, fmt);
+    valid_layer(pad, cin, H, W, p.wq + weight_offset(n, k), n->biases + bias_offset(n, k),
+                p.oscale + bias_offset(n, k), cout, k < K - 1, acts);
+    free(pad);
+    cur = acts;
+    acts += (size_t)cout * ny * nx;
+  }
+  free_net(&p);
+  return 0;
+}
+
+/* ======================================================================
+ * Likelihood gradient on a window (Eq. (sgs_pnp_ula_psgla:pnp_ula), the
+ * data term; Algorithm 1 "u_1", "u_2"; closed-form z draw from
+ * Eq. (sgs:marginal_z) with f2 the Gaussian data term, H2 = H):
+ *   Kx on the window's valid region, then (t >= 1 and rho > 0)
+ *   z = (rho y + sigma^2 m Kx)/(rho + sigma^2) + sqrt(rho sigma^2/(rho+sigma^2)) zeta,
+ *   res = m (Kx - v) inside the image (0 outside), v = y or z,
+ *   g = K^T res / s2 on the next valid region.
+ * `win` = x on [oy, oy+H) x [ox, ox+W) (zeros outside the image); g is
+ * written for the (H - 4r) x (W - 4r) region starting at (oy+2r, ox+2r).
+ * z (optional) receives the drawn z on the (H-2r) x (W-2r) region.
+ * ==================================================================== */
+typedef struct {
+  int32_t ny, nx, L;
+  const double *y, *k;
+  const uint8_t *m;
+  double sigma, rho;
+  uint64_t seed;
+  uint32_t chain;
+} grad_ctx;
+
+static void grad_window(const grad_ctx *gc, const double *win, int oy, int ox, int H, int W,
+                        int64_t t, double *g, double *zout) {
+  int L = gc->L, r = L / 2;
+  int H1 = H - 2 * r, W1 = W - 2 * r;   /* Kx region, origin (oy+r, ox+r) */
+  double *kx = xmalloc((size_t)H1 * W1 * sizeof(double));
+  valid_conv(win, H, W, gc->k, L, kx);
+  const int split = gc->rho > 0.0;
+  const double s2 = split ? gc->rho : gc->sigma * gc->sigma;
+  const double sig2 = gc->sigma * gc->sigma;
+  const double zsd = split ? sqrt(gc->rho * sig2 / (gc->rho + sig2)) : 0.0;
+  for (int i = 0; i < H1; ++i)
+    for (int j = 0; j < W1; ++j) {
+      int gi = oy + r + i, gj = ox + r + j;
+      size_t q = (size_t)i * W1 + j;
+      double res = 0.0, z = 0.0;
+      if (gi >= 0 && gi < gc->ny && gj >= 0 && gj < gc->nx) {
+        int64_t p = (int64_t)gi * gc->nx + gj;
+        double m = gc->m ? (double)gc->m[p] : 1.0;
+        double v;
+        if (split) {
+          if (t >= 1) {
+            double xi_unused, zeta;
+            draw_pixel(gc->seed, p, t, gc->chain, &xi_unused, &zeta);
+            z = (gc->rho * gc->y[p] + sig2 * (m * kx[q])) / (gc->rho + sig2) + zsd * zeta;
+          } else {
+            z = 0.0;  /* z^(0) = 0 (Sec. IV-B) */
+          }
+          v = z;
+        } else {
+          v = gc->y[p];
+        }
+        res = m * (kx[q] - v);
+      }
+      if (zout) zout[q] = z;
+      kx[q] = res;  /* reuse the buffer for the residual */
+    }
+  valid_xcorr(kx, H1, W1, gc->k, L, g);
+  int n2 = (H1 - 2 * r) * (W1 - 2 * r);
+  for (int i = 0; i < n2; ++i) g[i] /= s2;
+  free(kx);
+}
+
+static grad_ctx make_grad_ctx(const oracle_config *c) {
+  grad_ctx gc = {c->ny, c->nx, c->ksize, c->y, c->kernel, c->mask, c->sigma, c->rho,
+                 c->seed, c->chain};
+  return gc;
+}
+
+int oracle_data_grad(const oracle_config *c, const double *x, int64_t t, double *g) {
+  int ny = c->ny, nx = c->nx, r = c->ksize / 2;
+  grad_ctx gc = make_grad_ctx(c);
+  if (c->block_y <= 0 || c->block_x <= 0 || (c->block_y >= ny && c->block_x >= nx)) {
+    int H = ny + 4 * r, W = nx + 4 * r;
+    double *win = xmalloc((size_t)H * W * sizeof(double));
+    extract_window(x, 1, ny, nx, -2 * r, -2 * r, H, W, win);
+    grad_window(&gc, win, -2 * r, -2 * r, H, W, t, g, NULL);
+    free(win);
+    return 0;
+  }
+  int h = c->halo;
+  if (h < 2 * r) return -1;
+  for (int by = 0; by < ny; by += c->block_y)
+    for (int bx = 0; bx < nx; bx += c->block_x) {
+      int cy = (by + c->block_y <= ny) ? c->block_y : ny - by;
+      int cx = (bx + c->block_x <= nx) ? c->block_x : nx - bx;
+      int H = cy + 2 * h, W = cx + 2 * h;
+      double *win = xmalloc((size_t)H * W * sizeof(double));
+      extract_window(x, 1, ny, nx, by - h, bx - h, H, W, win);
+      int Hg = H - 4 * r, Wg = W - 4 * r, off = h - 2 * r;
+      double *gw = xmalloc((size_t)Hg * Wg * sizeof(double));
+      grad_window(&gc, win, by - h, bx - h, H, W, t, gw, NULL);
+      for (int i = 0; i < cy; ++i)
+        for (int j = 0; j < cx; ++j)
+          g[(size_t)(by + i) * nx + bx + j] = gw[(size_t)(i + off) * Wg + j + off];
+      free(gw);
+      free(win);
+    }
+  return 0;
+}
+
+/* ======================================================================
+ * The chain
+ * ==================================================================== */
+struct oracle_chain {
+  oracle_config cfg;       /* pointers below are owned copies */
+  double *y, *kernel, *w, *b, *act_scales;
+  int32_t *channels, *fmt;
+  uint8_t *mask;
+  double *x, *z;
+  int64_t t;
+  int64_t n;               /* Welford count */
+  int record_z;
+  double *mean, *m2;
+};
+
+static void *dup(const void *p, size_t n) {
+  if (!p) return NULL;
+  void *q = xmalloc(n);
+  memcpy(q, p, n);
+  return q;
+}
+
+oracle_chain *oracle_create(const oracle_config *cfg, char *err, int errlen) {
+#define FAIL(msg)                                   \
+  do {                                              \
+    if (err && errlen > 0) snprintf(err, errlen, "%s", msg); \
+    return NULL;                                    \
+  } while (0)
+  if (!cfg || cfg->ny <= 0 || cfg->nx <= 0) FAIL("image size must be positive");
+  if (!cfg->y) FAIL("y is required");
+  if (cfg->ksize < 1 || cfg->ksize % 2 == 0 || !cfg->kernel) FAIL("blur size must be odd");
+  if (!(cfg->sigma > 0) || !(cfg->eps > 0) || !(cfg->delta > 0) || !(cfg->rho >= 0) ||
+      !(cfg->alpha >= 0) || !(cfg->inv_lambda >= 0))
+    FAIL("sigma, eps, delta must be > 0; rho, alpha, inv_lambda >= 0");
+  const oracle_net *n = &cfg->net;
+  if (n->n_layers < 1 || !n->channels || n->channels[0] != 1 ||
+      n->channels[n->n_layers] != 1 || !n->weights || !n->biases)
+    FAIL("denoiser must map 1 channel to 1 channel");
+  int r = cfg->ksize / 2;
+  int blocked = cfg->block_y > 0 && cfg->block_x > 0 &&
+                !(cfg->block_y >= cfg->ny && cfg->block_x >= cfg->nx);
+  if (blocked && cfg->halo < (2 * r > n->n_layers ? 2 * r : n->n_layers))
+    FAIL("halo must be >= max(2r, K)");
+  oracle_chain *c = calloc(1, sizeof *c);
+  if (!c) FAIL("out of memory");
+  size_t N = (size_t)cfg->ny * cfg->nx;
+  c->cfg = *cfg;
+  c->y = dup(cfg->y, N * sizeof(double));
+  c->kernel = dup(cfg->kernel, (size_t)cfg->ksize * cfg->ksize * sizeof(double));
+  c->mask = dup(cfg->mask, N);
+  c->channels = dup(n->channels, (n->n_layers + 1) * sizeof(int32_t));
+  c->w = dup(n->weights, weight_offset(n, n->n_layers) * sizeof(double));
+  c->b = dup(n->biases, bias_offset(n, n->n_layers) * sizeof(double));
+  c->fmt = dup(n->layer_fmt, n->n_layers * sizeof(int32_t));
+  c->act_scales = dup(n->act_scales, n->n_layers * sizeof(double));
+  c->cfg.y = c->y;
+  c->cfg.kernel = c->kernel;
+  c->cfg.mask = c->mask;
+  c->cfg.net.channels = c->channels;
+  c->cfg.net.weights = c->w;
+  c->cfg.net.biases = c->b;
+  c->cfg.net.layer_fmt = c->fmt;
+  c->cfg.net.act_scales = c->act_scales;
+  c->cfg.x0 = NULL;
+  c->x = xmalloc(N * sizeof(double));
+  c->z = calloc(N, sizeof(double));
+  c->mean = calloc(N, sizeof(double));
+  c->m2 = calloc(N, sizeof(double));
+  if (cfg->x0) memcpy(c->x, cfg->x0, N * sizeof(double));
+  else memset(c->x, 0, N * sizeof(double));
+  c->t = 0;
+  c->n = 0;
+  return c;
+#undef FAIL
+}
+
+/* x^(t) -> x^(t+1) (Eq. (sgs_pnp_ula_psgla:pnp_ula), Algorithm 1) */
+static int one_step(oracle_chain *c) {
+  const oracle_config *cfg = &c->cfg;
+  int ny = cfg->ny, nx = cfg->nx;
+  size_t N = (size_t)ny * nx;
+  double *g = xmalloc(N * sizeof(double));
+  double *G = xmalloc(N * sizeof(double));
+  /* data term (blocked when the configuration has several blocks) */
+  oracle_data_grad(cfg, c->x, c->t, g);
+  /* record z for inspection (monolithic draw, identical values) */
+  if (cfg->rho > 0 && c->record_z) {
+    int r = cfg->ksize / 2;
+    int H = ny + 4 * r, W = nx + 4 * r;
+    double *win = xmalloc((size_t)H * W * sizeof(double));
+    double *gtmp = xmalloc(N * sizeof(double));
+    double *zw = xmalloc((size_t)(ny + 2 * r) * (nx + 2 * r) * sizeof(double));
+    grad_ctx gc = make_grad_ctx(cfg);
+    extract_window(c->x, 1, ny, nx, -2 * r, -2 * r, H, W, win);
+    grad_window(&gc, win, -2 * r, -2 * r, H, W, c->t, gtmp, zw);
+    for (int i = 0; i < ny; ++i)
+      for (int j = 0; j < nx; ++j)
+        c->z[(size_t)i * nx + j] = zw[(size_t)(i + r) * (nx + 2 * r) + j + r];
+    free(zw);
+    free(gtmp);
+    free(win);
+  }
+  /* prior term: G = Id - D_eps */
+  oracle_denoiser(&cfg->net, c->x, ny, nx, cfg->block_y, cfg->block_x, cfg->halo, G);
+  const double d = cfg->delta;
+  const double cprior = cfg->alpha * d / cfg->eps;
+  const double cproj = d * cfg->inv_lambda;
+  const double sq = sqrt(2.0 * d);
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int i = 0; i < ny; ++i)
+    for (int j = 0; j < nx; ++j) {
+      int64_t p = (int64_t)i * nx + j;
+      double xi, zeta_unused;
+      draw_pixel(cfg->seed, p, c->t, cfg->chain, &xi, &zeta_unused);
+      double x = c->x[p];
+      double proj = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+      double xn = x - d * g[p] - cprior * G[p] + cproj * (proj - x) + sq * xi;
+      if (!isfinite(xn)) bad = 1;
+      g[p] = xn;  /* x^(t+1) staged in g so every pixel reads x^(t) */
+    }
+  memcpy(c->x, g, N * sizeof(double));
+  c->t += 1;
+  /* online mean / variance of the samples after burn-in (Welford) */
+  if (c->t > cfg->burn_in) {
+    c->n += 1;
+    const double inv = 1.0 / (double)c->n;
+    for (size_t p = 0; p < N; ++p) {
+      double dlt = c->x[p] - c->mean[p];
+      c->mean[p] += dlt * inv;
+      c->m2[p] += dlt * (c->x[p] - c->mean[p]);
+    }
+  }
+  free(g);
+  free(G);
+  return bad ? -5 : 0;
+}
+
+int oracle_step(oracle_chain *c, int32_t n_iters) {
+  for (int32_t i = 0; i < n_iters; ++i) {
+    int rc = one_step(c);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+void oracle_get_state(const oracle_chain *c, double *x, int64_t *t) {
+  if (x) memcpy(x, c->x, (size_t)c->cfg.ny * c->cfg.nx * sizeof(double));
+  if (t) *t = c->t;
+}
+
+void oracle_set_state(oracle_chain *c, const double *x, int64_t t) {
+  memcpy(c->x, x, (size_t)c->cfg.ny * c->cfg.nx * sizeof(double));
+  c->t = t;
+}
+
+void oracle_stats(const oracle_chain *c, double *mean, double *m2, int64_t *n) {
+  size_t N = (size_t)c->cfg.ny * c->cfg.nx;
+  if (mean) memcpy(mean, c->mean, N * sizeof(double));
+  if (m2) memcpy(m2, c->m2, N * sizeof(double));
+  if (n) *n = c->n;
+}
+
+void oracle_last_z(const oracle_chain *c, double *z) {
+  memcpy(z, c->z, (size_t)c->cfg.ny * c->cfg.nx * sizeof(double));
+}
+
+void oracle_record_z(oracle_chain *c, int32_t on) { c->record_z = on; }
+
+void oracle_destroy(oracle_chain *c) {
+  if (!c) return;
+  free(c->y); free(c->kernel); free(c->mask); free(c->channels); free(c->w); free(c->b);
+  free(c->fmt); free(c->act_scales); free(c->x); free(c->z); free(c->mean); free(c->m2);
+  free(c);
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
