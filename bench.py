@@ -1,0 +1,173 @@
+"""Throughput of the PnP-ULA hot path on one MI355X.
+
+One step = one full iteration x^(t) -> x^(t+1) of the sampler over the whole
+image (denoiser layers, fused likelihood gradient / z draw / update /
+statistics).  Default workload: 4096 x 4096 image, 9x9 Gaussian blur,
+sigma = 0.02, 8 x 8 blocks of 512 x 512 with an 8-pixel halo, 8-layer
+64-channel denoiser in bf16 with FP32 accumulation, split rho = sigma^2,
+synthetic seeded inputs.  Timed steps run after burn-in, so the Welford
+statistics (and their FP64 merges) are part of every step.
+
+Prints one JSON line.  Extra fields: the same workload in FP32 and e4m3 for
+comparison, the roofline of the dominant kernel (middle convolution layers,
+matrix-core bound) and of the fused update kernel (HBM bound), and the FP64
+oracle timed on the host over a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {0: 157.3, 1: 2500.0, 2: 5000.0}     # MI355X dense: fp32, bf16, fp8
+PEAK_HBM_GBS = 8000.0
+DTYPE = {0: "fp32", 1: "bf16", 2: "fp8_e4m3"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--precision", type=int, default=None)
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-region", type=int, default=160)
+    return ap.parse_args()
+
+
+def fp8_scales(ctx_fp32, wl, x):
+    """Power-of-two e4m3 activation scales from the library's own FP32
+    calibration pass (twice the largest |input| of each layer)."""
+    from paper_2511_00870_amd import workloads as W
+    amax = ctx_fp32.calibrate(x)
+    fmt = W.layer_formats(wl.n_layers, 2)
+    return [float(2.0 ** np.ceil(np.log2(2 * a / 448))) if f == 2 else 1.0
+            for a, f in zip(amax, fmt)]
+
+
+def run_gpu(wl, precision, steps, warmup, stream, act_scales=None, profile=True):
+    import torch
+    from paper_2511_00870_amd import pnpula as P
+    cfg = P.Config.from_workload(wl, precision=precision, act_scales=act_scales, stream=stream)
+    ctx = P.Context(cfg)
+    # start after burn-in so every timed step updates the statistics
+    x0 = np.clip(wl.xbar, 0, 1).astype(np.float32)
+    ctx.set_state(x0, wl.burn_in + 1)
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rc = ctx.sync()
+    prof = {c: ctx.profile_read(c) for c in range(4)} if profile else None
+    ctx.close()
+    return dt, rc, prof
+
+
+def cpu_baseline(wl, region):
+    import oracle.oracle as O
+    oc = O.Chain.from_workload(wl, block=0)
+    x = np.clip(wl.xbar, 0, 1)
+    y0, x0 = wl.ny // 2 - region // 2, wl.nx // 2 - region // 2
+    t0 = time.perf_counter()
+    oc.step_region(x, wl.burn_in + 1, y0, x0, region, region)
+    dt = time.perf_counter() - t0
+    return {"value": round(region * region / dt / 1e6, 6), "unit": "Mpixel*iter/s",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"one FP64 iteration of a {region}x{region} region (plus its "
+                      f"max(2r,K) halo) of the same workload, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2511_00870_amd import workloads as W
+    from paper_2511_00870_amd.accounting import fused_update_bytes_per_pixel
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    wl = W.config(a.config)
+    prec = wl.precision if a.precision is None else a.precision
+    npx = wl.ny * wl.nx
+    F = wl.channels[1]
+    scales = None
+    if prec == 2:
+        from paper_2511_00870_amd import pnpula as P
+        c32 = P.Context(P.Config.from_workload(wl, precision=0, stream=stream))
+        scales = fp8_scales(c32, wl, np.clip(wl.xbar, 0, 1).astype(np.float32))
+        c32.close()
+    dt, rc, prof = run_gpu(wl, prec, a.steps, a.warmup, stream, scales)
+    ms = dt / a.steps * 1e3
+    value = npx * a.steps / dt / 1e6
+    mid_ms, mid_n = prof[0]
+    upd_ms, upd_n = prof[3]
+    flops_launch = 2.0 * 9 * F * F * npx
+    out = {
+        "metric": "Mpixel*Langevin-iter/s at 4096^2 (BF16/FP8 vs FP32); p50/p99 job latency",
+        "value": round(value, 2), "unit": "Mpixel*iter/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": wl.name, "image": [wl.ny, wl.nx], "blur": int(wl.kernel.shape[0]),
+                   "blocks": [wl.block_y, wl.block_x], "halo": wl.halo,
+                   "denoiser": f"{wl.n_layers}x{F}", "split_rho": wl.rho, "iters": wl.iters,
+                   "burn_in": wl.burn_in},
+        "status": rc,
+    }
+    if mid_n:
+        avg = mid_ms / mid_n / 1e3
+        ach = flops_launch / avg / 1e12
+        out["roofline"] = {"bound": "mfma", "kernel": "conv_mid_kernel",
+                           "achieved": round(ach, 2), "peak": PEAK_TFLOPS[prec],
+                           "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4),
+                           "traffic": None, "avg_launch_ms": round(avg * 1e3, 4),
+                           "flops_per_launch": flops_launch}
+    if upd_n:
+        avg = upd_ms / upd_n / 1e3
+        byt = fused_update_bytes_per_pixel(True, wl.mask is not None, wl.welford_window) * npx
+        out["roofline_fused_update"] = {"bound": "hbm", "achieved": round(byt / avg / 1e9, 1),
+                                        "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                        "frac": round(byt / avg / 1e9 / PEAK_HBM_GBS, 4),
+                                        "avg_launch_ms": round(avg * 1e3, 4),
+                                        "bytes_per_launch": byt}
+    out["kernel_ms_per_step"] = {name: round(prof[c][0] / a.steps, 4) for c, name in
+                                 [(0, "conv_mid"), (1, "conv_first"), (2, "conv_last"),
+                                  (3, "fused_update")]}
+    if not a.no_compare:
+        comp = {}
+        for p in (0, 1, 2):
+            if p == prec:
+                comp[DTYPE[p]] = round(value, 2)
+                continue
+            try:
+                sc = None
+                if p == 2:
+                    from paper_2511_00870_amd import pnpula as P
+                    c32 = P.Context(P.Config.from_workload(wl, precision=0, stream=stream))
+                    sc = fp8_scales(c32, wl, np.clip(wl.xbar, 0, 1).astype(np.float32))
+                    c32.close()
+                n = 4 if p == 0 else a.steps
+                d, _, _ = run_gpu(wl, p, n, 1, stream, sc, profile=False)
+                comp[DTYPE[p]] = round(npx * n / d / 1e6, 2)
+            except Exception as e:  # report, do not hide
+                comp[DTYPE[p]] = f"error: {e}"
+        out["compare_precisions"] = comp
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_region)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * pnpula.h -- C ABI of the MI355X plug-and-play ULA sampler (libpnpula.so).
+ *
+ * One context = one Markov chain of the split-Gibbs PnP-ULA sampler of
+ * arXiv 2511.00870 (Sec. II-C, Eq. (sgs_pnp_ula_psgla:pnp_ula) and
+ * Algorithm 1) for a grayscale image observed through y = m * (K x + noise):
+ *
+ *   z^(t) | x^(t)  ~ N((rho y + sigma^2 H x)/(rho + sigma^2),
+ *                      rho sigma^2/(rho + sigma^2) I)         (rho > 0, t >= 1;
+ *                                                               z^(0) = 0)
+ *   x^(t+1) = x - delta H^T (H x - v)/s2 - (alpha delta/eps) G(x)
+ *             + delta inv_lambda (clip_[0,1](x) - x) + sqrt(2 delta) xi
+ *
+ * with H = diag(m) K, (v, s2) = (y, sigma^2) when rho == 0 and (z, rho)
+ * when rho > 0 (approximate data augmentation, Eq.
+ * (general_posterior_l2_axda) with the Gaussian data term as f2), the
+ * denoiser D_eps = Id - G (DnCNN form, Sec. II-B1 Example 2: a stack of
+ * 3x3 convolutions with zero "half" padding, ReLU on all but the last
+ * layer), and online Welford mean / variance of the samples after burn-in
+ * (the MMSE estimate and the pixel-wise variance map, Sec. IV-C).
+ *
+ * The image is split into blocks of block_y x block_x pixels with a halo
+ * of `halo` pixels (Sec. II-A Defs. 1-2; Sec. II-B2): every block is
+ * computed from its extended window of the previous iterate, which stays in
+ * device memory, so the ghost-region exchange is an overlapping read.
+ *
+ * Noise: Philox4x32-10 (Salmon et al., SC'11), key = seed (low word, high
+ * word), counter = (pixel mod 2^32, t, chain, pixel >> 32) with pixel = row
+ * * nx + col; Box-Muller on u1 = ((w0 >> 8) + 1) 2^-24, u2 = (w1 >> 8) 2^-24:
+ * xi = sqrt(-2 ln u1) cos(2 pi u2) and zeta = sqrt(-2 ln u1) sin(2 pi u2).
+ *
+ * Conventions for every call:
+ *  - Host pointers unless stated otherwise.  Inputs are borrowed for the call
+ *    and copied; outputs are caller-allocated.
+ *  - Images are row-major ny x nx, float32 unless stated otherwise.
+ *  - Status codes are returned; nothing throws or aborts across the ABI.
+ *    pnpula_last_error() describes the last failure of a context, and
+ *    pnpula_create_error() the last failed pnpula_create on this thread.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Work is queued on the context's HIP stream; calls that return data
+ *    synchronise that stream first.
+ */
+#ifndef PNPULA_H
+#define PNPULA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pnpula_ctx pnpula_ctx;
+
+typedef enum {
+  PNPULA_OK = 0,
+  PNPULA_EINVAL = -1,     /* invalid argument or configuration */
+  PNPULA_ENOMEM = -2,     /* device allocation failed / over the memory budget */
+  PNPULA_EDEVICE = -3,    /* HIP runtime error or no usable gfx950 device */
+  PNPULA_ESTATE = -4,     /* call not valid in the current state */
+  PNPULA_EDIVERGED = -5   /* a sample became non-finite */
+} pnpula_status;
+
+/* arithmetic of the denoiser convolutions (chain state, likelihood
+ * gradient and noise are always FP32; statistics are merged in FP64) */
+typedef enum {
+  PNPULA_FP32 = 0,        /* FP32 inputs and weights, FP32 accumulation */
+  PNPULA_BF16 = 1,        /* bf16 (RNE) inputs and weights, FP32 accumulation */
+  PNPULA_FP8_E4M3 = 2     /* OCP e4m3fn (RNE, saturating) inputs and weights with
+                             per-output-channel power-of-two weight scales and
+                             per-layer power-of-two activation scales; first and
+                             last layer bf16; FP32 accumulation */
+} pnpula_precision;
+
+typedef struct {
+  int32_t ny, nx;                 /* image size (pixels) */
+  const float *y;                 /* ny*nx observation, zero where mask == 0 */
+  int32_t ksize;                  /* odd blur size L, 1 <= L <= 17 */
+  const float *kernel;            /* L*L blur, row-major; applied as a same-size
+                                     linear convolution with zero boundary */
+  const uint8_t *mask;            /* ny*nx of {0,1} applied after the blur; NULL:
+                                     every pixel observed */
+  double sigma;                   /* noise standard deviation (> 0) */
+  double eps;                     /* denoiser level, variance convention (> 0):
+                                     the prior term is (alpha delta/eps) G(x) */
+  double alpha;                   /* prior weight (>= 0) */
+  double delta;                   /* Langevin step (> 0) */
+  double rho;                     /* splitting parameter (>= 0; 0: no z) */
+  double inv_lambda;              /* 1/lambda of the [0,1] projection term (>= 0) */
+  int32_t block_y, block_x;       /* block size (>= 1); blocks tile the image,
+                                     the last row/column of blocks may be smaller */
+  int32_t halo;                   /* ghost-region width, >= max(2 r, n_layers) with
+                                     r = ksize/2, and < min(block_y, block_x) unless
+                                     a single block covers the image */
+  int32_t n_layers;               /* denoiser depth K >= 1 */
+  const int32_t *channels;        /* K+1 entries, channels[0] = channels[K] = 1,
+                                     inner entries equal F in {16, 32, 64}
+                                     (FP32) or {32, 64} (BF16) or 64 (FP8) */
+  const float *weights;           /* per layer OIHW [c_out][c_in][3][3], layers
+                                     concatenated (cross-correlation, as conv2d) */
+  const float *biases;            /* per layer [c_out], concatenated */
+  int32_t precision;              /* pnpula_precision */
+  const float *act_scales;        /* K entries: power-of-two scale of each layer's
+                                     input for e4m3 layers (others ignored);
+                                     required for PNPULA_FP8_E4M3, else NULL */
+  uint64_t seed;                  /* Philox key */
+  uint32_t chain;                 /* Philox counter word 2 (independent chains) */
+  int32_t burn_in;                /* samples x^(t) with t > burn_in enter the stats */
+  int32_t welford_window;         /* FP32 Welford window before each FP64 merge
+                                     (1..65536; 0: 256) */
+  const float *x0;                /* ny*nx initial state; NULL: zeros */
+  void *stream;                   /* hipStream_t to run on; NULL: a new stream */
+} pnpula_config;
+
+/* Validate cfg, allocate device memory, upload inputs and repack weights.
+ * On success *out holds a context at t = 0. */
+pnpula_status pnpula_create(const pnpula_config *cfg, pnpula_ctx **out);
+
+/* Queue n_iters >= 0 iterations x^(t) -> x^(t+1) on the stream (asynchronous). */
+pnpula_status pnpula_step(pnpula_ctx *ctx, int32_t n_iters);
+
+/* Wait for queued work; PNPULA_EDIVERGED if any sample so far was non-finite. */
+pnpula_status pnpula_sync(pnpula_ctx *ctx);
+
+/* MMSE estimate and pixel variance M2/(n-1) of the samples after burn-in
+ * (FP64 merge of the FP32 windows, rounded to FP32).  mean/var may be NULL.
+ * n_samples receives n (var is 0 when n < 2). */
+pnpula_status pnpula_stats(pnpula_ctx *ctx, float *mean, float *var, int64_t *n_samples);
+
+/* Same statistics in FP64: mean and the sum of squared deviations M2. */
+pnpula_status pnpula_stats_f64(pnpula_ctx *ctx, double *mean, double *m2, int64_t *n_samples);
+
+/* Checkpoint: the state is (x^(t), t) plus the statistics. */
+pnpula_status pnpula_get_state(pnpula_ctx *ctx, float *x, int64_t *t);
+/* Replace x and t (statistics are kept). */
+pnpula_status pnpula_set_state(pnpula_ctx *ctx, const float *x, int64_t t);
+/* Replace x, t and the FP64 statistics (mean, m2 of n samples). */
+pnpula_status pnpula_restore(pnpula_ctx *ctx, const float *x, int64_t t, const double *mean,
+                             const double *m2, int64_t n_samples);
+
+/* Apply the context's denoiser to an ny*nx image: G = x - D_eps(x) (FP32
+ * output).  layers (optional) receives every layer's output, dequantised
+ * to FP32, as channels[k+1] planes of ny*nx per layer (CHW), concatenated. */
+pnpula_status pnpula_denoise(pnpula_ctx *ctx, const float *x, float *G, float *layers);
+
+/* Largest |input| of every layer when the denoiser (in FP32) is applied to
+ * x: the data for choosing e4m3 activation scales. */
+pnpula_status pnpula_calibrate(pnpula_ctx *ctx, const float *x, float *amax);
+
+/* Per-kernel timing with HIP events on the context's stream.  Classes:
+ * 0 = middle convolution layers, 1 = first layer, 2 = last layer,
+ * 3 = fused likelihood/update/statistics kernel.  Enabling resets totals. */
+pnpula_status pnpula_profile(pnpula_ctx *ctx, int32_t enable);
+pnpula_status pnpula_profile_read(pnpula_ctx *ctx, int32_t kernel_class, double *total_ms,
+                                  int64_t *launches);
+
+/* Device pointer of the current x^(t) (padded layout: row pitch in floats
+ * in *pitch, image origin at element *offset), for zero-copy consumers. */
+pnpula_status pnpula_state_device(pnpula_ctx *ctx, const float **base, int64_t *pitch,
+                                  int64_t *offset);
+
+void pnpula_destroy(pnpula_ctx *ctx);
+const char *pnpula_last_error(const pnpula_ctx *ctx);
+const char *pnpula_create_error(void);
+
+/* Device memory one context of this configuration allocates (bytes). */
+pnpula_status pnpula_footprint(const pnpula_config *cfg, size_t *bytes);
+
+/* ------------------------------------------------------------------ *
+ * Serving: many chains of different sizes share one denoiser and one
+ * stream.  Each tick advances every resident job by one iteration with
+ * one launch per kernel over all resident jobs' tiles.  Jobs are admitted
+ * first-in first-out while their footprint fits the memory budget and a
+ * slot is free, and retire when their iteration count is reached.  A job's
+ * result does not depend on its co-residents.
+ * ------------------------------------------------------------------ */
+typedef struct pnpula_server pnpula_server;
+
+/* weights/biases/channels/precision/act_scales as in pnpula_config;
+ * hbm_budget bytes (0: no limit) for the jobs' footprints; max_slots >= 1;
+ * stream as in pnpula_config. */
+pnpula_status pnpula_server_create(int32_t n_layers, const int32_t *channels,
+                                   const float *weights, const float *biases,
+                                   int32_t precision, const float *act_scales,
+                                   size_t hbm_budget, int32_t max_slots, void *stream,
+                                   pnpula_server **out);
+/* Queue a job (the network fields of cfg are ignored; cfg->stream too).
+ * n_iters >= 1.  Inputs are copied.  *job_id identifies it. */
+pnpula_status pnpula_server_submit(pnpula_server *s, const pnpula_config *cfg, int32_t n_iters,
+                                   int64_t *job_id);
+/* Admit, run one tick, retire.  *active receives the number of resident
+ * plus queued jobs after the tick. */
+pnpula_status pnpula_server_tick(pnpula_server *s, int32_t *active);
+/* 1 when the job has finished (result available), 0 otherwise. */
+pnpula_status pnpula_server_poll(pnpula_server *s, int64_t job_id, int32_t *done);
+/* Statistics of a finished job (as pnpula_stats); releases the result. */
+pnpula_status pnpula_server_result(pnpula_server *s, int64_t job_id, float *mean, float *var,
+                                   int64_t *n_samples);
+pnpula_status pnpula_server_run_until_idle(pnpula_server *s);
+void pnpula_server_destroy(pnpula_server *s);
+const char *pnpula_server_last_error(const pnpula_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PNPULA_H */

@@ -706,6 +706,47 @@ static int one_step(oracle_chain *c) {
   return bad ? -5 : 0;
 }
 
+/* x^(t+1) on the region [y0, y0+h) x [x0, x0+w) of the image described by
+ * cfg, from the full x^(t): every operator is evaluated on the region's
+ * extended window of half-width max(2r, K) only (the same window
+ * computation as a block), so sampled outputs of very large images can be
+ * checked one region at a time. */
+int oracle_step_region(const oracle_config *c, const double *x, int64_t t, int32_t y0,
+                       int32_t x0, int32_t h, int32_t w, double *xnew) {
+  int ny = c->ny, nx = c->nx, r = c->ksize / 2, K = c->net.n_layers;
+  if (y0 < 0 || x0 < 0 || h < 1 || w < 1 || y0 + h > ny || x0 + w > nx) return -1;
+  int hh = 2 * r > K ? 2 * r : K;
+  int H = h + 2 * hh, W = w + 2 * hh;
+  double *win = xmalloc((size_t)H * W * sizeof(double));
+  extract_window(x, 1, ny, nx, y0 - hh, x0 - hh, H, W, win);
+  grad_ctx gc = make_grad_ctx(c);
+  int Hg = H - 4 * r, Wg = W - 4 * r, og = hh - 2 * r;
+  double *g = xmalloc((size_t)Hg * Wg * sizeof(double));
+  grad_window(&gc, win, y0 - hh, x0 - hh, H, W, t, g, NULL);
+  prepared_net pn;
+  prepare_net(&c->net, &pn);
+  double *res = denoise_window(&c->net, &pn, win, ny, nx, y0 - hh, x0 - hh, H, W, 0, NULL, NULL);
+  int Wd = W - 2 * K, od = hh - K;
+  const double d = c->delta, cprior = c->alpha * d / c->eps, cproj = d * c->inv_lambda;
+  const double sq = sqrt(2.0 * d);
+  for (int i = 0; i < h; ++i)
+    for (int j = 0; j < w; ++j) {
+      int64_t p = (int64_t)(y0 + i) * nx + (x0 + j);
+      double xi, zeta_unused;
+      draw_pixel(c->seed, p, t, c->chain, &xi, &zeta_unused);
+      double xv = x[p];
+      double proj = xv < 0.0 ? 0.0 : (xv > 1.0 ? 1.0 : xv);
+      double gv = g[(size_t)(i + og) * Wg + j + og];
+      double Gv = res[(size_t)(i + od) * Wd + j + od];
+      xnew[(size_t)i * w + j] = xv - d * gv - cprior * Gv + cproj * (proj - xv) + sq * xi;
+    }
+  free(res);
+  free_net(&pn);
+  free(g);
+  free(win);
+  return 0;
+}
+
 int oracle_step(oracle_chain *c, int32_t n_iters) {
   for (int32_t i = 0; i < n_iters; ++i) {
     int rc = one_step(c);

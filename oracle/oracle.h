@@ -97,6 +97,8 @@ int  oracle_denoiser(const oracle_net *net, const double *x, int32_t ny, int32_t
 int  oracle_denoiser_layers(const oracle_net *net, const double *x, int32_t ny,
                             int32_t nx, double *acts, double *amax);
 int  oracle_data_grad(const oracle_config *cfg, const double *x, int64_t t, double *g);
+int  oracle_step_region(const oracle_config *cfg, const double *x, int64_t t, int32_t y0,
+                        int32_t x0, int32_t h, int32_t w, double *xnew);
 
 #ifdef __cplusplus
 }

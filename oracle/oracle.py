@@ -91,6 +91,8 @@ def _declare(L):
                                          _dp, _dp]
     L.oracle_data_grad.argtypes = [C.POINTER(OracleConfig), _dp, C.c_int64, _dp]
     L.oracle_num_threads.restype = C.c_int
+    L.oracle_step_region.argtypes = [C.POINTER(OracleConfig), _dp, C.c_int64, C.c_int32,
+                                     C.c_int32, C.c_int32, C.c_int32, _dp]
 
 
 def _d(a: np.ndarray):
@@ -285,6 +287,15 @@ class Chain:
         if rc != 0:
             raise ValueError("halo smaller than 2r")
         return g
+
+    def step_region(self, x, t: int, y0: int, x0: int, h: int, w: int):
+        """x^(t+1) on a region, from the full x^(t) (cost ~ region size)."""
+        x = _f64(x)
+        out = np.empty((h, w))
+        rc = lib().oracle_step_region(C.byref(self.cfg), _d(x), t, y0, x0, h, w, _d(out))
+        if rc != 0:
+            raise ValueError("region outside the image")
+        return out
 
     def close(self):
         if getattr(self, "h", None):

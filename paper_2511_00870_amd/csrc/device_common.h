@@ -1,0 +1,137 @@
+// device_common.h -- data layout shared by the host runtime and the gfx950
+// kernels of the PnP-ULA sampler: per-chain job descriptors, tile lists,
+// the Philox4x32-10 generator and the bf16 / e4m3 conversions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pnp {
+
+enum Fmt : int { FMT_F32 = 0, FMT_BF16 = 1, FMT_E4M3 = 2 };
+
+constexpr int kMaxR = 8;           // largest blur half-width (L <= 17)
+constexpr int kUpdTileH = 16;      // fused-update tile (rows x cols)
+constexpr int kUpdTileW = 64;
+constexpr int kConvTileW = 32;     // convolution tiles are TH x 32 pixels
+
+// One chain resident on the device.  All images live in padded row-major
+// buffers whose zero border is never written, so stencils read it as the
+// zero boundary of the operators.
+struct JobDesc {
+  int32_t ny, nx;          // image size
+  int32_t xpitch;          // floats per row of the x / y / mask buffers
+  int32_t xborder;         // zero border (rows and columns) of those buffers
+  int32_t apitch;          // pixels per row of the activation buffers (border 1)
+  int32_t r;               // blur half-width
+  int32_t separable;       // blur kernel = u v^T
+  int32_t has_mask;
+  int32_t split;           // rho > 0
+  int32_t burn_in;
+  int32_t wwin;            // Welford window
+  int32_t pad0;
+  int64_t t_offset;        // this chain's t = tick + t_offset
+  int64_t wbase;           // sample number of the last out-of-band merge point
+                           // (flush, restore or state change); windows of wwin
+                           // samples are merged from there on
+  int64_t nbase;           // FP64 sample count at that point
+  // buffers (device)
+  float *x[2];             // ping-pong x^(t): x[t & 1] holds x^(t)
+  const float *y;          // padded observation
+  const uint8_t *mask;     // padded {0,1} mask or null
+  void *act[4];            // activation buffers (channels-last, border 1); each
+                           // holds one storage format (two per format in use)
+  float *G;                // ny*nx denoiser output (compact)
+  float *wmean, *wm2;      // FP32 Welford window (compact)
+  double *mean, *m2;       // FP64 merged statistics (compact)
+  int32_t *flag;           // non-finite flag
+  const float *kern;       // L*L blur (2-D path)
+  const float *ku, *kv;    // separable factors k[a][c] = ku[a] kv[c]
+  // coefficients, computed in FP64 on the host and rounded once
+  float delta;             // Langevin step
+  float cprior;            // alpha delta / eps
+  float cproj;             // delta / lambda
+  float sq2d;              // sqrt(2 delta)
+  float inv_s2;            // 1/sigma^2 (rho == 0) or 1/rho
+  float zmix;              // rho / (rho + sigma^2): Hx - z = zmix (Hx - y) - zsd zeta
+  float zsd;               // sqrt(rho sigma^2 / (rho + sigma^2))
+  float pad1;
+  uint32_t key0, key1, chain, pad2;
+};
+
+// A rectangle of one job's image: rows [y0, y0+h), cols [x0, x0+w).
+struct TileRef {
+  int32_t job;
+  int32_t y0, x0;
+  int16_t h, w;
+};
+
+// --------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+//   (X0..X3) -> (hi(M1 X2) ^ X1 ^ K0, lo(M1 X2), hi(M0 X0) ^ X3 ^ K1, lo(M0 X0))
+// with the key bumped by (W0, W1) between rounds.
+// --------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Two standard normals of pixel p at iteration t: (cos, sin) Box-Muller
+// branches on 24-bit uniforms, exact in FP32.
+__device__ __forceinline__ void gauss_pair(const JobDesc &j, int64_t p, int64_t t,
+                                           float &xi, float &zeta) {
+  uint4 c = make_uint4((uint32_t)p, (uint32_t)t, j.chain, (uint32_t)((uint64_t)p >> 32));
+  uint4 w = philox4x32_10(c, j.key0, j.key1);
+  const float u1 = (float)((w.x >> 8) + 1u) * 5.9604644775390625e-8f;  // 2^-24
+  const float u2 = (float)(w.y >> 8) * 5.9604644775390625e-8f;
+  const float rad = sqrtf(-2.0f * logf(u1));
+  float s, co;
+  sincospif(2.0f * u2, &s, &co);
+  xi = rad * co;
+  zeta = rad * s;
+}
+
+// --------------------------------------------------------------------
+// bf16 and OCP e4m3fn conversions (round to nearest even; e4m3 saturates)
+// --------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __uint_as_float((uint32_t)b << 16);
+}
+__device__ __forceinline__ float round_bf16(float v) { return bf16_to_f32(f32_to_bf16(v)); }
+
+__device__ __forceinline__ uint8_t f32_to_e4m3(float v) {
+  const uint32_t u = __float_as_uint(v);
+  const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+  const float a = fabsf(v);
+  if (a != a) return (uint8_t)(sign | 0x7f);
+  if (a >= 448.0f) return (uint8_t)(sign | 0x7e);            // saturate
+  if (a < 0.015625f) {                                        // below 2^-6: step 2^-9
+    const float q = rintf(a * 512.0f);                        // 0..8 (8 = 2^-6)
+    return (uint8_t)(sign | (uint8_t)q);
+  }
+  uint32_t b = __float_as_uint(a);
+  b += 0x7ffffu + ((b >> 20) & 1u);                           // RNE to 3 mantissa bits
+  const uint32_t e = (b >> 23) - 127u + 7u;
+  const uint32_t m = (b >> 20) & 7u;
+  return (uint8_t)(sign | (e << 3) | m);
+}
+__device__ __forceinline__ float e4m3_to_f32(uint8_t c) {
+  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  float v = (e == 0) ? (float)m * 0.001953125f                 // m 2^-9
+                     : __uint_as_float(((e + 120u) << 23) | (m << 20));
+  return (c & 0x80) ? -v : v;
+}
+
+}  // namespace pnp

@@ -1,0 +1,125 @@
+// engine.h -- host runtime of the PnP-ULA sampler: the shared denoiser,
+// resident chains (jobs), block/tile plans and the per-iteration launch
+// sequence.  A context is an engine with one job; the server is an engine
+// with a scheduler in front of it.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pnpula.h"
+#include "kernels.h"
+
+namespace pnp {
+
+struct Status {
+  pnpula_status code = PNPULA_OK;
+  std::string msg;
+  static Status ok() { return {}; }
+  static Status fail(pnpula_status c, std::string m) { return {c, std::move(m)}; }
+  bool good() const { return code == PNPULA_OK; }
+};
+
+// One layer of the denoiser as the kernels consume it.
+struct LayerPlan {
+  int cin = 0, cout = 0;
+  int in_fmt = FMT_F32;     // format of the layer's input and weights
+  int out_fmt = FMT_F32;    // format the output is stored in (next layer's input)
+  int relu = 0;
+  float in_inv_scale = 1.f, out_inv_scale = 1.f;
+  float in_scale = 1.f;     // scale of the stored input (e4m3), else 1
+  int in_buf = 0, out_buf = 0;  // activation buffers read / written
+  void *wblob = nullptr;    // middle layers: MFMA fragment order
+  float *wf32 = nullptr;    // first / last layer: [c][9]
+  float *bias = nullptr, *oscale = nullptr;
+};
+
+struct NetPlan {
+  int K = 0, F = 0, precision = PNPULA_FP32;
+  std::vector<int> channels;
+  std::vector<float> weights, biases, act_scales;  // host copies
+  std::vector<LayerPlan> layers;
+  int buf_fmt[4] = {-1, -1, -1, -1};  // storage format of each activation buffer
+  std::vector<void *> allocs;
+};
+
+struct Job {
+  JobDesc d{};              // host mirror of the device descriptor
+  int64_t t = 0;            // current iteration
+  int block_y = 0, block_x = 0, halo = 0;
+  int64_t target = 0;       // serving: iterations to run
+  int64_t id = 0;
+  bool diverged = false;
+  size_t footprint = 0;
+  std::vector<void *> allocs;
+  std::vector<TileRef> conv_tiles, upd_tiles;   // job field = 0 (set at planning)
+};
+
+struct ProfileRec {
+  int cls;
+  hipEvent_t a, b;
+};
+
+class Engine {
+ public:
+  ~Engine();
+  Status init(void *stream);
+  Status set_net(int K, const int32_t *channels, const float *w, const float *b, int precision,
+                 const float *act_scales);
+  static Status validate_job(const pnpula_config *cfg, int K, const std::vector<int> &ch);
+  static size_t job_footprint(const pnpula_config *cfg, const NetPlan &net);
+  Status make_job(const pnpula_config *cfg, Job **out);
+  void free_job(Job *j);
+
+  // run one iteration of every resident job
+  Status tick();
+  Status sync_check(bool *diverged);
+  Status upload_descs();
+  Status rebuild_plan();
+
+  // single-job helpers
+  Status get_state(Job *j, float *x);
+  Status set_state(Job *j, const float *x, int64_t t);
+  Status flush_stats(Job *j, int64_t *n_total);
+  Status read_stats(Job *j, double *mean, double *m2, int64_t *n);
+  Status restore_stats(Job *j, const double *mean, const double *m2, int64_t n);
+  Status denoise(Job *j, const float *x, float *G, float *layers, float *amax);
+
+  void profile_enable(bool on);
+  Status profile_read(int cls, double *ms, int64_t *launches);
+
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0, n_cu = 0;
+  NetPlan net;
+  std::vector<Job *> resident;
+  int64_t ticks = 0;
+  bool plan_dirty = true;
+  std::string err;
+
+ private:
+  Status run_denoiser(int64_t tick);
+  Status launch_layer(int k, int64_t tick, bool prof);
+  JobDesc *d_jobs = nullptr;
+  TileRef *d_conv = nullptr, *d_upd = nullptr;
+  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0;
+  int n_conv = 0, n_upd = 0, max_r = 0;
+  int conv_th = 16;
+  bool profiling = false;
+  std::vector<ProfileRec> prof_pending;
+  std::vector<hipEvent_t> prof_free;
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_n[4] = {0, 0, 0, 0};
+  void prof_begin(int cls, ProfileRec *r);
+  void prof_end(ProfileRec *r);
+};
+
+// host-side rounding used when repacking weights (round to nearest even)
+float host_round_bf16(float v);
+uint8_t host_f32_to_e4m3(float v);
+float host_e4m3_to_f32(uint8_t c);
+float host_pow2_scale(float amax);
+bool host_is_pow2(float v);
+
+}  // namespace pnp

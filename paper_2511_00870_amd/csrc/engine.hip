@@ -1,0 +1,878 @@
+// engine.hip -- host runtime: device memory, weight repacking, block and
+// tile plans, and the launch sequence of one PnP-ULA iteration.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace pnp {
+
+#define HIPOK(expr)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return Status::fail(PNPULA_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------
+// host rounding helpers (used only to repack weights on the host)
+// ---------------------------------------------------------------------
+float host_round_bf16(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return v;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  u &= 0xffff0000u;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return r;
+}
+
+uint8_t host_f32_to_e4m3(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+  const float a = std::fabs(v);
+  if (a != a) return (uint8_t)(sign | 0x7f);
+  if (a >= 448.0f) return (uint8_t)(sign | 0x7e);
+  if (a < 0.015625f) return (uint8_t)(sign | (uint8_t)std::nearbyint(a * 512.0f));
+  uint32_t b;
+  std::memcpy(&b, &a, 4);
+  b += 0x7ffffu + ((b >> 20) & 1u);
+  return (uint8_t)(sign | ((((b >> 23) - 120u) & 15u) << 3) | ((b >> 20) & 7u));
+}
+
+float host_e4m3_to_f32(uint8_t c) {
+  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  float v = (e == 0) ? (float)m * 0.001953125f : std::ldexp(1.0f + (float)m / 8.0f, (int)e - 7);
+  return (c & 0x80) ? -v : v;
+}
+
+float host_pow2_scale(float amax) {
+  if (!(amax > 0.0f)) return 1.0f;
+  int e;
+  const double f = std::frexp((double)amax / 448.0, &e);
+  return (float)((f == 0.5) ? std::ldexp(1.0, e - 1) : std::ldexp(1.0, e));
+}
+
+bool host_is_pow2(float v) {
+  if (!(v > 0.0f) || !std::isfinite(v)) return false;
+  int e;
+  return std::frexp(v, &e) == 0.5f;
+}
+
+static float quant_host(float v, int fmt) {
+  if (fmt == FMT_BF16) return host_round_bf16(v);
+  if (fmt == FMT_E4M3) return host_e4m3_to_f32(host_f32_to_e4m3(v));
+  return v;
+}
+
+static int fmt_bytes(int fmt) { return fmt == FMT_F32 ? 4 : (fmt == FMT_BF16 ? 2 : 1); }
+
+// ---------------------------------------------------------------------
+// engine lifetime
+// ---------------------------------------------------------------------
+Engine::~Engine() {
+  if (stream) hipStreamSynchronize(stream);
+  for (Job *j : resident) free_job(j);
+  resident.clear();
+  for (void *p : net.allocs) hipFree(p);
+  hipFree(d_jobs);
+  hipFree(d_conv);
+  hipFree(d_upd);
+  for (auto &r : prof_pending) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (auto e : prof_free) hipEventDestroy(e);
+  if (own_stream && stream) hipStreamDestroy(stream);
+}
+
+Status Engine::init(void *user_stream) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1)
+    return Status::fail(PNPULA_EDEVICE, "no HIP device");
+  HIPOK(hipGetDevice(&device));
+  hipDeviceProp_t prop;
+  HIPOK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return Status::fail(PNPULA_EDEVICE,
+                        std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+  n_cu = prop.multiProcessorCount;
+  if (user_stream) {
+    stream = reinterpret_cast<hipStream_t>(user_stream);
+    own_stream = false;
+  } else {
+    HIPOK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    own_stream = true;
+  }
+  return Status::ok();
+}
+
+// ---------------------------------------------------------------------
+// denoiser: formats, scales and weight repacking
+// ---------------------------------------------------------------------
+Status Engine::set_net(int K, const int32_t *ch, const float *w, const float *b, int precision,
+                       const float *act_scales) {
+  if (K < 1 || !ch || !w || !b) return Status::fail(PNPULA_EINVAL, "denoiser missing");
+  if (ch[0] != 1 || ch[K] != 1) return Status::fail(PNPULA_EINVAL, "channels must start and end at 1");
+  if (precision < PNPULA_FP32 || precision > PNPULA_FP8_E4M3)
+    return Status::fail(PNPULA_EINVAL, "unknown precision");
+  int F = K > 1 ? ch[1] : 1;
+  for (int k = 1; k < K; ++k)
+    if (ch[k] != F) return Status::fail(PNPULA_EINVAL, "inner channel counts must be equal");
+  if (K > 1) {
+    bool ok = (precision == PNPULA_FP32 && (F == 16 || F == 32 || F == 64)) ||
+              (precision == PNPULA_BF16 && (F == 32 || F == 64)) ||
+              (precision == PNPULA_FP8_E4M3 && F == 64);
+    if (!ok) return Status::fail(PNPULA_EINVAL, "unsupported feature count for this precision");
+  }
+  if (precision == PNPULA_FP8_E4M3 && K < 3)
+    return Status::fail(PNPULA_EINVAL, "e4m3 needs at least 3 layers (first and last are bf16)");
+  net = NetPlan();
+  net.K = K;
+  net.F = F;
+  net.precision = precision;
+  net.channels.assign(ch, ch + K + 1);
+  size_t nw = 0, nb = 0;
+  for (int k = 0; k < K; ++k) {
+    nw += (size_t)ch[k] * ch[k + 1] * 9;
+    nb += (size_t)ch[k + 1];
+  }
+  net.weights.assign(w, w + nw);
+  net.biases.assign(b, b + nb);
+  for (size_t i = 0; i < nw; ++i)
+    if (!std::isfinite(w[i])) return Status::fail(PNPULA_EINVAL, "non-finite weight");
+  // per-layer formats
+  std::vector<int> fmt(K);
+  for (int k = 0; k < K; ++k) {
+    if (precision == PNPULA_FP32) fmt[k] = FMT_F32;
+    else if (precision == PNPULA_BF16) fmt[k] = FMT_BF16;
+    else fmt[k] = (k == 0 || k == K - 1) ? FMT_BF16 : FMT_E4M3;
+  }
+  net.act_scales.assign(K, 1.0f);
+  if (precision == PNPULA_FP8_E4M3) {
+    if (!act_scales) return Status::fail(PNPULA_EINVAL, "e4m3 needs act_scales");
+    for (int k = 0; k < K; ++k) {
+      if (fmt[k] == FMT_E4M3 && !host_is_pow2(act_scales[k]))
+        return Status::fail(PNPULA_EINVAL, "activation scales must be powers of two");
+      net.act_scales[k] = fmt[k] == FMT_E4M3 ? act_scales[k] : 1.0f;
+    }
+  }
+  size_t woff = 0, boff = 0;
+  net.layers.resize(K);
+  for (int k = 0; k < K; ++k) {
+    LayerPlan &L = net.layers[k];
+    L.cin = ch[k];
+    L.cout = ch[k + 1];
+    L.in_fmt = fmt[k];
+    L.out_fmt = (k < K - 1) ? fmt[k + 1] : FMT_F32;
+    L.relu = k < K - 1;
+    L.in_scale = net.act_scales[k];
+    L.in_inv_scale = 1.0f / net.act_scales[k];
+    L.out_inv_scale = (k < K - 1) ? 1.0f / net.act_scales[k + 1] : 1.0f;
+    // weight scales (power of two per output channel for e4m3) and rounding
+    std::vector<float> sw(L.cout, 1.0f);
+    const float *wk = w + woff;
+    if (L.in_fmt == FMT_E4M3)
+      for (int co = 0; co < L.cout; ++co) {
+        float amax = 0.f;
+        for (int i = 0; i < L.cin * 9; ++i) amax = std::max(amax, std::fabs(wk[co * L.cin * 9 + i]));
+        sw[co] = host_pow2_scale(amax);
+      }
+    std::vector<float> wq((size_t)L.cout * L.cin * 9);
+    for (int co = 0; co < L.cout; ++co)
+      for (int i = 0; i < L.cin * 9; ++i)
+        wq[(size_t)co * L.cin * 9 + i] = quant_host(wk[(size_t)co * L.cin * 9 + i] / sw[co], L.in_fmt);
+    std::vector<float> osc(L.cout);
+    for (int co = 0; co < L.cout; ++co) osc[co] = sw[co] * L.in_scale;
+    // device copies: bias and oscale padded to 16 floats for vector loads
+    const int cpad = std::max(L.cout, 16);
+    std::vector<float> bias(cpad, 0.f), oscp(cpad, 0.f);
+    for (int co = 0; co < L.cout; ++co) {
+      bias[co] = b[boff + co];
+      oscp[co] = osc[co];
+    }
+    HIPOK(hipMalloc(&L.bias, cpad * sizeof(float)));
+    net.allocs.push_back(L.bias);
+    HIPOK(hipMalloc(&L.oscale, cpad * sizeof(float)));
+    net.allocs.push_back(L.oscale);
+    HIPOK(hipMemcpy(L.bias, bias.data(), cpad * sizeof(float), hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(L.oscale, oscp.data(), cpad * sizeof(float), hipMemcpyHostToDevice));
+    const bool mid = (k > 0 && k < K - 1);
+    if (!mid) {
+      // [c][9]: first layer c = c_out (c_in = 1); last layer c = c_in (c_out = 1)
+      std::vector<float> f((size_t)std::max(L.cin, L.cout) * 9);
+      for (int co = 0; co < L.cout; ++co)
+        for (int ci = 0; ci < L.cin; ++ci)
+          for (int tap = 0; tap < 9; ++tap)
+            f[(size_t)(L.cin == 1 ? co : ci) * 9 + tap] = wq[((size_t)co * L.cin + ci) * 9 + tap];
+      HIPOK(hipMalloc(&L.wf32, f.size() * sizeof(float)));
+      net.allocs.push_back(L.wf32);
+      HIPOK(hipMemcpy(L.wf32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      const int MB = F / 16;
+      auto W = [&](int co, int ci, int tap) { return wq[((size_t)co * F + ci) * 9 + tap]; };
+      std::vector<uint8_t> blob;
+      if (L.in_fmt == FMT_BF16) {
+        const int nstep = 9 * (F / 32);
+        blob.resize((size_t)nstep * MB * 64 * 16);
+        for (int s = 0; s < nstep; ++s)
+          for (int mb = 0; mb < MB; ++mb)
+            for (int l = 0; l < 64; ++l)
+              for (int e = 0; e < 8; ++e) {
+                const int tap = s / (F / 32), half = s % (F / 32);
+                const int co = mb * 16 + (l & 15), ci = half * 32 + (l >> 4) * 8 + e;
+                float v = W(co, ci, tap);
+                uint32_t u;
+                std::memcpy(&u, &v, 4);
+                const uint16_t hb = (uint16_t)(u >> 16);   // already bf16-rounded
+                std::memcpy(&blob[(((size_t)s * MB + mb) * 64 + l) * 16 + e * 2], &hb, 2);
+              }
+      } else if (L.in_fmt == FMT_F32) {
+        const int nstep = 9 * (F / 16);
+        blob.resize((size_t)nstep * MB * 64 * 16);
+        for (int s = 0; s < nstep; ++s)
+          for (int mb = 0; mb < MB; ++mb)
+            for (int l = 0; l < 64; ++l)
+              for (int e = 0; e < 4; ++e) {
+                const int tap = s / (F / 16), ss = s % (F / 16);
+                const int co = mb * 16 + (l & 15), ci = ss * 16 + (l >> 4) * 4 + e;
+                const float v = W(co, ci, tap);
+                std::memcpy(&blob[(((size_t)s * MB + mb) * 64 + l) * 16 + e * 4], &v, 4);
+              }
+      } else {  // e4m3, F == 64: 5 steps of two taps
+        blob.assign((size_t)5 * MB * 64 * 32, 0);
+        for (int s = 0; s < 5; ++s)
+          for (int mb = 0; mb < MB; ++mb)
+            for (int l = 0; l < 64; ++l)
+              for (int e = 0; e < 32; ++e) {
+                const int g = l >> 4, tap = 2 * s + (g >> 1);
+                if (tap > 8) continue;
+                const int co = mb * 16 + (l & 15), ci = 32 * (g & 1) + e;
+                blob[(((size_t)s * MB + mb) * 64 + l) * 32 + e] = host_f32_to_e4m3(W(co, ci, tap));
+              }
+      }
+      HIPOK(hipMalloc(&L.wblob, blob.size()));
+      net.allocs.push_back(L.wblob);
+      HIPOK(hipMemcpy(L.wblob, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    }
+    woff += (size_t)L.cin * L.cout * 9;
+    boff += (size_t)L.cout;
+  }
+  // activation buffers: every storage format gets its own pair (one buffer
+  // when a single layer writes it), so a buffer's zero border is never
+  // overwritten by pixels of a layout with a different pixel size
+  {
+    int base[3] = {-1, -1, -1}, count[3] = {0, 0, 0}, next = 0;
+    for (int k = 0; k + 1 < K; ++k) count[net.layers[k].out_fmt] += 1;
+    int parity[3] = {0, 0, 0};
+    for (int k = 0; k + 1 < K; ++k) {
+      const int f = net.layers[k].out_fmt;
+      if (base[f] < 0) {
+        base[f] = next;
+        const int nb = count[f] > 1 ? 2 : 1;
+        for (int i = 0; i < nb; ++i) net.buf_fmt[next + i] = f;
+        next += nb;
+      }
+      net.layers[k].out_buf = base[f] + parity[f];
+      if (count[f] > 1) parity[f] ^= 1;
+      net.layers[k + 1].in_buf = net.layers[k].out_buf;
+    }
+  }
+  conv_th = (K > 2) ? mid_tile_rows(net.layers[1].in_fmt) : 16;
+  plan_dirty = true;
+  return Status::ok();
+}
+
+// ---------------------------------------------------------------------
+// jobs
+// ---------------------------------------------------------------------
+Status Engine::validate_job(const pnpula_config *c, int K, const std::vector<int> &) {
+  if (!c) return Status::fail(PNPULA_EINVAL, "null config");
+  if (c->ny < 1 || c->nx < 1) return Status::fail(PNPULA_EINVAL, "image size must be positive");
+  if ((int64_t)c->ny * c->nx > (int64_t)1 << 40) return Status::fail(PNPULA_EINVAL, "image too large");
+  if (!c->y) return Status::fail(PNPULA_EINVAL, "y is required");
+  if (c->ksize < 1 || c->ksize % 2 == 0 || c->ksize > 2 * kMaxR + 1 || !c->kernel)
+    return Status::fail(PNPULA_EINVAL, "blur size must be odd and at most 17");
+  if (!(c->sigma > 0) || !(c->eps > 0) || !(c->delta > 0) || !(c->rho >= 0) ||
+      !(c->alpha >= 0) || !(c->inv_lambda >= 0) || !std::isfinite(c->sigma) ||
+      !std::isfinite(c->eps) || !std::isfinite(c->delta) || !std::isfinite(c->rho) ||
+      !std::isfinite(c->alpha) || !std::isfinite(c->inv_lambda))
+    return Status::fail(PNPULA_EINVAL, "sigma, eps, delta must be > 0; rho, alpha, inv_lambda >= 0");
+  if (c->block_y < 1 || c->block_x < 1) return Status::fail(PNPULA_EINVAL, "block size must be >= 1");
+  const int r = c->ksize / 2;
+  const bool single = c->block_y >= c->ny && c->block_x >= c->nx;
+  if (!single) {
+    if (c->halo < std::max(2 * r, K))
+      return Status::fail(PNPULA_EINVAL, "halo must be >= max(2r, n_layers)");
+    if (c->halo >= std::min(c->block_y, c->block_x))
+      return Status::fail(PNPULA_EINVAL, "halo must be smaller than the blocks");
+  }
+  if (c->burn_in < 0) return Status::fail(PNPULA_EINVAL, "burn_in must be >= 0");
+  if (c->welford_window < 0 || c->welford_window > 65536)
+    return Status::fail(PNPULA_EINVAL, "welford_window out of range");
+  return Status::ok();
+}
+
+struct Geometry {
+  int B, rows, pitch;        // padded x / y / mask buffers
+  int arows, apitch;         // activation buffers
+};
+
+static Geometry geometry(int ny, int nx, int r) {
+  Geometry g;
+  g.B = std::max(2 * r, 1);
+  g.rows = ny + 2 * g.B + kUpdTileH;
+  g.pitch = ((nx + 2 * g.B + kUpdTileW) + 63) / 64 * 64;
+  g.arows = ny + 2 + 16;
+  g.apitch = nx + 2 + kConvTileW;
+  return g;
+}
+
+size_t Engine::job_footprint(const pnpula_config *c, const NetPlan &n) {
+  const Geometry g = geometry(c->ny, c->nx, c->ksize / 2);
+  const size_t N = (size_t)c->ny * c->nx;
+  size_t bytes = 3 * (size_t)g.rows * g.pitch * sizeof(float);          // x[2], y
+  if (c->mask) bytes += (size_t)g.rows * g.pitch;
+  for (int b = 0; b < 4; ++b)
+    if (n.buf_fmt[b] >= 0) bytes += (size_t)g.arows * g.apitch * n.F * fmt_bytes(n.buf_fmt[b]);
+  bytes += N * (sizeof(float) * 3 + sizeof(double) * 2);                // G, Welford
+  bytes += 4096;
+  return bytes;
+}
+
+template <class T>
+static Status dalloc(Job *j, T **p, size_t bytes) {
+  void *v = nullptr;
+  hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return Status::fail(PNPULA_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  j->allocs.push_back(v);
+  *p = reinterpret_cast<T *>(v);
+  return Status::ok();
+}
+
+#define TRY(expr)                 \
+  do {                            \
+    Status s_ = (expr);           \
+    if (!s_.good()) return s_;    \
+  } while (0)
+
+static void make_tiles(std::vector<TileRef> &out, int ny, int nx, int by, int bx, int TH, int TW) {
+  out.clear();
+  for (int y0 = 0; y0 < ny; y0 += by)
+    for (int x0 = 0; x0 < nx; x0 += bx) {
+      const int bh = std::min(by, ny - y0), bw = std::min(bx, nx - x0);
+      for (int ty = 0; ty < bh; ty += TH)
+        for (int tx = 0; tx < bw; tx += TW) {
+          TileRef t;
+          t.job = 0;
+          t.y0 = y0 + ty;
+          t.x0 = x0 + tx;
+          t.h = (int16_t)std::min(TH, bh - ty);
+          t.w = (int16_t)std::min(TW, bw - tx);
+          out.push_back(t);
+        }
+    }
+}
+
+Status Engine::make_job(const pnpula_config *c, Job **out) {
+  TRY(validate_job(c, net.K, net.channels));
+  Job *j = new Job();
+  auto fail = [&](Status s) { free_job(j); return s; };
+  const int ny = c->ny, nx = c->nx, r = c->ksize / 2, L = c->ksize;
+  const Geometry g = geometry(ny, nx, r);
+  const size_t N = (size_t)ny * nx;
+  JobDesc &d = j->d;
+  d.ny = ny;
+  d.nx = nx;
+  d.xpitch = g.pitch;
+  d.xborder = g.B;
+  d.apitch = g.apitch;
+  d.r = r;
+  d.has_mask = c->mask != nullptr;
+  d.split = c->rho > 0;
+  d.burn_in = c->burn_in;
+  d.wwin = c->welford_window > 0 ? c->welford_window : 256;
+  j->block_y = std::min(c->block_y, ny);
+  j->block_x = std::min(c->block_x, nx);
+  j->halo = c->halo;
+  j->footprint = job_footprint(c, net);
+  const size_t xbytes = (size_t)g.rows * g.pitch * sizeof(float);
+  Status s;
+  if (!(s = dalloc(j, &d.x[0], xbytes)).good()) return fail(s);
+  if (!(s = dalloc(j, &d.x[1], xbytes)).good()) return fail(s);
+  float *yb = nullptr;
+  if (!(s = dalloc(j, &yb, xbytes)).good()) return fail(s);
+  d.y = yb;
+  hipError_t e = hipSuccess;
+  e = hipMemsetAsync(d.x[0], 0, xbytes, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.x[1], 0, xbytes, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(yb, 0, xbytes, stream);
+  const size_t hpitch = (size_t)nx * sizeof(float), dpitch = (size_t)g.pitch * sizeof(float);
+  const size_t origin = (size_t)g.B * g.pitch + g.B;
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(yb + origin, dpitch, c->y, hpitch, hpitch, ny, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && c->x0)
+    e = hipMemcpy2DAsync(d.x[0] + origin, dpitch, c->x0, hpitch, hpitch, ny, hipMemcpyHostToDevice,
+                         stream);
+  if (e == hipSuccess && c->mask) {
+    uint8_t *mb = nullptr;
+    if (!(s = dalloc(j, &mb, (size_t)g.rows * g.pitch)).good()) return fail(s);
+    e = hipMemsetAsync(mb, 0, (size_t)g.rows * g.pitch, stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(mb + origin, g.pitch, c->mask, nx, nx, ny, hipMemcpyHostToDevice, stream);
+    d.mask = mb;
+  }
+  if (e != hipSuccess) return fail(Status::fail(PNPULA_EDEVICE, hipGetErrorString(e)));
+  for (int b = 0; b < 4; ++b) {
+    if (net.buf_fmt[b] < 0) continue;
+    const size_t abytes = (size_t)g.arows * g.apitch * net.F * fmt_bytes(net.buf_fmt[b]);
+    uint8_t *ab = nullptr;
+    if (!(s = dalloc(j, &ab, abytes)).good()) return fail(s);
+    if (hipMemsetAsync(ab, 0, abytes, stream) != hipSuccess)
+      return fail(Status::fail(PNPULA_EDEVICE, "memset"));
+    d.act[b] = ab;
+  }
+  if (!(s = dalloc(j, &d.G, N * sizeof(float))).good()) return fail(s);
+  if (!(s = dalloc(j, &d.wmean, N * sizeof(float))).good()) return fail(s);
+  if (!(s = dalloc(j, &d.wm2, N * sizeof(float))).good()) return fail(s);
+  if (!(s = dalloc(j, &d.mean, N * sizeof(double))).good()) return fail(s);
+  if (!(s = dalloc(j, &d.m2, N * sizeof(double))).good()) return fail(s);
+  if (!(s = dalloc(j, &d.flag, 64)).good()) return fail(s);
+  if (hipMemsetAsync(d.flag, 0, 64, stream) != hipSuccess ||
+      hipMemsetAsync(d.mean, 0, N * sizeof(double), stream) != hipSuccess ||
+      hipMemsetAsync(d.m2, 0, N * sizeof(double), stream) != hipSuccess)
+    return fail(Status::fail(PNPULA_EDEVICE, "memset"));
+  // blur: full kernel, and its rank-1 factors when it is separable
+  std::vector<float> kern(c->kernel, c->kernel + L * L);
+  std::vector<float> ku(L, 0.f), kv(L, 0.f);
+  {
+    int pa = 0, pc = 0;
+    double best = -1;
+    for (int a = 0; a < L; ++a)
+      for (int b = 0; b < L; ++b)
+        if (std::fabs((double)kern[a * L + b]) > best) {
+          best = std::fabs((double)kern[a * L + b]);
+          pa = a;
+          pc = b;
+        }
+    bool sep = best > 0;
+    if (sep) {
+      const double piv = kern[pa * L + pc];
+      double scale = 0;
+      for (int a = 0; a < L * L; ++a) scale = std::max(scale, std::fabs((double)kern[a]));
+      for (int a = 0; a < L && sep; ++a)
+        for (int b = 0; b < L; ++b) {
+          const double pred = (double)kern[a * L + pc] * (double)kern[pa * L + b] / piv;
+          if (std::fabs(pred - (double)kern[a * L + b]) > 1e-6 * scale) {
+            sep = false;
+            break;
+          }
+        }
+      if (sep) {
+        const double sq = std::sqrt(std::fabs(piv));
+        for (int a = 0; a < L; ++a) ku[a] = (float)((double)kern[a * L + pc] / sq);
+        for (int b = 0; b < L; ++b) kv[b] = (float)((double)kern[pa * L + b] / sq * (piv < 0 ? -1 : 1));
+      }
+    }
+    d.separable = sep;
+  }
+  for (float v : kern)
+    if (!std::isfinite(v)) return fail(Status::fail(PNPULA_EINVAL, "non-finite blur kernel"));
+  float *kd = nullptr;
+  if (!(s = dalloc(j, &kd, (size_t)3 * L * L * sizeof(float))).good()) return fail(s);
+  std::vector<float> kall(3 * L * L, 0.f);
+  std::copy(kern.begin(), kern.end(), kall.begin());
+  std::copy(ku.begin(), ku.end(), kall.begin() + L * L);
+  std::copy(kv.begin(), kv.end(), kall.begin() + 2 * L * L);
+  if (hipMemcpyAsync(kd, kall.data(), kall.size() * sizeof(float), hipMemcpyHostToDevice, stream) !=
+      hipSuccess)
+    return fail(Status::fail(PNPULA_EDEVICE, "kernel upload"));
+  d.kern = kd;
+  d.ku = kd + L * L;
+  d.kv = kd + 2 * L * L;
+  // coefficients (FP64, rounded once)
+  const double sig2 = c->sigma * c->sigma;
+  d.delta = (float)c->delta;
+  d.cprior = (float)(c->alpha * c->delta / c->eps);
+  d.cproj = (float)(c->delta * c->inv_lambda);
+  d.sq2d = (float)std::sqrt(2.0 * c->delta);
+  d.inv_s2 = (float)(c->rho > 0 ? 1.0 / c->rho : 1.0 / sig2);
+  d.zmix = (float)(c->rho > 0 ? c->rho / (c->rho + sig2) : 0.0);
+  d.zsd = (float)(c->rho > 0 ? std::sqrt(c->rho * sig2 / (c->rho + sig2)) : 0.0);
+  d.key0 = (uint32_t)c->seed;
+  d.key1 = (uint32_t)(c->seed >> 32);
+  d.chain = c->chain;
+  d.wbase = 0;
+  d.nbase = 0;
+  j->t = 0;
+  make_tiles(j->conv_tiles, ny, nx, j->block_y, j->block_x, conv_th, kConvTileW);
+  make_tiles(j->upd_tiles, ny, nx, j->block_y, j->block_x, kUpdTileH, kUpdTileW);
+  if (hipStreamSynchronize(stream) != hipSuccess)
+    return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
+  *out = j;
+  return Status::ok();
+}
+
+void Engine::free_job(Job *j) {
+  if (!j) return;
+  for (void *p : j->allocs) hipFree(p);
+  delete j;
+}
+
+// ---------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------
+Status Engine::rebuild_plan() {
+  std::vector<TileRef> conv, upd;
+  max_r = 0;
+  for (size_t ji = 0; ji < resident.size(); ++ji) {
+    Job *j = resident[ji];
+    for (TileRef t : j->conv_tiles) {
+      t.job = (int)ji;
+      conv.push_back(t);
+    }
+    for (TileRef t : j->upd_tiles) {
+      t.job = (int)ji;
+      upd.push_back(t);
+    }
+    max_r = std::max(max_r, j->d.r);
+  }
+  auto grow = [&](auto **p, size_t &cap, size_t need, size_t elem) -> Status {
+    if (need > cap) {
+      hipFree(*p);
+      *p = nullptr;
+      size_t n = std::max(need, cap * 2);
+      void *v = nullptr;
+      if (hipMalloc(&v, n * elem) != hipSuccess)
+        return Status::fail(PNPULA_ENOMEM, "plan allocation failed");
+      *p = reinterpret_cast<std::remove_reference_t<decltype(**p)> *>(v);
+      cap = n;
+    }
+    return Status::ok();
+  };
+  HIPOK(hipStreamSynchronize(stream));
+  TRY(grow(&d_conv, cap_conv, std::max<size_t>(conv.size(), 1), sizeof(TileRef)));
+  TRY(grow(&d_upd, cap_upd, std::max<size_t>(upd.size(), 1), sizeof(TileRef)));
+  TRY(grow(&d_jobs, cap_jobs, std::max<size_t>(resident.size(), 1), sizeof(JobDesc)));
+  if (!conv.empty())
+    HIPOK(hipMemcpyAsync(d_conv, conv.data(), conv.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
+  if (!upd.empty())
+    HIPOK(hipMemcpyAsync(d_upd, upd.data(), upd.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
+  n_conv = (int)conv.size();
+  n_upd = (int)upd.size();
+  plan_dirty = false;
+  return upload_descs();
+}
+
+Status Engine::upload_descs() {
+  std::vector<JobDesc> ds(resident.size());
+  for (size_t i = 0; i < resident.size(); ++i) {
+    resident[i]->d.t_offset = resident[i]->t - ticks;
+    ds[i] = resident[i]->d;
+  }
+  if (!ds.empty())
+    HIPOK(hipMemcpyAsync(d_jobs, ds.data(), ds.size() * sizeof(JobDesc), hipMemcpyHostToDevice, stream));
+  // the staging copy of pageable memory completes before return only for
+  // small transfers; wait so that ds can be released safely
+  HIPOK(hipStreamSynchronize(stream));
+  return Status::ok();
+}
+
+// ---------------------------------------------------------------------
+// profiling with events on the engine's stream
+// ---------------------------------------------------------------------
+void Engine::profile_enable(bool on) {
+  hipStreamSynchronize(stream);
+  for (auto &r : prof_pending) {
+    prof_free.push_back(r.a);
+    prof_free.push_back(r.b);
+  }
+  prof_pending.clear();
+  for (int i = 0; i < 4; ++i) {
+    prof_ms[i] = 0;
+    prof_n[i] = 0;
+  }
+  profiling = on;
+}
+
+void Engine::prof_begin(int cls, ProfileRec *r) {
+  r->cls = cls;
+  r->a = r->b = nullptr;
+  if (!profiling) return;
+  for (hipEvent_t *e : {&r->a, &r->b}) {
+    if (!prof_free.empty()) {
+      *e = prof_free.back();
+      prof_free.pop_back();
+    } else {
+      hipEventCreate(e);
+    }
+  }
+  hipEventRecord(r->a, stream);
+}
+
+void Engine::prof_end(ProfileRec *r) {
+  if (!profiling || !r->a) return;
+  hipEventRecord(r->b, stream);
+  prof_pending.push_back(*r);
+}
+
+Status Engine::profile_read(int cls, double *ms, int64_t *launches) {
+  if (cls < 0 || cls > 3) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..3");
+  HIPOK(hipStreamSynchronize(stream));
+  for (auto &r : prof_pending) {
+    float e = 0;
+    if (hipEventElapsedTime(&e, r.a, r.b) == hipSuccess) {
+      prof_ms[r.cls] += e;
+      prof_n[r.cls] += 1;
+    }
+    prof_free.push_back(r.a);
+    prof_free.push_back(r.b);
+  }
+  prof_pending.clear();
+  if (ms) *ms = prof_ms[cls];
+  if (launches) *launches = prof_n[cls];
+  return Status::ok();
+}
+
+// ---------------------------------------------------------------------
+// one iteration of every resident job
+// ---------------------------------------------------------------------
+// launch layer k of the denoiser over all resident jobs' tiles, reading and
+// writing the activation buffers assigned to it when the network was set
+Status Engine::launch_layer(int k, int64_t tick, bool prof) {
+  const int K = net.K;
+  const LayerPlan &L = net.layers[k];
+  ConvArgs a{};
+  a.jobs = d_jobs;
+  a.tiles = d_conv;
+  a.n_tiles = n_conv;
+  a.tick = tick;
+  a.relu = L.relu;
+  a.bias = L.bias;
+  a.oscale = L.oscale;
+  a.in_inv_scale = L.in_inv_scale;
+  a.out_inv_scale = L.out_inv_scale;
+  a.in_slot = L.in_buf;
+  a.out_slot = L.out_buf;
+  ProfileRec pr;
+  if (K == 1) {
+    a.wf32 = L.wf32;
+    if (prof) prof_begin(1, &pr);
+    HIPOK(launch_conv_single(a, n_conv, stream));
+  } else if (k == 0) {
+    a.wf32 = L.wf32;
+    if (prof) prof_begin(1, &pr);
+    HIPOK(launch_conv_first(L.in_fmt, L.out_fmt, L.cout, a, n_conv, stream));
+  } else if (k == K - 1) {
+    a.wf32 = L.wf32;
+    if (prof) prof_begin(2, &pr);
+    HIPOK(launch_conv_last(L.in_fmt, L.cin, a, n_conv, stream));
+  } else {
+    a.wblob = L.wblob;
+    const size_t lds = mid_lds_bytes(L.in_fmt, net.F);
+    int occ = (int)std::max<size_t>(1, (160 * 1024) / lds);
+    occ = std::min(occ, 4);
+    const int need = ((n_conv + 7) / 8) * 8;
+    const int n_wg = std::max(8, std::min(n_cu * occ, need) / 8 * 8);
+    if (prof) prof_begin(0, &pr);
+    HIPOK(launch_conv_mid(L.in_fmt, L.out_fmt, net.F, a, n_wg, stream));
+  }
+  if (prof) prof_end(&pr);
+  return Status::ok();
+}
+
+Status Engine::run_denoiser(int64_t tick) {
+  for (int k = 0; k < net.K; ++k) TRY(launch_layer(k, tick, true));
+  return Status::ok();
+}
+
+Status Engine::tick() {
+  if (plan_dirty) TRY(rebuild_plan());
+  if (resident.empty()) return Status::ok();
+  TRY(run_denoiser(ticks));
+  UpdateArgs u{};
+  u.jobs = d_jobs;
+  u.tiles = d_upd;
+  u.n_tiles = n_upd;
+  u.tick = ticks;
+  ProfileRec pr;
+  prof_begin(3, &pr);
+  HIPOK(launch_fused_update(u, n_upd, max_r, stream));
+  prof_end(&pr);
+  ticks += 1;
+  for (Job *j : resident) j->t += 1;
+  return Status::ok();
+}
+
+Status Engine::sync_check(bool *diverged) {
+  HIPOK(hipStreamSynchronize(stream));
+  *diverged = false;
+  for (Job *j : resident) {
+    int32_t f = 0;
+    HIPOK(hipMemcpy(&f, j->d.flag, sizeof f, hipMemcpyDeviceToHost));
+    j->diverged = j->diverged || f != 0;
+    *diverged = *diverged || j->diverged;
+  }
+  return Status::ok();
+}
+
+// ---------------------------------------------------------------------
+// state and statistics of one job
+// ---------------------------------------------------------------------
+Status Engine::get_state(Job *j, float *x) {
+  HIPOK(hipStreamSynchronize(stream));
+  const JobDesc &d = j->d;
+  const size_t origin = (size_t)d.xborder * d.xpitch + d.xborder;
+  HIPOK(hipMemcpy2D(x, (size_t)d.nx * sizeof(float), d.x[j->t & 1] + origin,
+                    (size_t)d.xpitch * sizeof(float), (size_t)d.nx * sizeof(float), d.ny,
+                    hipMemcpyDeviceToHost));
+  return Status::ok();
+}
+
+static int64_t samples_at(const Job *j, int64_t t) {
+  return std::max<int64_t>(0, t - j->d.burn_in);
+}
+
+Status Engine::flush_stats(Job *j, int64_t *n_total) {
+  JobDesc &d = j->d;
+  const int64_t s = samples_at(j, j->t);
+  int64_t total = d.nbase;
+  if (s > d.wbase) {
+    const int64_t since = s - d.wbase;
+    const int64_t pending = since % d.wwin;
+    total = d.nbase + since;
+    if (pending > 0) {
+      const int64_t n_a = d.nbase + since - pending;
+      HIPOK(launch_welford_flush(d, (double)n_a, (double)pending, stream));
+    }
+    d.wbase = s;
+    d.nbase = total;
+    TRY(upload_descs());
+  }
+  if (n_total) *n_total = total;
+  return Status::ok();
+}
+
+Status Engine::read_stats(Job *j, double *mean, double *m2, int64_t *n) {
+  int64_t total = 0;
+  TRY(flush_stats(j, &total));
+  HIPOK(hipStreamSynchronize(stream));
+  const size_t N = (size_t)j->d.ny * j->d.nx;
+  if (mean) HIPOK(hipMemcpy(mean, j->d.mean, N * sizeof(double), hipMemcpyDeviceToHost));
+  if (m2) HIPOK(hipMemcpy(m2, j->d.m2, N * sizeof(double), hipMemcpyDeviceToHost));
+  if (n) *n = total;
+  return Status::ok();
+}
+
+Status Engine::set_state(Job *j, const float *x, int64_t t) {
+  if (t < 0) return Status::fail(PNPULA_EINVAL, "t must be >= 0");
+  TRY(flush_stats(j, nullptr));
+  JobDesc &d = j->d;
+  const size_t origin = (size_t)d.xborder * d.xpitch + d.xborder;
+  HIPOK(hipMemcpy2DAsync(d.x[t & 1] + origin, (size_t)d.xpitch * sizeof(float), x,
+                         (size_t)d.nx * sizeof(float), (size_t)d.nx * sizeof(float), d.ny,
+                         hipMemcpyHostToDevice, stream));
+  j->t = t;
+  d.wbase = samples_at(j, t);
+  TRY(upload_descs());
+  return Status::ok();
+}
+
+Status Engine::restore_stats(Job *j, const double *mean, const double *m2, int64_t n) {
+  if (n < 0) return Status::fail(PNPULA_EINVAL, "n_samples must be >= 0");
+  JobDesc &d = j->d;
+  const size_t N = (size_t)d.ny * d.nx;
+  HIPOK(hipMemcpyAsync(d.mean, mean, N * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIPOK(hipMemcpyAsync(d.m2, m2, N * sizeof(double), hipMemcpyHostToDevice, stream));
+  d.nbase = n;
+  d.wbase = samples_at(j, j->t);
+  TRY(upload_descs());
+  return Status::ok();
+}
+
+// Run the denoiser of job j on a given image (placed in the ping-pong
+// buffer that does not hold x^(t)); optionally read back every layer
+// (dequantised) or the largest |input| of every layer.
+Status Engine::denoise(Job *j, const float *x, float *G, float *layers, float *amax) {
+  if (plan_dirty) TRY(rebuild_plan());
+  if (resident.size() != 1 || resident[0] != j)
+    return Status::fail(PNPULA_ESTATE, "denoise needs a single-job engine");
+  JobDesc &d = j->d;
+  const size_t origin = (size_t)d.xborder * d.xpitch + d.xborder;
+  const int64_t alt = j->t + 1;       // parity of the spare buffer
+  HIPOK(hipMemcpy2DAsync(d.x[alt & 1] + origin, (size_t)d.xpitch * sizeof(float), x,
+                         (size_t)d.nx * sizeof(float), (size_t)d.nx * sizeof(float), d.ny,
+                         hipMemcpyHostToDevice, stream));
+  const int64_t tick_alt = ticks + 1;  // t = tick + t_offset = j->t + 1
+  const int K = net.K;
+  const size_t N = (size_t)d.ny * d.nx;
+  if (amax) {
+    float m = 0.f;
+    for (size_t p = 0; p < N; ++p) m = std::max(m, std::fabs(x[p]));
+    amax[0] = m;
+  }
+  uint32_t *d_amax = nullptr;
+  if (amax && K > 1) HIPOK(hipMalloc(&d_amax, sizeof(uint32_t) * K));
+  struct Free {
+    uint32_t *p;
+    ~Free() { if (p) hipFree(p); }
+  } guard{d_amax};
+  if (d_amax) HIPOK(hipMemsetAsync(d_amax, 0, sizeof(uint32_t) * K, stream));
+  float *lp = layers;
+  for (int k = 0; k < K; ++k) {
+    const LayerPlan &L = net.layers[k];
+    TRY(launch_layer(k, tick_alt, false));
+    if (k == K - 1) break;
+    const int ob = fmt_bytes(L.out_fmt), C = L.cout;
+    const size_t pixb = (size_t)net.F * ob;
+    if (d_amax) {
+      if (L.out_fmt != FMT_F32)
+        return Status::fail(PNPULA_ESTATE, "calibration runs on an FP32 denoiser");
+      HIPOK(launch_amax(reinterpret_cast<const float *>(d.act[L.out_buf]),
+                        (size_t)(d.ny + 2 + 16) * d.apitch * net.F, d_amax + k + 1, stream));
+    }
+    if (lp) {
+      HIPOK(hipStreamSynchronize(stream));
+      // dequantise the stored output: value = code * scale of the next layer's input
+      std::vector<uint8_t> buf((size_t)d.ny * d.nx * C * ob);
+      const uint8_t *src = reinterpret_cast<const uint8_t *>(d.act[L.out_buf]);
+      HIPOK(hipMemcpy2D(buf.data(), (size_t)d.nx * C * ob, src + ((size_t)d.apitch + 1) * pixb,
+                        (size_t)d.apitch * pixb, (size_t)d.nx * C * ob, d.ny,
+                        hipMemcpyDeviceToHost));
+      const float sc = net.act_scales[k + 1];
+      for (size_t p = 0; p < N; ++p)
+        for (int c = 0; c < C; ++c) {
+          const uint8_t *e = &buf[(p * C + c) * ob];
+          float v;
+          if (L.out_fmt == FMT_F32) {
+            std::memcpy(&v, e, 4);
+          } else if (L.out_fmt == FMT_BF16) {
+            uint32_t u = (uint32_t)(e[0] | (e[1] << 8)) << 16;
+            std::memcpy(&v, &u, 4);
+          } else {
+            v = host_e4m3_to_f32(e[0]) * sc;
+          }
+          lp[(size_t)c * N + p] = v;
+        }
+      lp += (size_t)C * N;
+    }
+  }
+  HIPOK(hipStreamSynchronize(stream));
+  if (lp) HIPOK(hipMemcpy(lp, d.G, N * sizeof(float), hipMemcpyDeviceToHost));
+  if (G) HIPOK(hipMemcpy(G, d.G, N * sizeof(float), hipMemcpyDeviceToHost));
+  if (d_amax) {
+    std::vector<uint32_t> h(K);
+    HIPOK(hipMemcpy(h.data(), d_amax, sizeof(uint32_t) * K, hipMemcpyDeviceToHost));
+    for (int k = 1; k < K; ++k) std::memcpy(&amax[k], &h[k], 4);
+  }
+  return Status::ok();
+}
+
+}  // namespace pnp

@@ -1,0 +1,49 @@
+// kernels.h -- launch interface of the gfx950 kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace pnp {
+
+struct ConvArgs {
+  const JobDesc *jobs;
+  const TileRef *tiles;
+  int32_t n_tiles;
+  int32_t in_slot, out_slot;   // activation ping-pong slots read / written
+  int32_t relu;
+  int64_t tick;
+  const void *wblob;           // middle layers: weights in MFMA fragment order
+  const float *wf32;           // first / last layer: quantised weights [c][9]
+  const float *bias;           // [c_out]
+  const float *oscale;         // [c_out]: weight scale x input scale
+  float in_inv_scale;          // first layer: 1 / scale of its input format
+  float out_inv_scale;         // 1 / scale of the next layer's input (e4m3), else 1
+};
+
+struct UpdateArgs {
+  const JobDesc *jobs;
+  const TileRef *tiles;
+  int32_t n_tiles;
+  int32_t pad;
+  int64_t tick;
+};
+
+// convolution tile height of the middle-layer kernel for an input format
+int mid_tile_rows(int in_fmt);
+size_t mid_lds_bytes(int in_fmt, int F);
+size_t update_lds_bytes(int r);
+
+hipError_t launch_conv_mid(int in_fmt, int out_fmt, int F, const ConvArgs &a, int n_wg,
+                           hipStream_t s);
+hipError_t launch_conv_first(int in_fmt, int out_fmt, int F, const ConvArgs &a, int n_tiles,
+                             hipStream_t s);
+hipError_t launch_conv_last(int in_fmt, int F, const ConvArgs &a, int n_tiles, hipStream_t s);
+hipError_t launch_conv_single(const ConvArgs &a, int n_tiles, hipStream_t s);
+hipError_t launch_fused_update(const UpdateArgs &a, int n_tiles, int max_r, hipStream_t s);
+hipError_t launch_amax(const float *p, size_t n, uint32_t *out, hipStream_t s);
+hipError_t launch_welford_flush(const JobDesc &j, double n_a, double n_b, hipStream_t s);
+
+}  // namespace pnp

@@ -1,0 +1,232 @@
+// update.hip -- the fused memory-bound part of one PnP-ULA iteration.
+//
+// For every 16 x 64 tile of a block (arXiv 2511.00870, Algorithm 1, the
+// x-update lines, with the z-update folded in):
+//   1. read the tile's window x^(t) on [core +- 2r] from the previous iterate
+//      (the block's ghost region is an overlapping read of device memory);
+//   2. K x on core +- r (separable row/column passes when K = u v^T);
+//   3. residual on core +- r, zero outside the image:
+//        rho == 0:  m (K x - y)
+//        rho > 0 :  m (K x - z),  z^(t) = (rho y + sigma^2 m K x)/(rho + sigma^2)
+//                                       + sqrt(rho sigma^2/(rho + sigma^2)) zeta
+//                   i.e. m (rho/(rho+sigma^2) (K x - y) - zsd zeta); z^(0) = 0.
+//      The generator is keyed by the global pixel, so overlapping tiles draw
+//      the same zeta and z never needs to be stored;
+//   4. K^T of the residual on the core;
+//   5. x^(t+1) = x - delta g - (alpha delta/eps) G + (delta/lambda)(clip x - x)
+//                + sqrt(2 delta) xi,   g = K^T res / s2;
+//   6. after burn-in, Welford update of the FP32 window mean / M2 and, when
+//      the window is full, the Chan-Golub-LeVeque merge into the FP64 maps.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace pnp {
+
+__global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  const TileRef tl = a.tiles[blockIdx.x];
+  const JobDesc &j = a.jobs[tl.job];
+  const int64_t t = a.tick + j.t_offset;
+  const int r = j.r, L = 2 * r + 1;
+  constexpr int TH = kUpdTileH, TW = kUpdTileW;
+  const int WH = TH + 4 * r, WW = TW + 4 * r;       // x window
+  const int RH = TH + 2 * r, RW = TW + 2 * r;       // K x / residual region
+  float *sx = smem;                                  // WH x WW
+  float *sh = sx + WH * WW;                          // WH x RW  (row pass of x)
+  float *sres = sh + WH * RW;                        // RH x RW
+  float *shr = sres + RH * RW;                       // RH x TW  (row pass of res)
+  float *sxi = shr + RH * TW;                        // TH x TW
+  const int tid = threadIdx.x;
+  const float *xin = j.x[t & 1];
+  const int B = j.xborder;
+
+  // 1. window of x^(t)
+  const int wy = tl.y0 - 2 * r, wx = tl.x0 - 2 * r;
+  for (int q = tid; q < WH * WW; q += 256) {
+    const int i = q / WW, c = q % WW;
+    sx[q] = xin[(int64_t)(wy + i + B) * j.xpitch + (wx + c + B)];
+  }
+  __syncthreads();
+
+  // 2. K x on the residual region
+  if (j.separable) {
+    for (int q = tid; q < WH * RW; q += 256) {
+      const int i = q / RW, c = q % RW;
+      const float *row = sx + i * WW + c + 2 * r;
+      float acc = 0.0f;
+      for (int k = 0; k < L; ++k) acc = fmaf(j.kv[k], row[-k], acc);
+      sh[q] = acc;
+    }
+    __syncthreads();
+  }
+  // 3. residual (K x kept in registers, written as the residual)
+  const int split = j.split;
+  const bool draw = split && t >= 1;
+  for (int q = tid; q < RH * RW; q += 256) {
+    const int i = q / RW, c = q % RW;
+    float kx = 0.0f;
+    if (j.separable) {
+      for (int k = 0; k < L; ++k) kx = fmaf(j.ku[k], sh[(i + 2 * r - k) * RW + c], kx);
+    } else {
+      for (int a2 = 0; a2 < L; ++a2)
+        for (int k = 0; k < L; ++k)
+          kx = fmaf(j.kern[a2 * L + k], sx[(i + 2 * r - a2) * WW + (c + 2 * r - k)], kx);
+    }
+    const int Y = tl.y0 - r + i, X = tl.x0 - r + c;
+    float res = 0.0f;
+    if (Y >= 0 && Y < j.ny && X >= 0 && X < j.nx) {
+      const int64_t pidx = (int64_t)(Y + B) * j.xpitch + (X + B);
+      const float m = j.has_mask ? (float)j.mask[pidx] : 1.0f;
+      const float yv = j.y[pidx];
+      if (!split) {
+        res = m * (kx - yv);
+      } else if (!draw) {
+        res = m * kx;                                      // z^(0) = 0
+      } else {
+        float xi, zeta;
+        gauss_pair(j, (int64_t)Y * j.nx + X, t, xi, zeta);
+        res = m * (j.zmix * (kx - yv) - j.zsd * zeta);
+        const int ci = i - r, cc = c - r;
+        if (ci >= 0 && ci < TH && cc >= 0 && cc < TW) sxi[ci * TW + cc] = xi;
+      }
+    }
+    sres[q] = res;
+  }
+  __syncthreads();
+
+  // 4. K^T res on the core
+  if (j.separable) {
+    for (int q = tid; q < RH * TW; q += 256) {
+      const int i = q / TW, c = q % TW;
+      const float *row = sres + i * RW + c;
+      float acc = 0.0f;
+      for (int k = 0; k < L; ++k) acc = fmaf(j.kv[k], row[k], acc);
+      shr[q] = acc;
+    }
+    __syncthreads();
+  }
+
+  // 5./6. update, statistics
+  float *xout = j.x[(t + 1) & 1];
+  const int64_t s = t + 1 - j.burn_in;                    // sample number of x^(t+1)
+  const bool stats = s >= 1;
+  int nw = 0;
+  bool merge = false;
+  if (stats) {
+    nw = (int)((s - j.wbase - 1) % j.wwin) + 1;
+    merge = nw == j.wwin;
+  }
+  const float inv_nw = stats ? 1.0f / (float)nw : 0.0f;
+  const int64_t na_i = j.nbase + (s - j.wbase - nw);       // merged before this window
+  const double n_a = (double)na_i, n_b = (double)nw;
+  bool bad = false;
+  for (int q = tid; q < TH * TW; q += 256) {
+    const int i = q / TW, c = q % TW;
+    if (i >= tl.h || c >= tl.w) continue;
+    float ktr = 0.0f;
+    if (j.separable) {
+      for (int k = 0; k < L; ++k) ktr = fmaf(j.ku[k], shr[(i + k) * TW + c], ktr);
+    } else {
+      for (int a2 = 0; a2 < L; ++a2)
+        for (int k = 0; k < L; ++k)
+          ktr = fmaf(j.kern[a2 * L + k], sres[(i + a2) * RW + (c + k)], ktr);
+    }
+    const int Y = tl.y0 + i, X = tl.x0 + c;
+    const int64_t p = (int64_t)Y * j.nx + X;
+    float xi;
+    if (draw) {
+      xi = sxi[q];
+    } else {
+      float zeta_unused;
+      gauss_pair(j, p, t, xi, zeta_unused);
+    }
+    const float xo = sx[(i + 2 * r) * WW + (c + 2 * r)];
+    const float proj = fminf(fmaxf(xo, 0.0f), 1.0f);
+    const float xn = xo - j.delta * (ktr * j.inv_s2) - j.cprior * j.G[p] +
+                     j.cproj * (proj - xo) + j.sq2d * xi;
+    bad |= !isfinite(xn);
+    xout[(int64_t)(Y + B) * j.xpitch + (X + B)] = xn;
+    if (stats) {
+      float m = 0.0f, M = 0.0f;
+      if (nw > 1) { m = j.wmean[p]; M = j.wm2[p]; }
+      const float d = xn - m;
+      m = fmaf(d, inv_nw, m);
+      M = fmaf(d, xn - m, M);
+      if (merge) {
+        const double n = n_a + n_b;
+        const double ma = na_i > 0 ? j.mean[p] : 0.0;
+        const double Ma = na_i > 0 ? j.m2[p] : 0.0;
+        const double dl = (double)m - ma;
+        j.mean[p] = ma + dl * (n_b / n);
+        j.m2[p] = Ma + (double)M + dl * dl * (n_a * n_b / n);
+      } else {
+        j.wmean[p] = m;
+        j.wm2[p] = M;
+      }
+    }
+  }
+  if (bad) j.flag[0] = 1;
+}
+
+// Merge a partially filled FP32 window (nw samples on top of n_a merged
+// ones) into the FP64 statistics of one job.
+__global__ __launch_bounds__(256) void welford_flush_kernel(JobDesc j, double n_a, double n_b) {
+  const int64_t n_pix = (int64_t)j.ny * j.nx;
+  const double n = n_a + n_b;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n_pix;
+       p += (int64_t)gridDim.x * 256) {
+    const double ma = n_a > 0 ? j.mean[p] : 0.0;
+    const double Ma = n_a > 0 ? j.m2[p] : 0.0;
+    const double dl = (double)j.wmean[p] - ma;
+    j.mean[p] = ma + dl * (n_b / n);
+    j.m2[p] = Ma + (double)j.wm2[p] + dl * dl * (n_a * n_b / n);
+  }
+}
+
+// max |p[i]| over n floats into *out (float bits; all values >= 0 so the
+// unsigned order is the float order)
+__global__ __launch_bounds__(256) void amax_kernel(const float *p, size_t n, uint32_t *out) {
+  float m = 0.0f;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    m = fmaxf(m, fabsf(p[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+hipError_t launch_amax(const float *p, size_t n, uint32_t *out, hipStream_t s) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(amax_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, out);
+  return hipGetLastError();
+}
+
+size_t update_lds_bytes(int r) {
+  const int TH = kUpdTileH, TW = kUpdTileW;
+  const int WH = TH + 4 * r, WW = TW + 4 * r, RH = TH + 2 * r, RW = TW + 2 * r;
+  return sizeof(float) * ((size_t)WH * WW + (size_t)WH * RW + (size_t)RH * RW +
+                          (size_t)RH * TW + (size_t)TH * TW);
+}
+
+hipError_t launch_fused_update(const UpdateArgs &a, int n_tiles, int max_r, hipStream_t s) {
+  const size_t lds = update_lds_bytes(max_r);
+  static size_t attr = 0;
+  if (lds > attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_update_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = lds;
+  }
+  hipLaunchKernelGGL(fused_update_kernel, dim3(n_tiles), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_welford_flush(const JobDesc &j, double n_a, double n_b, hipStream_t s) {
+  const int64_t n_pix = (int64_t)j.ny * j.nx;
+  int blocks = (int)((n_pix + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(welford_flush_kernel, dim3(blocks), dim3(256), 0, s, j, n_a, n_b);
+  return hipGetLastError();
+}
+
+}  // namespace pnp

@@ -32,6 +32,7 @@ s = 1000 * config number.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import List, Optional
 
@@ -102,7 +103,7 @@ def observe(xbar: np.ndarray, kernel: np.ndarray, sigma: float,
 # --------------------------------------------------------------------------
 # denoiser weights
 # --------------------------------------------------------------------------
-def conv_spectral_norm(w: np.ndarray, grid: int = 64) -> float:
+def conv_spectral_norm(w: np.ndarray, grid: int = 32) -> float:
     """max over a grid of frequencies of the largest singular value of the
     F_out x F_in symbol W(omega) = sum_taps w[:, :, a, b] exp(-i omega.(a,b)).
     For a zero-padded convolution this bounds the operator norm."""
@@ -117,10 +118,18 @@ def conv_spectral_norm(w: np.ndarray, grid: int = 64) -> float:
 
 def denoiser_weights(n_layers: int, features: int, seed: int = 7,
                      spectral: float = 0.9, bias_scale: float = 0.0):
+    ch, ws, bs = _denoiser_weights(n_layers, features, seed, spectral, bias_scale)
+    return list(ch), [w.copy() for w in ws], [b.copy() for b in bs]
+
+
+@functools.lru_cache(maxsize=16)
+def _denoiser_weights(n_layers: int, features: int, seed: int, spectral: float,
+                      bias_scale: float):
     """DnCNN-style layer stack 1 -> F -> ... -> F -> 1 with 3x3 kernels.
 
     Returns (channels, [w_k (OIHW float32)], [b_k float32]).  He-normal
-    init N(0, 2/(9 F_in)), each layer rescaled to spectral norm `spectral`.
+    init N(0, 2/(9 F_in)), each layer rescaled to spectral norm `spectral`
+    (maximum over a 32 x 32 frequency grid).
     Biases are zero unless bias_scale > 0 (then U(-bias_scale, bias_scale)).
     """
     rng = np.random.default_rng(seed)
@@ -135,7 +144,7 @@ def denoiser_weights(n_layers: int, features: int, seed: int = 7,
             bs.append(rng.uniform(-bias_scale, bias_scale, fo).astype(np.float32))
         else:
             bs.append(np.zeros(fo, np.float32))
-    return ch, ws, bs
+    return tuple(ch), tuple(ws), tuple(bs)
 
 
 def wiener_denoiser(a: float = 0.9, sigma_k: float = 1.0):

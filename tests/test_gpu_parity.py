@@ -1,0 +1,451 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+FP32 bar: per-step relative error ||x_gpu^(t+1) - x^(t+1)|| / ||x^(t+1)|| <= 1e-5
+with x_gpu^(t+1) the GPU step applied to the oracle's x^(t).  bf16 / e4m3
+layers are compared with the oracle's quantisation emulation: stored codes
+must match except where the FP32 and FP64 pre-rounding values straddle a
+rounding boundary (then they differ by one code step).
+"""
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+from paper_2511_00870_amd import pnpula as P
+from paper_2511_00870_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+# ------------------------------------------------------------ denoiser
+@pytest.mark.parametrize("K,F,shape,block", [(4, 16, (70, 45), 32), (8, 64, (53, 70), 24),
+                                             (3, 32, (40, 40), 40)])
+def test_denoiser_fp32_layers(K, F, shape, block):
+    say(f"case denoiser fp32 K={K} F={F} shape={shape} block={block}")
+    ch, ws, bs = W.denoiser_weights(K, F, seed=K + F, bias_scale=0.05)
+    ny, nx = shape
+    wl = W.make_workload("d", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=block, halo=max(4, K),
+                         n_layers=K, features=F, precision=0, iters=1, burn_in=0, seed=5,
+                         bias_scale=0.05)
+    wl.channels, wl.weights, wl.biases = ch, ws, bs
+    x = W.synthetic_image(ny, nx, 17).astype(np.float32)
+    ctx = P.Context(P.Config.from_workload(wl))
+    G, layers = ctx.denoise(x, layers=True)
+    ref, _ = O.denoiser_layers(O.Net(ch, ws, bs), x.astype(np.float64))
+    for k, (g, r) in enumerate(zip(layers, ref)):
+        e = rel(g, r)
+        say(f"  layer {k}: rel {e:.2e}")
+        assert e <= TOL
+    assert rel(G, ref[-1][0]) <= TOL
+
+
+def _q(v, fmt, scale=1.0):
+    return O.quantize(np.asarray(v) / scale, fmt) * scale
+
+
+def _ulp(v, fmt, scale=1.0):
+    """code step of format fmt (bf16 or e4m3 with scale) at the values v"""
+    a = np.abs(np.asarray(v, np.float64)) / scale
+    e = np.floor(np.log2(np.maximum(a, 1e-300)))
+    if fmt == 1:
+        return 2.0 ** (np.maximum(e, -126) - 7) * scale
+    return 2.0 ** (np.maximum(e, -6) - 3) * scale
+
+
+def _code_match(gpu, ref_exact, fmt, scale=1.0, exclude=None):
+    """gpu holds stored (rounded) values, ref_exact the oracle's value before
+    rounding.  Every stored value must lie within one code step of the exact
+    value plus an absolute slack of 1e-5 of the layer's largest value (the
+    FP32 accumulation error), except at pixels in `exclude` (outputs whose
+    inputs already differ by a rounding flip).  Returns the fraction of codes
+    that differ from the oracle's rounding and the mask of such pixels."""
+    refq = _q(ref_exact, fmt, scale)
+    diff = gpu.astype(np.float64) != refq
+    slack = 1e-5 * np.abs(ref_exact).max()
+    bad = np.abs(gpu - ref_exact) > _ulp(ref_exact, fmt, scale) + slack
+    if exclude is not None:
+        bad &= ~exclude[None]
+    assert not bad.any(), (np.argwhere(bad)[:5], gpu[bad][:5], ref_exact[bad][:5])
+    return diff.mean(), diff.any(axis=0)
+
+
+def _dilate(m):
+    out = m.copy()
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            out |= np.roll(np.roll(m, dy, 0), dx, 1)
+    return out
+
+
+@pytest.mark.parametrize("prec", [P.PNPULA_BF16, P.PNPULA_FP8_E4M3])
+def test_denoiser_low_precision_single_mid_layer(prec):
+    """K = 3: first layer (VALU), one MFMA layer, last layer."""
+    say(f"case denoiser precision={prec} K=3 F=64")
+    ny, nx = 53, 70
+    ch, ws, bs = W.denoiser_weights(3, 64, seed=11, bias_scale=0.05)
+    x = W.synthetic_image(ny, nx, 23)
+    fmt = [1, 1, 1] if prec == P.PNPULA_BF16 else [1, 2, 1]
+    scales = [1.0, 1.0, 1.0]
+    if prec == P.PNPULA_FP8_E4M3:
+        _, amax = O.denoiser_layers(O.Net(ch, ws, bs), x)
+        scales[1] = float(2.0 ** np.ceil(np.log2(2 * amax[1] / 448)))
+    net = O.Net(ch, ws, bs, fmt, scales)
+    ref, _ = O.denoiser_layers(net, x)
+    wl = W.make_workload("d", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=32, halo=4,
+                         n_layers=3, features=64, precision=prec, iters=1, burn_in=0, seed=5)
+    wl.channels, wl.weights, wl.biases = ch, ws, bs
+    ctx = P.Context(P.Config.from_workload(
+        wl, act_scales=scales if prec == P.PNPULA_FP8_E4M3 else None))
+    G, layers = ctx.denoise(x.astype(np.float32), layers=True)
+    f0, px0 = _code_match(layers[0], ref[0], fmt[1], scales[1])
+    f1, _ = _code_match(layers[1], ref[1], fmt[2], scales[2], exclude=_dilate(px0))
+    e = rel(G, ref[2][0])
+    say(f"  mismatched codes: layer0 {f0:.2e} ({px0.sum()} pixels) layer1 {f1:.2e}; "
+        f"G rel {e:.2e}")
+    assert f0 <= 2e-3 and f1 <= 2e-3
+    assert e <= 2e-3
+
+
+@pytest.mark.parametrize("prec", [P.PNPULA_BF16, P.PNPULA_FP8_E4M3])
+def test_denoiser_low_precision_deep(prec):
+    """K = 8 in bf16 / e4m3 against the emulating oracle: rounding flips
+    propagate, so the bar is a relative error, small against the format's
+    own step (2^-8 bf16, 2^-4 e4m3)."""
+    say(f"case deep denoiser precision={prec}")
+    ny, nx = 64, 96
+    K = 8
+    ch, ws, bs = W.denoiser_weights(K, 64, seed=3)
+    x = W.synthetic_image(ny, nx, 29)
+    fmt = W.layer_formats(K, prec)
+    scales = [1.0] * K
+    if prec == P.PNPULA_FP8_E4M3:
+        _, amax = O.denoiser_layers(O.Net(ch, ws, bs), x)
+        scales = [float(2.0 ** np.ceil(np.log2(2 * a / 448))) if f == 2 else 1.0
+                  for a, f in zip(amax, fmt)]
+    ref, _ = O.denoiser_layers(O.Net(ch, ws, bs, fmt, scales), x)
+    wl = W.make_workload("d", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=32, halo=8,
+                         n_layers=K, features=64, precision=prec, iters=1, burn_in=0, seed=5)
+    wl.channels, wl.weights, wl.biases = ch, ws, bs
+    ctx = P.Context(P.Config.from_workload(
+        wl, act_scales=scales if prec == P.PNPULA_FP8_E4M3 else None))
+    G = ctx.denoise(x.astype(np.float32))
+    e = rel(G, ref[-1][0])
+    say(f"  G rel {e:.2e}")
+    assert e <= (5e-3 if prec == P.PNPULA_BF16 else 5e-2)
+
+
+# -------------------------------------------------------- one iteration
+def _parity_run(wl, n_steps, block=None, label=""):
+    say(f"case step parity {label}: {wl.ny}x{wl.nx} L={wl.kernel.shape[0]} "
+        f"rho={wl.rho:.2e} mask={wl.mask is not None} block={block or wl.block_y}")
+    oc = O.Chain.from_workload(wl, block=0)
+    ctx = P.Context(P.Config.from_workload(wl, block=block))
+    worst = 0.0
+    for t in range(n_steps):
+        x_t, tt = oc.get_state()
+        assert tt == t
+        ctx.set_state(x_t.astype(np.float32), t)
+        ctx.step(1)
+        xg, tg = ctx.get_state()
+        oc.step(1)
+        x1, _ = oc.get_state()
+        assert tg == t + 1
+        worst = max(worst, rel(xg, x1))
+    say(f"  worst per-step rel {worst:.2e}")
+    assert worst <= TOL
+    return worst
+
+
+def test_step_parity_config1_every_step():
+    _parity_run(W.config(1), 200, label="64x64 K4F16 split")
+
+
+def test_step_parity_unsplit_masked_nonseparable_ragged():
+    wl = W.config(1, ny=61, nx=67, block=24, halo=8, split=False, mask_p=0.5, bias_scale=0.05)
+    rng = np.random.default_rng(0)
+    wl.kernel = rng.random((5, 5))
+    wl.kernel /= wl.kernel.sum()
+    wl.inv_lambda = 50.0
+    _parity_run(wl, 30, label="ragged masked 2-D blur")
+
+
+def test_step_parity_wide_blur_split_mask():
+    wl = W.config(1, ny=50, nx=90, block=30, halo=12, L=9, sigma_k=2.0, mask_p=0.3)
+    _parity_run(wl, 20, label="L=9 mask")
+
+
+def test_step_parity_identity_blur():
+    wl = W.config(1, ny=33, nx=47, block=33, halo=4, L=1, sigma_k=1.0)
+    wl.kernel = np.ones((1, 1))
+    _parity_run(wl, 10, label="L=1")
+
+
+@pytest.mark.parametrize("cfgno", [2, 3, 4])
+def test_step_parity_full_size_sampled(cfgno):
+    """Full-size configurations, in the bench's launch configuration, on
+    sampled 32x32 output regions the oracle computes from the same x^(t)."""
+    wl = W.config(cfgno)
+    say(f"case full-size sampled config {cfgno}: {wl.ny}x{wl.nx} precision={wl.precision}")
+    rng = np.random.default_rng(cfgno)
+    x_t = np.clip(wl.xbar + 0.03 * rng.standard_normal(wl.xbar.shape), -0.2, 1.2)
+    x_t = x_t.astype(np.float32)
+    t = 777
+    scales = None
+    fmt = None
+    if wl.precision != P.PNPULA_FP32:
+        fmt = W.layer_formats(wl.n_layers, wl.precision)
+    if wl.precision == P.PNPULA_FP8_E4M3:
+        crop = x_t[:256, :256].astype(np.float64)
+        _, amax = O.denoiser_layers(O.Net(wl.channels, wl.weights, wl.biases), crop)
+        scales = [float(2.0 ** np.ceil(np.log2(2 * a / 448))) if f == 2 else 1.0
+                  for a, f in zip(amax, fmt)]
+    ctx = P.Context(P.Config.from_workload(wl, act_scales=scales))
+    ctx.set_state(x_t, t)
+    ctx.step(1)
+    xg, _ = ctx.get_state()
+    del ctx
+    oc = O.Chain.from_workload(wl, block=0, layer_fmt=fmt, act_scales=scales)
+    b = wl.block_y
+    regions = [(0, 0), (wl.ny - 32, wl.nx - 32), (b - 16, b - 16), (wl.ny // 2 - 7, 3),
+               (int(rng.integers(0, wl.ny - 32)), int(rng.integers(0, wl.nx - 32)))]
+    tol = TOL if wl.precision == P.PNPULA_FP32 else (2e-4 if wl.precision == 1 else 2e-3)
+    for (y0, x0) in regions:
+        ref = oc.step_region(x_t.astype(np.float64), t, y0, x0, 32, 32)
+        e = rel(xg[y0:y0 + 32, x0:x0 + 32], ref)
+        say(f"  region ({y0},{x0}) rel {e:.2e}")
+        assert e <= tol
+
+
+# ------------------------------------------------------ invariances
+def test_blocking_does_not_change_results():
+    wl = W.config(1, ny=96, nx=80, block=96, halo=8, bias_scale=0.05, mask_p=0.7)
+    wl.burn_in = 2
+    outs = []
+    for blk in [(96, 80), (32, 32), (24, 40), (40, 24)]:
+        say(f"case blocks {blk}")
+        cfg = P.Config.from_workload(wl, block_y=blk[0], block_x=blk[1])
+        ctx = P.Context(cfg)
+        ctx.step(6)
+        x, t = ctx.get_state()
+        m, v, n = ctx.stats()
+        outs.append((x, m, v))
+    for x, m, v in outs[1:]:
+        assert np.array_equal(x, outs[0][0])
+        assert np.array_equal(m, outs[0][1]) and np.array_equal(v, outs[0][2])
+
+
+def test_blocking_invariance_bf16():
+    wl = W.config(3, ny=128, nx=96, block=128, halo=8)
+    ref = None
+    for blk in [(128, 96), (32, 32), (64, 48)]:
+        say(f"case bf16 blocks {blk}")
+        ctx = P.Context(P.Config.from_workload(wl, block_y=blk[0], block_x=blk[1]))
+        ctx.step(3)
+        x, _ = ctx.get_state()
+        if ref is None:
+            ref = x
+        assert np.array_equal(x, ref)
+
+
+def test_run_twice_bitwise():
+    wl = W.config(2, ny=128, nx=160, block=64)
+    xs = []
+    for rep in range(2):
+        say(f"case determinism rep {rep}")
+        ctx = P.Context(P.Config.from_workload(wl))
+        ctx.step(4)
+        xs.append(ctx.get_state()[0])
+    assert np.array_equal(xs[0], xs[1])
+
+
+def test_checkpoint_resume_bitwise():
+    wl = W.config(1, ny=64, nx=64)
+    wl.burn_in = 3
+    say("case checkpoint")
+    a = P.Context(P.Config.from_workload(wl))
+    a.step(20)
+    xa, ta = a.get_state()
+    ma, m2a, na = a.stats_f64()
+    b = P.Context(P.Config.from_workload(wl))
+    b.step(10)
+    xb, tb = b.get_state()
+    mb, m2b, nb = b.stats_f64()
+    c = P.Context(P.Config.from_workload(wl))
+    c.restore(xb, tb, mb, m2b, nb)
+    c.step(10)
+    xc, tc = c.get_state()
+    mc, m2c, nc = c.stats_f64()
+    assert ta == tc == 20 and np.array_equal(xa, xc)
+    assert na == nc == 17
+    assert np.abs(mc - ma).max() <= 1e-6 * np.abs(ma).max()
+    assert np.abs(m2c - m2a).max() <= 1e-5 * np.abs(m2a).max()
+
+
+# ---------------------------------------------------------- statistics
+def test_welford_windows_match_two_pass():
+    wl = W.config(1, ny=48, nx=40, block=48)
+    wl.burn_in = 5
+    wl.welford_window = 7
+    say("case welford windows")
+    ctx = P.Context(P.Config.from_workload(wl))
+    samples = []
+    for t in range(60):
+        ctx.step(1)
+        x, tt = ctx.get_state()
+        if tt > wl.burn_in:
+            samples.append(x.astype(np.float64))
+        if t == 23:
+            ctx.stats()      # out-of-band merge of a partial window
+    s = np.array(samples)
+    mean, m2, n = ctx.stats_f64()
+    assert n == len(samples) == 55
+    assert np.abs(mean - s.mean(0)).max() <= 1e-6 * np.abs(s).max()
+    ref = s.var(0, ddof=1)
+    assert np.abs(m2 / (n - 1) - ref).max() <= 1e-4 * ref.max()
+
+
+def test_free_running_chain_tracks_oracle():
+    """GPU FP32 and oracle FP64 chains driven by the same noise stay together
+    over a whole run of configuration 1; their statistics agree."""
+    wl = W.config(1)
+    say("case free-running config 1")
+    ctx = P.Context(P.Config.from_workload(wl))
+    ctx.step(wl.iters)
+    oc = O.Chain.from_workload(wl, block=0)
+    oc.step(wl.iters)
+    xg, _ = ctx.get_state()
+    xo, _ = oc.get_state()
+    mg, vg, ng = ctx.stats()
+    mo, m2o, no = oc.stats()
+    vo = m2o / (no - 1)
+    say(f"  final state rel {rel(xg, xo):.2e}; mean rel {rel(mg, mo):.2e}; var rel {rel(vg, vo):.2e}")
+    assert ng == no == wl.iters - wl.burn_in
+    assert rel(xg, xo) <= 1e-3
+    assert rel(mg, mo) <= 1e-3
+    assert rel(vg, vo) <= 2e-2
+
+
+def test_wiener_chain_matches_closed_form_on_gpu():
+    """Linear denoiser: the GPU chain's mean and variance against the exact
+    Gaussian stationary law (ULA-biased covariance)."""
+    from scipy.signal import convolve2d, correlate2d
+    n, sigma = 16, 0.05
+    wl = W.make_workload("g", n, n, L=5, sigma_k=1.0, sigma=sigma, block=n, halo=8, n_layers=1,
+                         features=1, precision=0, iters=1, burn_in=300, seed=31, split=False,
+                         wiener=True)
+    say("case wiener closed form")
+
+    def opm(fn):
+        M = np.zeros((n * n, n * n))
+        for p in range(n * n):
+            e = np.zeros(n * n)
+            e[p] = 1
+            M[:, p] = fn(e.reshape(n, n)).ravel()
+        return M
+    K = opm(lambda e: convolve2d(e, wl.kernel, mode="same"))
+    Gm = opm(lambda e: correlate2d(e, wl.weights[0][0, 0].astype(np.float64), mode="same"))
+    Pm = K.T @ K / sigma ** 2 + (wl.alpha / wl.eps) * Gm
+    m_exact = np.linalg.solve(Pm, K.T @ wl.y.ravel() / sigma ** 2)
+    S = np.linalg.inv(Pm - wl.delta * Pm @ Pm / 2)
+    ctx = P.Context(P.Config.from_workload(wl))
+    ctx.step(300)
+    bms, prev_s, prev_n = [], 0.0, 0
+    for _ in range(40):
+        ctx.step(1000)
+        mean, m2, cnt = ctx.stats_f64()
+        s = mean * cnt
+        bms.append(((s - prev_s) / (cnt - prev_n)).ravel())
+        prev_s, prev_n = s, cnt
+    bm = np.array(bms)
+    se = bm.std(0, ddof=1) / np.sqrt(len(bms))
+    z = (mean.ravel() - m_exact) / se
+    ratio = (m2.ravel() / (cnt - 1)) / np.diag(S)
+    say(f"  max|z| {np.abs(z).max():.2f} mean z^2 {np.mean(z ** 2):.2f} var ratio {ratio.mean():.4f}")
+    assert np.abs(z).max() < 5.5 and 0.4 < np.mean(z ** 2) < 1.8
+    assert abs(ratio.mean() - 1) < 0.03
+
+
+# ------------------------------------------------------------ failures
+def test_divergence_is_reported():
+    wl = W.config(1, ny=32, nx=32, block=32)
+    wl.delta *= 40.0           # far beyond 2/L: the chain blows up
+    say("case divergence")
+    ctx = P.Context(P.Config.from_workload(wl))
+    ctx.step(400)
+    assert ctx.sync() == P.PNPULA_EDIVERGED
+
+
+def test_step_after_bad_state_args():
+    wl = W.config(1, ny=32, nx=32, block=32)
+    ctx = P.Context(P.Config.from_workload(wl))
+    with pytest.raises(P.PnpulaError) as e:
+        ctx.set_state(np.zeros((32, 32), np.float32), -1)
+    assert e.value.code == P.PNPULA_EINVAL
+    with pytest.raises(P.PnpulaError) as e:
+        ctx.step(-1)
+    assert e.value.code == P.PNPULA_EINVAL
+
+
+# -------------------------------------------------------------- serving
+def _small_net():
+    return W.denoiser_weights(4, 16, seed=7)
+
+
+def _job(side, L, masked, sigma, seed, iters):
+    wl = W.make_workload(f"j{seed}", side, side + 8, L=L, sigma_k=L / 4.5, sigma=sigma,
+                         block=min(32, side), halo=8, n_layers=4, features=16, precision=0,
+                         iters=iters, burn_in=iters // 10, seed=seed,
+                         mask_p=0.5 if masked else None)
+    return wl
+
+
+def test_serving_alone_equals_mix():
+    ch, ws, bs = _small_net()
+    jobs = [_job(64, 5, False, 0.02, 100, 30), _job(96, 7, True, 0.01, 200, 50),
+            _job(40, 9, False, 0.03, 300, 40), _job(72, 5, True, 0.02, 400, 25)]
+    say("case serving alone vs mix")
+    srv = P.Server(ch, ws, bs, precision=P.PNPULA_FP32, max_slots=2)
+    ids = [srv.submit(P.Config.from_workload(wl), wl.iters) for wl in jobs]
+    ticks = 0
+    while srv.tick() > 0:
+        ticks += 1
+    mixed = [srv.result(i) for i in ids]
+    for wl, (m, v, n) in zip(jobs, mixed):
+        ctx = P.Context(P.Config.from_workload(wl))
+        ctx.step(wl.iters)
+        ma, va, na = ctx.stats()
+        assert n == na == wl.iters - wl.burn_in
+        assert np.array_equal(m, ma) and np.array_equal(v, va)
+    say(f"  {ticks} ticks")
+
+
+def test_serving_budget_admission_and_rejection():
+    ch, ws, bs = _small_net()
+    a, b = _job(64, 5, False, 0.02, 10, 12), _job(64, 5, False, 0.02, 11, 12)
+    fa = P.pnpula_footprint(P.Config.from_workload(a))
+    big = _job(128, 5, False, 0.02, 12, 5)
+    say("case serving budget")
+    srv = P.Server(ch, ws, bs, precision=P.PNPULA_FP32, max_slots=8,
+                   hbm_budget=int(fa * 1.5))
+    ia = srv.submit(P.Config.from_workload(a), a.iters)
+    ib = srv.submit(P.Config.from_workload(b), b.iters)
+    ic = srv.submit(P.Config.from_workload(big), big.iters)
+    n_ticks = 0
+    while srv.tick() > 0:
+        n_ticks += 1
+    # a and b could not be resident together: they ran one after the other
+    assert n_ticks >= a.iters + b.iters - 1
+    for i in (ia, ib):
+        m, v, n = srv.result(i)
+        assert n == 11
+    with pytest.raises(P.PnpulaError) as e:
+        srv.result(ic)
+    assert e.value.code == P.PNPULA_ENOMEM
