@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--precision", type=int, default=None)
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-region", type=int, default=160)
+    ap.add_argument("--cpu-region", type=int, default=2048)
     return ap.parse_args()
 
 

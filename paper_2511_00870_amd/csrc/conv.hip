@@ -89,111 +89,140 @@ template <> __device__ __forceinline__ void store4<FMT_E4M3>(void *p, f32x4 v, f
 }
 
 // ---------------------------------------------------------------------
-// First layer: 1 -> F.  One thread per (pixel, 16-byte group of output
-// channels).  Input: x^(t) (FP32), rounded to the layer's input format.
+// First layer: 1 -> F.  The tile's x window ((TH+2) x 34, rounded to the
+// layer's input format) is staged in LDS; each lane owns one 16-byte group
+// of output channels (weights, bias and scale in registers) and walks the
+// tile's pixels, so consecutive lanes write consecutive bytes.
 // ---------------------------------------------------------------------
 template <int IN_FMT, int OUT_FMT, int F>
 __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
   constexpr int OB = FmtInfo<OUT_FMT>::bytes;
-  constexpr int CG = 16 / OB;                  // channels per thread
-  constexpr int NG = F / CG;
+  constexpr int CG = 16 / OB;                  // channels per lane
+  constexpr int NG = F / CG;                   // lanes per pixel
+  constexpr int PPP = 256 / NG;                // pixels per pass
+  constexpr int WW = kConvTileW + 2;
+  __shared__ float sx[18 * WW];
   const TileRef tl = a.tiles[blockIdx.x];
   const JobDesc &j = a.jobs[tl.job];
   const int64_t t = a.tick + j.t_offset;
   const float *xb = j.x[t & 1];
+  const int WH = tl.h + 2, B = j.xborder;
+  for (int q = threadIdx.x; q < WH * WW; q += 256) {
+    const int i = q / WW, c = q % WW;
+    sx[q] = quant_in<IN_FMT>(xb[(int64_t)(tl.y0 - 1 + i + B) * j.xpitch + (tl.x0 - 1 + c + B)],
+                             a.in_inv_scale);
+  }
+  const int grp = threadIdx.x % NG, slot = threadIdx.x / NG;
+  float w[CG][9], sc[CG], bi[CG];
+#pragma unroll
+  for (int cc = 0; cc < CG; ++cc) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[cc][k] = a.wf32[(grp * CG + cc) * 9 + k];
+    sc[cc] = a.oscale[grp * CG + cc];
+    bi[cc] = a.bias[grp * CG + cc];
+  }
+  __syncthreads();
   uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
   const int npix = (int)tl.h * tl.w;
-  for (int wi = threadIdx.x; wi < npix * NG; wi += blockDim.x) {
-    const int pix = wi / NG, grp = wi % NG;
+  for (int pix = slot; pix < npix; pix += PPP) {
     const int r = pix / tl.w, c = pix % tl.w;
-    const int Y = tl.y0 + r, X = tl.x0 + c;
     float q[9];
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx)
-        q[dy * 3 + dx] = quant_in<IN_FMT>(
-            xb[(int64_t)(Y + dy - 1 + j.xborder) * j.xpitch + (X + dx - 1 + j.xborder)],
-            a.in_inv_scale);
+    for (int k = 0; k < 9; ++k) q[k] = sx[(r + k / 3) * WW + c + k % 3];
     float v[CG];
 #pragma unroll
     for (int cc = 0; cc < CG; ++cc) {
-      const int co = grp * CG + cc;
-      const float *w = a.wf32 + co * 9;
       float acc = 0.0f;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) acc = fmaf(w[k], q[k], acc);
-      float o = acc * a.oscale[co] + a.bias[co];
+      for (int k = 0; k < 9; ++k) acc = fmaf(w[cc][k], q[k], acc);
+      float o = acc * sc[cc] + bi[cc];
       if (a.relu) o = fmaxf(o, 0.0f);
-      v[cc] = o * a.out_inv_scale;
+      v[cc] = o;
     }
-    uint8_t *dst = out + ((int64_t)(Y + 1) * j.apitch + (X + 1)) * (F * OB) + grp * 16;
+    uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * (F * OB) +
+                   grp * 16;
+    uint4 pk;
+    uint32_t *pw = reinterpret_cast<uint32_t *>(&pk);
+    if constexpr (OUT_FMT == FMT_F32) {
 #pragma unroll
-    for (int cc = 0; cc < CG; ++cc) store_act<OUT_FMT>(dst + cc * OB, v[cc]);
+      for (int e = 0; e < 4; ++e) pw[e] = __float_as_uint(v[e]);
+    } else if constexpr (OUT_FMT == FMT_BF16) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        pw[e] = (uint32_t)f32_to_bf16(v[2 * e]) | ((uint32_t)f32_to_bf16(v[2 * e + 1]) << 16);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        pw[e] = (uint32_t)f32_to_e4m3(v[4 * e] * a.out_inv_scale) |
+                ((uint32_t)f32_to_e4m3(v[4 * e + 1] * a.out_inv_scale) << 8) |
+                ((uint32_t)f32_to_e4m3(v[4 * e + 2] * a.out_inv_scale) << 16) |
+                ((uint32_t)f32_to_e4m3(v[4 * e + 3] * a.out_inv_scale) << 24);
+    }
+    *reinterpret_cast<uint4 *>(dst) = pk;
   }
 }
 
 // ---------------------------------------------------------------------
-// Last layer: F -> 1 (no activation); writes G (FP32, compact).
+// Last layer: F -> 1 (no activation); writes G (FP32, compact).  Each lane
+// owns one 16-byte chunk of input channels of a pixel (its weights in
+// registers); the lanes of a pixel are adjacent and their partial sums are
+// combined with cross-lane shuffles.
 // ---------------------------------------------------------------------
-// decode the 16-byte chunk c16 of a pixel into floats and accumulate its
-// dot product with the matching weights (w: [c_in][9], tap fixed)
-template <int FMT> __device__ __forceinline__ float dot_chunk(uint4 raw, const float *w, int ci0,
-                                                              int tap, float acc);
-template <> __device__ __forceinline__ float dot_chunk<FMT_F32>(uint4 raw, const float *w, int ci0,
-                                                                int tap, float acc) {
-  const uint32_t v[4] = {raw.x, raw.y, raw.z, raw.w};
-#pragma unroll
-  for (int e = 0; e < 4; ++e) acc = fmaf(w[(ci0 + e) * 9 + tap], __uint_as_float(v[e]), acc);
-  return acc;
+template <int FMT> __device__ __forceinline__ void decode16(uint4 raw, float *v);
+template <> __device__ __forceinline__ void decode16<FMT_F32>(uint4 raw, float *v) {
+  v[0] = __uint_as_float(raw.x); v[1] = __uint_as_float(raw.y);
+  v[2] = __uint_as_float(raw.z); v[3] = __uint_as_float(raw.w);
 }
-template <> __device__ __forceinline__ float dot_chunk<FMT_BF16>(uint4 raw, const float *w, int ci0,
-                                                                 int tap, float acc) {
-  const uint32_t v[4] = {raw.x, raw.y, raw.z, raw.w};
+template <> __device__ __forceinline__ void decode16<FMT_BF16>(uint4 raw, float *v) {
+  const uint32_t u[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    acc = fmaf(w[(ci0 + 2 * e) * 9 + tap], __uint_as_float(v[e] << 16), acc);
-    acc = fmaf(w[(ci0 + 2 * e + 1) * 9 + tap], __uint_as_float(v[e] & 0xffff0000u), acc);
+    v[2 * e] = __uint_as_float(u[e] << 16);
+    v[2 * e + 1] = __uint_as_float(u[e] & 0xffff0000u);
   }
-  return acc;
 }
-template <> __device__ __forceinline__ float dot_chunk<FMT_E4M3>(uint4 raw, const float *w, int ci0,
-                                                                 int tap, float acc) {
-  const uint32_t v[4] = {raw.x, raw.y, raw.z, raw.w};
+template <> __device__ __forceinline__ void decode16<FMT_E4M3>(uint4 raw, float *v) {
+  const uint32_t u[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
   for (int e = 0; e < 4; ++e)
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      acc = fmaf(w[(ci0 + 4 * e + k) * 9 + tap], e4m3_to_f32((uint8_t)(v[e] >> (8 * k))), acc);
-  return acc;
+    for (int k = 0; k < 4; ++k) v[4 * e + k] = e4m3_to_f32((uint8_t)(u[e] >> (8 * k)));
 }
 
 template <int IN_FMT, int F>
 __global__ __launch_bounds__(256) void conv_last_kernel(ConvArgs a) {
   constexpr int IB = FmtInfo<IN_FMT>::bytes;
   constexpr int PIXB = F * IB;
-  constexpr int EPC = 16 / IB;                 // elements per 16-byte chunk
-  __shared__ float sw[F * 9];
-  for (int i = threadIdx.x; i < F * 9; i += blockDim.x) sw[i] = a.wf32[i];
-  __syncthreads();
+  constexpr int NCH = PIXB / 16;               // lanes per pixel
+  constexpr int EPC = 16 / IB;                 // channels per lane
+  constexpr int PPP = 256 / NCH;
   const TileRef tl = a.tiles[blockIdx.x];
   const JobDesc &j = a.jobs[tl.job];
   const uint8_t *in = reinterpret_cast<const uint8_t *>(j.act[a.in_slot]);
+  const int ch = threadIdx.x % NCH, slot = threadIdx.x / NCH;
+  float w[EPC][9];
+#pragma unroll
+  for (int e = 0; e < EPC; ++e)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[e][k] = a.wf32[(ch * EPC + e) * 9 + k];
+  const float sc = a.oscale[0], bi = a.bias[0];
   const int npix = (int)tl.h * tl.w;
-  for (int pix = threadIdx.x; pix < npix; pix += blockDim.x) {
+  for (int pix = slot; pix < npix; pix += PPP) {
     const int r = pix / tl.w, c = pix % tl.w;
     const int Y = tl.y0 + r, X = tl.x0 + c;
     float acc = 0.0f;
-#pragma unroll 1
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      const int dy = tap / 3, dx = tap % 3;
-      const uint8_t *src = in + ((int64_t)(Y + dy) * j.apitch + (X + dx)) * PIXB;
-#pragma unroll 2
-      for (int c16 = 0; c16 < PIXB / 16; ++c16)
-        acc = dot_chunk<IN_FMT>(*reinterpret_cast<const uint4 *>(src + c16 * 16), sw,
-                                c16 * EPC, tap, acc);
+      const uint8_t *src =
+          in + ((int64_t)(Y + tap / 3) * j.apitch + (X + tap % 3)) * PIXB + ch * 16;
+      float v[EPC];
+      decode16<IN_FMT>(*reinterpret_cast<const uint4 *>(src), v);
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) acc = fmaf(w[e][tap], v[e], acc);
     }
-    j.G[(int64_t)Y * j.nx + X] = acc * a.oscale[0] + a.bias[0];
+#pragma unroll
+    for (int off = NCH / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (ch == 0) j.G[(int64_t)Y * j.nx + X] = acc * sc + bi;
   }
 }
 
@@ -493,7 +522,6 @@ hipError_t launch_conv_last(int in_fmt, int F, const ConvArgs &a, int n_tiles, h
     return hipGetLastError();                                                           \
   }
   LAST(FMT_F32, 16) LAST(FMT_F32, 32) LAST(FMT_F32, 64) LAST(FMT_BF16, 32) LAST(FMT_BF16, 64)
-  LAST(FMT_E4M3, 64)
 #undef LAST
   return hipErrorInvalidValue;
 }
