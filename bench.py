@@ -39,6 +39,15 @@ def parse():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-region", type=int, default=2048)
+    ap.add_argument("--serving", action="store_true",
+                    help="continuous-batching run: Poisson job arrivals, p50/p99 latency")
+    ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--iters-scale", type=float, default=0.1,
+                    help="serving: fraction of the 1000-5000 iterations each job runs")
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (three times): the "
+                         "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
 
 
@@ -88,6 +97,57 @@ def cpu_baseline(wl, region):
                       f"max(2r,K) halo) of the same workload, {dt:.1f} s"}
 
 
+def serving(a, stream):
+    """Jobs arrive by a Poisson process (20/s); each is submitted at its
+    arrival, the server ticks continuously, latency = completion - arrival."""
+    from paper_2511_00870_amd import pnpula as P
+    from paper_2511_00870_amd import workloads as W
+    lo, hi = max(1, int(1000 * a.iters_scale)), max(1, int(5000 * a.iters_scale))
+    jobs = W.serving_jobs(n_jobs=a.jobs, iters=(lo, hi))
+    net = jobs[0].workload
+    srv = P.Server(net.channels, net.weights, net.biases, precision=P.PNPULA_BF16,
+                   max_slots=a.slots, stream=stream)
+    cfgs = [P.Config.from_workload(j.workload) for j in jobs]
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    submitted, done, lat = {}, set(), []
+    nxt = 0
+    work = 0.0
+    while len(done) < len(jobs):
+        now = time.perf_counter() - t0
+        while nxt < len(jobs) and jobs[nxt].arrival_s <= now:
+            jid = srv.submit(cfgs[nxt], jobs[nxt].workload.iters)
+            submitted[jid] = nxt
+            nxt += 1
+        if len(submitted) == len(done):
+            time.sleep(max(0.0, jobs[nxt].arrival_s - now))
+            continue
+        srv.tick()
+        now = time.perf_counter() - t0
+        for jid, k in submitted.items():
+            if k in done or not srv.poll(jid):
+                continue
+            m, v, n = srv.result(jid)
+            done.add(k)
+            wl = jobs[k].workload
+            lat.append(now - jobs[k].arrival_s)
+            work += wl.ny * wl.nx * wl.iters
+    span = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {
+        "metric": "p50/p99 job latency and aggregate Mpixel*Langevin-iter/s (serving)",
+        "value": round(work / span / 1e6, 2), "unit": "Mpixel*iter/s", "n_gpus": 1,
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+        "makespan_s": round(span, 2), "higher_is_better": True, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {a.jobs} jobs, Poisson 20/s, sides 256-2048, "
+                               f"blur 5-9 (+50% mask), iterations {lo}-{hi}, 8x64 bf16 "
+                               f"denoiser, {a.slots} slots"},
+    }
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -97,7 +157,18 @@ def main():
     from paper_2511_00870_amd import workloads as W
     from paper_2511_00870_amd.accounting import fused_update_bytes_per_pixel
     torch.cuda.set_device(0)
+    if a.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return
     stream = torch.cuda.current_stream().cuda_stream
+    if a.serving:
+        print(json.dumps(serving(a, stream)), flush=True)
+        return
     wl = W.config(a.config)
     prec = wl.precision if a.precision is None else a.precision
     npx = wl.ny * wl.nx

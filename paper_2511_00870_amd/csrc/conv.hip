@@ -23,8 +23,27 @@
 //   E4M3: v_mfma_f32_16x16x128_f8f6f4, two taps x 64 channels per step (the
 //         tenth tap slot has zero weights).
 // First (1 -> F) and last (F -> 1) layers are small VALU stencils.
+#include <algorithm>
+#include <type_traits>
+
 #include "device_common.h"
 #include "kernels.h"
+
+// Implementation choices of the middle-layer kernel (all compute the same
+// result): register pipeline across K steps, LDS-staged epilogue, and the
+// register-resident-weight kernel for bf16 / e4m3.
+#ifndef PNP_MID_PIPE
+#define PNP_MID_PIPE 1
+#endif
+#ifndef PNP_MID_STAGE
+#define PNP_MID_STAGE 1
+#endif
+#ifndef PNP_USE_RW
+#define PNP_USE_RW 0
+#endif
+#ifndef PNP_NW_LOWP
+#define PNP_NW_LOWP 8
+#endif
 
 namespace pnp {
 
@@ -266,19 +285,36 @@ struct MidCfg {
 };
 
 template <int IN_FMT, int OUT_FMT, int F, int NW>
+struct MidLayout {
+  using C = MidCfg<IN_FMT, F>;
+  static constexpr int TH = 2 * NW, TW = kConvTileW;
+  static constexpr int IH = TH + 2, IW = TW + 2;
+  static constexpr int OB = FmtInfo<OUT_FMT>::bytes;
+  static constexpr int OPIXB = F * OB;               // bytes of one output pixel
+  static constexpr int OSTR = OPIXB + 16;            // LDS stride of staged outputs
+  static constexpr int IN_BYTES = IH * IW * C::PSTR;
+  static constexpr int OUT_BYTES = PNP_MID_STAGE ? TH * TW * OSTR : 0;
+  static constexpr int TILE_BYTES = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
+  static constexpr int LDS_BYTES = TILE_BYTES + C::WBYTES;
+};
+
+template <int IN_FMT, int OUT_FMT, int F, int NW>
 __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
   using C = MidCfg<IN_FMT, F>;
-  constexpr int TH = 2 * NW, TW = kConvTileW;
-  constexpr int IH = TH + 2, IW = TW + 2;
+  using Lo = MidLayout<IN_FMT, OUT_FMT, F, NW>;
+  constexpr int TH = Lo::TH, IW = Lo::IW;
   constexpr int NT = NW * 64;
-  constexpr int NCHUNK = IH * IW * C::CPP;
+  constexpr int NCHUNK = Lo::IH * IW * C::CPP;
   constexpr int NLOAD = (NCHUNK + NT - 1) / NT;
-  constexpr int OB = FmtInfo<OUT_FMT>::bytes;
+  constexpr int OB = Lo::OB;
   constexpr int MB = C::MB;
+  // fragment types and per-step operand counts
+  using AT = typename std::conditional<IN_FMT == FMT_BF16, bf16x8,
+             typename std::conditional<IN_FMT == FMT_F32, f32x4, i32x8>::type>::type;
 
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-  uint8_t *lds_in = lds;
-  uint8_t *lds_w = lds + IH * IW * C::PSTR;
+  uint8_t *lds_in = lds;                 // input tile, then staged output tile
+  uint8_t *lds_w = lds + Lo::TILE_BYTES;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
@@ -290,14 +326,6 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
   const int per_xcd = (nwg - xcd + 7) >> 3;
   const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
   const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
-
-  // per-lane epilogue constants: 4 consecutive output channels per M block
-  f32x4 osc[MB], bia[MB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    osc[mb] = *reinterpret_cast<const f32x4 *>(a.oscale + mb * 16 + 4 * g);
-    bia[mb] = *reinterpret_cast<const f32x4 *>(a.bias + mb * 16 + 4 * g);
-  }
 
   auto load_weights = [&](int chunk) {
     const uint4 *src = reinterpret_cast<const uint4 *>(
@@ -333,12 +361,74 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
     }
   };
 
+  // pixel of N block nb for this lane, relative to the input tile origin
+  auto in_pix = [&](int nb, int tap) {
+    const int dy = tap / 3, dx = tap % 3;
+    return (2 * wave + (nb >> 1) + dy) * IW + (nb & 1) * 16 + l16 + dx;
+  };
+  // operands of K step `sl` (index within the LDS-resident weight chunk)
+  auto load_step = [&](int step, int sl, AT (&A)[MB], AT (&B)[4]) {
+    const uint8_t *wf = lds_w + (size_t)sl * MB * 64 * C::FRAGB + lane * C::FRAGB;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      A[mb] = *reinterpret_cast<const AT *>(wf + mb * 64 * C::FRAGB);
+    if constexpr (IN_FMT == FMT_BF16) {
+      const int tap = step / (F / 32), half = step % (F / 32);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        B[nb] = *reinterpret_cast<const bf16x8 *>(lds_in + in_pix(nb, tap) * C::PSTR +
+                                                   (half * 4 + g) * 16);
+    } else if constexpr (IN_FMT == FMT_F32) {
+      const int tap = step / (F / 16), ss = step % (F / 16);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        B[nb] = *reinterpret_cast<const f32x4 *>(lds_in + in_pix(nb, tap) * C::PSTR +
+                                                  (ss * 4 + g) * 16);
+    } else {  // e4m3: taps 2*step (lane groups 0,1) and 2*step+1 (2,3); slot 9 -> tap 8
+      const int tap_raw = 2 * step + (g >> 1);
+      const int tap = tap_raw > 8 ? 8 : tap_raw;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const uint8_t *src = lds_in + in_pix(nb, tap) * C::PSTR + (g & 1) * 32;
+        const uint4 lo = *reinterpret_cast<const uint4 *>(src);
+        const uint4 hi = *reinterpret_cast<const uint4 *>(src + 16);
+        B[nb] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+    }
+  };
+  auto mma_step = [&](const AT (&A)[MB], const AT (&B)[4], f32x4 (&acc)[MB][4]) {
+    if constexpr (IN_FMT == FMT_BF16) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mb], B[nb], acc[mb][nb], 0, 0, 0);
+    } else if constexpr (IN_FMT == FMT_F32) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mb][e], B[nb][e], acc[mb][nb],
+                                                               0, 0, 0);
+    } else {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+              A[mb], B[nb], acc[mb][nb], 0, 0, 0, 0, 0, 0);
+    }
+  };
+
   if (C::NCH == 1) load_weights(0);
   int ti = t_begin + slot;
   if (ti < t_end) issue_loads(ti);
 
   while (ti < t_end) {
-    __syncthreads();          // previous tile's LDS reads are done
+    __syncthreads();          // previous tile's output staging has been read
     store_lds();
     __syncthreads();
     const TileRef tl = a.tiles[ti];
@@ -351,12 +441,6 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // pixel of N block nb for this lane, relative to the input tile origin
-    auto in_pix = [&](int nb, int tap) {
-      const int dy = tap / 3, dx = tap % 3;
-      return (2 * wave + (nb >> 1) + dy) * IW + (nb & 1) * 16 + l16 + dx;
-    };
-
 #pragma unroll 1
     for (int ch = 0; ch < C::NCH; ++ch) {
       if (C::NCH > 1) {
@@ -364,91 +448,292 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
         load_weights(ch);
         __syncthreads();
       }
+#if PNP_MID_PIPE
+      // two-stage register pipeline: the next step's LDS reads are issued
+      // before the current step's MFMAs
+      AT A0[MB], B0[4], A1[MB], B1[4];
+      load_step(ch * C::STEPS_PER_CH, 0, A0, B0);
 #pragma unroll 1
-      for (int sl = 0; sl < C::STEPS_PER_CH; ++sl) {
+      for (int sl = 0; sl < C::STEPS_PER_CH; sl += 2) {
         const int step = ch * C::STEPS_PER_CH + sl;
-        const uint8_t *wf = lds_w + (size_t)sl * MB * 64 * C::FRAGB + lane * C::FRAGB;
-        if constexpr (IN_FMT == FMT_BF16) {
-          const int tap = step / (F / 32), half = step % (F / 32);
-          bf16x8 A[MB], B[4];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            A[mb] = *reinterpret_cast<const bf16x8 *>(wf + mb * 64 * 16);
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb)
-            B[nb] = *reinterpret_cast<const bf16x8 *>(lds_in + in_pix(nb, tap) * C::PSTR +
-                                                       (half * 4 + g) * 16);
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mb], B[nb], acc[mb][nb],
-                                                                    0, 0, 0);
-        } else if constexpr (IN_FMT == FMT_F32) {
-          const int tap = step / (F / 16), ss = step % (F / 16);
-          f32x4 A[MB], B[4];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            A[mb] = *reinterpret_cast<const f32x4 *>(wf + mb * 64 * 16);
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb)
-            B[nb] = *reinterpret_cast<const f32x4 *>(lds_in + in_pix(nb, tap) * C::PSTR +
-                                                      (ss * 4 + g) * 16);
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-              for (int nb = 0; nb < 4; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mb][e], B[nb][e],
-                                                                   acc[mb][nb], 0, 0, 0);
-        } else {  // E4M3: step covers taps 2*step (lane groups 0,1) and 2*step+1 (2,3)
-          const int tap_raw = 2 * step + (g >> 1);
-          const int tap = tap_raw > 8 ? 8 : tap_raw;   // zero-weight slot reads tap 8
-          i32x8 A[MB], B[4];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            A[mb] = *reinterpret_cast<const i32x8 *>(wf + mb * 64 * 32);
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb) {
-            const uint8_t *src = lds_in + in_pix(nb, tap) * C::PSTR + (g & 1) * 32;
-            const uint4 lo = *reinterpret_cast<const uint4 *>(src);
-            const uint4 hi = *reinterpret_cast<const uint4 *>(src + 16);
-            B[nb] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                          (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-          }
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                  A[mb], B[nb], acc[mb][nb], 0, 0, 0, 0, 0, 0);
+        if (sl + 1 < C::STEPS_PER_CH) load_step(step + 1, sl + 1, A1, B1);
+        mma_step(A0, B0, acc);
+        if (sl + 1 < C::STEPS_PER_CH) {
+          if (sl + 2 < C::STEPS_PER_CH) load_step(step + 2, sl + 2, A0, B0);
+          mma_step(A1, B1, acc);
         }
       }
+#else
+#pragma unroll 1
+      for (int sl = 0; sl < C::STEPS_PER_CH; ++sl) {
+        AT A0[MB], B0[4];
+        load_step(ch * C::STEPS_PER_CH + sl, sl, A0, B0);
+        mma_step(A0, B0, acc);
+      }
+#endif
     }
 
-    // epilogue: scale, bias, ReLU, round to the next layer's format, store
-    const JobDesc &j = a.jobs[tl.job];
-    uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
+#if PNP_MID_STAGE
+    // epilogue: scale, bias, ReLU, round to the next layer's format, stage
+    // the tile in LDS (over the consumed input tile), then store whole
+    // pixels with 16-byte lanes
+    __syncthreads();
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
       const int r = 2 * wave + (nb >> 1), c = (nb & 1) * 16 + l16;
-      if (r < tl.h && c < tl.w) {
-        uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * (F * OB);
+      uint8_t *dst = lds_in + (r * kConvTileW + c) * Lo::OSTR;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          f32x4 v;
+      for (int mb = 0; mb < MB; ++mb) {
+        // 4 consecutive output channels of this lane
+        const f32x4 osc = *reinterpret_cast<const f32x4 *>(a.oscale + mb * 16 + 4 * g);
+        const f32x4 bia = *reinterpret_cast<const f32x4 *>(a.bias + mb * 16 + 4 * g);
+        f32x4 v;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float o = acc[mb][nb][e] * osc[mb][e] + bia[mb][e];
-            if (a.relu) o = fmaxf(o, 0.0f);
-            v[e] = o;
+        for (int e = 0; e < 4; ++e) {
+          float o = acc[mb][nb][e] * osc[e] + bia[e];
+          if (a.relu) o = fmaxf(o, 0.0f);
+          v[e] = o;
+        }
+        store4<OUT_FMT>(dst + (mb * 16 + 4 * g) * OB, v, a.out_inv_scale);
+      }
+    }
+    __syncthreads();
+    {
+      const JobDesc &j = a.jobs[tl.job];
+      uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
+      constexpr int CPPO = Lo::OPIXB / 16;
+      constexpr int NQ = TH * kConvTileW * CPPO;
+#pragma unroll
+      for (int q0 = 0; q0 < NQ; q0 += NT) {
+        const int q = q0 + tid;
+        const int pix = q / CPPO, c16 = q % CPPO;
+        const int r = pix / kConvTileW, c = pix % kConvTileW;
+        if (q < NQ && r < tl.h && c < tl.w)
+          *reinterpret_cast<uint4 *>(out + ((int64_t)(tl.y0 + r + 1) * j.apitch +
+                                            (tl.x0 + c + 1)) * Lo::OPIXB + c16 * 16) =
+              *reinterpret_cast<const uint4 *>(lds_in + pix * Lo::OSTR + c16 * 16);
+      }
+    }
+#else
+    // epilogue: scale, bias, ReLU, round to the next layer's format, store
+    // 4 consecutive channels of one pixel per lane
+    {
+      const JobDesc &j = a.jobs[tl.job];
+      uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int r = 2 * wave + (nb >> 1), c = (nb & 1) * 16 + l16;
+        if (r < tl.h && c < tl.w) {
+          uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * Lo::OPIXB;
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            const f32x4 osc = *reinterpret_cast<const f32x4 *>(a.oscale + mb * 16 + 4 * g);
+            const f32x4 bia = *reinterpret_cast<const f32x4 *>(a.bias + mb * 16 + 4 * g);
+            f32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              float o = acc[mb][nb][e] * osc[e] + bia[e];
+              if (a.relu) o = fmaxf(o, 0.0f);
+              v[e] = o;
+            }
+            store4<OUT_FMT>(dst + (mb * 16 + 4 * g) * OB, v, a.out_inv_scale);
           }
-          store4<OUT_FMT>(dst + (mb * 16 + 4 * g) * OB, v, a.out_inv_scale);
         }
       }
     }
+#endif
     ti = tn;
+  }
+}
+
+// ---------------------------------------------------------------------
+// Middle layers, register-resident weights (bf16 and e4m3, F = 64).
+// Every wave keeps the whole layer's A fragments in registers (bf16: 288
+// VGPRs, e4m3: 160), so LDS serves only the activations: half the LDS
+// traffic of the LDS-resident-weight kernel.  One wave per SIMD; input
+// tiles (8 x 32 output pixels) are double-buffered in LDS with one barrier
+// per tile; each wave stages its own outputs in a private LDS region and
+// stores whole pixels with 16-byte lanes.
+// ---------------------------------------------------------------------
+template <int IN_FMT, int OUT_FMT>
+struct RwLayout {
+  using C = MidCfg<IN_FMT, 64>;
+  static constexpr int NW = 4, TH = 8, TW = kConvTileW;
+  static constexpr int IH = TH + 2, IW = TW + 2;
+  static constexpr int OB = FmtInfo<OUT_FMT>::bytes;
+  static constexpr int OPIXB = 64 * OB;
+  static constexpr int OSTR = OPIXB + 16;
+  static constexpr int IN_BYTES = IH * IW * C::PSTR;
+  static constexpr int STAGE_BYTES = 64 * OSTR;          // per wave
+  static constexpr int LDS_BYTES = 2 * IN_BYTES + NW * STAGE_BYTES;
+};
+
+template <int IN_FMT, int OUT_FMT>
+__global__ __launch_bounds__(256, 1) void conv_mid_rw_kernel(ConvArgs a) {
+  using C = MidCfg<IN_FMT, 64>;
+  using Lo = RwLayout<IN_FMT, OUT_FMT>;
+  constexpr int IW = Lo::IW, NT = 256, MB = 4;
+  constexpr int NCHUNK = Lo::IH * IW * C::CPP;
+  constexpr int NLOAD = (NCHUNK + NT - 1) / NT;
+  constexpr int NSTEP = C::NSTEP;
+  constexpr int OB = Lo::OB;
+  using AT = typename std::conditional<IN_FMT == FMT_BF16, bf16x8, i32x8>::type;
+
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  uint8_t *stage = lds + 2 * Lo::IN_BYTES + wave * Lo::STAGE_BYTES;
+
+  const int nwg = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3;
+  const int per_xcd = (nwg - xcd + 7) >> 3;
+  const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
+  const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
+
+  // the layer's weights, fragment order, into registers
+  AT W[NSTEP][MB];
+  {
+    const uint8_t *wb = reinterpret_cast<const uint8_t *>(a.wblob) + lane * C::FRAGB;
+#pragma unroll
+    for (int st = 0; st < NSTEP; ++st)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        W[st][mb] = *reinterpret_cast<const AT *>(wb + (size_t)(st * MB + mb) * 64 * C::FRAGB);
+  }
+
+  uint4 pre[NLOAD];
+  auto issue_loads = [&](int ti) {
+    const TileRef tl = a.tiles[ti];
+    const JobDesc &j = a.jobs[tl.job];
+    const uint8_t *in = reinterpret_cast<const uint8_t *>(j.act[a.in_slot]);
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) {
+      const int q = tid + i * NT;
+      if (q < NCHUNK) {
+        const int pix = q / C::CPP, c = q % C::CPP;
+        const int row = pix / IW, col = pix % IW;
+        pre[i] = *reinterpret_cast<const uint4 *>(
+            in + ((int64_t)(tl.y0 + row) * j.apitch + (tl.x0 + col)) * C::PIXB + c * 16);
+      }
+    }
+  };
+  auto store_lds = [&](uint8_t *buf) {
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) {
+      const int q = tid + i * NT;
+      if (q < NCHUNK) {
+        const int pix = q / C::CPP, c = q % C::CPP;
+        *reinterpret_cast<uint4 *>(buf + pix * C::PSTR + c * 16) = pre[i];
+      }
+    }
+  };
+  auto load_b = [&](const uint8_t *buf, int step, AT (&B)[4]) {
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      if constexpr (IN_FMT == FMT_BF16) {
+        const int tap = step / 2, half = step % 2;
+        const int pix = (2 * wave + (nb >> 1) + tap / 3) * IW + (nb & 1) * 16 + l16 + tap % 3;
+        B[nb] = *reinterpret_cast<const bf16x8 *>(buf + pix * C::PSTR + (half * 4 + g) * 16);
+      } else {
+        const int tap_raw = 2 * step + (g >> 1);
+        const int tap = tap_raw > 8 ? 8 : tap_raw;
+        const int pix = (2 * wave + (nb >> 1) + tap / 3) * IW + (nb & 1) * 16 + l16 + tap % 3;
+        const uint8_t *src = buf + pix * C::PSTR + (g & 1) * 32;
+        const uint4 lo = *reinterpret_cast<const uint4 *>(src);
+        const uint4 hi = *reinterpret_cast<const uint4 *>(src + 16);
+        B[nb] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+    }
+  };
+  auto mma = [&](const AT (&A)[MB], const AT (&B)[4], f32x4 (&acc)[MB][4]) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        if constexpr (IN_FMT == FMT_BF16)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mb], B[nb], acc[mb][nb], 0, 0, 0);
+        else
+          acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+              A[mb], B[nb], acc[mb][nb], 0, 0, 0, 0, 0, 0);
+      }
+  };
+
+  int ti = t_begin + slot;
+  int cur = 0;
+  if (ti < t_end) {
+    issue_loads(ti);
+    store_lds(lds);
+  }
+  int tn = ti + per_xcd;
+  if (tn < t_end) issue_loads(tn);
+
+  while (ti < t_end) {
+    __syncthreads();   // tile ti is in buffer cur; everyone is done with buffer cur^1
+    uint8_t *buf = lds + cur * Lo::IN_BYTES;
+    const int tnn = tn + per_xcd;
+    if (tn < t_end) {
+      store_lds(lds + (cur ^ 1) * Lo::IN_BYTES);
+      if (tnn < t_end) issue_loads(tnn);
+    }
+    const TileRef tl = a.tiles[ti];
+
+    f32x4 acc[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    AT B0[4], B1[4];
+    load_b(buf, 0, B0);
+#pragma unroll
+    for (int st = 0; st < NSTEP; st += 2) {
+      if (st + 1 < NSTEP) load_b(buf, st + 1, B1);
+      mma(W[st], B0, acc);
+      if (st + 1 < NSTEP) {
+        if (st + 2 < NSTEP) load_b(buf, st + 2, B0);
+        mma(W[st + 1], B1, acc);
+      }
+    }
+
+    // epilogue: this wave's 64 pixels, staged privately, stored whole
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      uint8_t *dst = stage + (nb * 16 + l16) * Lo::OSTR;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const f32x4 osc = *reinterpret_cast<const f32x4 *>(a.oscale + mb * 16 + 4 * g);
+        const f32x4 bia = *reinterpret_cast<const f32x4 *>(a.bias + mb * 16 + 4 * g);
+        f32x4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float o = acc[mb][nb][e] * osc[e] + bia[e];
+          if (a.relu) o = fmaxf(o, 0.0f);
+          v[e] = o;
+        }
+        store4<OUT_FMT>(dst + (mb * 16 + 4 * g) * OB, v, a.out_inv_scale);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+      const JobDesc &j = a.jobs[tl.job];
+      uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
+      constexpr int CPPO = Lo::OPIXB / 16;
+#pragma unroll
+      for (int q0 = 0; q0 < 64 * CPPO; q0 += 64) {
+        const int q = q0 + lane;
+        const int p = q / CPPO, c16 = q % CPPO;           // p = nb * 16 + pixel in block
+        const int r = 2 * wave + (p >> 5), c = p & 31;
+        if (r < tl.h && c < tl.w)
+          *reinterpret_cast<uint4 *>(out + ((int64_t)(tl.y0 + r + 1) * j.apitch +
+                                            (tl.x0 + c + 1)) * Lo::OPIXB + c16 * 16) =
+              *reinterpret_cast<const uint4 *>(stage + p * Lo::OSTR + c16 * 16);
+      }
+    }
+    ti = tn;
+    tn = tnn;
+    cur ^= 1;
   }
 }
 
@@ -457,9 +742,7 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
 // ---------------------------------------------------------------------
 template <int IN_FMT, int OUT_FMT, int F, int NW>
 static hipError_t launch_mid_t(const ConvArgs &a, int n_wg, hipStream_t s) {
-  using C = MidCfg<IN_FMT, F>;
-  constexpr int TH = 2 * NW;
-  const size_t lds = (size_t)(TH + 2) * (kConvTileW + 2) * C::PSTR + C::WBYTES;
+  const size_t lds = MidLayout<IN_FMT, OUT_FMT, F, NW>::LDS_BYTES;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(
@@ -473,30 +756,63 @@ static hipError_t launch_mid_t(const ConvArgs &a, int n_wg, hipStream_t s) {
   return hipGetLastError();
 }
 
-int mid_tile_rows(int in_fmt) { return in_fmt == FMT_F32 ? 8 : 16; }
+template <int IN_FMT, int OUT_FMT>
+static hipError_t launch_rw_t(const ConvArgs &a, int n_wg, hipStream_t s) {
+  const size_t lds = RwLayout<IN_FMT, OUT_FMT>::LDS_BYTES;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&conv_mid_rw_kernel<IN_FMT, OUT_FMT>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((conv_mid_rw_kernel<IN_FMT, OUT_FMT>), dim3(n_wg), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+// bf16 / e4m3 with F = 64 use the register-resident-weight kernel
+static bool use_rw(int in_fmt, int F) { return PNP_USE_RW && in_fmt != FMT_F32 && F == 64; }
+
+// tile rows of the middle-layer kernel for an input format
+int mid_tile_rows(int in_fmt) {
+  if (in_fmt == FMT_F32 || PNP_USE_RW) return 8;
+  return 2 * PNP_NW_LOWP;
+}
 
 size_t mid_lds_bytes(int in_fmt, int F) {
+  if (use_rw(in_fmt, F))
+    return in_fmt == FMT_BF16 ? RwLayout<FMT_BF16, FMT_BF16>::LDS_BYTES
+                              : RwLayout<FMT_E4M3, FMT_BF16>::LDS_BYTES;
   const int TH = mid_tile_rows(in_fmt);
   const int ib = in_fmt == FMT_F32 ? 4 : (in_fmt == FMT_BF16 ? 2 : 1);
-  const int pstr = F * ib + 16;
+  const int ob = in_fmt == FMT_E4M3 ? 2 : ib;          // widest output format
+  const int pstr = F * ib + 16, ostr = PNP_MID_STAGE ? F * ob + 16 : 0;
   int nstep = in_fmt == FMT_E4M3 ? 5 : 9 * (in_fmt == FMT_F32 ? F / 16 : F / 32);
   int nch = (in_fmt == FMT_F32 && F == 64) ? 3 : 1;
   int fragb = in_fmt == FMT_E4M3 ? 32 : 16;
-  return (size_t)(TH + 2) * (kConvTileW + 2) * pstr + (size_t)(nstep / nch) * (F / 16) * 64 * fragb;
+  const size_t in_b = (size_t)(TH + 2) * (kConvTileW + 2) * pstr;
+  const size_t out_b = (size_t)TH * kConvTileW * ostr;
+  return std::max(in_b, out_b) + (size_t)(nstep / nch) * (F / 16) * 64 * fragb;
 }
 
 hipError_t launch_conv_mid(int in_fmt, int out_fmt, int F, const ConvArgs &a, int n_wg,
                            hipStream_t s) {
+  if (use_rw(in_fmt, F)) {
+    if (in_fmt == FMT_BF16 && out_fmt == FMT_BF16) return launch_rw_t<FMT_BF16, FMT_BF16>(a, n_wg, s);
+    if (in_fmt == FMT_E4M3 && out_fmt == FMT_E4M3) return launch_rw_t<FMT_E4M3, FMT_E4M3>(a, n_wg, s);
+    if (in_fmt == FMT_E4M3 && out_fmt == FMT_BF16) return launch_rw_t<FMT_E4M3, FMT_BF16>(a, n_wg, s);
+  }
   if (in_fmt == FMT_F32 && out_fmt == FMT_F32) {
     if (F == 16) return launch_mid_t<FMT_F32, FMT_F32, 16, 4>(a, n_wg, s);
     if (F == 32) return launch_mid_t<FMT_F32, FMT_F32, 32, 4>(a, n_wg, s);
     if (F == 64) return launch_mid_t<FMT_F32, FMT_F32, 64, 4>(a, n_wg, s);
   } else if (in_fmt == FMT_BF16 && out_fmt == FMT_BF16) {
-    if (F == 32) return launch_mid_t<FMT_BF16, FMT_BF16, 32, 8>(a, n_wg, s);
-    if (F == 64) return launch_mid_t<FMT_BF16, FMT_BF16, 64, 8>(a, n_wg, s);
+    if (F == 32) return launch_mid_t<FMT_BF16, FMT_BF16, 32, PNP_NW_LOWP>(a, n_wg, s);
+    if (F == 64) return launch_mid_t<FMT_BF16, FMT_BF16, 64, PNP_NW_LOWP>(a, n_wg, s);
   } else if (in_fmt == FMT_E4M3 && F == 64) {
-    if (out_fmt == FMT_E4M3) return launch_mid_t<FMT_E4M3, FMT_E4M3, 64, 8>(a, n_wg, s);
-    if (out_fmt == FMT_BF16) return launch_mid_t<FMT_E4M3, FMT_BF16, 64, 8>(a, n_wg, s);
+    if (out_fmt == FMT_E4M3) return launch_mid_t<FMT_E4M3, FMT_E4M3, 64, PNP_NW_LOWP>(a, n_wg, s);
+    if (out_fmt == FMT_BF16) return launch_mid_t<FMT_E4M3, FMT_BF16, 64, PNP_NW_LOWP>(a, n_wg, s);
   }
   return hipErrorInvalidValue;
 }

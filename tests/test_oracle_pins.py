@@ -382,3 +382,19 @@ def test_table_counts():
     d = g["ddfb4"]
     assert 2 * d["layers"] * denoiser_flops_per_pixel(
         [d["channels_in"], d["features"]], elementwise=False) == d["flops_per_pixel"]
+
+
+def test_step_region_equals_full_step_bitwise():
+    """The sampled-region step (used to check full-size GPU runs) is the full
+    step restricted to the region, bit for bit, at corners, edges and inside."""
+    wl = W.config(1, ny=40, nx=50, block=64, mask_p=0.5, bias_scale=0.05)
+    ch = O.Chain.from_workload(wl, block=0)
+    x = np.random.default_rng(0).random((40, 50))
+    ch.set_state(x, 3)
+    ch.step(1)
+    full, _ = ch.get_state()
+    for (y0, x0, h, w) in [(0, 0, 40, 50), (5, 7, 20, 30), (0, 41, 13, 9), (33, 0, 7, 11)]:
+        reg = ch.step_region(x, 3, y0, x0, h, w)
+        assert np.array_equal(reg, full[y0:y0 + h, x0:x0 + w])
+    with pytest.raises(ValueError):
+        ch.step_region(x, 3, 35, 0, 10, 10)
