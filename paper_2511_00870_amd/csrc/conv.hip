@@ -44,12 +44,19 @@
 #ifndef PNP_NW_LOWP
 #define PNP_NW_LOWP 8
 #endif
+#ifndef PNP_XCD_MAP
+#define PNP_XCD_MAP 1
+#endif
 
 namespace pnp {
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) int i32x8;
+// native 16-byte vector: a first-class IR type, so arrays of it stay in
+// registers (HIP's u32x4 struct is copied with memcpy and can be left in
+// private memory)
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 
 template <int FMT> struct FmtInfo;
 template <> struct FmtInfo<FMT_F32>  { static constexpr int bytes = 4; };
@@ -160,39 +167,41 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
     }
     uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * (F * OB) +
                    grp * 16;
-    uint4 pk;
-    uint32_t *pw = reinterpret_cast<uint32_t *>(&pk);
+    u32x4 pk;
     if constexpr (OUT_FMT == FMT_F32) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) pw[e] = __float_as_uint(v[e]);
+      for (int e = 0; e < 4; ++e) pk[e] = __float_as_uint(v[e]);
     } else if constexpr (OUT_FMT == FMT_BF16) {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        pw[e] = (uint32_t)f32_to_bf16(v[2 * e]) | ((uint32_t)f32_to_bf16(v[2 * e + 1]) << 16);
+        pk[e] = (uint32_t)f32_to_bf16(v[2 * e]) | ((uint32_t)f32_to_bf16(v[2 * e + 1]) << 16);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        pw[e] = (uint32_t)f32_to_e4m3(v[4 * e] * a.out_inv_scale) |
+        pk[e] = (uint32_t)f32_to_e4m3(v[4 * e] * a.out_inv_scale) |
                 ((uint32_t)f32_to_e4m3(v[4 * e + 1] * a.out_inv_scale) << 8) |
                 ((uint32_t)f32_to_e4m3(v[4 * e + 2] * a.out_inv_scale) << 16) |
                 ((uint32_t)f32_to_e4m3(v[4 * e + 3] * a.out_inv_scale) << 24);
     }
-    *reinterpret_cast<uint4 *>(dst) = pk;
+    *reinterpret_cast<u32x4 *>(dst) = pk;
   }
 }
 
 // ---------------------------------------------------------------------
-// Last layer: F -> 1 (no activation); writes G (FP32, compact).  Each lane
-// owns one 16-byte chunk of input channels of a pixel (its weights in
-// registers); the lanes of a pixel are adjacent and their partial sums are
-// combined with cross-lane shuffles.
+// Last layer: F -> 1 (no activation); writes G (FP32, compact).  Every pixel
+// of the tile's input window is read from memory once: a lane owns one
+// 16-byte chunk of its channels (those channels' weights for all 9 taps in
+// registers) and forms 9 per-tap partial dot products.  The lanes of a pixel
+// combine them with a reduce-scatter of cross-lane exchanges, so each lane
+// ends with whole sums for a subset of taps, and park them in LDS.  An output
+// pixel is then the sum over taps of its neighbours' parked values.
 // ---------------------------------------------------------------------
-template <int FMT> __device__ __forceinline__ void decode16(uint4 raw, float *v);
-template <> __device__ __forceinline__ void decode16<FMT_F32>(uint4 raw, float *v) {
+template <int FMT> __device__ __forceinline__ void decode16(u32x4 raw, float *v);
+template <> __device__ __forceinline__ void decode16<FMT_F32>(u32x4 raw, float *v) {
   v[0] = __uint_as_float(raw.x); v[1] = __uint_as_float(raw.y);
   v[2] = __uint_as_float(raw.z); v[3] = __uint_as_float(raw.w);
 }
-template <> __device__ __forceinline__ void decode16<FMT_BF16>(uint4 raw, float *v) {
+template <> __device__ __forceinline__ void decode16<FMT_BF16>(u32x4 raw, float *v) {
   const uint32_t u[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -200,7 +209,7 @@ template <> __device__ __forceinline__ void decode16<FMT_BF16>(uint4 raw, float 
     v[2 * e + 1] = __uint_as_float(u[e] & 0xffff0000u);
   }
 }
-template <> __device__ __forceinline__ void decode16<FMT_E4M3>(uint4 raw, float *v) {
+template <> __device__ __forceinline__ void decode16<FMT_E4M3>(u32x4 raw, float *v) {
   const uint32_t u[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
   for (int e = 0; e < 4; ++e)
@@ -212,36 +221,81 @@ template <int IN_FMT, int F>
 __global__ __launch_bounds__(256) void conv_last_kernel(ConvArgs a) {
   constexpr int IB = FmtInfo<IN_FMT>::bytes;
   constexpr int PIXB = F * IB;
-  constexpr int NCH = PIXB / 16;               // lanes per pixel
+  constexpr int NCH = PIXB / 16;               // lanes per pixel (power of two, <= 64)
   constexpr int EPC = 16 / IB;                 // channels per lane
-  constexpr int PPP = 256 / NCH;
+  constexpr int IW = kConvTileW + 2, IHM = 18; // largest window (16-row tiles)
+  static_assert((NCH & (NCH - 1)) == 0 && NCH <= 64 && 256 % NCH == 0, "lanes per pixel");
+  __shared__ float sp[9][IHM * IW];
   const TileRef tl = a.tiles[blockIdx.x];
   const JobDesc &j = a.jobs[tl.job];
   const uint8_t *in = reinterpret_cast<const uint8_t *>(j.act[a.in_slot]);
-  const int ch = threadIdx.x % NCH, slot = threadIdx.x / NCH;
+  const int ch = threadIdx.x % NCH;
   float w[EPC][9];
 #pragma unroll
   for (int e = 0; e < EPC; ++e)
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[e][k] = a.wf32[(ch * EPC + e) * 9 + k];
+  const int IH = tl.h + 2, WW = tl.w + 2, NQ = IH * WW * NCH;
+  for (int q0 = 0; q0 < NQ; q0 += 256) {     // uniform trip count: all lanes exchange
+    const int q = q0 + threadIdx.x;
+    const bool ok = q < NQ;
+    const int pix = q / NCH, row = pix / WW, col = pix % WW;
+    float v[8], v8 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = 0.0f;
+    if (ok) {
+      float xv[EPC];
+      decode16<IN_FMT>(*reinterpret_cast<const u32x4 *>(
+                           in + ((int64_t)(tl.y0 + row) * j.apitch + (tl.x0 + col)) * PIXB +
+                           ch * 16), xv);
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = fmaf(w[e][k], xv[e], v[k]);
+        v8 = fmaf(w[e][8], xv[e], v8);
+      }
+    }
+    // reduce-scatter of taps 0..7 over the NCH lanes of the pixel; tap 8 is
+    // all-reduced.  Afterwards this lane holds taps base .. base + n - 1.
+    int n = 8, base = 0;
+#pragma unroll
+    for (int off = NCH / 2; off >= 1; off >>= 1) {
+      if (n > 1) {
+        const bool hi = (ch & off) != 0;
+        n >>= 1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (k < n) {
+            const float keep = hi ? v[n + k] : v[k];
+            const float send = hi ? v[k] : v[n + k];
+            v[k] = keep + __shfl_xor(send, off);
+          }
+        }
+        if (hi) base += n;
+      } else {
+        v[0] += __shfl_xor(v[0], off);
+      }
+      v8 += __shfl_xor(v8, off);
+    }
+    // with more than 8 lanes per pixel, groups of NCH/8 lanes share a tap
+    constexpr int DUP = NCH > 8 ? NCH / 8 : 1;
+    if (ok && (ch % DUP) == 0) {
+      const int at = row * IW + col;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < n) sp[base + k][at] = v[k];
+      if (ch == 0) sp[8][at] = v8;
+    }
+  }
+  __syncthreads();
   const float sc = a.oscale[0], bi = a.bias[0];
   const int npix = (int)tl.h * tl.w;
-  for (int pix = slot; pix < npix; pix += PPP) {
+  for (int pix = threadIdx.x; pix < npix; pix += 256) {
     const int r = pix / tl.w, c = pix % tl.w;
-    const int Y = tl.y0 + r, X = tl.x0 + c;
     float acc = 0.0f;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const uint8_t *src =
-          in + ((int64_t)(Y + tap / 3) * j.apitch + (X + tap % 3)) * PIXB + ch * 16;
-      float v[EPC];
-      decode16<IN_FMT>(*reinterpret_cast<const uint4 *>(src), v);
-#pragma unroll
-      for (int e = 0; e < EPC; ++e) acc = fmaf(w[e][tap], v[e], acc);
-    }
-#pragma unroll
-    for (int off = NCH / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (ch == 0) j.G[(int64_t)Y * j.nx + X] = acc * sc + bi;
+    for (int tap = 0; tap < 9; ++tap) acc += sp[tap][(r + tap / 3) * IW + c + tap % 3];
+    j.G[(int64_t)(tl.y0 + r) * j.nx + tl.x0 + c] = acc * sc + bi;
   }
 }
 
@@ -322,19 +376,23 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
   // contiguous tile ranges per XCD (workgroups are dispatched round-robin
   // over the 8 XCDs): neighbouring tiles share their halo rows in one L2
   const int nwg = gridDim.x, b = blockIdx.x;
+#if PNP_XCD_MAP
   const int xcd = b & 7, slot = b >> 3;
   const int per_xcd = (nwg - xcd + 7) >> 3;
   const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
   const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
+#else
+  const int slot = b, per_xcd = nwg, t_begin = 0, t_end = a.n_tiles;
+#endif
 
   auto load_weights = [&](int chunk) {
-    const uint4 *src = reinterpret_cast<const uint4 *>(
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(
         reinterpret_cast<const uint8_t *>(a.wblob) + (size_t)chunk * C::WBYTES);
-    uint4 *dst = reinterpret_cast<uint4 *>(lds_w);
+    u32x4 *dst = reinterpret_cast<u32x4 *>(lds_w);
     for (int i = tid; i < C::WBYTES / 16; i += NT) dst[i] = src[i];
   };
 
-  uint4 pre[NLOAD];
+  u32x4 pre[NLOAD];
   auto issue_loads = [&](int ti) {
     const TileRef tl = a.tiles[ti];
     const JobDesc &j = a.jobs[tl.job];
@@ -345,7 +403,7 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
       if (q < NCHUNK) {
         const int pix = q / C::CPP, c = q % C::CPP;
         const int row = pix / IW, col = pix % IW;
-        pre[i] = *reinterpret_cast<const uint4 *>(
+        pre[i] = *reinterpret_cast<const u32x4 *>(
             in + ((int64_t)(tl.y0 + row) * j.apitch + (tl.x0 + col)) * C::PIXB + c * 16);
       }
     }
@@ -356,7 +414,7 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
       const int q = tid + i * NT;
       if (q < NCHUNK) {
         const int pix = q / C::CPP, c = q % C::CPP;
-        *reinterpret_cast<uint4 *>(lds_in + pix * C::PSTR + c * 16) = pre[i];
+        *reinterpret_cast<u32x4 *>(lds_in + pix * C::PSTR + c * 16) = pre[i];
       }
     }
   };
@@ -390,8 +448,8 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
         const uint8_t *src = lds_in + in_pix(nb, tap) * C::PSTR + (g & 1) * 32;
-        const uint4 lo = *reinterpret_cast<const uint4 *>(src);
-        const uint4 hi = *reinterpret_cast<const uint4 *>(src + 16);
+        const u32x4 lo = *reinterpret_cast<const u32x4 *>(src);
+        const u32x4 hi = *reinterpret_cast<const u32x4 *>(src + 16);
         B[nb] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
                       (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
       }
@@ -509,9 +567,9 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
         const int pix = q / CPPO, c16 = q % CPPO;
         const int r = pix / kConvTileW, c = pix % kConvTileW;
         if (q < NQ && r < tl.h && c < tl.w)
-          *reinterpret_cast<uint4 *>(out + ((int64_t)(tl.y0 + r + 1) * j.apitch +
+          *reinterpret_cast<u32x4 *>(out + ((int64_t)(tl.y0 + r + 1) * j.apitch +
                                             (tl.x0 + c + 1)) * Lo::OPIXB + c16 * 16) =
-              *reinterpret_cast<const uint4 *>(lds_in + pix * Lo::OSTR + c16 * 16);
+              *reinterpret_cast<const u32x4 *>(lds_in + pix * Lo::OSTR + c16 * 16);
       }
     }
 #else
@@ -601,7 +659,7 @@ __global__ __launch_bounds__(256, 1) void conv_mid_rw_kernel(ConvArgs a) {
         W[st][mb] = *reinterpret_cast<const AT *>(wb + (size_t)(st * MB + mb) * 64 * C::FRAGB);
   }
 
-  uint4 pre[NLOAD];
+  u32x4 pre[NLOAD];
   auto issue_loads = [&](int ti) {
     const TileRef tl = a.tiles[ti];
     const JobDesc &j = a.jobs[tl.job];
@@ -612,7 +670,7 @@ __global__ __launch_bounds__(256, 1) void conv_mid_rw_kernel(ConvArgs a) {
       if (q < NCHUNK) {
         const int pix = q / C::CPP, c = q % C::CPP;
         const int row = pix / IW, col = pix % IW;
-        pre[i] = *reinterpret_cast<const uint4 *>(
+        pre[i] = *reinterpret_cast<const u32x4 *>(
             in + ((int64_t)(tl.y0 + row) * j.apitch + (tl.x0 + col)) * C::PIXB + c * 16);
       }
     }
@@ -623,7 +681,7 @@ __global__ __launch_bounds__(256, 1) void conv_mid_rw_kernel(ConvArgs a) {
       const int q = tid + i * NT;
       if (q < NCHUNK) {
         const int pix = q / C::CPP, c = q % C::CPP;
-        *reinterpret_cast<uint4 *>(buf + pix * C::PSTR + c * 16) = pre[i];
+        *reinterpret_cast<u32x4 *>(buf + pix * C::PSTR + c * 16) = pre[i];
       }
     }
   };
@@ -639,8 +697,8 @@ __global__ __launch_bounds__(256, 1) void conv_mid_rw_kernel(ConvArgs a) {
         const int tap = tap_raw > 8 ? 8 : tap_raw;
         const int pix = (2 * wave + (nb >> 1) + tap / 3) * IW + (nb & 1) * 16 + l16 + tap % 3;
         const uint8_t *src = buf + pix * C::PSTR + (g & 1) * 32;
-        const uint4 lo = *reinterpret_cast<const uint4 *>(src);
-        const uint4 hi = *reinterpret_cast<const uint4 *>(src + 16);
+        const u32x4 lo = *reinterpret_cast<const u32x4 *>(src);
+        const u32x4 hi = *reinterpret_cast<const u32x4 *>(src + 16);
         B[nb] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
                       (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
       }
@@ -726,9 +784,9 @@ __global__ __launch_bounds__(256, 1) void conv_mid_rw_kernel(ConvArgs a) {
         const int p = q / CPPO, c16 = q % CPPO;           // p = nb * 16 + pixel in block
         const int r = 2 * wave + (p >> 5), c = p & 31;
         if (r < tl.h && c < tl.w)
-          *reinterpret_cast<uint4 *>(out + ((int64_t)(tl.y0 + r + 1) * j.apitch +
+          *reinterpret_cast<u32x4 *>(out + ((int64_t)(tl.y0 + r + 1) * j.apitch +
                                             (tl.x0 + c + 1)) * Lo::OPIXB + c16 * 16) =
-              *reinterpret_cast<const uint4 *>(stage + p * Lo::OSTR + c16 * 16);
+              *reinterpret_cast<const u32x4 *>(stage + p * Lo::OSTR + c16 * 16);
       }
     }
     ti = tn;
@@ -832,10 +890,12 @@ hipError_t launch_conv_first(int in_fmt, int out_fmt, int F, const ConvArgs &a, 
 }
 
 hipError_t launch_conv_last(int in_fmt, int F, const ConvArgs &a, int n_tiles, hipStream_t s) {
-#define LAST(I, FF)                                                                     \
-  if (in_fmt == I && F == FF) {                                                         \
-    hipLaunchKernelGGL((conv_last_kernel<I, FF>), dim3(n_tiles), dim3(256), 0, s, a);  \
-    return hipGetLastError();                                                           \
+  // the LDS window holds at most 16-row tiles
+  if (a.tile_rows < 1 || a.tile_rows > 16) return hipErrorInvalidValue;
+#define LAST(I, FF)                                                                    \
+  if (in_fmt == I && F == FF) {                                                        \
+    hipLaunchKernelGGL((conv_last_kernel<I, FF>), dim3(n_tiles), dim3(256), 0, s, a); \
+    return hipGetLastError();                                                          \
   }
   LAST(FMT_F32, 16) LAST(FMT_F32, 32) LAST(FMT_F32, 64) LAST(FMT_BF16, 32) LAST(FMT_BF16, 64)
 #undef LAST

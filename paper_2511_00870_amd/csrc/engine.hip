@@ -282,7 +282,7 @@ Status Engine::set_net(int K, const int32_t *ch, const float *w, const float *b,
       net.layers[k + 1].in_buf = net.layers[k].out_buf;
     }
   }
-  conv_th = (K > 2) ? mid_tile_rows(net.layers[1].in_fmt) : 16;
+  conv_th = (K > 1) ? mid_tile_rows(net.layers[1].in_fmt) : 16;
   plan_dirty = true;
   return Status::ok();
 }
@@ -653,6 +653,7 @@ Status Engine::launch_layer(int k, int64_t tick, bool prof) {
   a.jobs = d_jobs;
   a.tiles = d_conv;
   a.n_tiles = n_conv;
+  a.tile_rows = conv_th;
   a.tick = tick;
   a.relu = L.relu;
   a.bias = L.bias;

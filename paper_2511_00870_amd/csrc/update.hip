@@ -29,6 +29,9 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   const int64_t t = a.tick + j.t_offset;
   const int r = j.r, L = 2 * r + 1;
   constexpr int TH = kUpdTileH, TW = kUpdTileW;
+  // per-thread register budgets (r <= kMaxR): residual region and core
+  constexpr int RQ = ((TH + 2 * kMaxR) * (TW + 2 * kMaxR) + 255) / 256;
+  constexpr int CQ = TH * TW / 256;
   const int WH = TH + 4 * r, WW = TW + 4 * r;       // x window
   const int RH = TH + 2 * r, RW = TW + 2 * r;       // K x / residual region
   float *sx = smem;                                  // WH x WW
@@ -39,6 +42,45 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   const int tid = threadIdx.x;
   const float *xin = j.x[t & 1];
   const int B = j.xborder;
+  const int64_t s = t + 1 - j.burn_in;              // sample number of x^(t+1)
+  const bool stats = s >= 1;
+  int nw = 0;
+  bool merge = false;
+  if (stats) {
+    nw = (int)((s - j.wbase - 1) % j.wwin) + 1;
+    merge = nw == j.wwin;
+  }
+
+  // 0. issue every global read of the tile up front: y and mask on the
+  //    residual region, G and the Welford window on the core
+  float yv[RQ], mv[RQ];
+#pragma unroll
+  for (int k = 0; k < RQ; ++k) {
+    const int q = tid + 256 * k;
+    yv[k] = 0.0f;
+    mv[k] = 0.0f;
+    if (q < RH * RW) {
+      const int Y = tl.y0 - r + q / RW, X = tl.x0 - r + q % RW;
+      const int64_t pidx = (int64_t)(Y + B) * j.xpitch + (X + B);   // inside the padded buffer
+      yv[k] = j.y[pidx];
+      mv[k] = j.has_mask ? (float)j.mask[pidx] : 1.0f;
+    }
+  }
+  float gv[CQ], wmv[CQ], wm2v[CQ];
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int q = tid + 256 * k;
+    const int i = q / TW, c = q % TW;
+    gv[k] = wmv[k] = wm2v[k] = 0.0f;
+    if (i < tl.h && c < tl.w) {
+      const int64_t p = (int64_t)(tl.y0 + i) * j.nx + tl.x0 + c;
+      gv[k] = j.G[p];
+      if (stats && nw > 1) {
+        wmv[k] = j.wmean[p];
+        wm2v[k] = j.wm2[p];
+      }
+    }
+  }
 
   // 1. window of x^(t)
   const int wy = tl.y0 - 2 * r, wx = tl.x0 - 2 * r;
@@ -59,33 +101,33 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
     }
     __syncthreads();
   }
-  // 3. residual (K x kept in registers, written as the residual)
+  // 3. residual (zero outside the image)
   const int split = j.split;
   const bool draw = split && t >= 1;
-  for (int q = tid; q < RH * RW; q += 256) {
+#pragma unroll
+  for (int k = 0; k < RQ; ++k) {
+    const int q = tid + 256 * k;
+    if (q >= RH * RW) break;
     const int i = q / RW, c = q % RW;
     float kx = 0.0f;
     if (j.separable) {
-      for (int k = 0; k < L; ++k) kx = fmaf(j.ku[k], sh[(i + 2 * r - k) * RW + c], kx);
+      for (int kk = 0; kk < L; ++kk) kx = fmaf(j.ku[kk], sh[(i + 2 * r - kk) * RW + c], kx);
     } else {
       for (int a2 = 0; a2 < L; ++a2)
-        for (int k = 0; k < L; ++k)
-          kx = fmaf(j.kern[a2 * L + k], sx[(i + 2 * r - a2) * WW + (c + 2 * r - k)], kx);
+        for (int kk = 0; kk < L; ++kk)
+          kx = fmaf(j.kern[a2 * L + kk], sx[(i + 2 * r - a2) * WW + (c + 2 * r - kk)], kx);
     }
     const int Y = tl.y0 - r + i, X = tl.x0 - r + c;
     float res = 0.0f;
     if (Y >= 0 && Y < j.ny && X >= 0 && X < j.nx) {
-      const int64_t pidx = (int64_t)(Y + B) * j.xpitch + (X + B);
-      const float m = j.has_mask ? (float)j.mask[pidx] : 1.0f;
-      const float yv = j.y[pidx];
       if (!split) {
-        res = m * (kx - yv);
+        res = mv[k] * (kx - yv[k]);
       } else if (!draw) {
-        res = m * kx;                                      // z^(0) = 0
+        res = mv[k] * kx;                                      // z^(0) = 0
       } else {
         float xi, zeta;
         gauss_pair(j, (int64_t)Y * j.nx + X, t, xi, zeta);
-        res = m * (j.zmix * (kx - yv) - j.zsd * zeta);
+        res = mv[k] * (j.zmix * (kx - yv[k]) - j.zsd * zeta);
         const int ci = i - r, cc = c - r;
         if (ci >= 0 && ci < TH && cc >= 0 && cc < TW) sxi[ci * TW + cc] = xi;
       }
@@ -108,28 +150,22 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
 
   // 5./6. update, statistics
   float *xout = j.x[(t + 1) & 1];
-  const int64_t s = t + 1 - j.burn_in;                    // sample number of x^(t+1)
-  const bool stats = s >= 1;
-  int nw = 0;
-  bool merge = false;
-  if (stats) {
-    nw = (int)((s - j.wbase - 1) % j.wwin) + 1;
-    merge = nw == j.wwin;
-  }
   const float inv_nw = stats ? 1.0f / (float)nw : 0.0f;
   const int64_t na_i = j.nbase + (s - j.wbase - nw);       // merged before this window
   const double n_a = (double)na_i, n_b = (double)nw;
   bool bad = false;
-  for (int q = tid; q < TH * TW; q += 256) {
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int q = tid + 256 * k;
     const int i = q / TW, c = q % TW;
     if (i >= tl.h || c >= tl.w) continue;
     float ktr = 0.0f;
     if (j.separable) {
-      for (int k = 0; k < L; ++k) ktr = fmaf(j.ku[k], shr[(i + k) * TW + c], ktr);
+      for (int kk = 0; kk < L; ++kk) ktr = fmaf(j.ku[kk], shr[(i + kk) * TW + c], ktr);
     } else {
       for (int a2 = 0; a2 < L; ++a2)
-        for (int k = 0; k < L; ++k)
-          ktr = fmaf(j.kern[a2 * L + k], sres[(i + a2) * RW + (c + k)], ktr);
+        for (int kk = 0; kk < L; ++kk)
+          ktr = fmaf(j.kern[a2 * L + kk], sres[(i + a2) * RW + (c + kk)], ktr);
     }
     const int Y = tl.y0 + i, X = tl.x0 + c;
     const int64_t p = (int64_t)Y * j.nx + X;
@@ -142,13 +178,12 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
     }
     const float xo = sx[(i + 2 * r) * WW + (c + 2 * r)];
     const float proj = fminf(fmaxf(xo, 0.0f), 1.0f);
-    const float xn = xo - j.delta * (ktr * j.inv_s2) - j.cprior * j.G[p] +
+    const float xn = xo - j.delta * (ktr * j.inv_s2) - j.cprior * gv[k] +
                      j.cproj * (proj - xo) + j.sq2d * xi;
     bad |= !isfinite(xn);
     xout[(int64_t)(Y + B) * j.xpitch + (X + B)] = xn;
     if (stats) {
-      float m = 0.0f, M = 0.0f;
-      if (nw > 1) { m = j.wmean[p]; M = j.wm2[p]; }
+      float m = wmv[k], M = wm2v[k];                       // zero when the window starts
       const float d = xn - m;
       m = fmaf(d, inv_nw, m);
       M = fmaf(d, xn - m, M);
