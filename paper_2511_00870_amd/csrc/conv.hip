@@ -29,20 +29,20 @@
 #include "device_common.h"
 #include "kernels.h"
 
-// Implementation choices of the middle-layer kernel (all compute the same
-// result): register pipeline across K steps, LDS-staged epilogue, and the
-// register-resident-weight kernel for bf16 / e4m3.
+// Implementation choices of the middle-layer kernels (all compute the same
+// result): register pipeline across K steps, LDS-staged epilogue, the
+// row-reuse kernel for bf16 with 64 channels, and the XCD-aware tile order.
 #ifndef PNP_MID_PIPE
 #define PNP_MID_PIPE 1
 #endif
 #ifndef PNP_MID_STAGE
 #define PNP_MID_STAGE 1
 #endif
-#ifndef PNP_USE_RW
-#define PNP_USE_RW 0
-#endif
 #ifndef PNP_NW_LOWP
 #define PNP_NW_LOWP 8
+#endif
+#ifndef PNP_MID_RR
+#define PNP_MID_RR 1
 #endif
 #ifndef PNP_XCD_MAP
 #define PNP_XCD_MAP 1
@@ -54,7 +54,7 @@ typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) int i32x8;
 // native 16-byte vector: a first-class IR type, so arrays of it stay in
-// registers (HIP's u32x4 struct is copied with memcpy and can be left in
+// registers (HIP's uint4 struct is copied with memcpy and can be left in
 // private memory)
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 
@@ -96,22 +96,24 @@ template <> __device__ __forceinline__ float quant_in<FMT_E4M3>(float v, float i
   return e4m3_to_f32(f32_to_e4m3(v * inv_scale));
 }
 
-// pack 4 consecutive output channels of one pixel and store them
-template <int FMT> __device__ __forceinline__ void store4(void *p, f32x4 v, float inv_s);
-template <> __device__ __forceinline__ void store4<FMT_F32>(void *p, f32x4 v, float) {
-  *reinterpret_cast<f32x4 *>(p) = v;
-}
-template <> __device__ __forceinline__ void store4<FMT_BF16>(void *p, f32x4 v, float) {
-  uint2 w;
-  w.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
-  w.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
-  *reinterpret_cast<uint2 *>(p) = w;
-}
-template <> __device__ __forceinline__ void store4<FMT_E4M3>(void *p, f32x4 v, float inv_s) {
-  uint32_t w = (uint32_t)f32_to_e4m3(v[0] * inv_s) | ((uint32_t)f32_to_e4m3(v[1] * inv_s) << 8) |
-               ((uint32_t)f32_to_e4m3(v[2] * inv_s) << 16) |
-               ((uint32_t)f32_to_e4m3(v[3] * inv_s) << 24);
-  *reinterpret_cast<uint32_t *>(p) = w;
+// pack 4 consecutive output channels of one pixel and store them (P is a
+// byte pointer into LDS or global memory)
+typedef __attribute__((ext_vector_type(2))) unsigned int u32x2;
+template <int FMT, class P> __device__ __forceinline__ void store4(P *p, f32x4 v, float inv_s) {
+  if constexpr (FMT == FMT_F32) {
+    *reinterpret_cast<f32x4 *>(p) = v;
+  } else if constexpr (FMT == FMT_BF16) {
+    u32x2 w;
+    w.x = pack_bf16x2(v[0], v[1]);
+    w.y = pack_bf16x2(v[2], v[3]);
+    *reinterpret_cast<u32x2 *>(p) = w;
+  } else {
+    const uint32_t w = (uint32_t)f32_to_e4m3(v[0] * inv_s) |
+                       ((uint32_t)f32_to_e4m3(v[1] * inv_s) << 8) |
+                       ((uint32_t)f32_to_e4m3(v[2] * inv_s) << 16) |
+                       ((uint32_t)f32_to_e4m3(v[3] * inv_s) << 24);
+    *reinterpret_cast<uint32_t *>(p) = w;
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -127,16 +129,26 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
   constexpr int NG = F / CG;                   // lanes per pixel
   constexpr int PPP = 256 / NG;                // pixels per pass
   constexpr int WW = kConvTileW + 2;
+  constexpr int XQ = (18 * WW + 255) / 256;     // window loads per thread (16-row tiles)
   __shared__ float sx[18 * WW];
-  const TileRef tl = a.tiles[blockIdx.x];
-  const JobDesc &j = a.jobs[tl.job];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
-  const float *xb = j.x[t & 1];
+  const PNP_GLOBAL float *xb = gp(j.x[t & 1]);
   const int WH = tl.h + 2, B = j.xborder;
-  for (int q = threadIdx.x; q < WH * WW; q += 256) {
+  const int64_t xpitch = j.xpitch;
+  // all window loads in flight at once (out-of-range lanes read the origin)
+  float xv[XQ];
+#pragma unroll
+  for (int k = 0; k < XQ; ++k) {
+    const int q0 = (int)threadIdx.x + 256 * k, q = q0 < WH * WW ? q0 : 0;
     const int i = q / WW, c = q % WW;
-    sx[q] = quant_in<IN_FMT>(xb[(int64_t)(tl.y0 - 1 + i + B) * j.xpitch + (tl.x0 - 1 + c + B)],
-                             a.in_inv_scale);
+    xv[k] = xb[(tl.y0 - 1 + i + B) * xpitch + (tl.x0 - 1 + c + B)];
+  }
+#pragma unroll
+  for (int k = 0; k < XQ; ++k) {
+    const int q = (int)threadIdx.x + 256 * k;
+    if (q < WH * WW) sx[q] = quant_in<IN_FMT>(xv[k], a.in_inv_scale);
   }
   const int grp = threadIdx.x % NG, slot = threadIdx.x / NG;
   float w[CG][9], sc[CG], bi[CG];
@@ -148,7 +160,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
     bi[cc] = a.bias[grp * CG + cc];
   }
   __syncthreads();
-  uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
+  PNP_GLOBAL uint8_t *out = gp(reinterpret_cast<uint8_t *>(j.act[a.out_slot]));
   const int npix = (int)tl.h * tl.w;
   for (int pix = slot; pix < npix; pix += PPP) {
     const int r = pix / tl.w, c = pix % tl.w;
@@ -165,7 +177,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
       if (a.relu) o = fmaxf(o, 0.0f);
       v[cc] = o;
     }
-    uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * (F * OB) +
+    PNP_GLOBAL uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * (F * OB) +
                    grp * 16;
     u32x4 pk;
     if constexpr (OUT_FMT == FMT_F32) {
@@ -174,7 +186,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
     } else if constexpr (OUT_FMT == FMT_BF16) {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        pk[e] = (uint32_t)f32_to_bf16(v[2 * e]) | ((uint32_t)f32_to_bf16(v[2 * e + 1]) << 16);
+        pk[e] = pack_bf16x2(v[2 * e], v[2 * e + 1]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
@@ -183,7 +195,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
                 ((uint32_t)f32_to_e4m3(v[4 * e + 2] * a.out_inv_scale) << 16) |
                 ((uint32_t)f32_to_e4m3(v[4 * e + 3] * a.out_inv_scale) << 24);
     }
-    *reinterpret_cast<u32x4 *>(dst) = pk;
+    *reinterpret_cast<PNP_GLOBAL u32x4 *>(dst) = pk;
   }
 }
 
@@ -226,9 +238,9 @@ __global__ __launch_bounds__(256) void conv_last_kernel(ConvArgs a) {
   constexpr int IW = kConvTileW + 2, IHM = 18; // largest window (16-row tiles)
   static_assert((NCH & (NCH - 1)) == 0 && NCH <= 64 && 256 % NCH == 0, "lanes per pixel");
   __shared__ float sp[9][IHM * IW];
-  const TileRef tl = a.tiles[blockIdx.x];
-  const JobDesc &j = a.jobs[tl.job];
-  const uint8_t *in = reinterpret_cast<const uint8_t *>(j.act[a.in_slot]);
+  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+  const PNP_GLOBAL uint8_t *in = gp(reinterpret_cast<const uint8_t *>(j.act[a.in_slot]));
   const int ch = threadIdx.x % NCH;
   float w[EPC][9];
 #pragma unroll
@@ -236,55 +248,67 @@ __global__ __launch_bounds__(256) void conv_last_kernel(ConvArgs a) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[e][k] = a.wf32[(ch * EPC + e) * 9 + k];
   const int IH = tl.h + 2, WW = tl.w + 2, NQ = IH * WW * NCH;
-  for (int q0 = 0; q0 < NQ; q0 += 256) {     // uniform trip count: all lanes exchange
-    const int q = q0 + threadIdx.x;
-    const bool ok = q < NQ;
-    const int pix = q / NCH, row = pix / WW, col = pix % WW;
-    float v[8], v8 = 0.0f;
+  const int64_t apitch = j.apitch;
+  constexpr int U = 8;                         // loads in flight per thread
+  for (int q0 = 0; q0 < NQ; q0 += 256 * U) {   // uniform trip count: all lanes exchange
+    u32x4 raw[U];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = 0.0f;
-    if (ok) {
-      float xv[EPC];
-      decode16<IN_FMT>(*reinterpret_cast<const u32x4 *>(
-                           in + ((int64_t)(tl.y0 + row) * j.apitch + (tl.x0 + col)) * PIXB +
-                           ch * 16), xv);
-#pragma unroll
-      for (int e = 0; e < EPC; ++e) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = fmaf(w[e][k], xv[e], v[k]);
-        v8 = fmaf(w[e][8], xv[e], v8);
-      }
+    for (int u = 0; u < U; ++u) {
+      const int qa = q0 + 256 * u + (int)threadIdx.x, q = qa < NQ ? qa : ch;
+      const int pix = q / NCH, row = pix / WW, col = pix % WW;
+      raw[u] = *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+          in + ((tl.y0 + row) * apitch + (tl.x0 + col)) * PIXB + ch * 16);
     }
-    // reduce-scatter of taps 0..7 over the NCH lanes of the pixel; tap 8 is
-    // all-reduced.  Afterwards this lane holds taps base .. base + n - 1.
-    int n = 8, base = 0;
 #pragma unroll
-    for (int off = NCH / 2; off >= 1; off >>= 1) {
-      if (n > 1) {
-        const bool hi = (ch & off) != 0;
-        n >>= 1;
+    for (int u = 0; u < U; ++u) {
+      if (q0 + 256 * u >= NQ) break;           // uniform
+      const int q = q0 + 256 * u + (int)threadIdx.x;
+      const bool ok = q < NQ;
+      const int pix = q / NCH, row = pix / WW, col = pix % WW;
+      float v[8], v8 = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (k < n) {
-            const float keep = hi ? v[n + k] : v[k];
-            const float send = hi ? v[k] : v[n + k];
-            v[k] = keep + __shfl_xor(send, off);
-          }
+      for (int k = 0; k < 8; ++k) v[k] = 0.0f;
+      if (ok) {
+        float xv[EPC];
+        decode16<IN_FMT>(raw[u], xv);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = fmaf(w[e][k], xv[e], v[k]);
+          v8 = fmaf(w[e][8], xv[e], v8);
         }
-        if (hi) base += n;
-      } else {
-        v[0] += __shfl_xor(v[0], off);
       }
-      v8 += __shfl_xor(v8, off);
-    }
-    // with more than 8 lanes per pixel, groups of NCH/8 lanes share a tap
-    constexpr int DUP = NCH > 8 ? NCH / 8 : 1;
-    if (ok && (ch % DUP) == 0) {
-      const int at = row * IW + col;
+      // reduce-scatter of taps 0..7 over the NCH lanes of the pixel; tap 8 is
+      // all-reduced.  Afterwards this lane holds taps base .. base + n - 1.
+      int n = 8, base = 0;
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k < n) sp[base + k][at] = v[k];
-      if (ch == 0) sp[8][at] = v8;
+      for (int off = NCH / 2; off >= 1; off >>= 1) {
+        if (n > 1) {
+          const bool hi = (ch & off) != 0;
+          n >>= 1;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (k < n) {
+              const float keep = hi ? v[n + k] : v[k];
+              const float send = hi ? v[k] : v[n + k];
+              v[k] = keep + __shfl_xor(send, off);
+            }
+          }
+          if (hi) base += n;
+        } else {
+          v[0] += __shfl_xor(v[0], off);
+        }
+        v8 += __shfl_xor(v8, off);
+      }
+      // with more than 8 lanes per pixel, groups of NCH/8 lanes share a tap
+      constexpr int DUP = NCH > 8 ? NCH / 8 : 1;
+      if (ok && (ch % DUP) == 0) {
+        const int at = row * IW + col;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k < n) sp[base + k][at] = v[k];
+        if (ch == 0) sp[8][at] = v8;
+      }
     }
   }
   __syncthreads();
@@ -295,16 +319,16 @@ __global__ __launch_bounds__(256) void conv_last_kernel(ConvArgs a) {
     float acc = 0.0f;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) acc += sp[tap][(r + tap / 3) * IW + c + tap % 3];
-    j.G[(int64_t)(tl.y0 + r) * j.nx + tl.x0 + c] = acc * sc + bi;
+    gp(j.G)[(int64_t)(tl.y0 + r) * j.nx + tl.x0 + c] = acc * sc + bi;
   }
 }
 
 // single 1 -> 1 layer (K = 1): reads x^(t) (FP32), writes G
 __global__ __launch_bounds__(256) void conv_single_kernel(ConvArgs a) {
-  const TileRef tl = a.tiles[blockIdx.x];
-  const JobDesc &j = a.jobs[tl.job];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
-  const float *xb = j.x[t & 1];
+  const PNP_GLOBAL float *xb = gp(j.x[t & 1]);
   const int npix = (int)tl.h * tl.w;
   for (int pix = threadIdx.x; pix < npix; pix += blockDim.x) {
     const int r = pix / tl.w, c = pix % tl.w;
@@ -317,13 +341,39 @@ __global__ __launch_bounds__(256) void conv_single_kernel(ConvArgs a) {
                  xb[(int64_t)(Y + dy - 1 + j.xborder) * j.xpitch + (X + dx - 1 + j.xborder)],
                  acc);
     }
-    j.G[(int64_t)Y * j.nx + X] = acc * a.oscale[0] + a.bias[0];
+    gp(j.G)[(int64_t)Y * j.nx + X] = acc * a.oscale[0] + a.bias[0];
   }
 }
 
 // ---------------------------------------------------------------------
 // Middle layers: F -> F on MFMA.
 // ---------------------------------------------------------------------
+// What a persistent conv kernel needs of one tile, held in registers.
+// Output lanes of a partial tile store to a trash pixel (last slack row and
+// column of the activation buffer, which no kernel reads), so every tile
+// issues the same stores: the memory counters the compiler waits on then
+// count exactly, and no wait for a tile's loads includes its stores.
+struct MidTile {
+  int y0, x0, h, w;
+  int64_t apitch, trash;      // pixels per row; pixel index of the trash pixel
+  const PNP_GLOBAL uint8_t *in;
+  PNP_GLOBAL uint8_t *out;
+};
+__device__ __forceinline__ MidTile mid_tile(const ConvArgs &a, int ti) {
+  const PNP_CONST TileRef &tl = cp(a.tiles)[ti];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+  MidTile c;
+  c.y0 = tl.y0;
+  c.x0 = tl.x0;
+  c.h = tl.h;
+  c.w = tl.w;
+  c.apitch = j.apitch;
+  c.trash = (int64_t)j.arows * j.apitch - 1;
+  c.in = gp(reinterpret_cast<const uint8_t *>(j.act[a.in_slot]));
+  c.out = gp(reinterpret_cast<uint8_t *>(j.act[a.out_slot]));
+  return c;
+}
+
 template <int IN_FMT, int F>
 struct MidCfg {
   static constexpr int IB = FmtInfo<IN_FMT>::bytes;
@@ -349,7 +399,8 @@ struct MidLayout {
   static constexpr int IN_BYTES = IH * IW * C::PSTR;
   static constexpr int OUT_BYTES = PNP_MID_STAGE ? TH * TW * OSTR : 0;
   static constexpr int TILE_BYTES = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
-  static constexpr int LDS_BYTES = TILE_BYTES + C::WBYTES;
+  static constexpr int LDS_BYTES = TILE_BYTES + C::WBYTES + 2 * F * 4;   // + scale, bias
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
 template <int IN_FMT, int OUT_FMT, int F, int NW>
@@ -369,6 +420,8 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   uint8_t *lds_in = lds;                 // input tile, then staged output tile
   uint8_t *lds_w = lds + Lo::TILE_BYTES;
+  float *lds_osc = reinterpret_cast<float *>(lds_w + C::WBYTES);
+  float *lds_bias = lds_osc + F;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
@@ -386,26 +439,25 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
 #endif
 
   auto load_weights = [&](int chunk) {
-    const u32x4 *src = reinterpret_cast<const u32x4 *>(
-        reinterpret_cast<const uint8_t *>(a.wblob) + (size_t)chunk * C::WBYTES);
+    const PNP_GLOBAL u32x4 *src = gp(reinterpret_cast<const u32x4 *>(
+        reinterpret_cast<const uint8_t *>(a.wblob) + (size_t)chunk * C::WBYTES));
     u32x4 *dst = reinterpret_cast<u32x4 *>(lds_w);
     for (int i = tid; i < C::WBYTES / 16; i += NT) dst[i] = src[i];
   };
+  for (int i = tid; i < F; i += NT) {
+    lds_osc[i] = gp(a.oscale)[i];
+    lds_bias[i] = gp(a.bias)[i];
+  }
 
   u32x4 pre[NLOAD];
-  auto issue_loads = [&](int ti) {
-    const TileRef tl = a.tiles[ti];
-    const JobDesc &j = a.jobs[tl.job];
-    const uint8_t *in = reinterpret_cast<const uint8_t *>(j.act[a.in_slot]);
+  auto issue_loads = [&](const MidTile &tl) {
 #pragma unroll
     for (int i = 0; i < NLOAD; ++i) {
-      const int q = tid + i * NT;
-      if (q < NCHUNK) {
-        const int pix = q / C::CPP, c = q % C::CPP;
-        const int row = pix / IW, col = pix % IW;
-        pre[i] = *reinterpret_cast<const u32x4 *>(
-            in + ((int64_t)(tl.y0 + row) * j.apitch + (tl.x0 + col)) * C::PIXB + c * 16);
-      }
+      const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
+      const int pix = q / C::CPP, c = q % C::CPP;
+      const int row = pix / IW, col = pix % IW;
+      pre[i] = *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+          tl.in + ((int64_t)(tl.y0 + row) * tl.apitch + (tl.x0 + col)) * C::PIXB + c * 16);
     }
   };
   auto store_lds = [&]() {
@@ -482,16 +534,21 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
   };
 
   if (C::NCH == 1) load_weights(0);
+  // tile descriptors run two tiles ahead of the tile being computed, so no
+  // load issued after a tile's output stores is waited on before the next
+  // tile's stores (loads and stores share one completion counter)
   int ti = t_begin + slot;
-  if (ti < t_end) issue_loads(ti);
+  MidTile tl = mid_tile(a, ti < t_end ? ti : t_begin);
+  MidTile nxt = mid_tile(a, ti + per_xcd < t_end ? ti + per_xcd : t_begin);
+  if (ti < t_end) issue_loads(tl);
 
   while (ti < t_end) {
     __syncthreads();          // previous tile's output staging has been read
     store_lds();
     __syncthreads();
-    const TileRef tl = a.tiles[ti];
-    const int tn = ti + per_xcd;
-    if (tn < t_end) issue_loads(tn);  // overlaps with the MFMA work below
+    const int tn = ti + per_xcd, tnn = tn + per_xcd;
+    if (tn < t_end) issue_loads(nxt);  // overlaps with the MFMA work below
+    const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
 
     f32x4 acc[MB][4];
 #pragma unroll
@@ -543,8 +600,8 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         // 4 consecutive output channels of this lane
-        const f32x4 osc = *reinterpret_cast<const f32x4 *>(a.oscale + mb * 16 + 4 * g);
-        const f32x4 bia = *reinterpret_cast<const f32x4 *>(a.bias + mb * 16 + 4 * g);
+        const f32x4 osc = *reinterpret_cast<const f32x4 *>(lds_osc + mb * 16 + 4 * g);
+        const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + mb * 16 + 4 * g);
         f32x4 v;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -557,8 +614,7 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
     }
     __syncthreads();
     {
-      const JobDesc &j = a.jobs[tl.job];
-      uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
+      PNP_GLOBAL uint8_t *out = tl.out;
       constexpr int CPPO = Lo::OPIXB / 16;
       constexpr int NQ = TH * kConvTileW * CPPO;
 #pragma unroll
@@ -566,27 +622,29 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
         const int q = q0 + tid;
         const int pix = q / CPPO, c16 = q % CPPO;
         const int r = pix / kConvTileW, c = pix % kConvTileW;
-        if (q < NQ && r < tl.h && c < tl.w)
-          *reinterpret_cast<u32x4 *>(out + ((int64_t)(tl.y0 + r + 1) * j.apitch +
-                                            (tl.x0 + c + 1)) * Lo::OPIXB + c16 * 16) =
+        if (q < NQ) {
+          const int64_t px = (r < tl.h && c < tl.w)
+                                 ? (int64_t)(tl.y0 + r + 1) * tl.apitch + (tl.x0 + c + 1)
+                                 : tl.trash;
+          *reinterpret_cast<PNP_GLOBAL u32x4 *>(out + px * Lo::OPIXB + c16 * 16) =
               *reinterpret_cast<const u32x4 *>(lds_in + pix * Lo::OSTR + c16 * 16);
+        }
       }
     }
 #else
     // epilogue: scale, bias, ReLU, round to the next layer's format, store
     // 4 consecutive channels of one pixel per lane
     {
-      const JobDesc &j = a.jobs[tl.job];
-      uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
+      PNP_GLOBAL uint8_t *out = tl.out;
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
         const int r = 2 * wave + (nb >> 1), c = (nb & 1) * 16 + l16;
         if (r < tl.h && c < tl.w) {
-          uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * Lo::OPIXB;
+          PNP_GLOBAL uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * tl.apitch + (tl.x0 + c + 1)) * Lo::OPIXB;
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) {
-            const f32x4 osc = *reinterpret_cast<const f32x4 *>(a.oscale + mb * 16 + 4 * g);
-            const f32x4 bia = *reinterpret_cast<const f32x4 *>(a.bias + mb * 16 + 4 * g);
+            const f32x4 osc = *reinterpret_cast<const f32x4 *>(lds_osc + mb * 16 + 4 * g);
+            const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + mb * 16 + 4 * g);
             f32x4 v;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -600,198 +658,216 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
       }
     }
 #endif
+    tl = nxt;
+    nxt = after;
     ti = tn;
   }
 }
 
 // ---------------------------------------------------------------------
-// Middle layers, register-resident weights (bf16 and e4m3, F = 64).
-// Every wave keeps the whole layer's A fragments in registers (bf16: 288
-// VGPRs, e4m3: 160), so LDS serves only the activations: half the LDS
-// traffic of the LDS-resident-weight kernel.  One wave per SIMD; input
-// tiles (8 x 32 output pixels) are double-buffered in LDS with one barrier
-// per tile; each wave stages its own outputs in a private LDS region and
-// stores whole pixels with 16-byte lanes.
+// Middle layers, row-reuse form (bf16 in and out, F = 64).  One persistent
+// workgroup of 4 waves per CU, one wave per SIMD; the layer's weights stay in
+// LDS in fragment order and the 16 x 32 tile's (18 x 34)-pixel input window
+// is staged beside them.  Wave w owns output rows 4w..4w+3 (all 32 columns,
+// all 64 channels: 32 accumulator blocks).  For one horizontal tap dx and one
+// 32-channel half kh of the input, the B fragment of input row ir serves the
+// three vertical taps dy (output row ir - dy), so every B fragment is read
+// from LDS once per (dx, kh) instead of once per tap: half the LDS traffic
+// of the two-rows-per-wave form.
 // ---------------------------------------------------------------------
-template <int IN_FMT, int OUT_FMT>
-struct RwLayout {
-  using C = MidCfg<IN_FMT, 64>;
-  static constexpr int NW = 4, TH = 8, TW = kConvTileW;
-  static constexpr int IH = TH + 2, IW = TW + 2;
-  static constexpr int OB = FmtInfo<OUT_FMT>::bytes;
-  static constexpr int OPIXB = 64 * OB;
-  static constexpr int OSTR = OPIXB + 16;
-  static constexpr int IN_BYTES = IH * IW * C::PSTR;
-  static constexpr int STAGE_BYTES = 64 * OSTR;          // per wave
-  static constexpr int LDS_BYTES = 2 * IN_BYTES + NW * STAGE_BYTES;
+struct RrLayout {
+  static constexpr int F = 64, MB = 4, PIXB = 128, PSTR = PIXB + 16, CPP = 8;
+  static constexpr int TH = 16, TW = kConvTileW, IH = TH + 2, IW = TW + 2;
+  static constexpr int ROWS = 4;                              // output rows per wave
+  static constexpr int NSTEP = 18;                            // 9 taps x 2 channel halves
+  static constexpr int WBYTES = NSTEP * MB * 64 * 16;
+  static constexpr int IN_BYTES = IH * IW * PSTR;
+  static constexpr int OSTR = PIXB + 16;                      // staged bf16 outputs
+  static constexpr int OUT_BYTES = TH * TW * OSTR;
+  static constexpr int TILE_BYTES = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
+  static constexpr int EPI_BYTES = 2 * F * 4;                  // output scale and bias
+  static constexpr int LDS_BYTES = TILE_BYTES + WBYTES + EPI_BYTES;
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
-template <int IN_FMT, int OUT_FMT>
-__global__ __launch_bounds__(256, 1) void conv_mid_rw_kernel(ConvArgs a) {
-  using C = MidCfg<IN_FMT, 64>;
-  using Lo = RwLayout<IN_FMT, OUT_FMT>;
-  constexpr int IW = Lo::IW, NT = 256, MB = 4;
-  constexpr int NCHUNK = Lo::IH * IW * C::CPP;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void conv_mid_rr_kernel(ConvArgs a) {
+  using Lo = RrLayout;
+  constexpr int NT = 256, MB = Lo::MB, IW = Lo::IW, PSTR = Lo::PSTR, ROWS = Lo::ROWS;
+  constexpr int NCHUNK = Lo::IH * IW * Lo::CPP;
   constexpr int NLOAD = (NCHUNK + NT - 1) / NT;
-  constexpr int NSTEP = C::NSTEP;
-  constexpr int OB = Lo::OB;
-  using AT = typename std::conditional<IN_FMT == FMT_BF16, bf16x8, i32x8>::type;
 
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  uint8_t *lds_in = lds;
+  uint8_t *lds_w = lds + Lo::TILE_BYTES;
+  float *lds_osc = reinterpret_cast<float *>(lds_w + Lo::WBYTES);
+  float *lds_bias = lds_osc + Lo::F;
+
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  uint8_t *stage = lds + 2 * Lo::IN_BYTES + wave * Lo::STAGE_BYTES;
 
   const int nwg = gridDim.x, b = blockIdx.x;
+#if PNP_XCD_MAP
   const int xcd = b & 7, slot = b >> 3;
   const int per_xcd = (nwg - xcd + 7) >> 3;
   const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
   const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
+#else
+  const int slot = b, per_xcd = nwg, t_begin = 0, t_end = a.n_tiles;
+#endif
 
-  // the layer's weights, fragment order, into registers
-  AT W[NSTEP][MB];
   {
-    const uint8_t *wb = reinterpret_cast<const uint8_t *>(a.wblob) + lane * C::FRAGB;
-#pragma unroll
-    for (int st = 0; st < NSTEP; ++st)
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-        W[st][mb] = *reinterpret_cast<const AT *>(wb + (size_t)(st * MB + mb) * 64 * C::FRAGB);
+    const PNP_GLOBAL u32x4 *src = gp(reinterpret_cast<const u32x4 *>(a.wblob));
+    u32x4 *dst = reinterpret_cast<u32x4 *>(lds_w);
+    for (int i = tid; i < Lo::WBYTES / 16; i += NT) dst[i] = src[i];
+    if (tid < Lo::F) {
+      lds_osc[tid] = gp(a.oscale)[tid];
+      lds_bias[tid] = gp(a.bias)[tid];
+    }
   }
 
   u32x4 pre[NLOAD];
-  auto issue_loads = [&](int ti) {
-    const TileRef tl = a.tiles[ti];
-    const JobDesc &j = a.jobs[tl.job];
-    const uint8_t *in = reinterpret_cast<const uint8_t *>(j.act[a.in_slot]);
+  auto issue_loads = [&](const MidTile &c) {
 #pragma unroll
     for (int i = 0; i < NLOAD; ++i) {
-      const int q = tid + i * NT;
-      if (q < NCHUNK) {
-        const int pix = q / C::CPP, c = q % C::CPP;
-        const int row = pix / IW, col = pix % IW;
-        pre[i] = *reinterpret_cast<const u32x4 *>(
-            in + ((int64_t)(tl.y0 + row) * j.apitch + (tl.x0 + col)) * C::PIXB + c * 16);
-      }
+      const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
+      const int pix = q / Lo::CPP, k = q % Lo::CPP;
+      const int row = pix / IW, col = pix % IW;
+      pre[i] = *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+          c.in + ((int64_t)(c.y0 + row) * c.apitch + (c.x0 + col)) * Lo::PIXB + k * 16);
     }
-  };
-  auto store_lds = [&](uint8_t *buf) {
-#pragma unroll
-    for (int i = 0; i < NLOAD; ++i) {
-      const int q = tid + i * NT;
-      if (q < NCHUNK) {
-        const int pix = q / C::CPP, c = q % C::CPP;
-        *reinterpret_cast<u32x4 *>(buf + pix * C::PSTR + c * 16) = pre[i];
-      }
-    }
-  };
-  auto load_b = [&](const uint8_t *buf, int step, AT (&B)[4]) {
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      if constexpr (IN_FMT == FMT_BF16) {
-        const int tap = step / 2, half = step % 2;
-        const int pix = (2 * wave + (nb >> 1) + tap / 3) * IW + (nb & 1) * 16 + l16 + tap % 3;
-        B[nb] = *reinterpret_cast<const bf16x8 *>(buf + pix * C::PSTR + (half * 4 + g) * 16);
-      } else {
-        const int tap_raw = 2 * step + (g >> 1);
-        const int tap = tap_raw > 8 ? 8 : tap_raw;
-        const int pix = (2 * wave + (nb >> 1) + tap / 3) * IW + (nb & 1) * 16 + l16 + tap % 3;
-        const uint8_t *src = buf + pix * C::PSTR + (g & 1) * 32;
-        const u32x4 lo = *reinterpret_cast<const u32x4 *>(src);
-        const u32x4 hi = *reinterpret_cast<const u32x4 *>(src + 16);
-        B[nb] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-      }
-    }
-  };
-  auto mma = [&](const AT (&A)[MB], const AT (&B)[4], f32x4 (&acc)[MB][4]) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        if constexpr (IN_FMT == FMT_BF16)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mb], B[nb], acc[mb][nb], 0, 0, 0);
-        else
-          acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-              A[mb], B[nb], acc[mb][nb], 0, 0, 0, 0, 0, 0);
-      }
   };
 
+  // branch-free: lanes past the window loaded chunk 0 and store it there
+  // again (the same bytes the lane that owns chunk 0 stores)
+  auto store_lds = [&]() {
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) {
+      const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
+      const int pix = q / Lo::CPP, k = q % Lo::CPP;
+      *reinterpret_cast<u32x4 *>(lds_in + pix * PSTR + k * 16) = pre[i];
+    }
+  };
+
+  // Every iteration issues the same memory operations in the same order:
+  // the next tile's loads (a real tile's, or any valid tile's on the last
+  // iteration), the MFMAs, this tile's stores, then the LDS copy of the
+  // loads.  The copy therefore waits for the loads only, never for the
+  // stores (loads and stores share one in-order completion counter).  Tile
+  // descriptors are read two tiles ahead, as scalar loads.
   int ti = t_begin + slot;
-  int cur = 0;
-  if (ti < t_end) {
-    issue_loads(ti);
-    store_lds(lds);
-  }
-  int tn = ti + per_xcd;
-  if (tn < t_end) issue_loads(tn);
+  if (ti >= t_end) return;                       // uniform over the workgroup
+  MidTile cur = mid_tile(a, ti);
+  MidTile nxt = mid_tile(a, ti + per_xcd < t_end ? ti + per_xcd : t_begin);
+  issue_loads(cur);
+  store_lds();
+  __syncthreads();
 
-  while (ti < t_end) {
-    __syncthreads();   // tile ti is in buffer cur; everyone is done with buffer cur^1
-    uint8_t *buf = lds + cur * Lo::IN_BYTES;
-    const int tnn = tn + per_xcd;
-    if (tn < t_end) {
-      store_lds(lds + (cur ^ 1) * Lo::IN_BYTES);
-      if (tnn < t_end) issue_loads(tnn);
-    }
-    const TileRef tl = a.tiles[ti];
+  while (true) {
+    const int tn = ti + per_xcd, tnn = tn + per_xcd;
+    issue_loads(nxt);                            // in flight during the MFMAs below
+    const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
+    __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
 
-    f32x4 acc[MB][4];
+    f32x4 acc[MB][ROWS][2];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    AT B0[4], B1[4];
-    load_b(buf, 0, B0);
+      for (int o = 0; o < ROWS; ++o)
 #pragma unroll
-    for (int st = 0; st < NSTEP; st += 2) {
-      if (st + 1 < NSTEP) load_b(buf, st + 1, B1);
-      mma(W[st], B0, acc);
-      if (st + 1 < NSTEP) {
-        if (st + 2 < NSTEP) load_b(buf, st + 2, B0);
-        mma(W[st + 1], B1, acc);
+        for (int h = 0; h < 2; ++h) acc[mb][o][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // this lane's B column inside the window and its 16-byte channel chunk
+    const uint8_t *bbase = lds_in + ((ROWS * wave) * IW + l16) * PSTR + g * 16;
+    const uint8_t *abase = lds_w + lane * 16;
+    // Software pipeline over 36 stages (6 (dx, kh) iterations x 6 input
+    // rows): the B fragments of input row r+2 and the next iteration's A
+    // fragments are read from LDS while row r's MFMAs run.  Scheduling
+    // barriers keep each stage's reads ahead of its MFMAs.
+    constexpr int NIT = 6, NR = ROWS + 2, NSTG = NIT * NR;
+    bf16x8 Ab[2][3][MB], Bb[3][2];
+    auto load_a = [&](int it, int dy) {
+      const int dx = it >> 1, kh = it & 1;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        Ab[it & 1][dy][mb] = *reinterpret_cast<const bf16x8 *>(
+            abase + (((3 * dy + dx) * 2 + kh) * MB + mb) * 1024);
+    };
+    auto load_b = [&](int stg) {
+      const int it = stg / NR, ir = stg % NR, dx = it >> 1, kh = it & 1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        Bb[stg % 3][h] = *reinterpret_cast<const bf16x8 *>(
+            bbase + (ir * IW + 16 * h + dx) * PSTR + kh * 64);
+    };
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) load_a(0, dy);
+    load_b(0);
+    load_b(1);
+#pragma unroll
+    for (int stg = 0; stg < NSTG; ++stg) {
+      const int it = stg / NR, ir = stg % NR;
+      if (stg + 2 < NSTG) load_b(stg + 2);
+      if (it + 1 < NIT && ir >= 2 && ir <= 4) load_a(it + 1, ir - 2);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int o = ir - dy;
+        if (o < 0 || o >= ROWS) continue;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[mb][o][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                Ab[it & 1][dy][mb], Bb[stg % 3][h], acc[mb][o][h], 0, 0, 0);
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
 
-    // epilogue: this wave's 64 pixels, staged privately, stored whole
+    // epilogue: scale, bias, ReLU, bf16; stage the tile over the consumed
+    // input window, then store whole pixels with 16-byte lanes
+    __syncthreads();
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      uint8_t *dst = stage + (nb * 16 + l16) * Lo::OSTR;
+    for (int mb = 0; mb < MB; ++mb) {
+      const f32x4 osc = *reinterpret_cast<const f32x4 *>(lds_osc + mb * 16 + 4 * g);
+      const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + mb * 16 + 4 * g);
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const f32x4 osc = *reinterpret_cast<const f32x4 *>(a.oscale + mb * 16 + 4 * g);
-        const f32x4 bia = *reinterpret_cast<const f32x4 *>(a.bias + mb * 16 + 4 * g);
-        f32x4 v;
+      for (int o = 0; o < ROWS; ++o)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          float o = acc[mb][nb][e] * osc[e] + bia[e];
-          if (a.relu) o = fmaxf(o, 0.0f);
-          v[e] = o;
+        for (int h = 0; h < 2; ++h) {
+          f32x4 v;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float x = acc[mb][o][h][e] * osc[e] + bia[e];
+            if (a.relu) x = fmaxf(x, 0.0f);
+            v[e] = x;
+          }
+          const int r = ROWS * wave + o, c = 16 * h + l16;
+          store4<FMT_BF16>(lds_in + (r * Lo::TW + c) * Lo::OSTR + (mb * 16 + 4 * g) * 2, v, 1.0f);
         }
-        store4<OUT_FMT>(dst + (mb * 16 + 4 * g) * OB, v, a.out_inv_scale);
-      }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();
     {
-      const JobDesc &j = a.jobs[tl.job];
-      uint8_t *out = reinterpret_cast<uint8_t *>(j.act[a.out_slot]);
-      constexpr int CPPO = Lo::OPIXB / 16;
+      constexpr int NQ = Lo::TH * Lo::TW * Lo::CPP;
 #pragma unroll
-      for (int q0 = 0; q0 < 64 * CPPO; q0 += 64) {
-        const int q = q0 + lane;
-        const int p = q / CPPO, c16 = q % CPPO;           // p = nb * 16 + pixel in block
-        const int r = 2 * wave + (p >> 5), c = p & 31;
-        if (r < tl.h && c < tl.w)
-          *reinterpret_cast<u32x4 *>(out + ((int64_t)(tl.y0 + r + 1) * j.apitch +
-                                            (tl.x0 + c + 1)) * Lo::OPIXB + c16 * 16) =
-              *reinterpret_cast<const u32x4 *>(stage + p * Lo::OSTR + c16 * 16);
+      for (int q0 = 0; q0 < NQ; q0 += NT) {
+        const int q = q0 + tid;
+        const int pix = q / Lo::CPP, k = q % Lo::CPP;
+        const int r = pix / Lo::TW, c = pix % Lo::TW;
+        const int64_t px = (r < cur.h && c < cur.w)
+                               ? (int64_t)(cur.y0 + r + 1) * cur.apitch + (cur.x0 + c + 1)
+                               : cur.trash;
+        *reinterpret_cast<PNP_GLOBAL u32x4 *>(cur.out + px * Lo::PIXB + k * 16) =
+            *reinterpret_cast<const u32x4 *>(lds_in + pix * Lo::OSTR + k * 16);
       }
     }
+    __syncthreads();                             // staged outputs are read
+    store_lds();
+    __syncthreads();
+    if (tn >= t_end) break;
+    cur = nxt;
+    nxt = after;
     ti = tn;
-    tn = tnn;
-    cur ^= 1;
   }
 }
 
@@ -814,34 +890,28 @@ static hipError_t launch_mid_t(const ConvArgs &a, int n_wg, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int IN_FMT, int OUT_FMT>
-static hipError_t launch_rw_t(const ConvArgs &a, int n_wg, hipStream_t s) {
-  const size_t lds = RwLayout<IN_FMT, OUT_FMT>::LDS_BYTES;
+static_assert(!PNP_MID_RR || 2 * PNP_NW_LOWP == RrLayout::TH, "bf16 tile rows");
+static hipError_t launch_rr(const ConvArgs &a, int n_wg, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&conv_mid_rw_kernel<IN_FMT, OUT_FMT>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_mid_rr_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)RrLayout::LDS_BYTES);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((conv_mid_rw_kernel<IN_FMT, OUT_FMT>), dim3(n_wg), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(conv_mid_rr_kernel, dim3(n_wg), dim3(256), RrLayout::LDS_BYTES, s, a);
   return hipGetLastError();
 }
 
-// bf16 / e4m3 with F = 64 use the register-resident-weight kernel
-static bool use_rw(int in_fmt, int F) { return PNP_USE_RW && in_fmt != FMT_F32 && F == 64; }
-
 // tile rows of the middle-layer kernel for an input format
 int mid_tile_rows(int in_fmt) {
-  if (in_fmt == FMT_F32 || PNP_USE_RW) return 8;
+  if (in_fmt == FMT_F32) return 8;
   return 2 * PNP_NW_LOWP;
 }
 
 size_t mid_lds_bytes(int in_fmt, int F) {
-  if (use_rw(in_fmt, F))
-    return in_fmt == FMT_BF16 ? RwLayout<FMT_BF16, FMT_BF16>::LDS_BYTES
-                              : RwLayout<FMT_E4M3, FMT_BF16>::LDS_BYTES;
+  if (PNP_MID_RR && in_fmt == FMT_BF16 && F == 64) return RrLayout::LDS_BYTES;
   const int TH = mid_tile_rows(in_fmt);
   const int ib = in_fmt == FMT_F32 ? 4 : (in_fmt == FMT_BF16 ? 2 : 1);
   const int ob = in_fmt == FMT_E4M3 ? 2 : ib;          // widest output format
@@ -851,21 +921,17 @@ size_t mid_lds_bytes(int in_fmt, int F) {
   int fragb = in_fmt == FMT_E4M3 ? 32 : 16;
   const size_t in_b = (size_t)(TH + 2) * (kConvTileW + 2) * pstr;
   const size_t out_b = (size_t)TH * kConvTileW * ostr;
-  return std::max(in_b, out_b) + (size_t)(nstep / nch) * (F / 16) * 64 * fragb;
+  return std::max(in_b, out_b) + (size_t)(nstep / nch) * (F / 16) * 64 * fragb + 2 * F * 4;
 }
 
 hipError_t launch_conv_mid(int in_fmt, int out_fmt, int F, const ConvArgs &a, int n_wg,
                            hipStream_t s) {
-  if (use_rw(in_fmt, F)) {
-    if (in_fmt == FMT_BF16 && out_fmt == FMT_BF16) return launch_rw_t<FMT_BF16, FMT_BF16>(a, n_wg, s);
-    if (in_fmt == FMT_E4M3 && out_fmt == FMT_E4M3) return launch_rw_t<FMT_E4M3, FMT_E4M3>(a, n_wg, s);
-    if (in_fmt == FMT_E4M3 && out_fmt == FMT_BF16) return launch_rw_t<FMT_E4M3, FMT_BF16>(a, n_wg, s);
-  }
   if (in_fmt == FMT_F32 && out_fmt == FMT_F32) {
     if (F == 16) return launch_mid_t<FMT_F32, FMT_F32, 16, 4>(a, n_wg, s);
     if (F == 32) return launch_mid_t<FMT_F32, FMT_F32, 32, 4>(a, n_wg, s);
     if (F == 64) return launch_mid_t<FMT_F32, FMT_F32, 64, 4>(a, n_wg, s);
   } else if (in_fmt == FMT_BF16 && out_fmt == FMT_BF16) {
+    if (F == 64 && PNP_MID_RR) return launch_rr(a, n_wg, s);
     if (F == 32) return launch_mid_t<FMT_BF16, FMT_BF16, 32, PNP_NW_LOWP>(a, n_wg, s);
     if (F == 64) return launch_mid_t<FMT_BF16, FMT_BF16, 64, PNP_NW_LOWP>(a, n_wg, s);
   } else if (in_fmt == FMT_E4M3 && F == 64) {

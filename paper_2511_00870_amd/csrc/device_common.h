@@ -28,7 +28,7 @@ struct JobDesc {
   int32_t split;           // rho > 0
   int32_t burn_in;
   int32_t wwin;            // Welford window
-  int32_t pad0;
+  int32_t arows;           // rows of the activation buffers (border 1, then slack)
   int64_t t_offset;        // this chain's t = tick + t_offset
   int64_t wbase;           // sample number of the last out-of-band merge point
                            // (flush, restore or state change); windows of wwin
@@ -59,11 +59,30 @@ struct JobDesc {
 };
 
 // A rectangle of one job's image: rows [y0, y0+h), cols [x0, x0+w).
+// 32-bit fields only: kernels read it with scalar loads.
 struct TileRef {
   int32_t job;
   int32_t y0, x0;
-  int16_t h, w;
+  int32_t h, w;
+  int32_t pad[3];
 };
+
+// Pointers read out of a JobDesc are generic pointers to the compiler, and
+// generic (flat) memory instructions also count against the LDS wait counter:
+// a kernel waiting for its LDS reads would wait for every outstanding flat load
+// too.  Device code therefore re-types them to the global address space.
+#define PNP_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ PNP_GLOBAL T *gp(T *p) {
+  return (PNP_GLOBAL T *)p;
+}
+// Descriptors (tile lists, JobDesc) are never written by a kernel; read
+// through the constant address space, uniform reads of them become scalar
+// loads, which a kernel can wait on without waiting for its outstanding
+// vector-memory loads and stores.
+#define PNP_CONST __attribute__((address_space(4)))
+template <class T> __device__ __forceinline__ const PNP_CONST T *cp(const T *p) {
+  return (const PNP_CONST T *)p;
+}
 
 // --------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
@@ -84,10 +103,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 
 // Two standard normals of pixel p at iteration t: (cos, sin) Box-Muller
 // branches on 24-bit uniforms, exact in FP32.
-__device__ __forceinline__ void gauss_pair(const JobDesc &j, int64_t p, int64_t t,
-                                           float &xi, float &zeta) {
-  uint4 c = make_uint4((uint32_t)p, (uint32_t)t, j.chain, (uint32_t)((uint64_t)p >> 32));
-  uint4 w = philox4x32_10(c, j.key0, j.key1);
+__device__ __forceinline__ void gauss_pair(uint32_t key0, uint32_t key1, uint32_t chain,
+                                           int64_t p, int64_t t, float &xi, float &zeta) {
+  uint4 c = make_uint4((uint32_t)p, (uint32_t)t, chain, (uint32_t)((uint64_t)p >> 32));
+  uint4 w = philox4x32_10(c, key0, key1);
   const float u1 = (float)((w.x >> 8) + 1u) * 5.9604644775390625e-8f;  // 2^-24
   const float u2 = (float)(w.y >> 8) * 5.9604644775390625e-8f;
   const float rad = sqrtf(-2.0f * logf(u1));
@@ -100,11 +119,16 @@ __device__ __forceinline__ void gauss_pair(const JobDesc &j, int64_t p, int64_t 
 // --------------------------------------------------------------------
 // bf16 and OCP e4m3fn conversions (round to nearest even; e4m3 saturates)
 // --------------------------------------------------------------------
+// gfx950 converts in hardware (v_cvt_pk_bf16_f32, round to nearest even; a
+// NaN stays a quiet NaN)
+typedef __attribute__((ext_vector_type(2))) float pnp_f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 pnp_bf16x2;
 __device__ __forceinline__ uint16_t f32_to_bf16(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+// two values: the low half holds lo
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(pnp_f32x2{lo, hi}, pnp_bf16x2));
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
   return __uint_as_float((uint32_t)b << 16);

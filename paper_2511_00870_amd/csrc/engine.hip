@@ -370,12 +370,12 @@ static void make_tiles(std::vector<TileRef> &out, int ny, int nx, int by, int bx
       const int bh = std::min(by, ny - y0), bw = std::min(bx, nx - x0);
       for (int ty = 0; ty < bh; ty += TH)
         for (int tx = 0; tx < bw; tx += TW) {
-          TileRef t;
+          TileRef t{};
           t.job = 0;
           t.y0 = y0 + ty;
           t.x0 = x0 + tx;
-          t.h = (int16_t)std::min(TH, bh - ty);
-          t.w = (int16_t)std::min(TW, bw - tx);
+          t.h = std::min(TH, bh - ty);
+          t.w = std::min(TW, bw - tx);
           out.push_back(t);
         }
     }
@@ -394,6 +394,7 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   d.xpitch = g.pitch;
   d.xborder = g.B;
   d.apitch = g.apitch;
+  d.arows = g.arows;
   d.r = r;
   d.has_mask = c->mask != nullptr;
   d.split = c->rho > 0;

@@ -24,14 +24,15 @@ namespace pnp {
 
 __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
-  const TileRef tl = a.tiles[blockIdx.x];
-  const JobDesc &j = a.jobs[tl.job];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
   const int r = j.r, L = 2 * r + 1;
   constexpr int TH = kUpdTileH, TW = kUpdTileW;
   // per-thread register budgets (r <= kMaxR): residual region and core
   constexpr int RQ = ((TH + 2 * kMaxR) * (TW + 2 * kMaxR) + 255) / 256;
   constexpr int CQ = TH * TW / 256;
+  constexpr int XQ = ((TH + 4 * kMaxR) * (TW + 4 * kMaxR) + 255) / 256;
   const int WH = TH + 4 * r, WW = TW + 4 * r;       // x window
   const int RH = TH + 2 * r, RW = TW + 2 * r;       // K x / residual region
   float *sx = smem;                                  // WH x WW
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   float *shr = sres + RH * RW;                       // RH x TW  (row pass of res)
   float *sxi = shr + RH * TW;                        // TH x TW
   const int tid = threadIdx.x;
-  const float *xin = j.x[t & 1];
+  const PNP_GLOBAL float *xin = gp(j.x[t & 1]);
   const int B = j.xborder;
   const int64_t s = t + 1 - j.burn_in;              // sample number of x^(t+1)
   const bool stats = s >= 1;
@@ -51,42 +52,74 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
     merge = nw == j.wwin;
   }
 
-  // 0. issue every global read of the tile up front: y and mask on the
-  //    residual region, G and the Welford window on the core
-  float yv[RQ], mv[RQ];
+  // blur taps, staged in LDS once per workgroup: their loads go first
+  constexpr int KMAX = (2 * kMaxR + 1) * (2 * kMaxR + 1);
+  __shared__ float sku[2 * kMaxR + 1], skv[2 * kMaxR + 1], skern[KMAX];
+  const bool sep = j.separable;
+  const int nk = sep ? L : L * L;
+  float tap0, tap1;
+  {
+    const PNP_GLOBAL float *k0 = gp(sep ? j.ku : j.kern);
+    const PNP_GLOBAL float *k1 = gp(sep ? j.kv : j.kern);
+    const int i0 = tid < nk ? tid : 0;
+    const int i1 = sep ? i0 : (tid + 256 < nk ? tid + 256 : 0);
+    tap0 = k0[i0];
+    tap1 = k1[i1];
+  }
+
+  // 0. issue every global read of the tile up front: the x window, y and
+  //    mask on the residual region, G and the Welford window on the core
+  //    (no branch around a load: out-of-range lanes read a valid address and
+  //    ignore the value, so the waits fall where the values are used)
+  const int wy = tl.y0 - 2 * r, wx = tl.x0 - 2 * r;
+  const int64_t xpitch = j.xpitch;
+  float xv[XQ];
+#pragma unroll
+  for (int k = 0; k < XQ; ++k) {
+    const int q0 = tid + 256 * k, q = q0 < WH * WW ? q0 : 0;
+    const int i = q / WW, c = q % WW;
+    xv[k] = xin[(wy + i + B) * xpitch + (wx + c + B)];
+  }
+  const PNP_GLOBAL float *yb = gp(j.y);
+  const PNP_GLOBAL uint8_t *mk = gp(j.has_mask ? j.mask : reinterpret_cast<const uint8_t *>(j.y));
+  float yv[RQ];
+  uint32_t mraw[RQ];
 #pragma unroll
   for (int k = 0; k < RQ; ++k) {
-    const int q = tid + 256 * k;
-    yv[k] = 0.0f;
-    mv[k] = 0.0f;
-    if (q < RH * RW) {
-      const int Y = tl.y0 - r + q / RW, X = tl.x0 - r + q % RW;
-      const int64_t pidx = (int64_t)(Y + B) * j.xpitch + (X + B);   // inside the padded buffer
-      yv[k] = j.y[pidx];
-      mv[k] = j.has_mask ? (float)j.mask[pidx] : 1.0f;
-    }
+    const int q0 = tid + 256 * k, q = q0 < RH * RW ? q0 : 0;
+    const int Y = tl.y0 - r + q / RW, X = tl.x0 - r + q % RW;
+    const int64_t pidx = (Y + B) * xpitch + (X + B);   // inside the padded buffer
+    yv[k] = yb[pidx];
+    mraw[k] = mk[pidx];
   }
   float gv[CQ], wmv[CQ], wm2v[CQ];
 #pragma unroll
   for (int k = 0; k < CQ; ++k) {
     const int q = tid + 256 * k;
     const int i = q / TW, c = q % TW;
-    gv[k] = wmv[k] = wm2v[k] = 0.0f;
-    if (i < tl.h && c < tl.w) {
-      const int64_t p = (int64_t)(tl.y0 + i) * j.nx + tl.x0 + c;
-      gv[k] = j.G[p];
-      if (stats && nw > 1) {
-        wmv[k] = j.wmean[p];
-        wm2v[k] = j.wm2[p];
-      }
+    const int64_t p = (i < tl.h && c < tl.w) ? (int64_t)(tl.y0 + i) * j.nx + tl.x0 + c : 0;
+    gv[k] = gp(j.G)[p];
+    wmv[k] = wm2v[k] = 0.0f;
+    if (stats && nw > 1) {                           // uniform
+      wmv[k] = gp(j.wmean)[p];
+      wm2v[k] = gp(j.wm2)[p];
     }
   }
 
-  // 1. window of x^(t)
-  const int wy = tl.y0 - 2 * r, wx = tl.x0 - 2 * r;
-  for (int q = tid; q < WH * WW; q += 256) {
-    const int i = q / WW, c = q % WW;
-    sx[q] = xin[(int64_t)(wy + i + B) * j.xpitch + (wx + c + B)];
+  // 1. blur taps and the window of x^(t) into LDS (their loads went first)
+  if (sep) {
+    if (tid < L) {
+      sku[tid] = tap0;
+      skv[tid] = tap1;
+    }
+  } else {
+    if (tid < nk) skern[tid] = tap0;
+    if (tid + 256 < nk) skern[tid + 256] = tap1;
+  }
+#pragma unroll
+  for (int k = 0; k < XQ; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k < WH * WW && q < WH * WW) sx[q] = xv[k];
   }
   __syncthreads();
 
@@ -96,7 +129,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
       const int i = q / RW, c = q % RW;
       const float *row = sx + i * WW + c + 2 * r;
       float acc = 0.0f;
-      for (int k = 0; k < L; ++k) acc = fmaf(j.kv[k], row[-k], acc);
+      for (int k = 0; k < L; ++k) acc = fmaf(skv[k], row[-k], acc);
       sh[q] = acc;
     }
     __syncthreads();
@@ -111,23 +144,24 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
     const int i = q / RW, c = q % RW;
     float kx = 0.0f;
     if (j.separable) {
-      for (int kk = 0; kk < L; ++kk) kx = fmaf(j.ku[kk], sh[(i + 2 * r - kk) * RW + c], kx);
+      for (int kk = 0; kk < L; ++kk) kx = fmaf(sku[kk], sh[(i + 2 * r - kk) * RW + c], kx);
     } else {
       for (int a2 = 0; a2 < L; ++a2)
         for (int kk = 0; kk < L; ++kk)
-          kx = fmaf(j.kern[a2 * L + kk], sx[(i + 2 * r - a2) * WW + (c + 2 * r - kk)], kx);
+          kx = fmaf(skern[a2 * L + kk], sx[(i + 2 * r - a2) * WW + (c + 2 * r - kk)], kx);
     }
     const int Y = tl.y0 - r + i, X = tl.x0 - r + c;
+    const float mv = j.has_mask ? (float)mraw[k] : 1.0f;
     float res = 0.0f;
     if (Y >= 0 && Y < j.ny && X >= 0 && X < j.nx) {
       if (!split) {
-        res = mv[k] * (kx - yv[k]);
+        res = mv * (kx - yv[k]);
       } else if (!draw) {
-        res = mv[k] * kx;                                      // z^(0) = 0
+        res = mv * kx;                                      // z^(0) = 0
       } else {
         float xi, zeta;
-        gauss_pair(j, (int64_t)Y * j.nx + X, t, xi, zeta);
-        res = mv[k] * (j.zmix * (kx - yv[k]) - j.zsd * zeta);
+        gauss_pair(j.key0, j.key1, j.chain, (int64_t)Y * j.nx + X, t, xi, zeta);
+        res = mv * (j.zmix * (kx - yv[k]) - j.zsd * zeta);
         const int ci = i - r, cc = c - r;
         if (ci >= 0 && ci < TH && cc >= 0 && cc < TW) sxi[ci * TW + cc] = xi;
       }
@@ -142,14 +176,14 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
       const int i = q / TW, c = q % TW;
       const float *row = sres + i * RW + c;
       float acc = 0.0f;
-      for (int k = 0; k < L; ++k) acc = fmaf(j.kv[k], row[k], acc);
+      for (int k = 0; k < L; ++k) acc = fmaf(skv[k], row[k], acc);
       shr[q] = acc;
     }
     __syncthreads();
   }
 
   // 5./6. update, statistics
-  float *xout = j.x[(t + 1) & 1];
+  PNP_GLOBAL float *xout = gp(j.x[(t + 1) & 1]);
   const float inv_nw = stats ? 1.0f / (float)nw : 0.0f;
   const int64_t na_i = j.nbase + (s - j.wbase - nw);       // merged before this window
   const double n_a = (double)na_i, n_b = (double)nw;
@@ -161,11 +195,11 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
     if (i >= tl.h || c >= tl.w) continue;
     float ktr = 0.0f;
     if (j.separable) {
-      for (int kk = 0; kk < L; ++kk) ktr = fmaf(j.ku[kk], shr[(i + kk) * TW + c], ktr);
+      for (int kk = 0; kk < L; ++kk) ktr = fmaf(sku[kk], shr[(i + kk) * TW + c], ktr);
     } else {
       for (int a2 = 0; a2 < L; ++a2)
         for (int kk = 0; kk < L; ++kk)
-          ktr = fmaf(j.kern[a2 * L + kk], sres[(i + a2) * RW + (c + kk)], ktr);
+          ktr = fmaf(skern[a2 * L + kk], sres[(i + a2) * RW + (c + kk)], ktr);
     }
     const int Y = tl.y0 + i, X = tl.x0 + c;
     const int64_t p = (int64_t)Y * j.nx + X;
@@ -174,7 +208,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
       xi = sxi[q];
     } else {
       float zeta_unused;
-      gauss_pair(j, p, t, xi, zeta_unused);
+      gauss_pair(j.key0, j.key1, j.chain, p, t, xi, zeta_unused);
     }
     const float xo = sx[(i + 2 * r) * WW + (c + 2 * r)];
     const float proj = fminf(fmaxf(xo, 0.0f), 1.0f);
@@ -189,18 +223,18 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
       M = fmaf(d, xn - m, M);
       if (merge) {
         const double n = n_a + n_b;
-        const double ma = na_i > 0 ? j.mean[p] : 0.0;
-        const double Ma = na_i > 0 ? j.m2[p] : 0.0;
+        const double ma = na_i > 0 ? gp(j.mean)[p] : 0.0;
+        const double Ma = na_i > 0 ? gp(j.m2)[p] : 0.0;
         const double dl = (double)m - ma;
-        j.mean[p] = ma + dl * (n_b / n);
-        j.m2[p] = Ma + (double)M + dl * dl * (n_a * n_b / n);
+        gp(j.mean)[p] = ma + dl * (n_b / n);
+        gp(j.m2)[p] = Ma + (double)M + dl * dl * (n_a * n_b / n);
       } else {
-        j.wmean[p] = m;
-        j.wm2[p] = M;
+        gp(j.wmean)[p] = m;
+        gp(j.wm2)[p] = M;
       }
     }
   }
-  if (bad) j.flag[0] = 1;
+  if (bad) gp(j.flag)[0] = 1;
 }
 
 // Merge a partially filled FP32 window (nw samples on top of n_a merged
@@ -210,11 +244,11 @@ __global__ __launch_bounds__(256) void welford_flush_kernel(JobDesc j, double n_
   const double n = n_a + n_b;
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n_pix;
        p += (int64_t)gridDim.x * 256) {
-    const double ma = n_a > 0 ? j.mean[p] : 0.0;
-    const double Ma = n_a > 0 ? j.m2[p] : 0.0;
-    const double dl = (double)j.wmean[p] - ma;
-    j.mean[p] = ma + dl * (n_b / n);
-    j.m2[p] = Ma + (double)j.wm2[p] + dl * dl * (n_a * n_b / n);
+    const double ma = n_a > 0 ? gp(j.mean)[p] : 0.0;
+    const double Ma = n_a > 0 ? gp(j.m2)[p] : 0.0;
+    const double dl = (double)gp(j.wmean)[p] - ma;
+    gp(j.mean)[p] = ma + dl * (n_b / n);
+    gp(j.m2)[p] = Ma + (double)gp(j.wm2)[p] + dl * dl * (n_a * n_b / n);
   }
 }
 
