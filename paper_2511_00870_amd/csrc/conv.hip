@@ -44,6 +44,9 @@
 #ifndef PNP_MID_RR
 #define PNP_MID_RR 1
 #endif
+#ifndef PNP_RR_PD
+#define PNP_RR_PD 3
+#endif
 #ifndef PNP_XCD_MAP
 #define PNP_XCD_MAP 1
 #endif
@@ -99,6 +102,13 @@ template <> __device__ __forceinline__ float quant_in<FMT_E4M3>(float v, float i
 // pack 4 consecutive output channels of one pixel and store them (P is a
 // byte pointer into LDS or global memory)
 typedef __attribute__((ext_vector_type(2))) unsigned int u32x2;
+typedef __attribute__((ext_vector_type(2))) short i16x2;
+// ReLU of two packed bf16 values: as signed 16-bit integers the negative
+// ones (sign bit set) are below zero
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t u) {
+  return __builtin_bit_cast(uint32_t,
+                            __builtin_elementwise_max(__builtin_bit_cast(i16x2, u), i16x2{0, 0}));
+}
 template <int FMT, class P> __device__ __forceinline__ void store4(P *p, f32x4 v, float inv_s) {
   if constexpr (FMT == FMT_F32) {
     *reinterpret_cast<f32x4 *>(p) = v;
@@ -676,32 +686,35 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
 // of the two-rows-per-wave form.
 // ---------------------------------------------------------------------
 struct RrLayout {
-  static constexpr int F = 64, MB = 4, PIXB = 128, PSTR = PIXB + 16, CPP = 8;
+  static constexpr int F = 64, MB = 4, PIXB = 128, CPP = 8;
   static constexpr int TH = 16, TW = kConvTileW, IH = TH + 2, IW = TW + 2;
   static constexpr int ROWS = 4;                              // output rows per wave
   static constexpr int NSTEP = 18;                            // 9 taps x 2 channel halves
   static constexpr int WBYTES = NSTEP * MB * 64 * 16;
-  static constexpr int IN_BYTES = IH * IW * PSTR;
-  static constexpr int OSTR = PIXB + 16;                      // staged bf16 outputs
-  static constexpr int OUT_BYTES = TH * TW * OSTR;
+  static constexpr int IN_BYTES = IH * IW * PIXB;
+  static constexpr int OUT_BYTES = TH * TW * PIXB;
   static constexpr int TILE_BYTES = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
-  static constexpr int EPI_BYTES = 2 * F * 4;                  // output scale and bias
+  static constexpr int EPI_BYTES = F * 4;                     // bias
   static constexpr int LDS_BYTES = TILE_BYTES + WBYTES + EPI_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
+// LDS byte offset of 16-byte chunk k of pixel p: pixels are 128 bytes with no
+// padding and the chunks of a pixel are permuted by the pixel's low 3 bits,
+// so 8 lanes reading the same chunk of 8 consecutive pixels hit 8 different
+// bank groups (a padded stride conflicts two ways at full LDS rate).
+__device__ __forceinline__ int rr_off(int p, int k) { return p * 128 + ((k ^ (p & 7)) << 4); }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void conv_mid_rr_kernel(ConvArgs a) {
   using Lo = RrLayout;
-  constexpr int NT = 256, MB = Lo::MB, IW = Lo::IW, PSTR = Lo::PSTR, ROWS = Lo::ROWS;
+  constexpr int NT = 256, MB = Lo::MB, IW = Lo::IW, ROWS = Lo::ROWS;
   constexpr int NCHUNK = Lo::IH * IW * Lo::CPP;
   constexpr int NLOAD = (NCHUNK + NT - 1) / NT;
 
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   uint8_t *lds_in = lds;
   uint8_t *lds_w = lds + Lo::TILE_BYTES;
-  float *lds_osc = reinterpret_cast<float *>(lds_w + Lo::WBYTES);
-  float *lds_bias = lds_osc + Lo::F;
+  float *lds_bias = reinterpret_cast<float *>(lds_w + Lo::WBYTES);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
@@ -720,10 +733,7 @@ void conv_mid_rr_kernel(ConvArgs a) {
     const PNP_GLOBAL u32x4 *src = gp(reinterpret_cast<const u32x4 *>(a.wblob));
     u32x4 *dst = reinterpret_cast<u32x4 *>(lds_w);
     for (int i = tid; i < Lo::WBYTES / 16; i += NT) dst[i] = src[i];
-    if (tid < Lo::F) {
-      lds_osc[tid] = gp(a.oscale)[tid];
-      lds_bias[tid] = gp(a.bias)[tid];
-    }
+    if (tid < Lo::F) lds_bias[tid] = gp(a.bias)[tid];
   }
 
   u32x4 pre[NLOAD];
@@ -744,8 +754,7 @@ void conv_mid_rr_kernel(ConvArgs a) {
 #pragma unroll
     for (int i = 0; i < NLOAD; ++i) {
       const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
-      const int pix = q / Lo::CPP, k = q % Lo::CPP;
-      *reinterpret_cast<u32x4 *>(lds_in + pix * PSTR + k * 16) = pre[i];
+      *reinterpret_cast<u32x4 *>(lds_in + rr_off(q / Lo::CPP, q % Lo::CPP)) = pre[i];
     }
   };
 
@@ -769,23 +778,27 @@ void conv_mid_rr_kernel(ConvArgs a) {
     const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
     __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
 
+    // accumulators start at the bias (this kernel runs layers whose output
+    // scale is 1 and that end in ReLU)
     f32x4 acc[MB][ROWS][2];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+    for (int mb = 0; mb < MB; ++mb) {
+      const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + mb * 16 + 4 * g);
 #pragma unroll
       for (int o = 0; o < ROWS; ++o)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) acc[mb][o][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int h = 0; h < 2; ++h) acc[mb][o][h] = bia;
+    }
 
-    // this lane's B column inside the window and its 16-byte channel chunk
-    const uint8_t *bbase = lds_in + ((ROWS * wave) * IW + l16) * PSTR + g * 16;
+    // this lane's B column inside the window: pixel (ROWS*wave + ir, 16h + dx + l16)
+    const int bpix = (ROWS * wave) * IW + l16;
     const uint8_t *abase = lds_w + lane * 16;
     // Software pipeline over 36 stages (6 (dx, kh) iterations x 6 input
-    // rows): the B fragments of input row r+2 and the next iteration's A
-    // fragments are read from LDS while row r's MFMAs run.  Scheduling
-    // barriers keep each stage's reads ahead of its MFMAs.
-    constexpr int NIT = 6, NR = ROWS + 2, NSTG = NIT * NR;
-    bf16x8 Ab[2][3][MB], Bb[3][2];
+    // rows): the B fragments of the stage PD ahead and the next iteration's
+    // A fragments are read from LDS while this stage's MFMAs run.
+    // Scheduling barriers keep each stage's reads ahead of its MFMAs.
+    constexpr int NIT = 6, NR = ROWS + 2, NSTG = NIT * NR, PD = PNP_RR_PD;
+    bf16x8 Ab[2][3][MB], Bb[PD + 1][2];
     auto load_a = [&](int it, int dy) {
       const int dx = it >> 1, kh = it & 1;
 #pragma unroll
@@ -797,17 +810,17 @@ void conv_mid_rr_kernel(ConvArgs a) {
       const int it = stg / NR, ir = stg % NR, dx = it >> 1, kh = it & 1;
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        Bb[stg % 3][h] = *reinterpret_cast<const bf16x8 *>(
-            bbase + (ir * IW + 16 * h + dx) * PSTR + kh * 64);
+        Bb[stg % (PD + 1)][h] = *reinterpret_cast<const bf16x8 *>(
+            lds_in + rr_off(bpix + ir * IW + 16 * h + dx, kh * 4 + g));
     };
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) load_a(0, dy);
-    load_b(0);
-    load_b(1);
+#pragma unroll
+    for (int k = 0; k < PD; ++k) load_b(k);
 #pragma unroll
     for (int stg = 0; stg < NSTG; ++stg) {
       const int it = stg / NR, ir = stg % NR;
-      if (stg + 2 < NSTG) load_b(stg + 2);
+      if (stg + PD < NSTG) load_b(stg + PD);
       if (it + 1 < NIT && ir >= 2 && ir <= 4) load_a(it + 1, ir - 2);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -819,46 +832,47 @@ void conv_mid_rr_kernel(ConvArgs a) {
 #pragma unroll
           for (int h = 0; h < 2; ++h)
             acc[mb][o][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                Ab[it & 1][dy][mb], Bb[stg % 3][h], acc[mb][o][h], 0, 0, 0);
+                Ab[it & 1][dy][mb], Bb[stg % (PD + 1)][h], acc[mb][o][h], 0, 0, 0);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
 
-    // epilogue: scale, bias, ReLU, bf16; stage the tile over the consumed
-    // input window, then store whole pixels with 16-byte lanes
+    // epilogue: round to bf16, ReLU on the rounded pairs (as signed 16-bit
+    // integers: a negative bf16 is a negative int16), stage the tile over the
+    // consumed input window, then store whole pixels with 16-byte lanes
     __syncthreads();
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const f32x4 osc = *reinterpret_cast<const f32x4 *>(lds_osc + mb * 16 + 4 * g);
-      const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + mb * 16 + 4 * g);
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int o = 0; o < ROWS; ++o)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          f32x4 v;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float x = acc[mb][o][h][e] * osc[e] + bia[e];
-            if (a.relu) x = fmaxf(x, 0.0f);
-            v[e] = x;
-          }
-          const int r = ROWS * wave + o, c = 16 * h + l16;
-          store4<FMT_BF16>(lds_in + (r * Lo::TW + c) * Lo::OSTR + (mb * 16 + 4 * g) * 2, v, 1.0f);
+          const f32x4 v = acc[mb][o][h];
+          u32x2 w;
+          w.x = relu_bf16x2(pack_bf16x2(v[0], v[1]));
+          w.y = relu_bf16x2(pack_bf16x2(v[2], v[3]));
+          const int p = (ROWS * wave + o) * Lo::TW + 16 * h + l16;
+          // channels mb*16 + 4g .. +3: chunk 2mb + g/2, bytes 8(g&1) .. +7
+          *reinterpret_cast<u32x2 *>(lds_in + rr_off(p, 2 * mb + (g >> 1)) + 8 * (g & 1)) = w;
         }
-    }
     __syncthreads();
     {
-      constexpr int NQ = Lo::TH * Lo::TW * Lo::CPP;
+      constexpr int NQ = Lo::TH * Lo::TW * Lo::CPP, NS = NQ / NT;
+      u32x4 st[NS];
 #pragma unroll
-      for (int q0 = 0; q0 < NQ; q0 += NT) {
-        const int q = q0 + tid;
+      for (int i = 0; i < NS; ++i) {
+        const int q = i * NT + tid;
+        st[i] = *reinterpret_cast<const u32x4 *>(lds_in + rr_off(q / Lo::CPP, q % Lo::CPP));
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int q = i * NT + tid;
         const int pix = q / Lo::CPP, k = q % Lo::CPP;
         const int r = pix / Lo::TW, c = pix % Lo::TW;
         const int64_t px = (r < cur.h && c < cur.w)
                                ? (int64_t)(cur.y0 + r + 1) * cur.apitch + (cur.x0 + c + 1)
                                : cur.trash;
-        *reinterpret_cast<PNP_GLOBAL u32x4 *>(cur.out + px * Lo::PIXB + k * 16) =
-            *reinterpret_cast<const u32x4 *>(lds_in + pix * Lo::OSTR + k * 16);
+        *reinterpret_cast<PNP_GLOBAL u32x4 *>(cur.out + px * Lo::PIXB + k * 16) = st[i];
       }
     }
     __syncthreads();                             // staged outputs are read
@@ -931,7 +945,7 @@ hipError_t launch_conv_mid(int in_fmt, int out_fmt, int F, const ConvArgs &a, in
     if (F == 32) return launch_mid_t<FMT_F32, FMT_F32, 32, 4>(a, n_wg, s);
     if (F == 64) return launch_mid_t<FMT_F32, FMT_F32, 64, 4>(a, n_wg, s);
   } else if (in_fmt == FMT_BF16 && out_fmt == FMT_BF16) {
-    if (F == 64 && PNP_MID_RR) return launch_rr(a, n_wg, s);
+    if (F == 64 && PNP_MID_RR && a.relu && a.unit_scale) return launch_rr(a, n_wg, s);
     if (F == 32) return launch_mid_t<FMT_BF16, FMT_BF16, 32, PNP_NW_LOWP>(a, n_wg, s);
     if (F == 64) return launch_mid_t<FMT_BF16, FMT_BF16, 64, PNP_NW_LOWP>(a, n_wg, s);
   } else if (in_fmt == FMT_E4M3 && F == 64) {

@@ -27,6 +27,7 @@ struct LayerPlan {
   int in_fmt = FMT_F32;     // format of the layer's input and weights
   int out_fmt = FMT_F32;    // format the output is stored in (next layer's input)
   int relu = 0;
+  int unit_scale = 0;        // every output scale is 1 (no e4m3 weight or input scale)
   float in_inv_scale = 1.f, out_inv_scale = 1.f;
   float in_scale = 1.f;     // scale of the stored input (e4m3), else 1
   int in_buf = 0, out_buf = 0;  // activation buffers read / written

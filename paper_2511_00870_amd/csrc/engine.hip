@@ -188,6 +188,7 @@ Status Engine::set_net(int K, const int32_t *ch, const float *w, const float *b,
         wq[(size_t)co * L.cin * 9 + i] = quant_host(wk[(size_t)co * L.cin * 9 + i] / sw[co], L.in_fmt);
     std::vector<float> osc(L.cout);
     for (int co = 0; co < L.cout; ++co) osc[co] = sw[co] * L.in_scale;
+    L.unit_scale = std::all_of(osc.begin(), osc.end(), [](float v) { return v == 1.0f; });
     // device copies: bias and oscale padded to 16 floats for vector loads
     const int cpad = std::max(L.cout, 16);
     std::vector<float> bias(cpad, 0.f), oscp(cpad, 0.f);
@@ -657,6 +658,7 @@ Status Engine::launch_layer(int k, int64_t tick, bool prof) {
   a.tile_rows = conv_th;
   a.tick = tick;
   a.relu = L.relu;
+  a.unit_scale = L.unit_scale;
   a.bias = L.bias;
   a.oscale = L.oscale;
   a.in_inv_scale = L.in_inv_scale;

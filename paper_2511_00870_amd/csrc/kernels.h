@@ -15,7 +15,7 @@ struct ConvArgs {
   int32_t in_slot, out_slot;   // activation ping-pong slots read / written
   int32_t relu;
   int32_t tile_rows;           // rows of the conv tiles (<= 16)
-  int32_t pad;
+  int32_t unit_scale;          // every output scale is 1
   int64_t tick;
   const void *wblob;           // middle layers: weights in MFMA fragment order
   const float *wf32;           // first / last layer: quantised weights [c][9]
