@@ -333,6 +333,72 @@ __global__ __launch_bounds__(256) void conv_last_kernel(ConvArgs a) {
   }
 }
 
+// Last layer for bf16 input on the matrix cores: the per-tap partial dot
+// products s_tap(p) = sum_c w[c][tap] in[p][c] of every window pixel p are
+// one small GEMM (M = 9 taps padded to 16, K = F channels, N = pixels), read
+// straight from memory into B fragments: lane (g, l16) of a 16-pixel block
+// holds channels 8g..8g+7 (+32 per K step) of pixel l16.  The 9 useful rows
+// of each result block are parked in LDS and summed over the taps as in the
+// VALU form above.
+template <int F>
+__global__ __launch_bounds__(256) void conv_last_mfma_kernel(ConvArgs a) {
+  constexpr int PIXB = F * 2, KS = F / 32;     // bytes per pixel, K steps
+  constexpr int IW = kConvTileW + 2, IHM = 18, NPIX = IHM * IW;
+  constexpr int NB = (NPIX + 15) / 16, BPW = (NB + 3) / 4;   // blocks, blocks per wave
+  __shared__ float sp[9][NPIX];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+  const PNP_GLOBAL uint8_t *in = gp(reinterpret_cast<const uint8_t *>(j.act[a.in_slot]));
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int WW = tl.w + 2, np = (tl.h + 2) * WW;
+  const int64_t apitch = j.apitch;
+  // every load of this wave first (out-of-window lanes read pixel 0)
+  u32x4 raw[BPW][KS];
+#pragma unroll
+  for (int u = 0; u < BPW; ++u) {
+    const int q0 = (wave + 4 * u) * 16 + l16, q = q0 < np ? q0 : 0;
+    const int row = q / WW, col = q % WW;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      raw[u][ks] = *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+          in + ((tl.y0 + row) * apitch + (tl.x0 + col)) * PIXB + (ks * 4 + g) * 16);
+  }
+  // A fragments: row l16 = tap (zero past 8), channels 32 ks + 8 g .. +7
+  bf16x8 A[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      A[ks][e] = (__bf16)(l16 < 9 ? a.wf32[(32 * ks + 8 * g + e) * 9 + l16] : 0.0f);
+#pragma unroll
+  for (int u = 0; u < BPW; ++u) {
+    const int blk = wave + 4 * u;
+    if (blk * 16 >= np) break;                 // uniform
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks], __builtin_bit_cast(bf16x8, raw[u][ks]),
+                                                    acc, 0, 0, 0);
+    const int q = blk * 16 + l16;
+    if (q < np) {
+      // this lane holds taps 4g .. 4g+3 of pixel q
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * g + i < 9) sp[4 * g + i][(q / WW) * IW + q % WW] = acc[i];
+    }
+  }
+  __syncthreads();
+  const float sc = a.oscale[0], bi = a.bias[0];
+  const int npix = tl.h * tl.w;
+  for (int pix = tid; pix < npix; pix += 256) {
+    const int r = pix / tl.w, c = pix % tl.w;
+    float acc = 0.0f;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) acc += sp[tap][(r + tap / 3) * IW + c + tap % 3];
+    gp(j.G)[(int64_t)(tl.y0 + r) * j.nx + tl.x0 + c] = acc * sc + bi;
+  }
+}
+
 // single 1 -> 1 layer (K = 1): reads x^(t) (FP32), writes G
 __global__ __launch_bounds__(256) void conv_single_kernel(ConvArgs a) {
   const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
@@ -977,8 +1043,13 @@ hipError_t launch_conv_last(int in_fmt, int F, const ConvArgs &a, int n_tiles, h
     hipLaunchKernelGGL((conv_last_kernel<I, FF>), dim3(n_tiles), dim3(256), 0, s, a); \
     return hipGetLastError();                                                          \
   }
-  LAST(FMT_F32, 16) LAST(FMT_F32, 32) LAST(FMT_F32, 64) LAST(FMT_BF16, 32) LAST(FMT_BF16, 64)
+  LAST(FMT_F32, 16) LAST(FMT_F32, 32) LAST(FMT_F32, 64)
 #undef LAST
+  if (in_fmt == FMT_BF16 && (F == 32 || F == 64)) {
+    if (F == 32) hipLaunchKernelGGL(conv_last_mfma_kernel<32>, dim3(n_tiles), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(conv_last_mfma_kernel<64>, dim3(n_tiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 
