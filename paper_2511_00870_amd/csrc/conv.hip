@@ -434,6 +434,10 @@ struct MidTile {
   int64_t apitch, trash;      // pixels per row; pixel index of the trash pixel
   const PNP_GLOBAL uint8_t *in;
   PNP_GLOBAL uint8_t *out;
+  // fused first layer: x^(t) (padded, zero border xb), and the image size
+  const PNP_GLOBAL float *x;
+  int64_t xpitch;
+  int xb, ny, nx;
 };
 __device__ __forceinline__ MidTile mid_tile(const ConvArgs &a, int ti) {
   const PNP_CONST TileRef &tl = cp(a.tiles)[ti];
@@ -447,6 +451,11 @@ __device__ __forceinline__ MidTile mid_tile(const ConvArgs &a, int ti) {
   c.trash = (int64_t)j.arows * j.apitch - 1;
   c.in = gp(reinterpret_cast<const uint8_t *>(j.act[a.in_slot]));
   c.out = gp(reinterpret_cast<uint8_t *>(j.act[a.out_slot]));
+  c.x = gp(j.x[(a.tick + j.t_offset) & 1]);
+  c.xpitch = j.xpitch;
+  c.xb = j.xborder;
+  c.ny = j.ny;
+  c.nx = j.nx;
   return c;
 }
 
@@ -761,8 +770,12 @@ struct RrLayout {
   static constexpr int OUT_BYTES = TH * TW * PIXB;
   static constexpr int TILE_BYTES = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
   static constexpr int EPI_BYTES = F * 4;                     // bias
+  // fused first layer: x window (TH+4) x (TW+4) as bf16, and its bias
+  static constexpr int XH = TH + 4, XW = TW + 4, XBYTES = XH * XW * 2;
   static constexpr int LDS_BYTES = TILE_BYTES + WBYTES + EPI_BYTES;
-  static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+  static constexpr int A0BYTES = MB * 64 * 16;                // first-layer A fragments
+  static constexpr int LDS_BYTES_FIRST = LDS_BYTES + XBYTES + F * 4 + A0BYTES;
+  static_assert(LDS_BYTES_FIRST <= 160 * 1024, "LDS");
 };
 // LDS byte offset of 16-byte chunk k of pixel p: pixels are 128 bytes with no
 // padding and the chunks of a pixel are permuted by the pixel's low 3 bits,
@@ -770,6 +783,7 @@ struct RrLayout {
 // bank groups (a padded stride conflicts two ways at full LDS rate).
 __device__ __forceinline__ int rr_off(int p, int k) { return p * 128 + ((k ^ (p & 7)) << 4); }
 
+template <bool FIRST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void conv_mid_rr_kernel(ConvArgs a) {
   using Lo = RrLayout;
@@ -781,6 +795,11 @@ void conv_mid_rr_kernel(ConvArgs a) {
   uint8_t *lds_in = lds;
   uint8_t *lds_w = lds + Lo::TILE_BYTES;
   float *lds_bias = reinterpret_cast<float *>(lds_w + Lo::WBYTES);
+  uint16_t *lds_x = reinterpret_cast<uint16_t *>(lds_bias + Lo::F);     // FIRST only
+  float *lds_bias0 = reinterpret_cast<float *>(lds_x + Lo::XH * Lo::XW);  // FIRST only
+  uint8_t *lds_a0 = reinterpret_cast<uint8_t *>(lds_bias0 + Lo::F);        // FIRST only
+  constexpr int NX = Lo::XH * Lo::XW, XQ = (NX + NT - 1) / NT;
+  constexpr int NWIN = Lo::IH * IW, NB0 = (NWIN + 15) / 16, BPW0 = (NB0 + 3) / 4;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
@@ -800,10 +819,38 @@ void conv_mid_rr_kernel(ConvArgs a) {
     u32x4 *dst = reinterpret_cast<u32x4 *>(lds_w);
     for (int i = tid; i < Lo::WBYTES / 16; i += NT) dst[i] = src[i];
     if (tid < Lo::F) lds_bias[tid] = gp(a.bias)[tid];
+    if (FIRST && tid < Lo::F) lds_bias0[tid] = gp(a.first_bias)[tid];
+  }
+  // fused first layer: A fragments (rows = its 64 output channels in blocks of
+  // 16, K = its 9 taps padded to 32) in LDS, fragment order
+  if constexpr (FIRST) {
+    if (wave == 0) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        bf16x8 f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int t = 8 * g + e;
+          f[e] = (__bf16)(t < 9 ? gp(a.first_w)[(mb * 16 + l16) * 9 + t] : 0.0f);
+        }
+        *reinterpret_cast<bf16x8 *>(lds_a0 + (mb * 64 + lane) * 16) = f;
+      }
+    }
   }
 
-  u32x4 pre[NLOAD];
+  u32x4 pre[FIRST ? 1 : NLOAD];
+  float prex[FIRST ? XQ : 1];
   auto issue_loads = [&](const MidTile &c) {
+    if constexpr (FIRST) {
+      // x window: image rows y0-2 .. y0+TH+1, columns x0-2 .. x0+TW+1
+#pragma unroll
+      for (int i = 0; i < XQ; ++i) {
+        const int q0 = tid + i * NT, q = q0 < NX ? q0 : 0;
+        const int xr = q / Lo::XW, xc = q % Lo::XW;
+        prex[i] = c.x[(int64_t)(c.y0 - 2 + xr + c.xb) * c.xpitch + (c.x0 - 2 + xc + c.xb)];
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < NLOAD; ++i) {
       const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
@@ -817,10 +864,53 @@ void conv_mid_rr_kernel(ConvArgs a) {
   // branch-free: lanes past the window loaded chunk 0 and store it there
   // again (the same bytes the lane that owns chunk 0 stores)
   auto store_lds = [&]() {
+    if constexpr (FIRST) {
+#pragma unroll
+      for (int i = 0; i < XQ; ++i) {
+        const int q0 = tid + i * NT, q = q0 < NX ? q0 : 0;
+        lds_x[q] = f32_to_bf16(prex[i]);
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < NLOAD; ++i) {
       const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
       *reinterpret_cast<u32x4 *>(lds_in + rr_off(q / Lo::CPP, q % Lo::CPP)) = pre[i];
+    }
+  };
+
+  // Fused first layer on the staged x window: the 64-channel output of every
+  // window pixel (an MFMA per 16-pixel block and 16 channels; K = the 9 taps),
+  // + bias, ReLU, bf16, written into the layer input window; window pixels
+  // outside the image are the next layer's zero padding.
+  auto layer0 = [&](const MidTile &c) {
+#pragma unroll
+    for (int u = 0; u < BPW0; ++u) {
+      const int blk = wave + 4 * u;
+      if (blk >= NB0) break;                                  // uniform
+      const int q0 = blk * 16 + l16, q = q0 < NWIN ? q0 : 0;
+      const int wr = q / IW, wc = q % IW;
+      bf16x8 Bx;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int t = 8 * g + e;
+        const int tt = t < 9 ? t : 0;
+        const uint16_t v = lds_x[(wr + tt / 3) * Lo::XW + wc + tt % 3];
+        Bx[e] = __builtin_bit_cast(__bf16, t < 9 ? v : (uint16_t)0);
+      }
+      const int Y = c.y0 - 1 + wr, X = c.x0 - 1 + wc;
+      const bool inside = Y >= 0 && Y < c.ny && X >= 0 && X < c.nx;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias0 + mb * 16 + 4 * g);
+        const bf16x8 A0 = *reinterpret_cast<const bf16x8 *>(lds_a0 + (mb * 64 + lane) * 16);
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, Bx, bia, 0, 0, 0);
+        u32x2 w;
+        w.x = inside ? relu_bf16x2(pack_bf16x2(d[0], d[1])) : 0u;
+        w.y = inside ? relu_bf16x2(pack_bf16x2(d[2], d[3])) : 0u;
+        if (q0 < NWIN)
+          *reinterpret_cast<u32x2 *>(lds_in + rr_off(q, 2 * mb + (g >> 1)) + 8 * (g & 1)) = w;
+      }
     }
   };
 
@@ -837,6 +927,10 @@ void conv_mid_rr_kernel(ConvArgs a) {
   issue_loads(cur);
   store_lds();
   __syncthreads();
+  if constexpr (FIRST) {
+    layer0(cur);
+    __syncthreads();
+  }
 
   while (true) {
     const int tn = ti + per_xcd, tnn = tn + per_xcd;
@@ -944,6 +1038,10 @@ void conv_mid_rr_kernel(ConvArgs a) {
     __syncthreads();                             // staged outputs are read
     store_lds();
     __syncthreads();
+    if constexpr (FIRST) {
+      layer0(nxt);
+      __syncthreads();
+    }
     if (tn >= t_end) break;
     cur = nxt;
     nxt = after;
@@ -971,17 +1069,32 @@ static hipError_t launch_mid_t(const ConvArgs &a, int n_wg, hipStream_t s) {
 }
 
 static_assert(!PNP_MID_RR || 2 * PNP_NW_LOWP == RrLayout::TH, "bf16 tile rows");
-static hipError_t launch_rr(const ConvArgs &a, int n_wg, hipStream_t s) {
+template <bool FIRST>
+static hipError_t launch_rr_t(const ConvArgs &a, int n_wg, hipStream_t s) {
+  constexpr int lds = FIRST ? RrLayout::LDS_BYTES_FIRST : RrLayout::LDS_BYTES;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_mid_rr_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)RrLayout::LDS_BYTES);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_mid_rr_kernel<FIRST>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(conv_mid_rr_kernel, dim3(n_wg), dim3(256), RrLayout::LDS_BYTES, s, a);
+  hipLaunchKernelGGL((conv_mid_rr_kernel<FIRST>), dim3(n_wg), dim3(256), lds, s, a);
   return hipGetLastError();
+}
+static hipError_t launch_rr(const ConvArgs &a, int n_wg, hipStream_t s) {
+  return launch_rr_t<false>(a, n_wg, s);
+}
+
+bool first_mid_fusable(int in_fmt0, int out_fmt0, int cout0, int relu0, int unit0, int in_fmt1,
+                       int out_fmt1, int F, int relu1, int unit1) {
+  return PNP_MID_RR && in_fmt0 == FMT_BF16 && out_fmt0 == FMT_BF16 && cout0 == 64 && relu0 &&
+         unit0 && in_fmt1 == FMT_BF16 && out_fmt1 == FMT_BF16 && F == 64 && relu1 && unit1;
+}
+
+hipError_t launch_conv_first_mid(const ConvArgs &a, int n_wg, hipStream_t s) {
+  if (!a.first_w || !a.first_bias || a.tile_rows != RrLayout::TH) return hipErrorInvalidValue;
+  return launch_rr_t<true>(a, n_wg, s);
 }
 
 // tile rows of the middle-layer kernel for an input format

@@ -101,6 +101,8 @@ class Engine {
 
  private:
   Status run_denoiser(int64_t tick);
+  bool first_mid_fused() const;
+  Status launch_first_mid(int64_t tick, bool prof);
   Status launch_layer(int k, int64_t tick, bool prof);
   JobDesc *d_jobs = nullptr;
   TileRef *d_conv = nullptr, *d_upd = nullptr;
@@ -110,8 +112,8 @@ class Engine {
   bool profiling = false;
   std::vector<ProfileRec> prof_pending;
   std::vector<hipEvent_t> prof_free;
-  double prof_ms[4] = {0, 0, 0, 0};
-  int64_t prof_n[4] = {0, 0, 0, 0};
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  int64_t prof_n[5] = {0, 0, 0, 0, 0};
   void prof_begin(int cls, ProfileRec *r);
   void prof_end(ProfileRec *r);
 };

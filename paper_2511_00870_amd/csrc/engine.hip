@@ -325,7 +325,7 @@ struct Geometry {
 
 static Geometry geometry(int ny, int nx, int r) {
   Geometry g;
-  g.B = std::max(2 * r, 1);
+  g.B = std::max(2 * r, 2);          // >= 2: the fused first layer reads x two pixels out
   g.rows = ny + 2 * g.B + kUpdTileH;
   g.pitch = ((nx + 2 * g.B + kUpdTileW) + 63) / 64 * 64;
   g.arows = ny + 2 + 16;
@@ -597,7 +597,7 @@ void Engine::profile_enable(bool on) {
     prof_free.push_back(r.b);
   }
   prof_pending.clear();
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 5; ++i) {
     prof_ms[i] = 0;
     prof_n[i] = 0;
   }
@@ -626,7 +626,7 @@ void Engine::prof_end(ProfileRec *r) {
 }
 
 Status Engine::profile_read(int cls, double *ms, int64_t *launches) {
-  if (cls < 0 || cls > 3) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..3");
+  if (cls < 0 || cls > 4) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..4");
   HIPOK(hipStreamSynchronize(stream));
   for (auto &r : prof_pending) {
     float e = 0;
@@ -692,8 +692,51 @@ Status Engine::launch_layer(int k, int64_t tick, bool prof) {
   return Status::ok();
 }
 
+// first layer and first middle layer in one kernel when the network allows it
+// (bf16, 64 channels, ReLU, unit output scales)
+bool Engine::first_mid_fused() const {
+  if (net.K < 3) return false;
+  const LayerPlan &L0 = net.layers[0], &L1 = net.layers[1];
+  return first_mid_fusable(L0.in_fmt, L0.out_fmt, L0.cout, L0.relu, L0.unit_scale, L1.in_fmt,
+                           L1.out_fmt, net.F, L1.relu, L1.unit_scale) &&
+         conv_th == 16;
+}
+
+Status Engine::launch_first_mid(int64_t tick, bool prof) {
+  const LayerPlan &L0 = net.layers[0], &L1 = net.layers[1];
+  ConvArgs a{};
+  a.jobs = d_jobs;
+  a.tiles = d_conv;
+  a.n_tiles = n_conv;
+  a.tile_rows = conv_th;
+  a.tick = tick;
+  a.relu = L1.relu;
+  a.unit_scale = L1.unit_scale;
+  a.bias = L1.bias;
+  a.oscale = L1.oscale;
+  a.in_inv_scale = L1.in_inv_scale;
+  a.out_inv_scale = L1.out_inv_scale;
+  a.in_slot = L1.in_buf;
+  a.out_slot = L1.out_buf;
+  a.wblob = L1.wblob;
+  a.first_w = L0.wf32;
+  a.first_bias = L0.bias;
+  const int need = ((n_conv + 7) / 8) * 8;
+  const int n_wg = std::max(8, std::min(n_cu, need) / 8 * 8);
+  ProfileRec pr;
+  if (prof) prof_begin(4, &pr);
+  HIPOK(launch_conv_first_mid(a, n_wg, stream));
+  if (prof) prof_end(&pr);
+  return Status::ok();
+}
+
 Status Engine::run_denoiser(int64_t tick) {
-  for (int k = 0; k < net.K; ++k) TRY(launch_layer(k, tick, true));
+  int k0 = 0;
+  if (first_mid_fused()) {
+    TRY(launch_first_mid(tick, true));
+    k0 = 2;
+  }
+  for (int k = k0; k < net.K; ++k) TRY(launch_layer(k, tick, true));
   return Status::ok();
 }
 
@@ -830,7 +873,12 @@ Status Engine::denoise(Job *j, const float *x, float *G, float *layers, float *a
   } guard{d_amax};
   if (d_amax) HIPOK(hipMemsetAsync(d_amax, 0, sizeof(uint32_t) * K, stream));
   float *lp = layers;
-  for (int k = 0; k < K; ++k) {
+  int k0 = 0;
+  if (!layers && !amax && first_mid_fused()) {   // the path the sampler runs
+    TRY(launch_first_mid(tick_alt, false));
+    k0 = 2;
+  }
+  for (int k = k0; k < K; ++k) {
     const LayerPlan &L = net.layers[k];
     TRY(launch_layer(k, tick_alt, false));
     if (k == K - 1) break;

@@ -23,6 +23,9 @@ struct ConvArgs {
   const float *oscale;         // [c_out]: weight scale x input scale
   float in_inv_scale;          // first layer: 1 / scale of its input format
   float out_inv_scale;         // 1 / scale of the next layer's input (e4m3), else 1
+  // first layer fused into the first middle layer: its weights [c][9] and bias
+  const float *first_w;
+  const float *first_bias;
 };
 
 struct UpdateArgs {
@@ -38,6 +41,11 @@ int mid_tile_rows(int in_fmt);
 size_t mid_lds_bytes(int in_fmt, int F);
 size_t update_lds_bytes(int r);
 
+// first layer (1 -> 64, bf16) and first middle layer in one kernel; a holds the
+// middle layer's arguments plus first_w / first_bias
+hipError_t launch_conv_first_mid(const ConvArgs &a, int n_wg, hipStream_t s);
+bool first_mid_fusable(int in_fmt0, int out_fmt0, int cout0, int relu0, int unit0, int in_fmt1,
+                       int out_fmt1, int F, int relu1, int unit1);
 hipError_t launch_conv_mid(int in_fmt, int out_fmt, int F, const ConvArgs &a, int n_wg,
                            hipStream_t s);
 hipError_t launch_conv_first(int in_fmt, int out_fmt, int F, const ConvArgs &a, int n_tiles,

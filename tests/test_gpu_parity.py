@@ -142,6 +142,30 @@ def test_denoiser_low_precision_deep(prec):
     assert e <= (5e-3 if prec == P.PNPULA_BF16 else 5e-2)
 
 
+@pytest.mark.parametrize("shape,block", [((53, 83), 32), ((40, 70), 64)])
+def test_first_layer_fused_matches_per_layer_path(shape, block):
+    """bf16: the sampler's path (first layer fused into the first middle
+    layer) against the layer-by-layer path and the emulating oracle, on ragged
+    images (partial tiles, window pixels outside the image = zero padding)."""
+    ny, nx = shape
+    say(f"case fused first layer {ny}x{nx} block={block}")
+    K = 6
+    ch, ws, bs = W.denoiser_weights(K, 64, seed=11)
+    x = W.synthetic_image(ny, nx, 31)
+    fmt = W.layer_formats(K, P.PNPULA_BF16)
+    ref, _ = O.denoiser_layers(O.Net(ch, ws, bs, fmt, [1.0] * K), x)
+    wl = W.make_workload("f", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=block, halo=8,
+                         n_layers=K, features=64, precision=P.PNPULA_BF16, iters=1, burn_in=0,
+                         seed=5)
+    wl.channels, wl.weights, wl.biases = ch, ws, bs
+    ctx = P.Context(P.Config.from_workload(wl))
+    G_fused = ctx.denoise(x.astype(np.float32))
+    G_layers, _ = ctx.denoise(x.astype(np.float32), layers=True)
+    e_f, e_l, e_fl = rel(G_fused, ref[-1][0]), rel(G_layers, ref[-1][0]), rel(G_fused, G_layers)
+    say(f"  fused {e_f:.2e}  per-layer {e_l:.2e}  fused vs per-layer {e_fl:.2e}")
+    assert e_f <= 5e-3 and e_l <= 5e-3 and e_fl <= 5e-3
+
+
 # -------------------------------------------------------- one iteration
 def _parity_run(wl, n_steps, block=None, label=""):
     say(f"case step parity {label}: {wl.ny}x{wl.nx} L={wl.kernel.shape[0]} "
