@@ -47,6 +47,9 @@
 #ifndef PNP_RR_PD
 #define PNP_RR_PD 3
 #endif
+#ifndef PNP_RR_LPS
+#define PNP_RR_LPS 1
+#endif
 #ifndef PNP_XCD_MAP
 #define PNP_XCD_MAP 1
 #endif
@@ -840,6 +843,14 @@ void conv_mid_rr_kernel(ConvArgs a) {
 
   u32x4 pre[FIRST ? 1 : NLOAD];
   float prex[FIRST ? XQ : 1];
+  // load i of the next tile's window (one 16-byte chunk per lane)
+  auto issue_load = [&](const MidTile &c, int i) {
+    const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
+    const int pix = q / Lo::CPP, k = q % Lo::CPP;
+    const int row = pix / IW, col = pix % IW;
+    pre[i] = *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+        c.in + ((int64_t)(c.y0 + row) * c.apitch + (c.x0 + col)) * Lo::PIXB + k * 16);
+  };
   auto issue_loads = [&](const MidTile &c) {
     if constexpr (FIRST) {
       // x window: image rows y0-2 .. y0+TH+1, columns x0-2 .. x0+TW+1
@@ -934,9 +945,12 @@ void conv_mid_rr_kernel(ConvArgs a) {
 
   while (true) {
     const int tn = ti + per_xcd, tnn = tn + per_xcd;
-    issue_loads(nxt);                            // in flight during the MFMAs below
+    // the next tile's loads are issued a few per pipeline stage below (all at
+    // once, they would wait behind this tile's predecessor's stores in the
+    // memory pipeline and hold up the first MFMAs)
+    if constexpr (FIRST) issue_loads(nxt);
     const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
-    __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
+    __builtin_amdgcn_sched_barrier(0);
 
     // accumulators start at the bias (this kernel runs layers whose output
     // scale is 1 and that end in ReLU)
@@ -982,6 +996,12 @@ void conv_mid_rr_kernel(ConvArgs a) {
       const int it = stg / NR, ir = stg % NR;
       if (stg + PD < NSTG) load_b(stg + PD);
       if (it + 1 < NIT && ir >= 2 && ir <= 4) load_a(it + 1, ir - 2);
+      if constexpr (!FIRST) {
+        constexpr int LPS = PNP_RR_LPS;                  // global loads per stage
+#pragma unroll
+        for (int i = stg * LPS; i < (stg + 1) * LPS; ++i)
+          if (i < NLOAD) issue_load(nxt, i);
+      }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {

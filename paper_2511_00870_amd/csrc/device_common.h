@@ -92,9 +92,12 @@ template <class T> __device__ __forceinline__ const PNP_CONST T *cp(const T *p) 
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    // one 32x32 -> 64-bit product each (v_mad_u64_u32) instead of a low and
+    // a high multiply
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                   (uint32_t)p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -109,11 +112,12 @@ __device__ __forceinline__ void gauss_pair(uint32_t key0, uint32_t key1, uint32_
   uint4 w = philox4x32_10(c, key0, key1);
   const float u1 = (float)((w.x >> 8) + 1u) * 5.9604644775390625e-8f;  // 2^-24
   const float u2 = (float)(w.y >> 8) * 5.9604644775390625e-8f;
-  const float rad = sqrtf(-2.0f * logf(u1));
-  float s, co;
-  sincospif(2.0f * u2, &s, &co);
-  xi = rad * co;
-  zeta = rad * s;
+  // hardware transcendentals: v_log_f32 (log2), v_sqrt_f32, and v_sin_f32 /
+  // v_cos_f32, whose argument is in revolutions, so sin(2 pi u2) takes u2
+  // as is (|error| ~1e-7, far below the noise scale's effect on x)
+  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+  xi = rad * __builtin_amdgcn_cosf(u2);
+  zeta = rad * __builtin_amdgcn_sinf(u2);
 }
 
 // --------------------------------------------------------------------
