@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
   constexpr int WW = kConvTileW + 2;
   constexpr int XQ = (18 * WW + 255) / 256;     // window loads per thread (16-row tiles)
   __shared__ float sx[18 * WW];
-  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
   const PNP_GLOBAL float *xb = gp(j.x[t & 1]);
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void conv_last_kernel(ConvArgs a) {
   constexpr int IW = kConvTileW + 2, IHM = 18; // largest window (16-row tiles)
   static_assert((NCH & (NCH - 1)) == 0 && NCH <= 64 && 256 % NCH == 0, "lanes per pixel");
   __shared__ float sp[9][IHM * IW];
-  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const PNP_GLOBAL uint8_t *in = gp(reinterpret_cast<const uint8_t *>(j.act[a.in_slot]));
   const int ch = threadIdx.x % NCH;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void conv_last_mfma_kernel(ConvArgs a) {
   constexpr int IW = kConvTileW + 2, IHM = 18, NPIX = IHM * IW;
   constexpr int NB = (NPIX + 15) / 16, BPW = (NB + 3) / 4;   // blocks, blocks per wave
   __shared__ float sp[9][NPIX];
-  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const PNP_GLOBAL uint8_t *in = gp(reinterpret_cast<const uint8_t *>(j.act[a.in_slot]));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void conv_last_mfma_kernel(ConvArgs a) {
 
 // single 1 -> 1 layer (K = 1): reads x^(t) (FP32), writes G
 __global__ __launch_bounds__(256) void conv_single_kernel(ConvArgs a) {
-  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
   const PNP_GLOBAL float *xb = gp(j.x[t & 1]);

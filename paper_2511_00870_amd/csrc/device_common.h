@@ -84,6 +84,15 @@ template <class T> __device__ __forceinline__ const PNP_CONST T *cp(const T *p) 
   return (const PNP_CONST T *)p;
 }
 
+// Tile of a one-workgroup-per-tile launch.  Workgroups are dispatched round
+// robin over the 8 XCDs (workgroup b runs on XCD b mod 8); each XCD is given
+// a contiguous run of the block-major tile list, so the halo rows that
+// neighbouring tiles share are read once into that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, rem = n & 7, x = b & 7;
+  return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
 // --------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
 //   (X0..X3) -> (hi(M1 X2) ^ X1 ^ K0, lo(M1 X2), hi(M0 X0) ^ X3 ^ K1, lo(M0 X0))

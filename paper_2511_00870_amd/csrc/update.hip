@@ -24,7 +24,7 @@ namespace pnp {
 
 __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
-  const PNP_CONST TileRef &tl = cp(a.tiles)[blockIdx.x];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
   const int r = j.r, L = 2 * r + 1;
