@@ -121,10 +121,7 @@ template <int FMT, class P> __device__ __forceinline__ void store4(P *p, f32x4 v
     w.y = pack_bf16x2(v[2], v[3]);
     *reinterpret_cast<u32x2 *>(p) = w;
   } else {
-    const uint32_t w = (uint32_t)f32_to_e4m3(v[0] * inv_s) |
-                       ((uint32_t)f32_to_e4m3(v[1] * inv_s) << 8) |
-                       ((uint32_t)f32_to_e4m3(v[2] * inv_s) << 16) |
-                       ((uint32_t)f32_to_e4m3(v[3] * inv_s) << 24);
+    const uint32_t w = pack_e4m3x4(v[0] * inv_s, v[1] * inv_s, v[2] * inv_s, v[3] * inv_s);
     *reinterpret_cast<uint32_t *>(p) = w;
   }
 }
@@ -203,10 +200,8 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        pk[e] = (uint32_t)f32_to_e4m3(v[4 * e] * a.out_inv_scale) |
-                ((uint32_t)f32_to_e4m3(v[4 * e + 1] * a.out_inv_scale) << 8) |
-                ((uint32_t)f32_to_e4m3(v[4 * e + 2] * a.out_inv_scale) << 16) |
-                ((uint32_t)f32_to_e4m3(v[4 * e + 3] * a.out_inv_scale) << 24);
+        pk[e] = pack_e4m3x4(v[4 * e] * a.out_inv_scale, v[4 * e + 1] * a.out_inv_scale,
+                            v[4 * e + 2] * a.out_inv_scale, v[4 * e + 3] * a.out_inv_scale);
     }
     *reinterpret_cast<PNP_GLOBAL u32x4 *>(dst) = pk;
   }
@@ -1070,6 +1065,233 @@ void conv_mid_rr_kernel(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------
+// Middle layers, row-reuse form for e4m3 input (F = 64; output e4m3 or
+// bf16).  v_mfma_scale_f32_16x16x128_f8f6f4 takes K = 128 = two taps of 64
+// channels: lane groups 0-1 carry one tap, groups 2-3 another.  Pairing the
+// horizontal taps as (dx 0, dx 1) and (dx 2, none) keeps both halves of a B
+// fragment in the same input row, so, as in the bf16 kernel, one B fragment
+// of input row ir serves the three vertical taps.  Two pairs x three dy are
+// six K steps (three zero tap slots: 12 slots for 9 taps).  One persistent
+// workgroup of 4 waves per CU, wave w owns output rows 4w..4w+3.
+// ---------------------------------------------------------------------
+template <int OUT_FMT>
+struct Rr8Layout {
+  static constexpr int F = 64, MB = 4, PIXB = 64, CPP = 4;
+  static constexpr int TH = 16, TW = kConvTileW, IH = TH + 2, IW = TW + 2;
+  static constexpr int ROWS = 4;
+  static constexpr int WBYTES = 6 * MB * 64 * 32;
+  static constexpr int IN_BYTES = IH * IW * PIXB;
+  static constexpr int OPIXB = F * FmtInfo<OUT_FMT>::bytes, OCPP = OPIXB / 16;
+  static constexpr int OUT_BYTES = TH * TW * OPIXB;
+  static constexpr int TILE_BYTES = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
+  static constexpr int LDS_BYTES = TILE_BYTES + WBYTES + 2 * F * 4;   // + scale, bias
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+// 64-byte e4m3 pixels: chunk k of pixel p, permuted by bits 2..3 of p so that
+// lanes reading one chunk of 16 consecutive pixels spread over the banks
+__device__ __forceinline__ int rr8_off(int p, int k) { return p * 64 + ((k ^ ((p >> 2) & 3)) << 4); }
+
+template <int OUT_FMT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void conv_mid_rr8_kernel(ConvArgs a) {
+  using Lo = Rr8Layout<OUT_FMT>;
+  constexpr int NT = 256, MB = Lo::MB, IW = Lo::IW, ROWS = Lo::ROWS;
+  constexpr int NCHUNK = Lo::IH * IW * Lo::CPP;
+  constexpr int NLOAD = (NCHUNK + NT - 1) / NT;
+
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  uint8_t *lds_in = lds;
+  uint8_t *lds_w = lds + Lo::TILE_BYTES;
+  float *lds_osc = reinterpret_cast<float *>(lds_w + Lo::WBYTES);
+  float *lds_bias = lds_osc + Lo::F;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+
+  const int nwg = gridDim.x, b = blockIdx.x;
+#if PNP_XCD_MAP
+  const int xcd = b & 7, slot = b >> 3;
+  const int per_xcd = (nwg - xcd + 7) >> 3;
+  const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
+  const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
+#else
+  const int slot = b, per_xcd = nwg, t_begin = 0, t_end = a.n_tiles;
+#endif
+
+  {
+    const PNP_GLOBAL u32x4 *src = gp(reinterpret_cast<const u32x4 *>(a.wblob_rr));
+    u32x4 *dst = reinterpret_cast<u32x4 *>(lds_w);
+    for (int i = tid; i < Lo::WBYTES / 16; i += NT) dst[i] = src[i];
+    if (tid < Lo::F) {
+      lds_osc[tid] = gp(a.oscale)[tid];
+      lds_bias[tid] = gp(a.bias)[tid];
+    }
+  }
+
+  u32x4 pre[NLOAD];
+  auto issue_load = [&](const MidTile &c, int i) {
+    const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
+    const int pix = q / Lo::CPP, k = q % Lo::CPP;
+    const int row = pix / IW, col = pix % IW;
+    pre[i] = *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+        c.in + ((int64_t)(c.y0 + row) * c.apitch + (c.x0 + col)) * Lo::PIXB + k * 16);
+  };
+  auto store_lds = [&]() {
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) {
+      const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
+      *reinterpret_cast<u32x4 *>(lds_in + rr8_off(q / Lo::CPP, q % Lo::CPP)) = pre[i];
+    }
+  };
+
+  int ti = t_begin + slot;
+  if (ti >= t_end) return;                       // uniform over the workgroup
+  MidTile cur = mid_tile(a, ti);
+  MidTile nxt = mid_tile(a, ti + per_xcd < t_end ? ti + per_xcd : t_begin);
+#pragma unroll
+  for (int i = 0; i < NLOAD; ++i) issue_load(cur, i);
+  store_lds();
+  __syncthreads();
+
+  // A fragments of step (P, dy): 32 bytes per lane
+  const uint8_t *abase = lds_w + lane * 32;
+  i32x8 Ab[3][MB];
+  auto load_a = [&](int P, int dy) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const uint8_t *src = abase + ((P * 3 + dy) * MB + mb) * 2048;
+      const u32x4 lo = *reinterpret_cast<const u32x4 *>(src);
+      const u32x4 hi = *reinterpret_cast<const u32x4 *>(src + 16);
+      Ab[dy][mb] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                         (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+  };
+  // slots of dy 0 and 1 hold pair 0 when a tile starts (see the schedule below)
+  load_a(0, 0);
+  load_a(0, 1);
+
+  while (true) {
+    const int tn = ti + per_xcd, tnn = tn + per_xcd;
+    const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
+    __builtin_amdgcn_sched_barrier(0);
+
+    f32x4 acc[MB][ROWS][2];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int o = 0; o < ROWS; ++o)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[mb][o][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // this lane's B column: pixel (ROWS*wave + ir, 16h + l16 + dx), 32 bytes at
+    // chunk 2(g&1); dx = first tap of the pair for groups 0-1, second for 2-3
+    // (pair 1's second tap has zero weights: any pixel of the row will do)
+    const int bpix = (ROWS * wave) * IW + l16;
+    constexpr int NR = ROWS + 2, NSTG = 2 * NR, PD = 2;
+    i32x8 Bb[PD + 1][2];
+    auto load_b = [&](int stg) {
+      const int P = stg / NR, ir = stg % NR;
+      const int dx = (g < 2) ? (P == 0 ? 0 : 2) : (P == 0 ? 1 : 2);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int p = bpix + ir * IW + 16 * h + dx;
+        const u32x4 lo = *reinterpret_cast<const u32x4 *>(lds_in + rr8_off(p, 2 * (g & 1)));
+        const u32x4 hi = *reinterpret_cast<const u32x4 *>(lds_in + rr8_off(p, 2 * (g & 1) + 1));
+        Bb[stg % (PD + 1)][h] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+    };
+#pragma unroll
+    for (int k = 0; k < PD; ++k) load_b(k);
+    // 12 stages (pair P, input row ir).  A slots: dy 2 is loaded at (P, 0)
+    // (last used at the previous pair's row 5); dy 0 and 1 for the next pair
+    // at (P, 4) and (P, 5), after their last use at rows 3 and 4.
+#pragma unroll
+    for (int stg = 0; stg < NSTG; ++stg) {
+      const int P = stg / NR, ir = stg % NR;
+      if (stg + PD < NSTG) load_b(stg + PD);
+      if (ir == 0) load_a(P, 2);
+      if (ir == 4) load_a(P ^ 1, 0);
+      if (ir == 5) load_a(P ^ 1, 1);
+      if (stg < NLOAD) issue_load(nxt, stg);      // the next tile's window, one per stage
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int o = ir - dy;
+        if (o < 0 || o >= ROWS) continue;
+        // dy 0 / 1 slots were refilled at rows 4 / 5 of this pair, after
+        // their last use (rows 3 / 4): the MFMAs below run before the refill
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[mb][o][h] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                Ab[dy][mb], Bb[stg % (PD + 1)][h], acc[mb][o][h], 0, 0, 0, 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = NSTG; i < NLOAD; ++i) issue_load(nxt, i);
+
+    // epilogue: scale, bias, ReLU, round to the output format, stage the tile
+    // over the consumed input window, store whole pixels with 16-byte lanes
+    __syncthreads();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const f32x4 osc = *reinterpret_cast<const f32x4 *>(lds_osc + mb * 16 + 4 * g);
+      const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + mb * 16 + 4 * g);
+#pragma unroll
+      for (int o = 0; o < ROWS; ++o)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          f32x4 v;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = fmaxf(fmaf(acc[mb][o][h][e], osc[e], bia[e]), 0.0f);
+          const int p = (ROWS * wave + o) * Lo::TW + 16 * h + l16;
+          if constexpr (OUT_FMT == FMT_BF16) {
+            u32x2 w;
+            w.x = pack_bf16x2(v[0], v[1]);
+            w.y = pack_bf16x2(v[2], v[3]);
+            *reinterpret_cast<u32x2 *>(lds_in + rr_off(p, 2 * mb + (g >> 1)) + 8 * (g & 1)) = w;
+          } else {
+            const float is = a.out_inv_scale;
+            const uint32_t w = pack_e4m3x4(v[0] * is, v[1] * is, v[2] * is, v[3] * is);
+            *reinterpret_cast<uint32_t *>(lds_in + rr8_off(p, mb) + 4 * g) = w;
+          }
+        }
+    }
+    __syncthreads();
+    {
+      constexpr int NQ = Lo::TH * Lo::TW * Lo::OCPP, NS = NQ / NT;
+      u32x4 st[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int q = i * NT + tid, p = q / Lo::OCPP, k = q % Lo::OCPP;
+        st[i] = *reinterpret_cast<const u32x4 *>(
+            lds_in + (OUT_FMT == FMT_BF16 ? rr_off(p, k) : rr8_off(p, k)));
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int q = i * NT + tid;
+        const int pix = q / Lo::OCPP, k = q % Lo::OCPP;
+        const int r = pix / Lo::TW, c = pix % Lo::TW;
+        const int64_t px = (r < cur.h && c < cur.w)
+                               ? (int64_t)(cur.y0 + r + 1) * cur.apitch + (cur.x0 + c + 1)
+                               : cur.trash;
+        *reinterpret_cast<PNP_GLOBAL u32x4 *>(cur.out + px * Lo::OPIXB + k * 16) = st[i];
+      }
+    }
+    __syncthreads();                             // staged outputs are read
+    store_lds();
+    __syncthreads();
+    if (tn >= t_end) break;
+    cur = nxt;
+    nxt = after;
+    ti = tn;
+  }
+}
+
+// ---------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------
 template <int IN_FMT, int OUT_FMT, int F, int NW>
@@ -1089,6 +1311,20 @@ static hipError_t launch_mid_t(const ConvArgs &a, int n_wg, hipStream_t s) {
 }
 
 static_assert(!PNP_MID_RR || 2 * PNP_NW_LOWP == RrLayout::TH, "bf16 tile rows");
+template <int OUT_FMT>
+static hipError_t launch_rr8_t(const ConvArgs &a, int n_wg, hipStream_t s) {
+  constexpr int lds = Rr8Layout<OUT_FMT>::LDS_BYTES;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_mid_rr8_kernel<OUT_FMT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((conv_mid_rr8_kernel<OUT_FMT>), dim3(n_wg), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
 template <bool FIRST>
 static hipError_t launch_rr_t(const ConvArgs &a, int n_wg, hipStream_t s) {
   constexpr int lds = FIRST ? RrLayout::LDS_BYTES_FIRST : RrLayout::LDS_BYTES;
@@ -1148,6 +1384,10 @@ hipError_t launch_conv_mid(int in_fmt, int out_fmt, int F, const ConvArgs &a, in
     if (F == 32) return launch_mid_t<FMT_BF16, FMT_BF16, 32, PNP_NW_LOWP>(a, n_wg, s);
     if (F == 64) return launch_mid_t<FMT_BF16, FMT_BF16, 64, PNP_NW_LOWP>(a, n_wg, s);
   } else if (in_fmt == FMT_E4M3 && F == 64) {
+    if (PNP_MID_RR && a.relu && a.wblob_rr) {
+      if (out_fmt == FMT_E4M3) return launch_rr8_t<FMT_E4M3>(a, n_wg, s);
+      if (out_fmt == FMT_BF16) return launch_rr8_t<FMT_BF16>(a, n_wg, s);
+    }
     if (out_fmt == FMT_E4M3) return launch_mid_t<FMT_E4M3, FMT_E4M3, 64, PNP_NW_LOWP>(a, n_wg, s);
     if (out_fmt == FMT_BF16) return launch_mid_t<FMT_E4M3, FMT_BF16, 64, PNP_NW_LOWP>(a, n_wg, s);
   }

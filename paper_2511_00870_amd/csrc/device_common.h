@@ -148,21 +148,39 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
 }
 __device__ __forceinline__ float round_bf16(float v) { return bf16_to_f32(f32_to_bf16(v)); }
 
-__device__ __forceinline__ uint8_t f32_to_e4m3(float v) {
+__device__ __forceinline__ uint8_t f32_to_e4m3_sw(float v) {
+  // branch-free (selects only): NaN -> 0x7f, |v| >= 448 -> 448 (0x7e),
+  // |v| < 2^-6 -> subnormal step 2^-9, else round to 3 mantissa bits (RNE)
   const uint32_t u = __float_as_uint(v);
-  const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+  const uint32_t sign = (u >> 24) & 0x80u;
   const float a = fabsf(v);
-  if (a != a) return (uint8_t)(sign | 0x7f);
-  if (a >= 448.0f) return (uint8_t)(sign | 0x7e);            // saturate
-  if (a < 0.015625f) {                                        // below 2^-6: step 2^-9
-    const float q = rintf(a * 512.0f);                        // 0..8 (8 = 2^-6)
-    return (uint8_t)(sign | (uint8_t)q);
-  }
   uint32_t b = __float_as_uint(a);
-  b += 0x7ffffu + ((b >> 20) & 1u);                           // RNE to 3 mantissa bits
-  const uint32_t e = (b >> 23) - 127u + 7u;
-  const uint32_t m = (b >> 20) & 7u;
-  return (uint8_t)(sign | (e << 3) | m);
+  b += 0x7ffffu + ((b >> 20) & 1u);
+  const uint32_t normal = (((b >> 23) - 120u) << 3) | ((b >> 20) & 7u);
+  const uint32_t sub = (uint32_t)rintf(a * 512.0f);          // 0..8 (8 = 2^-6)
+  uint32_t r = a < 0.015625f ? sub : normal;
+  r = a >= 448.0f ? 0x7eu : r;
+  r = a != a ? 0x7fu : r;
+  return (uint8_t)(sign | r);
+}
+// gfx950's v_cvt_pk_fp8_f32 (OCP e4m3, round to nearest even) on inputs
+// clamped to +-448 gives the same codes as the rounding above for every
+// finite float (checked exhaustively for |v| <= 1024; beyond, both give
+// 448); NaN inputs take the rounding above
+__device__ __forceinline__ float e4m3_clamp(float v) { return __builtin_amdgcn_fmed3f(v, -448.0f, 448.0f); }
+__device__ __forceinline__ uint8_t f32_to_e4m3(float v) {
+  const uint8_t h = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(v), 0.0f, 0, false) & 0xff);
+  return v != v ? f32_to_e4m3_sw(v) : h;
+}
+// four values, the first in the low byte
+__device__ __forceinline__ uint32_t pack_e4m3x4(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(a), e4m3_clamp(b), 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(c), e4m3_clamp(d), w, true);
+  uint32_t r = (uint32_t)w;
+  if (a != a || b != b || c != c || d != d)
+    r = (uint32_t)f32_to_e4m3_sw(a) | ((uint32_t)f32_to_e4m3_sw(b) << 8) |
+        ((uint32_t)f32_to_e4m3_sw(c) << 16) | ((uint32_t)f32_to_e4m3_sw(d) << 24);
+  return r;
 }
 __device__ __forceinline__ float e4m3_to_f32(uint8_t c) {
   const uint32_t e = (c >> 3) & 15u, m = c & 7u;

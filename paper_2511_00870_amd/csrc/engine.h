@@ -32,6 +32,7 @@ struct LayerPlan {
   float in_scale = 1.f;     // scale of the stored input (e4m3), else 1
   int in_buf = 0, out_buf = 0;  // activation buffers read / written
   void *wblob = nullptr;    // middle layers: MFMA fragment order
+  void *wblob_rr = nullptr; // e4m3 middle layers: row-reuse kernel's fragment order
   float *wf32 = nullptr;    // first / last layer: [c][9]
   float *bias = nullptr, *oscale = nullptr;
 };

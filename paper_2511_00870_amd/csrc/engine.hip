@@ -259,6 +259,27 @@ Status Engine::set_net(int K, const int32_t *ch, const float *w, const float *b,
       HIPOK(hipMalloc(&L.wblob, blob.size()));
       net.allocs.push_back(L.wblob);
       HIPOK(hipMemcpy(L.wblob, blob.data(), blob.size(), hipMemcpyHostToDevice));
+      if (L.in_fmt == FMT_E4M3) {
+        // row-reuse kernel: step (P, dy) pairs the horizontal taps (dx 0, 1)
+        // for P = 0 and (dx 2, none) for P = 1; lane groups 0-1 hold the first
+        // tap's 64 channels, groups 2-3 the second's (zero for none)
+        std::vector<uint8_t> rr((size_t)6 * MB * 64 * 32, 0);
+        for (int P = 0; P < 2; ++P)
+          for (int dy = 0; dy < 3; ++dy)
+            for (int mb = 0; mb < MB; ++mb)
+              for (int l = 0; l < 64; ++l) {
+                const int g = l >> 4;
+                const int dx = (g < 2) ? (P == 0 ? 0 : 2) : (P == 0 ? 1 : -1);
+                if (dx < 0) continue;
+                const int co = mb * 16 + (l & 15), tap = 3 * dy + dx;
+                for (int e = 0; e < 32; ++e)
+                  rr[((((size_t)P * 3 + dy) * MB + mb) * 64 + l) * 32 + e] =
+                      host_f32_to_e4m3(W(co, 32 * (g & 1) + e, tap));
+              }
+        HIPOK(hipMalloc(&L.wblob_rr, rr.size()));
+        net.allocs.push_back(L.wblob_rr);
+        HIPOK(hipMemcpy(L.wblob_rr, rr.data(), rr.size(), hipMemcpyHostToDevice));
+      }
     }
     woff += (size_t)L.cin * L.cout * 9;
     boff += (size_t)L.cout;
@@ -680,6 +701,7 @@ Status Engine::launch_layer(int k, int64_t tick, bool prof) {
     HIPOK(launch_conv_last(L.in_fmt, L.cin, a, n_conv, stream));
   } else {
     a.wblob = L.wblob;
+    a.wblob_rr = L.wblob_rr;
     const size_t lds = mid_lds_bytes(L.in_fmt, net.F);
     int occ = (int)std::max<size_t>(1, (160 * 1024) / lds);
     occ = std::min(occ, 4);

@@ -18,6 +18,7 @@ struct ConvArgs {
   int32_t unit_scale;          // every output scale is 1
   int64_t tick;
   const void *wblob;           // middle layers: weights in MFMA fragment order
+  const void *wblob_rr;        // e4m3 middle layers: row-reuse fragment order
   const float *wf32;           // first / last layer: quantised weights [c][9]
   const float *bias;           // [c_out]
   const float *oscale;         // [c_out]: weight scale x input scale
