@@ -78,7 +78,7 @@ def run_gpu(wl, precision, steps, warmup, stream, act_scales=None, profile=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rc = ctx.sync()
-    prof = {c: ctx.profile_read(c) for c in range(5)} if profile else None
+    prof = {c: ctx.profile_read(c) for c in range(6)} if profile else None
     ctx.close()
     return dt, rc, prof
 
@@ -215,7 +215,8 @@ def main():
                                         "bytes_per_launch": byt}
     out["kernel_ms_per_step"] = {name: round(prof[c][0] / a.steps, 4) for c, name in
                                  [(0, "conv_mid"), (1, "conv_first"), (2, "conv_last"),
-                                  (3, "fused_update"), (4, "conv_first_mid")]}
+                                  (3, "fused_update"), (4, "conv_first_mid"),
+                                  (5, "conv_mid_last")]}
     if not a.no_compare:
         comp = {}
         for p in (0, 1, 2):

@@ -150,7 +150,9 @@ pnpula_status pnpula_calibrate(pnpula_ctx *ctx, const float *x, float *amax);
 /* Per-kernel timing with HIP events on the context's stream.  Classes:
  * 0 = middle convolution layers, 1 = first layer, 2 = last layer,
  * 3 = fused likelihood/update/statistics kernel, 4 = first layer fused with
- * the first middle layer (bf16 networks).  Enabling resets totals. */
+ * the first middle layer, 5 = last middle layer writing the last layer's
+ * per-tap partials (both bf16 networks; class 2 then times the kernel that
+ * sums the partials into G).  Enabling resets totals. */
 pnpula_status pnpula_profile(pnpula_ctx *ctx, int32_t enable);
 pnpula_status pnpula_profile_read(pnpula_ctx *ctx, int32_t kernel_class, double *total_ms,
                                   int64_t *launches);

@@ -436,6 +436,8 @@ struct MidTile {
   const PNP_GLOBAL float *x;
   int64_t xpitch;
   int xb, ny, nx;
+  // fused last layer: per-tap partial records (16 floats, zero border 1)
+  PNP_GLOBAL float *S;
 };
 __device__ __forceinline__ MidTile mid_tile(const ConvArgs &a, int ti) {
   const PNP_CONST TileRef &tl = cp(a.tiles)[ti];
@@ -454,6 +456,7 @@ __device__ __forceinline__ MidTile mid_tile(const ConvArgs &a, int ti) {
   c.xb = j.xborder;
   c.ny = j.ny;
   c.nx = j.nx;
+  c.S = gp(j.S);
   return c;
 }
 
@@ -772,16 +775,20 @@ struct RrLayout {
   static constexpr int XH = TH + 4, XW = TW + 4, XBYTES = XH * XW * 2;
   static constexpr int LDS_BYTES = TILE_BYTES + WBYTES + EPI_BYTES;
   static constexpr int A0BYTES = MB * 64 * 16;                // first-layer A fragments
-  static constexpr int LDS_BYTES_FIRST = LDS_BYTES + XBYTES + F * 4 + A0BYTES;
-  static_assert(LDS_BYTES_FIRST <= 160 * 1024, "LDS");
+  static constexpr int FIRST_BYTES = XBYTES + F * 4 + A0BYTES;
+  static constexpr int ALBYTES = 2 * 64 * 16;                  // last-layer A fragments
+  static constexpr int lds_bytes(bool first, bool last) {
+    return LDS_BYTES + (first ? FIRST_BYTES : 0) + (last ? ALBYTES : 0);
+  }
 };
+static_assert(RrLayout::lds_bytes(true, true) <= 160 * 1024, "LDS");
 // LDS byte offset of 16-byte chunk k of pixel p: pixels are 128 bytes with no
 // padding and the chunks of a pixel are permuted by the pixel's low 3 bits,
 // so 8 lanes reading the same chunk of 8 consecutive pixels hit 8 different
 // bank groups (a padded stride conflicts two ways at full LDS rate).
 __device__ __forceinline__ int rr_off(int p, int k) { return p * 128 + ((k ^ (p & 7)) << 4); }
 
-template <bool FIRST>
+template <bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void conv_mid_rr_kernel(ConvArgs a) {
   using Lo = RrLayout;
@@ -796,6 +803,7 @@ void conv_mid_rr_kernel(ConvArgs a) {
   uint16_t *lds_x = reinterpret_cast<uint16_t *>(lds_bias + Lo::F);     // FIRST only
   float *lds_bias0 = reinterpret_cast<float *>(lds_x + Lo::XH * Lo::XW);  // FIRST only
   uint8_t *lds_a0 = reinterpret_cast<uint8_t *>(lds_bias0 + Lo::F);        // FIRST only
+  uint8_t *lds_al = lds + Lo::LDS_BYTES + (FIRST ? Lo::FIRST_BYTES : 0);  // LAST only
   constexpr int NX = Lo::XH * Lo::XW, XQ = (NX + NT - 1) / NT;
   constexpr int NWIN = Lo::IH * IW, NB0 = (NWIN + 15) / 16, BPW0 = (NB0 + 3) / 4;
 
@@ -838,9 +846,14 @@ void conv_mid_rr_kernel(ConvArgs a) {
 
   u32x4 pre[FIRST ? 1 : NLOAD];
   float prex[FIRST ? XQ : 1];
-  // load i of the next tile's window (one 16-byte chunk per lane)
+  // load i of the next tile's window (one 16-byte chunk per lane); with the
+  // fused last layer the empty asm keeps the compiler from hoisting 20
+  // loop-invariant lane offsets into registers for the whole tile loop
+  // (which would spill)
   auto issue_load = [&](const MidTile &c, int i) {
-    const int q0 = tid + i * NT, q = q0 < NCHUNK ? q0 : 0;
+    int q0 = tid + i * NT;
+    if constexpr (LAST) asm volatile("" : "+v"(q0));
+    const int q = q0 < NCHUNK ? q0 : 0;
     const int pix = q / Lo::CPP, k = q % Lo::CPP;
     const int row = pix / IW, col = pix % IW;
     pre[i] = *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
@@ -884,6 +897,21 @@ void conv_mid_rr_kernel(ConvArgs a) {
       *reinterpret_cast<u32x4 *>(lds_in + rr_off(q / Lo::CPP, q % Lo::CPP)) = pre[i];
     }
   };
+
+  // fused last layer: A fragments (rows = the 9 taps padded to 16, K = the 64
+  // input channels in two steps) in LDS, fragment order
+  if constexpr (LAST) {
+    if (wave == 1) {
+#pragma unroll
+      for (int kh = 0; kh < 2; ++kh) {
+        bf16x8 f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          f[e] = (__bf16)(l16 < 9 ? gp(a.last_w)[(32 * kh + 8 * g + e) * 9 + l16] : 0.0f);
+        *reinterpret_cast<bf16x8 *>(lds_al + (kh * 64 + lane) * 16) = f;
+      }
+    }
+  }
 
   // Fused first layer on the staged x window: the 64-channel output of every
   // window pixel (an MFMA per 16-pixel block and 16 channels; K = the 9 taps),
@@ -1031,7 +1059,30 @@ void conv_mid_rr_kernel(ConvArgs a) {
           *reinterpret_cast<u32x2 *>(lds_in + rr_off(p, 2 * mb + (g >> 1)) + 8 * (g & 1)) = w;
         }
     __syncthreads();
-    {
+    if constexpr (LAST) {
+      // the last layer's per-tap partials of every pixel of the tile, from the
+      // staged (bf16, ReLU) outputs: one record of 16 floats per pixel (taps
+      // 9..15 have zero weights), written with one 16-byte store per lane
+      const bf16x8 AL0 = *reinterpret_cast<const bf16x8 *>(lds_al + lane * 16);
+      const bf16x8 AL1 = *reinterpret_cast<const bf16x8 *>(lds_al + (64 + lane) * 16);
+      const int64_t spitch = cur.nx + 2, strash = (int64_t)(cur.ny + 2) * spitch;
+#pragma unroll
+      for (int o = 0; o < ROWS; ++o)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = ROWS * wave + o, c = 16 * h + l16, p = r * Lo::TW + c;
+          const bf16x8 B0 = *reinterpret_cast<const bf16x8 *>(lds_in + rr_off(p, g));
+          const bf16x8 B1 = *reinterpret_cast<const bf16x8 *>(lds_in + rr_off(p, 4 + g));
+          f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL0, B0, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                            0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL1, B1, d, 0, 0, 0);
+          // this lane: taps 4g .. 4g+3 of pixel l16 of the block
+          const int64_t rec = (r < cur.h && c < cur.w)
+                                  ? (int64_t)(cur.y0 + r + 1) * spitch + (cur.x0 + c + 1)
+                                  : strash;
+          *reinterpret_cast<PNP_GLOBAL f32x4 *>(cur.S + rec * 16 + 4 * g) = d;
+        }
+    } else {
       constexpr int NQ = Lo::TH * Lo::TW * Lo::CPP, NS = NQ / NT;
       u32x4 st[NS];
 #pragma unroll
@@ -1291,6 +1342,29 @@ void conv_mid_rr8_kernel(ConvArgs a) {
   }
 }
 
+// G from the fused last layer's partials: G(p) = scale * sum over taps of the
+// tap's partial at the neighbour the tap reads, + bias.  The records' zero
+// border supplies the zero padding at the image edge.
+__global__ __launch_bounds__(256) void g_from_s_kernel(ConvArgs a) {
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+  const PNP_GLOBAL float *S = gp(j.S);
+  const int64_t spitch = j.nx + 2;
+  const float sc = a.oscale[0], bi = a.bias[0];
+  const int npix = tl.h * tl.w;
+  for (int pix = threadIdx.x; pix < npix; pix += 256) {
+    const int Y = tl.y0 + pix / tl.w, X = tl.x0 + pix % tl.w;
+    float acc = 0.0f;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      // output (Y, X) reads input (Y + dy - 1, X + dx - 1): record (Y + dy, X + dx)
+      const int dy = tap / 3, dx = tap % 3;
+      acc += S[((Y + dy) * spitch + (X + dx)) * 16 + tap];
+    }
+    gp(j.G)[(int64_t)Y * j.nx + X] = acc * sc + bi;
+  }
+}
+
 // ---------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------
@@ -1325,21 +1399,40 @@ static hipError_t launch_rr8_t(const ConvArgs &a, int n_wg, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <bool FIRST>
+template <bool FIRST, bool LAST>
 static hipError_t launch_rr_t(const ConvArgs &a, int n_wg, hipStream_t s) {
-  constexpr int lds = FIRST ? RrLayout::LDS_BYTES_FIRST : RrLayout::LDS_BYTES;
+  constexpr int lds = RrLayout::lds_bytes(FIRST, LAST);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_mid_rr_kernel<FIRST>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_mid_rr_kernel<FIRST, LAST>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((conv_mid_rr_kernel<FIRST>), dim3(n_wg), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((conv_mid_rr_kernel<FIRST, LAST>), dim3(n_wg), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 static hipError_t launch_rr(const ConvArgs &a, int n_wg, hipStream_t s) {
-  return launch_rr_t<false>(a, n_wg, s);
+  return launch_rr_t<false, false>(a, n_wg, s);
+}
+
+bool mid_last_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int last_in_fmt,
+                      int last_cin, int last_cout) {
+  return PNP_MID_RR && in_fmt == FMT_BF16 && out_fmt == FMT_BF16 && F == 64 && relu && unit &&
+         last_in_fmt == FMT_BF16 && last_cin == 64 && last_cout == 1;
+}
+
+hipError_t launch_conv_mid_last(const ConvArgs &a, int n_wg, bool first, hipStream_t s) {
+  // first and last fused into one middle layer (K = 3) is not built: the
+  // engine fuses the last layer only when K >= 4
+  if (first || !a.last_w || a.tile_rows != RrLayout::TH) return hipErrorInvalidValue;
+  return launch_rr_t<false, true>(a, n_wg, s);
+}
+
+hipError_t launch_g_from_s(const ConvArgs &a, int n_tiles, hipStream_t s) {
+  hipLaunchKernelGGL(g_from_s_kernel, dim3(n_tiles), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 bool first_mid_fusable(int in_fmt0, int out_fmt0, int cout0, int relu0, int unit0, int in_fmt1,
@@ -1350,7 +1443,7 @@ bool first_mid_fusable(int in_fmt0, int out_fmt0, int cout0, int relu0, int unit
 
 hipError_t launch_conv_first_mid(const ConvArgs &a, int n_wg, hipStream_t s) {
   if (!a.first_w || !a.first_bias || a.tile_rows != RrLayout::TH) return hipErrorInvalidValue;
-  return launch_rr_t<true>(a, n_wg, s);
+  return launch_rr_t<true, false>(a, n_wg, s);
 }
 
 // tile rows of the middle-layer kernel for an input format

@@ -44,6 +44,9 @@ struct JobDesc {
   float *wmean, *wm2;      // FP32 Welford window (compact)
   double *mean, *m2;       // FP64 merged statistics (compact)
   int32_t *flag;           // non-finite flag
+  float *S;                // last layer fused into the last middle layer: per pixel 16
+                           // floats, the 9 per-tap partial dot products (zero border 1,
+                           // row pitch nx + 2 records; one trash record at the end)
   const float *kern;       // L*L blur (2-D path)
   const float *ku, *kv;    // separable factors k[a][c] = ku[a] kv[c]
   // coefficients, computed in FP64 on the host and rounded once

@@ -43,6 +43,7 @@ struct NetPlan {
   std::vector<float> weights, biases, act_scales;  // host copies
   std::vector<LayerPlan> layers;
   int buf_fmt[4] = {-1, -1, -1, -1};  // storage format of each activation buffer
+  bool last_fused = false;   // the last layer runs inside the last middle layer's kernel
   std::vector<void *> allocs;
 };
 
@@ -104,6 +105,9 @@ class Engine {
   Status run_denoiser(int64_t tick);
   bool first_mid_fused() const;
   Status launch_first_mid(int64_t tick, bool prof);
+  Status launch_mid_last(int k, int64_t tick, bool first, bool prof);
+  Status launch_g_from_s(int64_t tick, bool prof);
+  Status run_fused_denoiser(int64_t tick, bool prof);
   Status launch_layer(int k, int64_t tick, bool prof);
   JobDesc *d_jobs = nullptr;
   TileRef *d_conv = nullptr, *d_upd = nullptr;
@@ -113,8 +117,8 @@ class Engine {
   bool profiling = false;
   std::vector<ProfileRec> prof_pending;
   std::vector<hipEvent_t> prof_free;
-  double prof_ms[5] = {0, 0, 0, 0, 0};
-  int64_t prof_n[5] = {0, 0, 0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_n[6] = {0, 0, 0, 0, 0, 0};
   void prof_begin(int cls, ProfileRec *r);
   void prof_end(ProfileRec *r);
 };

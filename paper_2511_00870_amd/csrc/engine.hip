@@ -305,6 +305,13 @@ Status Engine::set_net(int K, const int32_t *ch, const float *w, const float *b,
     }
   }
   conv_th = (K > 1) ? mid_tile_rows(net.layers[1].in_fmt) : 16;
+  net.last_fused = false;
+  if (K >= 4) {
+    const LayerPlan &Lm = net.layers[K - 2], &Ll = net.layers[K - 1];
+    net.last_fused = mid_last_fusable(Lm.in_fmt, Lm.out_fmt, net.F, Lm.relu, Lm.unit_scale,
+                                      Ll.in_fmt, Ll.cin, Ll.cout) &&
+                     conv_th == 16;
+  }
   plan_dirty = true;
   return Status::ok();
 }
@@ -362,6 +369,7 @@ size_t Engine::job_footprint(const pnpula_config *c, const NetPlan &n) {
   for (int b = 0; b < 4; ++b)
     if (n.buf_fmt[b] >= 0) bytes += (size_t)g.arows * g.apitch * n.F * fmt_bytes(n.buf_fmt[b]);
   bytes += N * (sizeof(float) * 3 + sizeof(double) * 2);                // G, Welford
+  if (n.last_fused) bytes += ((size_t)(c->ny + 2) * (c->nx + 2) + 1) * 16 * sizeof(float);
   bytes += 4096;
   return bytes;
 }
@@ -463,6 +471,13 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
     d.act[b] = ab;
   }
   if (!(s = dalloc(j, &d.G, N * sizeof(float))).good()) return fail(s);
+  d.S = nullptr;
+  if (net.last_fused) {
+    const size_t sbytes = ((size_t)(ny + 2) * (nx + 2) + 1) * 16 * sizeof(float);
+    if (!(s = dalloc(j, &d.S, sbytes)).good()) return fail(s);
+    if (hipMemsetAsync(d.S, 0, sbytes, stream) != hipSuccess)
+      return fail(Status::fail(PNPULA_EDEVICE, "memset"));
+  }
   if (!(s = dalloc(j, &d.wmean, N * sizeof(float))).good()) return fail(s);
   if (!(s = dalloc(j, &d.wm2, N * sizeof(float))).good()) return fail(s);
   if (!(s = dalloc(j, &d.mean, N * sizeof(double))).good()) return fail(s);
@@ -618,7 +633,7 @@ void Engine::profile_enable(bool on) {
     prof_free.push_back(r.b);
   }
   prof_pending.clear();
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < 6; ++i) {
     prof_ms[i] = 0;
     prof_n[i] = 0;
   }
@@ -647,7 +662,7 @@ void Engine::prof_end(ProfileRec *r) {
 }
 
 Status Engine::profile_read(int cls, double *ms, int64_t *launches) {
-  if (cls < 0 || cls > 4) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..4");
+  if (cls < 0 || cls > 5) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..5");
   HIPOK(hipStreamSynchronize(stream));
   for (auto &r : prof_pending) {
     float e = 0;
@@ -752,15 +767,75 @@ Status Engine::launch_first_mid(int64_t tick, bool prof) {
   return Status::ok();
 }
 
-Status Engine::run_denoiser(int64_t tick) {
-  int k0 = 0;
-  if (first_mid_fused()) {
-    TRY(launch_first_mid(tick, true));
-    k0 = 2;
+// middle layer k writing the last layer's per-tap partials (JobDesc::S)
+Status Engine::launch_mid_last(int k, int64_t tick, bool first, bool prof) {
+  const LayerPlan &L = net.layers[k], &LL = net.layers[net.K - 1];
+  ConvArgs a{};
+  a.jobs = d_jobs;
+  a.tiles = d_conv;
+  a.n_tiles = n_conv;
+  a.tile_rows = conv_th;
+  a.tick = tick;
+  a.relu = L.relu;
+  a.unit_scale = L.unit_scale;
+  a.bias = L.bias;
+  a.oscale = L.oscale;
+  a.in_slot = L.in_buf;
+  a.out_slot = L.out_buf;
+  a.wblob = L.wblob;
+  a.last_w = LL.wf32;
+  if (first) {
+    a.first_w = net.layers[0].wf32;
+    a.first_bias = net.layers[0].bias;
   }
-  for (int k = k0; k < net.K; ++k) TRY(launch_layer(k, tick, true));
+  const int need = ((n_conv + 7) / 8) * 8;
+  const int n_wg = std::max(8, std::min(n_cu, need) / 8 * 8);
+  ProfileRec pr;
+  if (prof) prof_begin(5, &pr);
+  HIPOK(launch_conv_mid_last(a, n_wg, first, stream));
+  if (prof) prof_end(&pr);
   return Status::ok();
 }
+
+Status Engine::launch_g_from_s(int64_t tick, bool prof) {
+  const LayerPlan &LL = net.layers[net.K - 1];
+  ConvArgs a{};
+  a.jobs = d_jobs;
+  a.tiles = d_conv;
+  a.n_tiles = n_conv;
+  a.tile_rows = conv_th;
+  a.tick = tick;
+  a.bias = LL.bias;
+  a.oscale = LL.oscale;
+  ProfileRec pr;
+  if (prof) prof_begin(2, &pr);
+  HIPOK(::pnp::launch_g_from_s(a, n_conv, stream));
+  if (prof) prof_end(&pr);
+  return Status::ok();
+}
+
+// the denoiser as the sampler runs it: first layer inside the first middle
+// layer's kernel and last layer inside the last middle layer's (when the
+// network allows), the rest layer by layer
+Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
+  const int K = net.K;
+  const bool ff = first_mid_fused(), lf = net.last_fused;
+  int k = 0;
+  if (ff) {
+    TRY(launch_first_mid(tick, prof));
+    k = 2;
+  }
+  for (; k < K; ++k) {
+    if (lf && k == K - 2) {
+      TRY(launch_mid_last(k, tick, false, prof));
+      return launch_g_from_s(tick, prof);
+    }
+    TRY(launch_layer(k, tick, prof));
+  }
+  return Status::ok();
+}
+
+Status Engine::run_denoiser(int64_t tick) { return run_fused_denoiser(tick, true); }
 
 Status Engine::tick() {
   if (plan_dirty) TRY(rebuild_plan());
@@ -896,9 +971,9 @@ Status Engine::denoise(Job *j, const float *x, float *G, float *layers, float *a
   if (d_amax) HIPOK(hipMemsetAsync(d_amax, 0, sizeof(uint32_t) * K, stream));
   float *lp = layers;
   int k0 = 0;
-  if (!layers && !amax && first_mid_fused()) {   // the path the sampler runs
-    TRY(launch_first_mid(tick_alt, false));
-    k0 = 2;
+  if (!layers && !amax) {                         // the path the sampler runs
+    TRY(run_fused_denoiser(tick_alt, false));
+    k0 = K;
   }
   for (int k = k0; k < K; ++k) {
     const LayerPlan &L = net.layers[k];

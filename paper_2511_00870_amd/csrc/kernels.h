@@ -27,6 +27,8 @@ struct ConvArgs {
   // first layer fused into the first middle layer: its weights [c][9] and bias
   const float *first_w;
   const float *first_bias;
+  // last layer fused into the last middle layer: its weights [c][9]
+  const float *last_w;
 };
 
 struct UpdateArgs {
@@ -45,6 +47,14 @@ size_t update_lds_bytes(int r);
 // first layer (1 -> 64, bf16) and first middle layer in one kernel; a holds the
 // middle layer's arguments plus first_w / first_bias
 hipError_t launch_conv_first_mid(const ConvArgs &a, int n_wg, hipStream_t s);
+// middle layer whose output feeds the last layer directly: writes the last
+// layer's per-tap partials (JobDesc::S) instead of its activations (first
+// must be false: a middle layer with both fusions is not built)
+hipError_t launch_conv_mid_last(const ConvArgs &a, int n_wg, bool first, hipStream_t s);
+// G = sum over taps of the partials at the tap's neighbour, plus the bias
+hipError_t launch_g_from_s(const ConvArgs &a, int n_tiles, hipStream_t s);
+bool mid_last_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int last_in_fmt,
+                      int last_cin, int last_cout);
 bool first_mid_fusable(int in_fmt0, int out_fmt0, int cout0, int relu0, int unit0, int in_fmt1,
                        int out_fmt1, int F, int relu1, int unit1);
 hipError_t launch_conv_mid(int in_fmt, int out_fmt, int F, const ConvArgs &a, int n_wg,
