@@ -436,7 +436,7 @@ struct MidTile {
   const PNP_GLOBAL float *x;
   int64_t xpitch;
   int xb, ny, nx;
-  // fused last layer: per-tap partial records (16 floats, zero border 1)
+  // fused last layer: per-tap partial records (12 floats, zero border 1)
   PNP_GLOBAL float *S;
 };
 __device__ __forceinline__ MidTile mid_tile(const ConvArgs &a, int ti) {
@@ -1061,8 +1061,9 @@ void conv_mid_rr_kernel(ConvArgs a) {
     __syncthreads();
     if constexpr (LAST) {
       // the last layer's per-tap partials of every pixel of the tile, from the
-      // staged (bf16, ReLU) outputs: one record of 16 floats per pixel (taps
-      // 9..15 have zero weights), written with one 16-byte store per lane
+      // staged (bf16, ReLU) outputs: one record of 12 floats per pixel (taps
+      // 9..11 have zero weights), written with one 16-byte store per lane of
+      // lane groups 0-2
       const bf16x8 AL0 = *reinterpret_cast<const bf16x8 *>(lds_al + lane * 16);
       const bf16x8 AL1 = *reinterpret_cast<const bf16x8 *>(lds_al + (64 + lane) * 16);
       const int64_t spitch = cur.nx + 2, strash = (int64_t)(cur.ny + 2) * spitch;
@@ -1080,7 +1081,7 @@ void conv_mid_rr_kernel(ConvArgs a) {
           const int64_t rec = (r < cur.h && c < cur.w)
                                   ? (int64_t)(cur.y0 + r + 1) * spitch + (cur.x0 + c + 1)
                                   : strash;
-          *reinterpret_cast<PNP_GLOBAL f32x4 *>(cur.S + rec * 16 + 4 * g) = d;
+          if (g < 3) *reinterpret_cast<PNP_GLOBAL f32x4 *>(cur.S + rec * 12 + 4 * g) = d;
         }
     } else {
       constexpr int NQ = Lo::TH * Lo::TW * Lo::CPP, NS = NQ / NT;
@@ -1359,7 +1360,7 @@ __global__ __launch_bounds__(256) void g_from_s_kernel(ConvArgs a) {
     for (int tap = 0; tap < 9; ++tap) {
       // output (Y, X) reads input (Y + dy - 1, X + dx - 1): record (Y + dy, X + dx)
       const int dy = tap / 3, dx = tap % 3;
-      acc += S[((Y + dy) * spitch + (X + dx)) * 16 + tap];
+      acc += S[((Y + dy) * spitch + (X + dx)) * 12 + tap];
     }
     gp(j.G)[(int64_t)Y * j.nx + X] = acc * sc + bi;
   }

@@ -44,7 +44,7 @@ struct JobDesc {
   float *wmean, *wm2;      // FP32 Welford window (compact)
   double *mean, *m2;       // FP64 merged statistics (compact)
   int32_t *flag;           // non-finite flag
-  float *S;                // last layer fused into the last middle layer: per pixel 16
+  float *S;                // last layer fused into the last middle layer: per pixel 12
                            // floats, the 9 per-tap partial dot products (zero border 1,
                            // row pitch nx + 2 records; one trash record at the end)
   const float *kern;       // L*L blur (2-D path)

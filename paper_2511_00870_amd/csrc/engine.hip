@@ -369,7 +369,7 @@ size_t Engine::job_footprint(const pnpula_config *c, const NetPlan &n) {
   for (int b = 0; b < 4; ++b)
     if (n.buf_fmt[b] >= 0) bytes += (size_t)g.arows * g.apitch * n.F * fmt_bytes(n.buf_fmt[b]);
   bytes += N * (sizeof(float) * 3 + sizeof(double) * 2);                // G, Welford
-  if (n.last_fused) bytes += ((size_t)(c->ny + 2) * (c->nx + 2) + 1) * 16 * sizeof(float);
+  if (n.last_fused) bytes += ((size_t)(c->ny + 2) * (c->nx + 2) + 1) * 12 * sizeof(float);
   bytes += 4096;
   return bytes;
 }
@@ -473,7 +473,7 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   if (!(s = dalloc(j, &d.G, N * sizeof(float))).good()) return fail(s);
   d.S = nullptr;
   if (net.last_fused) {
-    const size_t sbytes = ((size_t)(ny + 2) * (nx + 2) + 1) * 16 * sizeof(float);
+    const size_t sbytes = ((size_t)(ny + 2) * (nx + 2) + 1) * 12 * sizeof(float);
     if (!(s = dalloc(j, &d.S, sbytes)).good()) return fail(s);
     if (hipMemsetAsync(d.S, 0, sbytes, stream) != hipSuccess)
       return fail(Status::fail(PNPULA_EDEVICE, "memset"));
