@@ -1117,6 +1117,245 @@ void conv_mid_rr_kernel(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------
+// Two consecutive bf16 middle layers (F = 64, ReLU, unit output scales) in
+// one persistent kernel, so that the activation between them never goes to
+// memory.  Per output tile of 14 x 30 pixels: layer A computes the 16 x 32
+// intermediate activation (the tile and a one-pixel ring, plus two padding
+// columns) from the 18 x 34 input window into LDS -- bf16, ReLU, and zero at
+// positions outside the image, which is layer B's zero padding -- and layer B
+// computes the tile from it.
+//
+// Wave w owns output channels 16w .. 16w+15 of both layers and keeps their A
+// fragments (18 K steps each) in registers for the whole kernel, so LDS holds
+// activations only; every wave reads every B fragment.  Work runs input row
+// by input row: the B fragment of input row ir serves output rows ir, ir-1
+// and ir-2 (taps dy = 0, 1, 2), so output row o is complete after input row
+// o + 2 and four accumulator row slots suffice.  The next tile's window is
+// loaded into registers in two halves, one issued during layer A and one at
+// the start of layer B, and each is copied into the input buffer once layer
+// A has finished reading it: three barriers per tile.
+// ---------------------------------------------------------------------
+// calls fn(std::integral_constant<int, i>) for i = I .. N-1 in order (a loop
+// unrolled by construction, whatever its body's size)
+template <int I, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn &&fn) {
+  if constexpr (I < N) {
+    fn(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(fn);
+  }
+}
+
+struct PairLayout {
+  static constexpr int F = 64, PIXB = 128, CPP = 8, NSTEP = 18, NT = 256;
+  static constexpr int TH = kPairTileH, TW = kPairTileW;   // output tile
+  static constexpr int MH = TH + 2, MW = TW + 2;            // intermediate rows x columns
+  static constexpr int IH = TH + 4, IW = TW + 4;            // input window
+  static constexpr int IN_BYTES = IH * IW * PIXB;
+  static constexpr int MID_BYTES = MH * IW * PIXB;          // row pitch IW, like the window
+  static constexpr int LDS_BYTES = IN_BYTES + MID_BYTES + 2 * F * 4;
+  static constexpr int NCHUNK = IH * IW * CPP, NLOAD = (NCHUNK + NT - 1) / NT;
+  static constexpr int NL1 = NLOAD / 2, NL2 = NLOAD - NL1;  // the two prefetch halves
+};
+static_assert(PairLayout::MW == 32 && PairLayout::LDS_BYTES <= 160 * 1024, "pair layout");
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void conv_pair_kernel(ConvArgs a) {
+  using Lo = PairLayout;
+  constexpr int NT = Lo::NT, IW = Lo::IW, NL1 = Lo::NL1, NL2 = Lo::NL2;
+  constexpr int NIT = 6, PD = 2;                  // (dx, kh) steps per row; B reads ahead
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  uint8_t *lds_in = lds;
+  uint8_t *lds_mid = lds + Lo::IN_BYTES;
+  float *lds_bias = reinterpret_cast<float *>(lds_mid + Lo::MID_BYTES);   // [layer][64]
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nwg = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3;
+  const int per_xcd = (nwg - xcd + 7) >> 3;
+  const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
+  const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
+
+  // this wave's A fragments of both layers: fragment (step s, block wave)
+  bf16x8 WA[Lo::NSTEP], WB[Lo::NSTEP];
+  {
+    const PNP_GLOBAL bf16x8 *wa = gp(reinterpret_cast<const bf16x8 *>(a.wblob));
+    const PNP_GLOBAL bf16x8 *wb = gp(reinterpret_cast<const bf16x8 *>(a.wblob2));
+#pragma unroll
+    for (int s = 0; s < Lo::NSTEP; ++s) {
+      WA[s] = wa[(s * 4 + wave) * 64 + lane];
+      WB[s] = wb[(s * 4 + wave) * 64 + lane];
+    }
+  }
+  if (tid < Lo::F) lds_bias[tid] = gp(a.bias)[tid];
+  else if (tid < 2 * Lo::F) lds_bias[tid] = gp(a.bias2)[tid - Lo::F];
+  // the intermediate's columns MW .. IW-1 are read only for the two padding
+  // output columns and never written: zero them once
+  for (int i = tid; i < Lo::MID_BYTES / 16; i += NT)
+    reinterpret_cast<u32x4 *>(lds_mid)[i] = u32x4{0u, 0u, 0u, 0u};
+
+  // chunk i of this lane's share of a window (16 bytes); window pixel (r, c)
+  // is image pixel (y0 - 2 + r, x0 - 2 + c), and positions beyond the
+  // one-pixel zero border read the border.  Lanes past the window load chunk
+  // 0 and store it again (the bytes its owner stores).  The empty asm keeps
+  // the compiler from holding every chunk's lane offsets across the tile loop.
+  auto load_chunk = [&](const MidTile &c, int i) -> u32x4 {
+    int q0 = tid + i * NT;
+    asm volatile("" : "+v"(q0));
+    const int q = q0 < Lo::NCHUNK ? q0 : 0;
+    const int pix = q / Lo::CPP, k = q % Lo::CPP;
+    const int r = pix / IW, col = pix % IW;
+    const int Y = min(max(c.y0 - 2 + r, -1), c.ny), X = min(max(c.x0 - 2 + col, -1), c.nx);
+    return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+        c.in + ((int64_t)(Y + 1) * c.apitch + (X + 1)) * Lo::PIXB + k * 16);
+  };
+  auto put_chunk = [&](int i, const u32x4 &v) {
+    int q0 = tid + i * NT;
+    asm volatile("" : "+v"(q0));
+    const int q = q0 < Lo::NCHUNK ? q0 : 0;
+    *reinterpret_cast<u32x4 *>(lds_in + rr_off(q / Lo::CPP, q % Lo::CPP)) = v;
+  };
+
+  int ti = t_begin + slot;
+  if (ti >= t_end) return;                       // uniform over the workgroup
+  MidTile cur = mid_tile(a, ti);
+  MidTile nxt = mid_tile(a, ti + per_xcd < t_end ? ti + per_xcd : t_begin);
+  u32x4 pre[NL2];
+#pragma unroll
+  for (int i = 0; i < NL1; ++i) pre[i] = load_chunk(cur, i);
+#pragma unroll
+  for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+#pragma unroll
+  for (int i = 0; i < NL2; ++i) pre[i] = load_chunk(cur, NL1 + i);
+#pragma unroll
+  for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+  __syncthreads();
+  int base_in[8][2], base_mid[8][2];
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+      int v = 128 * l16 + (((4 * kh + g) ^ ((m + l16) & 7)) << 4);
+      asm volatile("" : "+v"(v));               // keep as a register, not re-derived
+      base_in[m][kh] = v;
+      base_mid[m][kh] = v + Lo::IN_BYTES;
+    }
+
+  while (true) {
+    const int tn = ti + per_xcd, tnn = tn + per_xcd;
+    const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
+    f32x4 acc[4][2];
+    bf16x8 Bb[PD + 1][2];
+
+    // one layer over NR input rows of src (pitch IW) into NO = NR - 2 output
+    // rows; ep(o) takes output row o's finished accumulators.  pf(stage)
+    // issues the global loads placed at that stage.
+    // base[m][kh]: the lane's part of the swizzled address of chunk 4kh + g
+    // of window pixel c + l16 for any c = m (mod 8): rr_off(c + l16, 4kh + g)
+    // = 128 c + base[m][kh], so every B read is a base plus an immediate
+    auto layer = [&](const int (&base)[8][2], const bf16x8 *W, auto NRc, auto BIc, auto ep,
+                     auto pf) {
+      constexpr int NR = decltype(NRc)::value, NO = NR - 2, NSTG = NR * NIT;
+      constexpr int BI = decltype(BIc)::value;          // bias row in LDS
+      auto load_b = [&](auto stc) {
+        constexpr int stg = decltype(stc)::value;
+        constexpr int ir = stg / NIT, it = stg % NIT, dx = it >> 1, kh = it & 1;
+        static_for<0, 2>([&](auto hc) {
+          constexpr int c = ir * IW + 16 * decltype(hc)::value + dx;
+          Bb[stg % (PD + 1)][decltype(hc)::value] =
+              *reinterpret_cast<const bf16x8 *>(lds + base[c & 7][kh] + 128 * c);
+        });
+      };
+      static_for<0, PD>(load_b);
+      static_for<0, NSTG>([&](auto stc) {
+        constexpr int stg = decltype(stc)::value;
+        constexpr int ir = stg / NIT, it = stg % NIT, dx = it >> 1, kh = it & 1;
+        if constexpr (stg + PD < NSTG) load_b(std::integral_constant<int, stg + PD>{});
+        pf(stc);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (it == 0 && ir < NO) {
+          const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + BI * Lo::F + 16 * wave + 4 * g);
+          acc[ir & 3][0] = bia;
+          acc[ir & 3][1] = bia;
+        }
+        static_for<0, 3>([&](auto dyc) {
+          constexpr int dy = decltype(dyc)::value, o = ir - dy;
+          if constexpr (o >= 0 && o < NO) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              acc[o & 3][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  W[(3 * dy + dx) * 2 + kh], Bb[stg % (PD + 1)][h], acc[o & 3][h], 0, 0, 0);
+          }
+        });
+        // output row ir - 3 finished one input row ago
+        if constexpr (it == 1 && ir >= 3 && ir - 3 < NO) ep(std::integral_constant<int, ir - 3>{});
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      static_for<(NR - 3 > 0 ? NR - 3 : 0), NO>(ep);
+    };
+
+    // layer A: intermediate rows into LDS (zero outside the image)
+    auto epA = [&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      const int Y = cur.y0 - 1 + o;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int X = cur.x0 - 1 + 16 * h + l16;
+        const bool inside = (unsigned)Y < (unsigned)cur.ny && (unsigned)X < (unsigned)cur.nx;
+        const f32x4 v = acc[o & 3][h];
+        u32x2 w;
+        w.x = inside ? relu_bf16x2(pack_bf16x2(v[0], v[1])) : 0u;
+        w.y = inside ? relu_bf16x2(pack_bf16x2(v[2], v[3])) : 0u;
+        *reinterpret_cast<u32x2 *>(lds_mid + rr_off(o * IW + 16 * h + l16, 2 * wave + (g >> 1)) +
+                                   8 * (g & 1)) = w;
+      }
+    };
+    // first half of the next tile's window, a load per stage from stage 6
+    auto pfA = [&](auto stc) {
+      constexpr int stg = decltype(stc)::value;
+      if constexpr (stg >= 6 && stg < 6 + NL1) pre[stg - 6] = load_chunk(nxt, stg - 6);
+    };
+    layer(base_in, WA, std::integral_constant<int, Lo::IH>{}, std::integral_constant<int, 0>{}, epA,
+          pfA);
+    __syncthreads();                             // intermediate written, window read
+#pragma unroll
+    for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+
+    // layer B: the tile's rows to memory; lanes outside the tile (and the
+    // two padding columns) store to the trash pixel
+    auto epB = [&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = 16 * h + l16;
+        const int64_t px = (o < cur.h && c < cur.w)
+                               ? (int64_t)(cur.y0 + o + 1) * cur.apitch + (cur.x0 + c + 1)
+                               : cur.trash;
+        const f32x4 v = acc[o & 3][h];
+        u32x2 w;
+        w.x = relu_bf16x2(pack_bf16x2(v[0], v[1]));
+        w.y = relu_bf16x2(pack_bf16x2(v[2], v[3]));
+        *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + px * Lo::PIXB + 32 * wave + 8 * g) = w;
+      }
+    };
+    auto pfB = [&](auto stc) {
+      constexpr int stg = decltype(stc)::value;
+      if constexpr (stg >= 1 && stg < 1 + NL2) pre[stg - 1] = load_chunk(nxt, NL1 + stg - 1);
+    };
+    layer(base_mid, WB, std::integral_constant<int, Lo::MH>{}, std::integral_constant<int, 1>{}, epB,
+          pfB);
+#pragma unroll
+    for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+    __syncthreads();                             // next window in place, intermediate read
+    if (tn >= t_end) break;
+    cur = nxt;
+    nxt = after;
+    ti = tn;
+  }
+}
+
+// ---------------------------------------------------------------------
 // Middle layers, row-reuse form for e4m3 input (F = 64; output e4m3 or
 // bf16).  v_mfma_scale_f32_16x16x128_f8f6f4 takes K = 128 = two taps of 64
 // channels: lane groups 0-1 carry one tap, groups 2-3 another.  Pairing the
@@ -1433,6 +1672,27 @@ hipError_t launch_conv_mid_last(const ConvArgs &a, int n_wg, bool first, hipStre
 
 hipError_t launch_g_from_s(const ConvArgs &a, int n_tiles, hipStream_t s) {
   hipLaunchKernelGGL(g_from_s_kernel, dim3(n_tiles), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt2, int out_fmt2,
+                  int relu2, int unit2) {
+  return PNP_MID_RR && in_fmt == FMT_BF16 && out_fmt == FMT_BF16 && F == 64 && relu && unit &&
+         in_fmt2 == FMT_BF16 && out_fmt2 == FMT_BF16 && relu2 && unit2;
+}
+
+hipError_t launch_conv_pair(const ConvArgs &a, int n_wg, hipStream_t s) {
+  if (!a.wblob || !a.wblob2 || !a.bias || !a.bias2 || n_wg <= 0 || n_wg % 8 != 0)
+    return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_pair_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       PairLayout::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(conv_pair_kernel, dim3(n_wg), dim3(256), PairLayout::LDS_BYTES, s, a);
   return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@ constexpr int kMaxR = 8;           // largest blur half-width (L <= 17)
 constexpr int kUpdTileH = 16;      // fused-update tile (rows x cols)
 constexpr int kUpdTileW = 64;
 constexpr int kConvTileW = 32;     // convolution tiles are TH x 32 pixels
+constexpr int kPairTileH = 14;     // two-layer middle kernel: output tiles of 14 x 30
+constexpr int kPairTileW = 30;
 
 // One chain resident on the device.  All images live in padded row-major
 // buffers whose zero border is never written, so stencils read it as the

@@ -57,6 +57,7 @@ struct Job {
   size_t footprint = 0;
   std::vector<void *> allocs;
   std::vector<TileRef> conv_tiles, upd_tiles;   // job field = 0 (set at planning)
+  std::vector<TileRef> pair_tiles;              // two-layer kernel: whole-image tiling
 };
 
 struct ProfileRec {
@@ -105,20 +106,23 @@ class Engine {
   Status run_denoiser(int64_t tick);
   bool first_mid_fused() const;
   Status launch_first_mid(int64_t tick, bool prof);
-  Status launch_mid_last(int k, int64_t tick, bool first, bool prof);
+  Status launch_mid_last(int k, int in_slot, int64_t tick, bool first, bool prof);
+  Status launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof);
+  bool pair_ok(int k) const;
   Status launch_g_from_s(int64_t tick, bool prof);
   Status run_fused_denoiser(int64_t tick, bool prof);
-  Status launch_layer(int k, int64_t tick, bool prof);
+  Status launch_layer(int k, int64_t tick, bool prof, int in_slot = -1, int out_slot = -1);
   JobDesc *d_jobs = nullptr;
-  TileRef *d_conv = nullptr, *d_upd = nullptr;
-  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0;
-  int n_conv = 0, n_upd = 0, max_r = 0;
+  TileRef *d_conv = nullptr, *d_upd = nullptr, *d_pair = nullptr;
+  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0, cap_pair = 0;
+  int n_conv = 0, n_upd = 0, n_pair = 0, max_r = 0;
   int conv_th = 16;
   bool profiling = false;
   std::vector<ProfileRec> prof_pending;
   std::vector<hipEvent_t> prof_free;
-  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
-  int64_t prof_n[6] = {0, 0, 0, 0, 0, 0};
+  static constexpr int kProfClasses = 7;
+  double prof_ms[kProfClasses] = {};
+  int64_t prof_n[kProfClasses] = {};
   void prof_begin(int cls, ProfileRec *r);
   void prof_end(ProfileRec *r);
 };

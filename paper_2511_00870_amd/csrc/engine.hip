@@ -82,6 +82,7 @@ Engine::~Engine() {
   hipFree(d_jobs);
   hipFree(d_conv);
   hipFree(d_upd);
+  hipFree(d_pair);
   for (auto &r : prof_pending) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
@@ -552,6 +553,9 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   j->t = 0;
   make_tiles(j->conv_tiles, ny, nx, j->block_y, j->block_x, conv_th, kConvTileW);
   make_tiles(j->upd_tiles, ny, nx, j->block_y, j->block_x, kUpdTileH, kUpdTileW);
+  // the two-layer kernel tiles the whole image: every block of one job lives
+  // in one set of activation buffers, so block edges need no tile edge
+  make_tiles(j->pair_tiles, ny, nx, ny, nx, kPairTileH, kPairTileW);
   if (hipStreamSynchronize(stream) != hipSuccess)
     return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
   *out = j;
@@ -568,7 +572,7 @@ void Engine::free_job(Job *j) {
 // plans
 // ---------------------------------------------------------------------
 Status Engine::rebuild_plan() {
-  std::vector<TileRef> conv, upd;
+  std::vector<TileRef> conv, upd, pair;
   max_r = 0;
   for (size_t ji = 0; ji < resident.size(); ++ji) {
     Job *j = resident[ji];
@@ -579,6 +583,10 @@ Status Engine::rebuild_plan() {
     for (TileRef t : j->upd_tiles) {
       t.job = (int)ji;
       upd.push_back(t);
+    }
+    for (TileRef t : j->pair_tiles) {
+      t.job = (int)ji;
+      pair.push_back(t);
     }
     max_r = std::max(max_r, j->d.r);
   }
@@ -598,12 +606,16 @@ Status Engine::rebuild_plan() {
   HIPOK(hipStreamSynchronize(stream));
   TRY(grow(&d_conv, cap_conv, std::max<size_t>(conv.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_upd, cap_upd, std::max<size_t>(upd.size(), 1), sizeof(TileRef)));
+  TRY(grow(&d_pair, cap_pair, std::max<size_t>(pair.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_jobs, cap_jobs, std::max<size_t>(resident.size(), 1), sizeof(JobDesc)));
   if (!conv.empty())
     HIPOK(hipMemcpyAsync(d_conv, conv.data(), conv.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
   if (!upd.empty())
     HIPOK(hipMemcpyAsync(d_upd, upd.data(), upd.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
+  if (!pair.empty())
+    HIPOK(hipMemcpyAsync(d_pair, pair.data(), pair.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
   n_conv = (int)conv.size();
+  n_pair = (int)pair.size();
   n_upd = (int)upd.size();
   plan_dirty = false;
   return upload_descs();
@@ -633,7 +645,7 @@ void Engine::profile_enable(bool on) {
     prof_free.push_back(r.b);
   }
   prof_pending.clear();
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < kProfClasses; ++i) {
     prof_ms[i] = 0;
     prof_n[i] = 0;
   }
@@ -662,7 +674,7 @@ void Engine::prof_end(ProfileRec *r) {
 }
 
 Status Engine::profile_read(int cls, double *ms, int64_t *launches) {
-  if (cls < 0 || cls > 5) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..5");
+  if (cls < 0 || cls >= kProfClasses) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..6");
   HIPOK(hipStreamSynchronize(stream));
   for (auto &r : prof_pending) {
     float e = 0;
@@ -684,7 +696,7 @@ Status Engine::profile_read(int cls, double *ms, int64_t *launches) {
 // ---------------------------------------------------------------------
 // launch layer k of the denoiser over all resident jobs' tiles, reading and
 // writing the activation buffers assigned to it when the network was set
-Status Engine::launch_layer(int k, int64_t tick, bool prof) {
+Status Engine::launch_layer(int k, int64_t tick, bool prof, int in_slot, int out_slot) {
   const int K = net.K;
   const LayerPlan &L = net.layers[k];
   ConvArgs a{};
@@ -699,8 +711,8 @@ Status Engine::launch_layer(int k, int64_t tick, bool prof) {
   a.oscale = L.oscale;
   a.in_inv_scale = L.in_inv_scale;
   a.out_inv_scale = L.out_inv_scale;
-  a.in_slot = L.in_buf;
-  a.out_slot = L.out_buf;
+  a.in_slot = in_slot >= 0 ? in_slot : L.in_buf;
+  a.out_slot = out_slot >= 0 ? out_slot : L.out_buf;
   ProfileRec pr;
   if (K == 1) {
     a.wf32 = L.wf32;
@@ -768,7 +780,7 @@ Status Engine::launch_first_mid(int64_t tick, bool prof) {
 }
 
 // middle layer k writing the last layer's per-tap partials (JobDesc::S)
-Status Engine::launch_mid_last(int k, int64_t tick, bool first, bool prof) {
+Status Engine::launch_mid_last(int k, int in_slot, int64_t tick, bool first, bool prof) {
   const LayerPlan &L = net.layers[k], &LL = net.layers[net.K - 1];
   ConvArgs a{};
   a.jobs = d_jobs;
@@ -780,7 +792,7 @@ Status Engine::launch_mid_last(int k, int64_t tick, bool first, bool prof) {
   a.unit_scale = L.unit_scale;
   a.bias = L.bias;
   a.oscale = L.oscale;
-  a.in_slot = L.in_buf;
+  a.in_slot = in_slot >= 0 ? in_slot : L.in_buf;
   a.out_slot = L.out_buf;
   a.wblob = L.wblob;
   a.last_w = LL.wf32;
@@ -793,6 +805,40 @@ Status Engine::launch_mid_last(int k, int64_t tick, bool first, bool prof) {
   ProfileRec pr;
   if (prof) prof_begin(5, &pr);
   HIPOK(launch_conv_mid_last(a, n_wg, first, stream));
+  if (prof) prof_end(&pr);
+  return Status::ok();
+}
+
+// middle layers k and k+1 in one kernel (bf16, 64 channels, ReLU, unit
+// output scales), reading activation buffer in_slot and writing out_slot
+bool Engine::pair_ok(int k) const {
+  if (k < 1 || k + 1 > net.K - 2) return false;
+  const LayerPlan &A = net.layers[k], &B = net.layers[k + 1];
+  return pair_fusable(A.in_fmt, A.out_fmt, net.F, A.relu, A.unit_scale, B.in_fmt, B.out_fmt,
+                      B.relu, B.unit_scale);
+}
+
+Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof) {
+  const LayerPlan &A = net.layers[k], &B = net.layers[k + 1];
+  ConvArgs a{};
+  a.jobs = d_jobs;
+  a.tiles = d_pair;
+  a.n_tiles = n_pair;
+  a.tick = tick;
+  a.relu = 1;
+  a.unit_scale = 1;
+  a.in_slot = in_slot;
+  a.out_slot = out_slot;
+  a.wblob = A.wblob;
+  a.bias = A.bias;
+  a.oscale = A.oscale;
+  a.wblob2 = B.wblob;
+  a.bias2 = B.bias;
+  const int need = ((n_pair + 7) / 8) * 8;
+  const int n_wg = std::max(8, std::min(n_cu, need) / 8 * 8);
+  ProfileRec pr;
+  if (prof) prof_begin(6, &pr);
+  HIPOK(launch_conv_pair(a, n_wg, stream));
   if (prof) prof_end(&pr);
   return Status::ok();
 }
@@ -820,17 +866,41 @@ Status Engine::launch_g_from_s(int64_t tick, bool prof) {
 Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
   const int K = net.K;
   const bool ff = first_mid_fused(), lf = net.last_fused;
+  // cur: the activation buffer holding the latest layer's output once a
+  // pair kernel has run (a pair writes the buffer its second layer would
+  // have read, so later layers follow cur instead of the per-layer plan)
+  int cur = -1;
+  auto other = [&](int slot) {
+    for (int i = 0; i < 4; ++i)
+      if (i != slot && net.buf_fmt[i] == net.buf_fmt[slot]) return i;
+    return -1;
+  };
   int k = 0;
   if (ff) {
     TRY(launch_first_mid(tick, prof));
     k = 2;
   }
   for (; k < K; ++k) {
+    const LayerPlan &L = net.layers[k];
+    const int in = cur >= 0 ? cur : L.in_buf;
     if (lf && k == K - 2) {
-      TRY(launch_mid_last(k, tick, false, prof));
+      TRY(launch_mid_last(k, in, tick, false, prof));
       return launch_g_from_s(tick, prof);
     }
-    TRY(launch_layer(k, tick, prof));
+    if (pair_ok(k) && !(lf && k + 1 == K - 2) && other(in) >= 0) {
+      const int out = other(in);
+      TRY(launch_pair(k, in, out, tick, prof));
+      cur = out;
+      ++k;
+      continue;
+    }
+    if (cur < 0) {
+      TRY(launch_layer(k, tick, prof));
+      continue;
+    }
+    const int out = (k + 1 < K && L.out_fmt == net.buf_fmt[cur]) ? other(cur) : L.out_buf;
+    TRY(launch_layer(k, tick, prof, in, out));
+    cur = k + 1 < K ? out : -1;
   }
   return Status::ok();
 }

@@ -29,6 +29,9 @@ struct ConvArgs {
   const float *first_bias;
   // last layer fused into the last middle layer: its weights [c][9]
   const float *last_w;
+  // second layer of a fused pair of middle layers: weights (fragment order), bias
+  const void *wblob2;
+  const float *bias2;
 };
 
 struct UpdateArgs {
@@ -52,6 +55,12 @@ hipError_t launch_conv_first_mid(const ConvArgs &a, int n_wg, hipStream_t s);
 // must be false: a middle layer with both fusions is not built)
 hipError_t launch_conv_mid_last(const ConvArgs &a, int n_wg, bool first, hipStream_t s);
 // G = sum over taps of the partials at the tap's neighbour, plus the bias
+// two consecutive bf16 middle layers in one kernel (a: the first layer's
+// arguments plus wblob2 / bias2; tiles of kPairTileH x kPairTileW); n_wg a
+// positive multiple of 8
+hipError_t launch_conv_pair(const ConvArgs &a, int n_wg, hipStream_t s);
+bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt2, int out_fmt2,
+                  int relu2, int unit2);
 hipError_t launch_g_from_s(const ConvArgs &a, int n_tiles, hipStream_t s);
 bool mid_last_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int last_in_fmt,
                       int last_cin, int last_cout);

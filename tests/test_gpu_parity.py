@@ -166,6 +166,39 @@ def test_first_layer_fused_matches_per_layer_path(shape, block):
     assert e_f <= 5e-3 and e_l <= 5e-3 and e_fl <= 5e-3
 
 
+@pytest.mark.parametrize("shape,block", [((5, 7), 32), ((28, 60), 64), ((53, 83), 32),
+                                         ((150, 190), 64), ((403, 371), 128)])
+def test_layer_pairs_match_per_layer_path(shape, block):
+    """bf16, 8 layers: the sampler's path (first layer fused into the first
+    middle layer, the next middle layers two per kernel on whole-image 14x30
+    tiles, the last layer's partials fused into the last middle layer) against
+    the layer-by-layer path and the emulating oracle.  Shapes: smaller than
+    one tile, exact multiples of the tile, ragged, and several tiles per
+    workgroup of the persistent kernel."""
+    ny, nx = shape
+    say(f"case layer pairs {ny}x{nx} block={block}")
+    K = 8
+    ch, ws, bs = W.denoiser_weights(K, 64, seed=13)
+    x = W.synthetic_image(ny, nx, 37)
+    fmt = W.layer_formats(K, P.PNPULA_BF16)
+    wl = W.make_workload("p", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=block, halo=8,
+                         n_layers=K, features=64, precision=P.PNPULA_BF16, iters=1, burn_in=0,
+                         seed=5)
+    wl.channels, wl.weights, wl.biases = ch, ws, bs
+    ctx = P.Context(P.Config.from_workload(wl))
+    G_fused = ctx.denoise(x.astype(np.float32))
+    G_layers, _ = ctx.denoise(x.astype(np.float32), layers=True)
+    e_fl = rel(G_fused, G_layers)
+    if ny * nx <= 150 * 190:
+        ref, _ = O.denoiser_layers(O.Net(ch, ws, bs, fmt, [1.0] * K), x)
+        e_f, e_l = rel(G_fused, ref[-1][0]), rel(G_layers, ref[-1][0])
+    else:
+        e_f = e_l = 0.0                                  # per-layer path checked above
+    say(f"  fused {e_f:.2e}  per-layer {e_l:.2e}  fused vs per-layer {e_fl:.2e}")
+    assert np.all(np.isfinite(G_fused))
+    assert e_f <= 5e-3 and e_l <= 5e-3 and e_fl <= 5e-3
+
+
 # -------------------------------------------------------- one iteration
 def _parity_run(wl, n_steps, block=None, label=""):
     say(f"case step parity {label}: {wl.ny}x{wl.nx} L={wl.kernel.shape[0]} "
