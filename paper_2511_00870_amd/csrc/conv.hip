@@ -44,6 +44,9 @@
 #ifndef PNP_MID_RR
 #define PNP_MID_RR 1
 #endif
+#ifndef PNP_PAIR_IGLP
+#define PNP_PAIR_IGLP 4   // two-layer kernel: vector ops placed after each MFMA (0: none)
+#endif
 #ifndef PNP_RR_PD
 #define PNP_RR_PD 3
 #endif
@@ -1195,56 +1198,80 @@ void conv_pair_kernel(ConvArgs a) {
   for (int i = tid; i < Lo::MID_BYTES / 16; i += NT)
     reinterpret_cast<u32x4 *>(lds_mid)[i] = u32x4{0u, 0u, 0u, 0u};
 
-  // chunk i of this lane's share of a window (16 bytes); window pixel (r, c)
-  // is image pixel (y0 - 2 + r, x0 - 2 + c), and positions beyond the
-  // one-pixel zero border read the border.  Lanes past the window load chunk
-  // 0 and store it again (the bytes its owner stores).  The empty asm keeps
-  // the compiler from holding every chunk's lane offsets across the tile loop.
-  auto load_chunk = [&](const MidTile &c, int i) -> u32x4 {
-    int q0 = tid + i * NT;
-    asm volatile("" : "+v"(q0));
-    const int q = q0 < Lo::NCHUNK ? q0 : 0;
-    const int pix = q / Lo::CPP, k = q % Lo::CPP;
-    const int r = pix / IW, col = pix % IW;
-    const int Y = min(max(c.y0 - 2 + r, -1), c.ny), X = min(max(c.x0 - 2 + col, -1), c.nx);
-    return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
-        c.in + ((int64_t)(Y + 1) * c.apitch + (X + 1)) * Lo::PIXB + k * 16);
+  // Window loads, 16 bytes per lane: load r < IH is window row r, lane
+  // (c = tid / 8, k = tid % 8) taking chunk k of column c < 32; the last two
+  // loads take the 36 pixels of columns 32 and 33 (lanes past them repeat
+  // one, storing the bytes its owner stores).  Window pixel (r, c) is image
+  // pixel (y0 - 2 + r, x0 - 2 + c); positions beyond the one-pixel zero
+  // border read the border.  A row load's address is a scalar row part plus
+  // a per-tile lane part (lane_col).
+  const int lc = tid >> 3, lk = tid & 7;
+  auto lane_col = [&](const MidTile &c) -> uint32_t {
+    const int X = min(max(c.x0 - 2 + lc, -1), c.nx) + 1;
+    return (uint32_t)X * Lo::PIXB + (uint32_t)lk * 16u;
   };
-  auto put_chunk = [&](int i, const u32x4 &v) {
-    int q0 = tid + i * NT;
-    asm volatile("" : "+v"(q0));
-    const int q = q0 < Lo::NCHUNK ? q0 : 0;
-    *reinterpret_cast<u32x4 *>(lds_in + rr_off(q / Lo::CPP, q % Lo::CPP)) = v;
+  auto load_chunk = [&](const MidTile &c, uint32_t lcol, auto ic) -> u32x4 {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (i < Lo::IH) {
+      const int Y = min(max(c.y0 - 2 + i, -1), c.ny) + 1;
+      return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+          c.in + (int64_t)Y * c.apitch * Lo::PIXB + lcol);
+    } else {
+      const int e = i == Lo::IH ? lc : 32 + (lc & 3);
+      const int Y = min(max(c.y0 - 2 + (e >> 1), -1), c.ny) + 1;
+      const int X = min(max(c.x0 + 30 + (e & 1), -1), c.nx) + 1;
+      return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+          c.in + ((int64_t)Y * c.apitch + X) * Lo::PIXB + lk * 16);
+    }
   };
+  auto put_chunk = [&](auto ic, const u32x4 &v) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (i < Lo::IH) {
+      // pixel i*IW + lc: its low three bits are (2i + lc) mod 8
+      const int off = (lc << 7) + ((lk ^ ((2 * (i & 3) + lc) & 7)) << 4);
+      *reinterpret_cast<u32x4 *>(lds_in + i * IW * Lo::PIXB + off) = v;
+    } else {
+      const int e = i == Lo::IH ? lc : 32 + (lc & 3);
+      *reinterpret_cast<u32x4 *>(lds_in + rr_off((e >> 1) * IW + 32 + (e & 1), lk)) = v;
+    }
+  };
+  static_assert(Lo::IW == 34 && Lo::NLOAD == Lo::IH + 2, "window load mapping");
 
   int ti = t_begin + slot;
   if (ti >= t_end) return;                       // uniform over the workgroup
   MidTile cur = mid_tile(a, ti);
   MidTile nxt = mid_tile(a, ti + per_xcd < t_end ? ti + per_xcd : t_begin);
   u32x4 pre[NL2];
-#pragma unroll
-  for (int i = 0; i < NL1; ++i) pre[i] = load_chunk(cur, i);
-#pragma unroll
-  for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
-#pragma unroll
-  for (int i = 0; i < NL2; ++i) pre[i] = load_chunk(cur, NL1 + i);
-#pragma unroll
-  for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+  {
+    const uint32_t lcol = lane_col(cur);
+    static_for<0, NL1>([&](auto ic) { pre[decltype(ic)::value] = load_chunk(cur, lcol, ic); });
+    static_for<0, NL1>([&](auto ic) { put_chunk(ic, pre[decltype(ic)::value]); });
+    static_for<0, NL2>([&](auto ic) {
+      pre[decltype(ic)::value] =
+          load_chunk(cur, lcol, std::integral_constant<int, NL1 + decltype(ic)::value>{});
+    });
+    static_for<0, NL2>([&](auto ic) {
+      put_chunk(std::integral_constant<int, NL1 + decltype(ic)::value>{}, pre[decltype(ic)::value]);
+    });
+  }
   __syncthreads();
   int base_in[8][2], base_mid[8][2];
 #pragma unroll
   for (int m = 0; m < 8; ++m)
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
-      int v = 128 * l16 + (((4 * kh + g) ^ ((m + l16) & 7)) << 4);
-      asm volatile("" : "+v"(v));               // keep as a register, not re-derived
+      // opaque registers: folded back into the immediates, the intermediate's
+      // offsets would exceed the 16-bit LDS offset field
+      int v = 128 * l16 + (((4 * kh + g) ^ ((m + l16) & 7)) << 4), u = v + Lo::IN_BYTES;
+      asm volatile("" : "+v"(v), "+v"(u));
       base_in[m][kh] = v;
-      base_mid[m][kh] = v + Lo::IN_BYTES;
+      base_mid[m][kh] = u;
     }
 
   while (true) {
     const int tn = ti + per_xcd, tnn = tn + per_xcd;
     const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
+    const uint32_t lcol_n = lane_col(nxt);
     f32x4 acc[4][2];
     bf16x8 Bb[PD + 1][2];
 
@@ -1273,7 +1300,9 @@ void conv_pair_kernel(ConvArgs a) {
         constexpr int ir = stg / NIT, it = stg % NIT, dx = it >> 1, kh = it & 1;
         if constexpr (stg + PD < NSTG) load_b(std::integral_constant<int, stg + PD>{});
         pf(stc);
+#if !PNP_PAIR_IGLP
         __builtin_amdgcn_sched_barrier(0);
+#endif
         if constexpr (it == 0 && ir < NO) {
           const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + BI * Lo::F + 16 * wave + 4 * g);
           acc[ir & 3][0] = bia;
@@ -1290,63 +1319,92 @@ void conv_pair_kernel(ConvArgs a) {
         });
         // output row ir - 3 finished one input row ago
         if constexpr (it == 1 && ir >= 3 && ir - 3 < NO) ep(std::integral_constant<int, ir - 3>{});
+#if PNP_PAIR_IGLP
+        // one wave per SIMD issues in order: place the stage's LDS reads, the
+        // global load and the epilogue's vector work between its MFMAs, where
+        // they issue while the matrix core is busy
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global load
+        static_for<0, 4>([&](auto) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, PNP_PAIR_IGLP, 0);   // VALU
+          __builtin_amdgcn_sched_group_barrier(0x240, 1, 0); // LDS write / global store
+        });
+#endif
         __builtin_amdgcn_sched_barrier(0);
       });
       static_for<(NR - 3 > 0 ? NR - 3 : 0), NO>(ep);
     };
 
-    // layer A: intermediate rows into LDS (zero outside the image)
-    auto epA = [&](auto oc) {
+    // Both layers' epilogues round a row's two blocks to bf16 with ReLU and
+    // then swap halves between neighbouring 16-lane rows (v_permlane16_swap):
+    // lanes of even rows end up with 8 channels of a block-0 pixel, lanes of
+    // odd rows with 8 channels of a block-1 pixel, so each lane stores one
+    // whole 16-byte chunk (half as many stores as 8-byte pieces).
+    auto pack_row = [&](auto oc) -> u32x4 {
       constexpr int o = decltype(oc)::value;
-      const int Y = cur.y0 - 1 + o;
+      u32x2 w[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int X = cur.x0 - 1 + 16 * h + l16;
-        const bool inside = (unsigned)Y < (unsigned)cur.ny && (unsigned)X < (unsigned)cur.nx;
         const f32x4 v = acc[o & 3][h];
-        u32x2 w;
-        w.x = inside ? relu_bf16x2(pack_bf16x2(v[0], v[1])) : 0u;
-        w.y = inside ? relu_bf16x2(pack_bf16x2(v[2], v[3])) : 0u;
-        *reinterpret_cast<u32x2 *>(lds_mid + rr_off(o * IW + 16 * h + l16, 2 * wave + (g >> 1)) +
-                                   8 * (g & 1)) = w;
+        w[h].x = relu_bf16x2(pack_bf16x2(v[0], v[1]));
+        w[h].y = relu_bf16x2(pack_bf16x2(v[2], v[3]));
       }
+      const auto sx = __builtin_amdgcn_permlane16_swap(w[0].x, w[1].x, false, false);
+      const auto sy = __builtin_amdgcn_permlane16_swap(w[0].y, w[1].y, false, false);
+      return u32x4{sx[0], sy[0], sx[1], sy[1]};
+    };
+    const int hb = g & 1;                        // block of this lane's pixel after the swap
+    const int cpos = 16 * hb + l16;              // its column in the tile
+
+    // layer A: intermediate rows into LDS (zero outside the image)
+    const bool in_x = (unsigned)(cur.x0 - 1 + cpos) < (unsigned)cur.nx;
+    auto epA = [&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      const bool in_y = (unsigned)(cur.y0 - 1 + o) < (unsigned)cur.ny;     // uniform
+      u32x4 q = pack_row(oc);
+      if (!(in_y && in_x)) q = u32x4{0u, 0u, 0u, 0u};
+      // pixel o*IW + cpos: o*IW = 2o (mod 8) moves the swizzle by the row
+      *reinterpret_cast<u32x4 *>(lds_mid + rr_off(o * IW + cpos, 2 * wave + (g >> 1))) = q;
     };
     // first half of the next tile's window, a load per stage from stage 6
     auto pfA = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
-      if constexpr (stg >= 6 && stg < 6 + NL1) pre[stg - 6] = load_chunk(nxt, stg - 6);
+      if constexpr (stg >= 6 && stg < 6 + NL1)
+        pre[stg - 6] = load_chunk(nxt, lcol_n, std::integral_constant<int, stg - 6>{});
     };
     layer(base_in, WA, std::integral_constant<int, Lo::IH>{}, std::integral_constant<int, 0>{}, epA,
           pfA);
     __syncthreads();                             // intermediate written, window read
-#pragma unroll
-    for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+    static_for<0, NL1>([&](auto ic) { put_chunk(ic, pre[decltype(ic)::value]); });
 
     // layer B: the tile's rows to memory; lanes outside the tile (and the
     // two padding columns) store to the trash pixel
+    PNP_GLOBAL uint8_t *const trash_p = cur.out + cur.trash * Lo::PIXB + 32 * wave + 16 * (g >> 1);
+    const bool ok_c = cpos < cur.w;
+    PNP_GLOBAL uint8_t *const col_p =
+        cur.out + (int64_t)(cur.x0 + cpos + 1) * Lo::PIXB + 32 * wave + 16 * (g >> 1);
     auto epB = [&](auto oc) {
       constexpr int o = decltype(oc)::value;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = 16 * h + l16;
-        const int64_t px = (o < cur.h && c < cur.w)
-                               ? (int64_t)(cur.y0 + o + 1) * cur.apitch + (cur.x0 + c + 1)
-                               : cur.trash;
-        const f32x4 v = acc[o & 3][h];
-        u32x2 w;
-        w.x = relu_bf16x2(pack_bf16x2(v[0], v[1]));
-        w.y = relu_bf16x2(pack_bf16x2(v[2], v[3]));
-        *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + px * Lo::PIXB + 32 * wave + 8 * g) = w;
-      }
+      const bool ok_r = o < cur.h;                                         // uniform
+      const int64_t roff = (int64_t)(cur.y0 + o + 1) * cur.apitch * Lo::PIXB;
+      const u32x4 q = pack_row(oc);
+      PNP_GLOBAL uint8_t *p = (ok_r && ok_c) ? col_p + roff : trash_p;
+      *reinterpret_cast<PNP_GLOBAL u32x4 *>(p) = q;
     };
     auto pfB = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
-      if constexpr (stg >= 1 && stg < 1 + NL2) pre[stg - 1] = load_chunk(nxt, NL1 + stg - 1);
+      if constexpr (stg >= 1 && stg < 1 + NL2)
+        pre[stg - 1] = load_chunk(nxt, lcol_n, std::integral_constant<int, NL1 + stg - 1>{});
     };
     layer(base_mid, WB, std::integral_constant<int, Lo::MH>{}, std::integral_constant<int, 1>{}, epB,
           pfB);
-#pragma unroll
-    for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+    static_for<0, NL2>([&](auto ic) {
+      put_chunk(std::integral_constant<int, NL1 + decltype(ic)::value>{}, pre[decltype(ic)::value]);
+    });
     __syncthreads();                             // next window in place, intermediate read
     if (tn >= t_end) break;
     cur = nxt;
