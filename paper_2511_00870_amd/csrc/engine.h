@@ -116,6 +116,7 @@ class Engine {
   TileRef *d_conv = nullptr, *d_upd = nullptr, *d_pair = nullptr;
   size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0, cap_pair = 0;
   int n_conv = 0, n_upd = 0, n_pair = 0, max_r = 0;
+  bool uniform_r = true;      // every resident job has blur half-width max_r
   int conv_th = 16;
   bool profiling = false;
   std::vector<ProfileRec> prof_pending;

@@ -574,6 +574,7 @@ void Engine::free_job(Job *j) {
 Status Engine::rebuild_plan() {
   std::vector<TileRef> conv, upd, pair;
   max_r = 0;
+  uniform_r = true;
   for (size_t ji = 0; ji < resident.size(); ++ji) {
     Job *j = resident[ji];
     for (TileRef t : j->conv_tiles) {
@@ -588,6 +589,7 @@ Status Engine::rebuild_plan() {
       t.job = (int)ji;
       pair.push_back(t);
     }
+    if (ji > 0 && j->d.r != max_r) uniform_r = false;
     max_r = std::max(max_r, j->d.r);
   }
   auto grow = [&](auto **p, size_t &cap, size_t need, size_t elem) -> Status {
@@ -918,7 +920,7 @@ Status Engine::tick() {
   u.tick = ticks;
   ProfileRec pr;
   prof_begin(3, &pr);
-  HIPOK(launch_fused_update(u, n_upd, max_r, stream));
+  HIPOK(launch_fused_update(u, n_upd, max_r, uniform_r, stream));
   prof_end(&pr);
   ticks += 1;
   for (Job *j : resident) j->t += 1;

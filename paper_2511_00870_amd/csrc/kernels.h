@@ -72,7 +72,9 @@ hipError_t launch_conv_first(int in_fmt, int out_fmt, int F, const ConvArgs &a, 
                              hipStream_t s);
 hipError_t launch_conv_last(int in_fmt, int F, const ConvArgs &a, int n_tiles, hipStream_t s);
 hipError_t launch_conv_single(const ConvArgs &a, int n_tiles, hipStream_t s);
-hipError_t launch_fused_update(const UpdateArgs &a, int n_tiles, int max_r, hipStream_t s);
+// uniform_r: every resident job's blur half-width equals max_r
+hipError_t launch_fused_update(const UpdateArgs &a, int n_tiles, int max_r, bool uniform_r,
+                               hipStream_t s);
 hipError_t launch_amax(const float *p, size_t n, uint32_t *out, hipStream_t s);
 hipError_t launch_welford_flush(const JobDesc &j, double n_a, double n_b, hipStream_t s);
 

@@ -22,17 +22,21 @@
 
 namespace pnp {
 
+// RT > 0: every tile's blur half-width is RT (window sizes, divisions and
+// tap loops become compile-time constants); RT = 0: read per job.
+template <int RT>
 __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
-  const int r = j.r, L = 2 * r + 1;
+  const int r = RT > 0 ? RT : j.r, L = 2 * r + 1;
   constexpr int TH = kUpdTileH, TW = kUpdTileW;
-  // per-thread register budgets (r <= kMaxR): residual region and core
-  constexpr int RQ = ((TH + 2 * kMaxR) * (TW + 2 * kMaxR) + 255) / 256;
+  // per-thread register budgets (r <= RM): residual region and core
+  constexpr int RM = RT > 0 ? RT : kMaxR;
+  constexpr int RQ = ((TH + 2 * RM) * (TW + 2 * RM) + 255) / 256;
   constexpr int CQ = TH * TW / 256;
-  constexpr int XQ = ((TH + 4 * kMaxR) * (TW + 4 * kMaxR) + 255) / 256;
+  constexpr int XQ = ((TH + 4 * RM) * (TW + 4 * RM) + 255) / 256;
   const int WH = TH + 4 * r, WW = TW + 4 * r;       // x window
   const int RH = TH + 2 * r, RW = TW + 2 * r;       // K x / residual region
   float *sx = smem;                                  // WH x WW
@@ -277,17 +281,31 @@ size_t update_lds_bytes(int r) {
                           (size_t)RH * TW + (size_t)TH * TW);
 }
 
-hipError_t launch_fused_update(const UpdateArgs &a, int n_tiles, int max_r, hipStream_t s) {
+template <int RT>
+static hipError_t launch_update_t(const UpdateArgs &a, int n_tiles, int max_r, hipStream_t s) {
   const size_t lds = update_lds_bytes(max_r);
   static size_t attr = 0;
   if (lds > attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_update_kernel),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_update_kernel<RT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = lds;
   }
-  hipLaunchKernelGGL(fused_update_kernel, dim3(n_tiles), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((fused_update_kernel<RT>), dim3(n_tiles), dim3(256), lds, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_fused_update(const UpdateArgs &a, int n_tiles, int max_r, bool uniform_r,
+                               hipStream_t s) {
+  if (uniform_r) {
+    switch (max_r) {                             // the blur sizes 5, 7 and 9
+      case 2: return launch_update_t<2>(a, n_tiles, max_r, s);
+      case 3: return launch_update_t<3>(a, n_tiles, max_r, s);
+      case 4: return launch_update_t<4>(a, n_tiles, max_r, s);
+      default: break;
+    }
+  }
+  return launch_update_t<0>(a, n_tiles, max_r, s);
 }
 
 hipError_t launch_welford_flush(const JobDesc &j, double n_a, double n_b, hipStream_t s) {
