@@ -1360,13 +1360,17 @@ void conv_pair_kernel(ConvArgs a) {
     const int hb = g & 1;                        // block of this lane's pixel after the swap
     const int cpos = 16 * hb + l16;              // its column in the tile
 
+    // Epilogue selections are bit masks, not branches: a branch would end
+    // the scheduling region and leave the epilogue's dependent chain with no
+    // MFMAs to issue beside it.
     // layer A: intermediate rows into LDS (zero outside the image)
-    const bool in_x = (unsigned)(cur.x0 - 1 + cpos) < (unsigned)cur.nx;
+    const uint32_t in_x = (unsigned)(cur.x0 - 1 + cpos) < (unsigned)cur.nx ? ~0u : 0u;
     auto epA = [&](auto oc) {
       constexpr int o = decltype(oc)::value;
-      const bool in_y = (unsigned)(cur.y0 - 1 + o) < (unsigned)cur.ny;     // uniform
+      const uint32_t in_y = (unsigned)(cur.y0 - 1 + o) < (unsigned)cur.ny ? ~0u : 0u;  // uniform
+      const uint32_t keep = in_y & in_x;
       u32x4 q = pack_row(oc);
-      if (!(in_y && in_x)) q = u32x4{0u, 0u, 0u, 0u};
+      q &= u32x4{keep, keep, keep, keep};
       // pixel o*IW + cpos: o*IW = 2o (mod 8) moves the swizzle by the row
       *reinterpret_cast<u32x4 *>(lds_mid + rr_off(o * IW + cpos, 2 * wave + (g >> 1))) = q;
     };
@@ -1383,17 +1387,18 @@ void conv_pair_kernel(ConvArgs a) {
 
     // layer B: the tile's rows to memory; lanes outside the tile (and the
     // two padding columns) store to the trash pixel
-    PNP_GLOBAL uint8_t *const trash_p = cur.out + cur.trash * Lo::PIXB + 32 * wave + 16 * (g >> 1);
-    const bool ok_c = cpos < cur.w;
-    PNP_GLOBAL uint8_t *const col_p =
-        cur.out + (int64_t)(cur.x0 + cpos + 1) * Lo::PIXB + 32 * wave + 16 * (g >> 1);
+    // byte offsets from cur.out: the lane's column in row o, or the trash pixel
+    const int64_t lane_b = 32 * wave + 16 * (g >> 1);
+    const int64_t trash_b = cur.trash * Lo::PIXB + lane_b;
+    const int64_t col_b = (int64_t)(cur.x0 + cpos + 1) * Lo::PIXB + lane_b;
+    const int64_t ok_c = cpos < cur.w ? -1 : 0;
     auto epB = [&](auto oc) {
       constexpr int o = decltype(oc)::value;
-      const bool ok_r = o < cur.h;                                         // uniform
+      const int64_t ok = (o < cur.h ? -1 : 0) & ok_c;
       const int64_t roff = (int64_t)(cur.y0 + o + 1) * cur.apitch * Lo::PIXB;
       const u32x4 q = pack_row(oc);
-      PNP_GLOBAL uint8_t *p = (ok_r && ok_c) ? col_p + roff : trash_p;
-      *reinterpret_cast<PNP_GLOBAL u32x4 *>(p) = q;
+      const int64_t b = ((col_b + roff) & ok) | (trash_b & ~ok);
+      *reinterpret_cast<PNP_GLOBAL u32x4 *>(cur.out + b) = q;
     };
     auto pfB = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
