@@ -10,8 +10,9 @@ namespace pnp {
 enum Fmt : int { FMT_F32 = 0, FMT_BF16 = 1, FMT_E4M3 = 2 };
 
 constexpr int kMaxR = 8;           // largest blur half-width (L <= 17)
-constexpr int kUpdTileH = 16;      // fused-update tile (rows x cols)
+constexpr int kUpdTileH = 32;      // fused-update tile (rows x cols) and workgroup size
 constexpr int kUpdTileW = 64;
+constexpr int kUpdThreads = 512;
 constexpr int kConvTileW = 32;     // convolution tiles are TH x 32 pixels
 constexpr int kPairTileH = 14;     // two-layer middle kernel: output tiles of 14 x 30
 constexpr int kPairTileW = 30;

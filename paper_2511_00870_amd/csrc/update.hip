@@ -25,18 +25,18 @@ namespace pnp {
 // RT > 0: every tile's blur half-width is RT (window sizes, divisions and
 // tap loops become compile-time constants); RT = 0: read per job.
 template <int RT>
-__global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
+__global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
   const int r = RT > 0 ? RT : j.r, L = 2 * r + 1;
-  constexpr int TH = kUpdTileH, TW = kUpdTileW;
+  constexpr int TH = kUpdTileH, TW = kUpdTileW, NT = kUpdThreads;
   // per-thread register budgets (r <= RM): residual region and core
   constexpr int RM = RT > 0 ? RT : kMaxR;
-  constexpr int RQ = ((TH + 2 * RM) * (TW + 2 * RM) + 255) / 256;
-  constexpr int CQ = TH * TW / 256;
-  constexpr int XQ = ((TH + 4 * RM) * (TW + 4 * RM) + 255) / 256;
+  constexpr int RQ = ((TH + 2 * RM) * (TW + 2 * RM) + NT - 1) / NT;
+  constexpr int CQ = TH * TW / NT;
+  constexpr int XQ = ((TH + 4 * RM) * (TW + 4 * RM) + NT - 1) / NT;
   const int WH = TH + 4 * r, WW = TW + 4 * r;       // x window
   const int RH = TH + 2 * r, RW = TW + 2 * r;       // K x / residual region
   float *sx = smem;                                  // WH x WW
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
     const PNP_GLOBAL float *k0 = gp(sep ? j.ku : j.kern);
     const PNP_GLOBAL float *k1 = gp(sep ? j.kv : j.kern);
     const int i0 = tid < nk ? tid : 0;
-    const int i1 = sep ? i0 : (tid + 256 < nk ? tid + 256 : 0);
+    const int i1 = sep ? i0 : (tid + NT < nk ? tid + NT : 0);
     tap0 = k0[i0];
     tap1 = k1[i1];
   }
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   float xv[XQ];
 #pragma unroll
   for (int k = 0; k < XQ; ++k) {
-    const int q0 = tid + 256 * k, q = q0 < WH * WW ? q0 : 0;
+    const int q0 = tid + NT * k, q = q0 < WH * WW ? q0 : 0;
     const int i = q / WW, c = q % WW;
     xv[k] = xin[(wy + i + B) * xpitch + (wx + c + B)];
   }
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   uint32_t mraw[RQ];
 #pragma unroll
   for (int k = 0; k < RQ; ++k) {
-    const int q0 = tid + 256 * k, q = q0 < RH * RW ? q0 : 0;
+    const int q0 = tid + NT * k, q = q0 < RH * RW ? q0 : 0;
     const int Y = tl.y0 - r + q / RW, X = tl.x0 - r + q % RW;
     const int64_t pidx = (Y + B) * xpitch + (X + B);   // inside the padded buffer
     yv[k] = yb[pidx];
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   float gv[CQ], wmv[CQ], wm2v[CQ];
 #pragma unroll
   for (int k = 0; k < CQ; ++k) {
-    const int q = tid + 256 * k;
+    const int q = tid + NT * k;
     const int i = q / TW, c = q % TW;
     const int64_t p = (i < tl.h && c < tl.w) ? (int64_t)(tl.y0 + i) * j.nx + tl.x0 + c : 0;
     gv[k] = gp(j.G)[p];
@@ -118,18 +118,18 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
     }
   } else {
     if (tid < nk) skern[tid] = tap0;
-    if (tid + 256 < nk) skern[tid + 256] = tap1;
+    if (tid + NT < nk) skern[tid + NT] = tap1;
   }
 #pragma unroll
   for (int k = 0; k < XQ; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k < WH * WW && q < WH * WW) sx[q] = xv[k];
+    const int q = tid + NT * k;
+    if (NT * k < WH * WW && q < WH * WW) sx[q] = xv[k];
   }
   __syncthreads();
 
   // 2. K x on the residual region
   if (j.separable) {
-    for (int q = tid; q < WH * RW; q += 256) {
+    for (int q = tid; q < WH * RW; q += NT) {
       const int i = q / RW, c = q % RW;
       const float *row = sx + i * WW + c + 2 * r;
       float acc = 0.0f;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   const bool draw = split && t >= 1;
 #pragma unroll
   for (int k = 0; k < RQ; ++k) {
-    const int q = tid + 256 * k;
+    const int q = tid + NT * k;
     if (q >= RH * RW) break;
     const int i = q / RW, c = q % RW;
     float kx = 0.0f;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
 
   // 4. K^T res on the core
   if (j.separable) {
-    for (int q = tid; q < RH * TW; q += 256) {
+    for (int q = tid; q < RH * TW; q += NT) {
       const int i = q / TW, c = q % TW;
       const float *row = sres + i * RW + c;
       float acc = 0.0f;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void fused_update_kernel(UpdateArgs a) {
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < CQ; ++k) {
-    const int q = tid + 256 * k;
+    const int q = tid + NT * k;
     const int i = q / TW, c = q % TW;
     if (i >= tl.h || c >= tl.w) continue;
     float ktr = 0.0f;
@@ -291,7 +291,7 @@ static hipError_t launch_update_t(const UpdateArgs &a, int n_tiles, int max_r, h
     if (e != hipSuccess) return e;
     attr = lds;
   }
-  hipLaunchKernelGGL((fused_update_kernel<RT>), dim3(n_tiles), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((fused_update_kernel<RT>), dim3(n_tiles), dim3(kUpdThreads), lds, s, a);
   return hipGetLastError();
 }
 
