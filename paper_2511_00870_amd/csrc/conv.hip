@@ -1645,6 +1645,253 @@ void conv_mid_rr8_kernel(ConvArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------
+// Two consecutive e4m3 middle layers (F = 64, ReLU, e4m3 in and out) in one
+// persistent kernel: the bf16 pair kernel's tiles, order and prefetch with
+// 64-byte pixels.  v_mfma_scale_f32_16x16x128_f8f6f4 takes K = 128 = two
+// taps of 64 channels; as in the single-layer e4m3 kernel the horizontal
+// taps are paired as (dx 0, dx 1) and (dx 2, zero weights), so an input row
+// takes two steps P, each serving the three vertical taps.  Output-channel
+// scales, bias and ReLU apply in the epilogue; each layer's output is rounded
+// to e4m3 with the next layer's activation scale.  LDS pixels are 64 bytes
+// with 16 bytes of padding after every 4 pixels, which keeps the B reads of
+// 16 consecutive pixels conflict-free without a swizzle.  Both windows fit in
+// 80 KB, so two workgroups can share a CU.
+// ---------------------------------------------------------------------
+struct Pair8Layout {
+  static constexpr int F = 64, PIXB = 64, CPP = 4, NT = 256;
+  static constexpr int TH = kPairTileH, TW = kPairTileW;
+  static constexpr int MH = TH + 2, MW = TW + 2;
+  static constexpr int IH = TH + 4, IW = TW + 4;
+  static constexpr int GRP = 4 * PIXB + 16;                      // 4 pixels + padding
+  static constexpr int IN_BYTES = (IH * IW + 3) / 4 * GRP;
+  static constexpr int MID_BYTES = (MH * IW + 3) / 4 * GRP;
+  static constexpr int LDS_BYTES = IN_BYTES + MID_BYTES + 4 * F * 4;  // scale, bias per layer
+  static constexpr int NCHUNK = IH * IW * CPP, NLOAD = (NCHUNK + NT - 1) / NT;
+  static constexpr int NL1 = NLOAD / 2, NL2 = NLOAD - NL1;
+};
+static_assert(Pair8Layout::MW == 32 && Pair8Layout::LDS_BYTES <= 80 * 1024, "e4m3 pair layout");
+// LDS byte offset of pixel p in the padded e4m3 layout
+__device__ __forceinline__ constexpr int p8_off(int p) {
+  return (p >> 2) * Pair8Layout::GRP + (p & 3) * Pair8Layout::PIXB;
+}
+
+#ifndef PNP_PAIR8_WPE
+#define PNP_PAIR8_WPE 2   // waves per SIMD the e4m3 pair kernel is compiled for
+#endif
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PNP_PAIR8_WPE, PNP_PAIR8_WPE)))
+void conv_pair8_kernel(ConvArgs a) {
+  using Lo = Pair8Layout;
+  constexpr int NT = Lo::NT, IW = Lo::IW, NL1 = Lo::NL1, NL2 = Lo::NL2;
+  constexpr int NP = 2, PD = 2;                   // steps per input row; B reads ahead
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  uint8_t *lds_in = lds;
+  uint8_t *lds_mid = lds + Lo::IN_BYTES;
+  float *lds_ep = reinterpret_cast<float *>(lds_mid + Lo::MID_BYTES);  // [layer][scale | bias]
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nwg = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3;
+  const int per_xcd = (nwg - xcd + 7) >> 3;
+  const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
+  const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
+
+  // this wave's A fragments of both layers: step (P, dy), block `wave`, 32 B
+  i32x8 WA[3 * NP], WB[3 * NP];
+  {
+    const PNP_GLOBAL u32x4 *wa = gp(reinterpret_cast<const u32x4 *>(a.wblob_rr));
+    const PNP_GLOBAL u32x4 *wb = gp(reinterpret_cast<const u32x4 *>(a.wblob2));
+#pragma unroll
+    for (int s = 0; s < 3 * NP; ++s) {
+      const int i = ((s * 4 + wave) * 64 + lane) * 2;
+      const u32x4 a0 = wa[i], a1 = wa[i + 1], b0 = wb[i], b1 = wb[i + 1];
+      WA[s] = i32x8{(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+      WB[s] = i32x8{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+    }
+  }
+  {
+    const float *src = tid < 64 ? a.oscale : tid < 128 ? a.bias : tid < 192 ? a.oscale2 : a.bias2;
+    lds_ep[tid] = gp(src)[tid & 63];
+  }
+  // the intermediate's columns MW .. IW-1 are read only for the two padding
+  // output columns and never written: zero the buffer once
+  for (int i = tid; i < Lo::MID_BYTES / 16; i += NT)
+    reinterpret_cast<u32x4 *>(lds_mid)[i] = u32x4{0u, 0u, 0u, 0u};
+
+  // Window loads: load i takes pixels 64i .. 64i+63 of the window (row-major,
+  // IW per row), lane (tid / 4, chunk tid % 4); lanes past the window repeat
+  // a pixel of load 0 (storing the bytes its owner stores).  Positions beyond
+  // the one-pixel zero border read the border.
+  auto win_pix = [&](int i) {
+    int q0 = 64 * i + (tid >> 2);
+    asm volatile("" : "+v"(q0));
+    return q0 < Lo::IH * IW ? q0 : ((tid >> 2) & 31);
+  };
+  auto load_chunk = [&](const MidTile &c, int i) -> u32x4 {
+    const int q = win_pix(i);
+    const int r = q / IW, col = q % IW;
+    const int Y = min(max(c.y0 - 2 + r, -1), c.ny) + 1, X = min(max(c.x0 - 2 + col, -1), c.nx) + 1;
+    return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+        c.in + ((int64_t)Y * c.apitch + X) * Lo::PIXB + (tid & 3) * 16);
+  };
+  auto put_chunk = [&](int i, const u32x4 &v) {
+    *reinterpret_cast<u32x4 *>(lds_in + p8_off(win_pix(i)) + (tid & 3) * 16) = v;
+  };
+  static_assert(Lo::NLOAD * 64 >= Lo::IH * Lo::IW && Lo::NLOAD <= 2 * NL2, "window loads");
+
+  int ti = t_begin + slot;
+  if (ti >= t_end) return;                       // uniform over the workgroup
+  MidTile cur = mid_tile(a, ti);
+  MidTile nxt = mid_tile(a, ti + per_xcd < t_end ? ti + per_xcd : t_begin);
+  u32x4 pre[NL2];
+#pragma unroll
+  for (int i = 0; i < NL1; ++i) pre[i] = load_chunk(cur, i);
+#pragma unroll
+  for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+#pragma unroll
+  for (int i = 0; i < NL2; ++i) pre[i] = load_chunk(cur, NL1 + i);
+#pragma unroll
+  for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+  __syncthreads();
+
+  // B fragment of step P at window row ir, block h: this lane's pixel is
+  // ir*IW + 16h + dx + l16 with dx = the tap its lane group carries, 32
+  // bytes at channel 32(g&1).  ir*IW + 16h = 4m + 2(ir&1), so the address is
+  // 272m (an immediate) plus base[ir&1][P] (per lane).
+  int base_in[2][NP], base_mid[2][NP];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int P = 0; P < NP; ++P) {
+      const int dx = (g < 2) ? (P == 0 ? 0 : 2) : (P == 0 ? 1 : 2);
+      int v = p8_off(2 * s + dx + l16) + 32 * (g & 1), u = v + Lo::IN_BYTES;
+      asm volatile("" : "+v"(v), "+v"(u));
+      base_in[s][P] = v;
+      base_mid[s][P] = u;
+    }
+
+  while (true) {
+    const int tn = ti + per_xcd, tnn = tn + per_xcd;
+    const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
+    f32x4 acc[4][2];
+    i32x8 Bb[PD + 1][2];
+
+    auto layer = [&](const int (&base)[2][NP], const i32x8 *W, auto NRc, auto ep, auto pf) {
+      constexpr int NR = decltype(NRc)::value, NO = NR - 2, NSTG = NR * NP;
+      auto load_b = [&](auto stc) {
+        constexpr int stg = decltype(stc)::value;
+        constexpr int ir = stg / NP, P = stg % NP;
+        static_for<0, 2>([&](auto hc) {
+          constexpr int c = ir * IW + 16 * decltype(hc)::value;   // = 4m + 2(ir&1)
+          const uint8_t *src = lds + base[ir & 1][P] + (c >> 2) * Lo::GRP;
+          const u32x4 lo = *reinterpret_cast<const u32x4 *>(src);
+          const u32x4 hi = *reinterpret_cast<const u32x4 *>(src + 16);
+          Bb[stg % (PD + 1)][decltype(hc)::value] =
+              i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        });
+      };
+      static_for<0, PD>(load_b);
+      static_for<0, NSTG>([&](auto stc) {
+        constexpr int stg = decltype(stc)::value;
+        constexpr int ir = stg / NP, P = stg % NP;
+        if constexpr (stg + PD < NSTG) load_b(std::integral_constant<int, stg + PD>{});
+        pf(stc);
+        if constexpr (P == 0 && ir < NO) {
+          acc[ir & 3][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+          acc[ir & 3][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        static_for<0, 3>([&](auto dyc) {
+          constexpr int dy = decltype(dyc)::value, o = ir - dy;
+          if constexpr (o >= 0 && o < NO) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              acc[o & 3][h] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                  W[P * 3 + dy], Bb[stg % (PD + 1)][h], acc[o & 3][h], 0, 0, 0, 0, 0, 0);
+          }
+        });
+        // output row ir - 3 finished one input row ago
+        if constexpr (P == 0 && ir >= 3 && ir - 3 < NO) ep(std::integral_constant<int, ir - 3>{});
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      static_for<(NR - 3 > 0 ? NR - 3 : 0), NO>(ep);
+    };
+
+    // Epilogue: scale, bias, ReLU, e4m3 with the next layer's scale; then
+    // halves are swapped between neighbouring 16-lane rows so that each lane
+    // holds 8 channels (8 bytes) of one pixel: block 0's for even rows, block
+    // 1's for odd rows.
+    auto pack_row = [&](auto oc, int layer_i, float is) -> u32x2 {
+      constexpr int o = decltype(oc)::value;
+      const float *ep = lds_ep + layer_i * 2 * Lo::F;
+      const f32x4 osc = *reinterpret_cast<const f32x4 *>(ep + 16 * wave + 4 * g);
+      const f32x4 bia = *reinterpret_cast<const f32x4 *>(ep + Lo::F + 16 * wave + 4 * g);
+      uint32_t w[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f32x4 v = acc[o & 3][h];
+        // after the ReLU (fmaxf returns the non-NaN operand) no value is NaN
+        w[h] = pack_e4m3x4_nonan(fmaxf(fmaf(v[0], osc[0], bia[0]), 0.0f) * is,
+                           fmaxf(fmaf(v[1], osc[1], bia[1]), 0.0f) * is,
+                           fmaxf(fmaf(v[2], osc[2], bia[2]), 0.0f) * is,
+                           fmaxf(fmaf(v[3], osc[3], bia[3]), 0.0f) * is);
+      }
+      const auto s = __builtin_amdgcn_permlane16_swap(w[0], w[1], false, false);
+      return u32x2{s[0], s[1]};
+    };
+    const int cpos = 16 * (g & 1) + l16;         // column of this lane's pixel after the swap
+    const int cbyte = 16 * wave + 8 * (g >> 1);  // its 8 channels inside the pixel
+
+    // layer A: intermediate rows into LDS (zero outside the image)
+    const uint32_t in_x = (unsigned)(cur.x0 - 1 + cpos) < (unsigned)cur.nx ? ~0u : 0u;
+    const float isA = a.out_inv_scale, isB = a.out_inv_scale2;
+    auto epA = [&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      const uint32_t in_y = (unsigned)(cur.y0 - 1 + o) < (unsigned)cur.ny ? ~0u : 0u;  // uniform
+      const uint32_t keep = in_y & in_x;
+      u32x2 q = pack_row(oc, 0, isA);
+      q &= u32x2{keep, keep};
+      *reinterpret_cast<u32x2 *>(lds_mid + p8_off(o * IW + cpos) + cbyte) = q;
+    };
+    auto pfA = [&](auto stc) {
+      constexpr int stg = decltype(stc)::value;
+      if constexpr (stg >= 4 && stg < 4 + NL1) pre[stg - 4] = load_chunk(nxt, stg - 4);
+    };
+    layer(base_in, WA, std::integral_constant<int, Lo::IH>{}, epA, pfA);
+    __syncthreads();                             // intermediate written, window read
+#pragma unroll
+    for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+
+    // layer B: the tile's rows to memory; lanes outside the tile (and the
+    // two padding columns) store to the trash pixel
+    const int64_t trash_b = cur.trash * Lo::PIXB + cbyte;
+    const int64_t col_b = (int64_t)(cur.x0 + cpos + 1) * Lo::PIXB + cbyte;
+    const int64_t ok_c = cpos < cur.w ? -1 : 0;
+    auto epB = [&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      const int64_t ok = (o < cur.h ? -1 : 0) & ok_c;
+      const int64_t roff = (int64_t)(cur.y0 + o + 1) * cur.apitch * Lo::PIXB;
+      const u32x2 q = pack_row(oc, 1, isB);
+      const int64_t bo = ((col_b + roff) & ok) | (trash_b & ~ok);
+      *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + bo) = q;
+    };
+    auto pfB = [&](auto stc) {
+      constexpr int stg = decltype(stc)::value;
+      if constexpr (stg >= 1 && stg < 1 + NL2) pre[stg - 1] = load_chunk(nxt, NL1 + stg - 1);
+    };
+    layer(base_mid, WB, std::integral_constant<int, Lo::MH>{}, epB, pfB);
+#pragma unroll
+    for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+    __syncthreads();                             // next window in place, intermediate read
+    if (tn >= t_end) break;
+    cur = nxt;
+    nxt = after;
+    ti = tn;
+  }
+}
+
 // G from the fused last layer's partials: G(p) = scale * sum over taps of the
 // tap's partial at the neighbour the tap reads, + bias.  The records' zero
 // border supplies the zero padding at the image edge.
@@ -1756,6 +2003,30 @@ hipError_t launch_conv_pair(const ConvArgs &a, int n_wg, hipStream_t s) {
     attr_set = true;
   }
   hipLaunchKernelGGL(conv_pair_kernel, dim3(n_wg), dim3(256), PairLayout::LDS_BYTES, s, a);
+  return hipGetLastError();
+}
+
+bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
+                   int relu2) {
+  return PNP_MID_RR && in_fmt == FMT_E4M3 && out_fmt == FMT_E4M3 && F == 64 && relu &&
+         in_fmt2 == FMT_E4M3 && out_fmt2 == FMT_E4M3 && relu2;
+}
+
+int pair8_wg_per_cu() { return PNP_PAIR8_WPE; }
+
+hipError_t launch_conv_pair8(const ConvArgs &a, int n_wg, hipStream_t s) {
+  if (!a.wblob_rr || !a.wblob2 || !a.bias || !a.bias2 || !a.oscale || !a.oscale2 || n_wg <= 0 ||
+      n_wg % 8 != 0)
+    return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_pair8_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       Pair8Layout::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(conv_pair8_kernel, dim3(n_wg), dim3(256), Pair8Layout::LDS_BYTES, s, a);
   return hipGetLastError();
 }
 

@@ -188,6 +188,13 @@ __device__ __forceinline__ uint32_t pack_e4m3x4(float a, float b, float c, float
         ((uint32_t)f32_to_e4m3_sw(c) << 16) | ((uint32_t)f32_to_e4m3_sw(d) << 24);
   return r;
 }
+// four values known not to be NaN (e.g. after a ReLU taken with fmaxf,
+// which returns the non-NaN operand): no fallback branch
+__device__ __forceinline__ uint32_t pack_e4m3x4_nonan(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(a), e4m3_clamp(b), 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(c), e4m3_clamp(d), w, true);
+  return (uint32_t)w;
+}
 __device__ __forceinline__ float e4m3_to_f32(uint8_t c) {
   const uint32_t e = (c >> 3) & 15u, m = c & 7u;
   float v = (e == 0) ? (float)m * 0.001953125f                 // m 2^-9

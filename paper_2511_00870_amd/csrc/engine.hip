@@ -811,13 +811,16 @@ Status Engine::launch_mid_last(int k, int in_slot, int64_t tick, bool first, boo
   return Status::ok();
 }
 
-// middle layers k and k+1 in one kernel (bf16, 64 channels, ReLU, unit
-// output scales), reading activation buffer in_slot and writing out_slot
+// middle layers k and k+1 in one kernel (64 channels, ReLU; bf16 with unit
+// output scales, or e4m3), reading activation buffer in_slot and writing
+// out_slot
 bool Engine::pair_ok(int k) const {
   if (k < 1 || k + 1 > net.K - 2) return false;
   const LayerPlan &A = net.layers[k], &B = net.layers[k + 1];
   return pair_fusable(A.in_fmt, A.out_fmt, net.F, A.relu, A.unit_scale, B.in_fmt, B.out_fmt,
-                      B.relu, B.unit_scale);
+                      B.relu, B.unit_scale) ||
+         (pair8_fusable(A.in_fmt, A.out_fmt, net.F, A.relu, B.in_fmt, B.out_fmt, B.relu) &&
+          A.wblob_rr && B.wblob_rr);
 }
 
 Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof) {
@@ -834,13 +837,25 @@ Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool 
   a.wblob = A.wblob;
   a.bias = A.bias;
   a.oscale = A.oscale;
+  a.out_inv_scale = A.out_inv_scale;
   a.wblob2 = B.wblob;
   a.bias2 = B.bias;
+  a.oscale2 = B.oscale;
+  a.out_inv_scale2 = B.out_inv_scale;
+  const bool e4m3 = A.in_fmt == FMT_E4M3;
+  if (e4m3) {
+    a.wblob_rr = A.wblob_rr;
+    a.wblob2 = B.wblob_rr;
+  }
+  const int per_cu = e4m3 ? pair8_wg_per_cu() : 1;
   const int need = ((n_pair + 7) / 8) * 8;
-  const int n_wg = std::max(8, std::min(n_cu, need) / 8 * 8);
+  const int n_wg = std::max(8, std::min(n_cu * per_cu, need) / 8 * 8);
   ProfileRec pr;
   if (prof) prof_begin(6, &pr);
-  HIPOK(launch_conv_pair(a, n_wg, stream));
+  if (e4m3)
+    HIPOK(launch_conv_pair8(a, n_wg, stream));
+  else
+    HIPOK(launch_conv_pair(a, n_wg, stream));
   if (prof) prof_end(&pr);
   return Status::ok();
 }

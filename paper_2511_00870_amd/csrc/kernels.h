@@ -29,9 +29,12 @@ struct ConvArgs {
   const float *first_bias;
   // last layer fused into the last middle layer: its weights [c][9]
   const float *last_w;
-  // second layer of a fused pair of middle layers: weights (fragment order), bias
+  // second layer of a fused pair of middle layers: weights (fragment order;
+  // e4m3: row-reuse order), bias, output scales, 1 / next layer's input scale
   const void *wblob2;
   const float *bias2;
+  const float *oscale2;
+  float out_inv_scale2;
 };
 
 struct UpdateArgs {
@@ -61,6 +64,13 @@ hipError_t launch_conv_mid_last(const ConvArgs &a, int n_wg, bool first, hipStre
 hipError_t launch_conv_pair(const ConvArgs &a, int n_wg, hipStream_t s);
 bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt2, int out_fmt2,
                   int relu2, int unit2);
+// two consecutive e4m3 middle layers in one kernel (a: the first layer's
+// arguments with wblob_rr; wblob2 / bias2 / oscale2 / out_inv_scale2 the
+// second's); n_wg a positive multiple of 8, pair8_wg_per_cu() per CU
+hipError_t launch_conv_pair8(const ConvArgs &a, int n_wg, hipStream_t s);
+bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
+                   int relu2);
+int pair8_wg_per_cu();
 hipError_t launch_g_from_s(const ConvArgs &a, int n_tiles, hipStream_t s);
 bool mid_last_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int last_in_fmt,
                       int last_cin, int last_cout);

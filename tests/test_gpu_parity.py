@@ -199,6 +199,51 @@ def test_layer_pairs_match_per_layer_path(shape, block):
     assert e_f <= 5e-3 and e_l <= 5e-3 and e_fl <= 5e-3
 
 
+@pytest.mark.parametrize("shape,block", [((5, 7), 32), ((28, 60), 64), ((53, 83), 32),
+                                         ((150, 190), 64), ((403, 371), 128)])
+def test_fp8_layer_pairs_match_per_layer_path(shape, block):
+    """e4m3 middle layers, 8 layers: the sampler's path (layers 1-2 and 3-4
+    two per kernel, e4m3 in and out with per-channel scales) against the
+    layer-by-layer path (tight: both take the same products, summed in a
+    different order) and the emulating oracle.  Against the oracle the bar
+    is two e4m3 steps: per layer a few codes in a thousand round the other
+    way (the single-layer code-match test bounds that at 2e-3), and six e4m3
+    layers compound them; for these seeds both GPU paths land at 7-10%
+    (the deep-network test's 5e-2 holds for its seed), while a wrong tap,
+    channel or scale gives errors of order one."""
+    ny, nx = shape
+    say(f"case e4m3 layer pairs {ny}x{nx} block={block}")
+    K = 8
+    ch, ws, bs = W.denoiser_weights(K, 64, seed=17)
+    x = W.synthetic_image(ny, nx, 41)
+    fmt = W.layer_formats(K, P.PNPULA_FP8_E4M3)
+    small = ny * nx <= 150 * 190
+    # activation scales calibrated (FP64) on the image itself where the oracle
+    # checks the result, as in the single-layer e4m3 test; the large case
+    # compares the two GPU paths only, on scales from a crop
+    xs = x if small else x[:64, :64]
+    _, amax = O.denoiser_layers(O.Net(ch, ws, bs), xs)
+    scales = [float(2.0 ** np.ceil(np.log2(2 * a / 448))) if f == 2 else 1.0
+              for a, f in zip(amax, fmt)]
+    wl = W.make_workload("p8", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=block, halo=8,
+                         n_layers=K, features=64, precision=P.PNPULA_FP8_E4M3, iters=1,
+                         burn_in=0, seed=5)
+    wl.channels, wl.weights, wl.biases = ch, ws, bs
+    ctx = P.Context(P.Config.from_workload(wl, act_scales=scales))
+    G_fused = ctx.denoise(x.astype(np.float32))
+    G_layers, _ = ctx.denoise(x.astype(np.float32), layers=True)
+    e_fl = rel(G_fused, G_layers)
+    if small:
+        ref, _ = O.denoiser_layers(O.Net(ch, ws, bs, fmt, scales), x)
+        e_f, e_l = rel(G_fused, ref[-1][0]), rel(G_layers, ref[-1][0])
+    else:
+        e_f = e_l = 0.0                                  # per-layer path checked above
+    say(f"  fused {e_f:.2e}  per-layer {e_l:.2e}  fused vs per-layer {e_fl:.2e}")
+    assert np.all(np.isfinite(G_fused))
+    assert e_fl <= 1e-2
+    assert e_f <= 0.125 and e_l <= 0.125
+
+
 # -------------------------------------------------------- one iteration
 def _parity_run(wl, n_steps, block=None, label=""):
     say(f"case step parity {label}: {wl.ny}x{wl.nx} L={wl.kernel.shape[0]} "
