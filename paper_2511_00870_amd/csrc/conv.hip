@@ -1680,6 +1680,9 @@ __device__ __forceinline__ constexpr int p8_off(int p) {
 #define PNP_PAIR8_WPE 2   // waves per SIMD the e4m3 pair kernel is compiled for
 #endif
 
+// OUT2: storage format of the second layer's output (e4m3, or bf16 when the
+// next layer reads bf16, e.g. the last layer)
+template <int OUT2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PNP_PAIR8_WPE, PNP_PAIR8_WPE)))
 void conv_pair8_kernel(ConvArgs a) {
   using Lo = Pair8Layout;
@@ -1865,17 +1868,37 @@ void conv_pair8_kernel(ConvArgs a) {
     for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
 
     // layer B: the tile's rows to memory; lanes outside the tile (and the
-    // two padding columns) store to the trash pixel
-    const int64_t trash_b = cur.trash * Lo::PIXB + cbyte;
-    const int64_t col_b = (int64_t)(cur.x0 + cpos + 1) * Lo::PIXB + cbyte;
+    // two padding columns) store to the trash pixel.  bf16 output: 128-byte
+    // pixels, this lane's 8 channels are 16 bytes at 32 wave + 16 (g >> 1).
+    constexpr int OPIXB = OUT2 == FMT_BF16 ? 2 * Lo::PIXB : Lo::PIXB;
+    const int obyte = OUT2 == FMT_BF16 ? 2 * cbyte : cbyte;
+    const int64_t trash_b = cur.trash * OPIXB + obyte;
+    const int64_t col_b = (int64_t)(cur.x0 + cpos + 1) * OPIXB + obyte;
     const int64_t ok_c = cpos < cur.w ? -1 : 0;
     auto epB = [&](auto oc) {
       constexpr int o = decltype(oc)::value;
       const int64_t ok = (o < cur.h ? -1 : 0) & ok_c;
-      const int64_t roff = (int64_t)(cur.y0 + o + 1) * cur.apitch * Lo::PIXB;
-      const u32x2 q = pack_row(oc, 1, isB);
+      const int64_t roff = (int64_t)(cur.y0 + o + 1) * cur.apitch * OPIXB;
       const int64_t bo = ((col_b + roff) & ok) | (trash_b & ~ok);
-      *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + bo) = q;
+      if constexpr (OUT2 == FMT_BF16) {
+        const float *ep = lds_ep + 2 * Lo::F;
+        const f32x4 osc = *reinterpret_cast<const f32x4 *>(ep + 16 * wave + 4 * g);
+        const f32x4 bia = *reinterpret_cast<const f32x4 *>(ep + Lo::F + 16 * wave + 4 * g);
+        u32x2 w[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const f32x4 v = acc[o & 3][h];
+          w[h].x = pack_bf16x2(fmaxf(fmaf(v[0], osc[0], bia[0]), 0.0f),
+                               fmaxf(fmaf(v[1], osc[1], bia[1]), 0.0f));
+          w[h].y = pack_bf16x2(fmaxf(fmaf(v[2], osc[2], bia[2]), 0.0f),
+                               fmaxf(fmaf(v[3], osc[3], bia[3]), 0.0f));
+        }
+        const auto sx = __builtin_amdgcn_permlane16_swap(w[0].x, w[1].x, false, false);
+        const auto sy = __builtin_amdgcn_permlane16_swap(w[0].y, w[1].y, false, false);
+        *reinterpret_cast<PNP_GLOBAL u32x4 *>(cur.out + bo) = u32x4{sx[0], sy[0], sx[1], sy[1]};
+      } else {
+        *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + bo) = pack_row(oc, 1, isB);
+      }
     };
     auto pfB = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
@@ -2009,25 +2032,33 @@ hipError_t launch_conv_pair(const ConvArgs &a, int n_wg, hipStream_t s) {
 bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
                    int relu2) {
   return PNP_MID_RR && in_fmt == FMT_E4M3 && out_fmt == FMT_E4M3 && F == 64 && relu &&
-         in_fmt2 == FMT_E4M3 && out_fmt2 == FMT_E4M3 && relu2;
+         in_fmt2 == FMT_E4M3 && (out_fmt2 == FMT_E4M3 || out_fmt2 == FMT_BF16) && relu2;
 }
 
 int pair8_wg_per_cu() { return PNP_PAIR8_WPE; }
 
-hipError_t launch_conv_pair8(const ConvArgs &a, int n_wg, hipStream_t s) {
-  if (!a.wblob_rr || !a.wblob2 || !a.bias || !a.bias2 || !a.oscale || !a.oscale2 || n_wg <= 0 ||
-      n_wg % 8 != 0)
-    return hipErrorInvalidValue;
+template <int OUT2>
+static hipError_t launch_pair8_t(const ConvArgs &a, int n_wg, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_pair8_kernel),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_pair8_kernel<OUT2>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        Pair8Layout::LDS_BYTES);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(conv_pair8_kernel, dim3(n_wg), dim3(256), Pair8Layout::LDS_BYTES, s, a);
+  hipLaunchKernelGGL((conv_pair8_kernel<OUT2>), dim3(n_wg), dim3(256), Pair8Layout::LDS_BYTES, s,
+                     a);
   return hipGetLastError();
+}
+
+hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, int n_wg, hipStream_t s) {
+  if (!a.wblob_rr || !a.wblob2 || !a.bias || !a.bias2 || !a.oscale || !a.oscale2 || n_wg <= 0 ||
+      n_wg % 8 != 0)
+    return hipErrorInvalidValue;
+  if (out_fmt2 == FMT_E4M3) return launch_pair8_t<FMT_E4M3>(a, n_wg, s);
+  if (out_fmt2 == FMT_BF16) return launch_pair8_t<FMT_BF16>(a, n_wg, s);
+  return hipErrorInvalidValue;
 }
 
 bool first_mid_fusable(int in_fmt0, int out_fmt0, int cout0, int relu0, int unit0, int in_fmt1,

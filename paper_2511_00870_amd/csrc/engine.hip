@@ -853,7 +853,7 @@ Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool 
   ProfileRec pr;
   if (prof) prof_begin(6, &pr);
   if (e4m3)
-    HIPOK(launch_conv_pair8(a, n_wg, stream));
+    HIPOK(launch_conv_pair8(a, B.out_fmt, n_wg, stream));
   else
     HIPOK(launch_conv_pair(a, n_wg, stream));
   if (prof) prof_end(&pr);
@@ -904,8 +904,13 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
       TRY(launch_mid_last(k, in, tick, false, prof));
       return launch_g_from_s(tick, prof);
     }
-    if (pair_ok(k) && !(lf && k + 1 == K - 2) && other(in) >= 0) {
-      const int out = other(in);
+    // a pair writes the other buffer of its input's format, or the plan's
+    // buffer when its second layer changes the format
+    const int pair_out = net.layers[k + 1 < K ? k + 1 : k].out_fmt == net.buf_fmt[in]
+                             ? other(in)
+                             : net.layers[k + 1 < K ? k + 1 : k].out_buf;
+    if (pair_ok(k) && !(lf && k + 1 == K - 2) && pair_out >= 0) {
+      const int out = pair_out;
       TRY(launch_pair(k, in, out, tick, prof));
       cur = out;
       ++k;

@@ -66,8 +66,9 @@ bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt
                   int relu2, int unit2);
 // two consecutive e4m3 middle layers in one kernel (a: the first layer's
 // arguments with wblob_rr; wblob2 / bias2 / oscale2 / out_inv_scale2 the
-// second's); n_wg a positive multiple of 8, pair8_wg_per_cu() per CU
-hipError_t launch_conv_pair8(const ConvArgs &a, int n_wg, hipStream_t s);
+// second's); out_fmt2: the second layer's output format (e4m3 or bf16);
+// n_wg a positive multiple of 8, pair8_wg_per_cu() per CU
+hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, int n_wg, hipStream_t s);
 bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
                    int relu2);
 int pair8_wg_per_cu();
