@@ -109,6 +109,7 @@ template <> __device__ __forceinline__ float quant_in<FMT_E4M3>(float v, float i
 // byte pointer into LDS or global memory)
 typedef __attribute__((ext_vector_type(2))) unsigned int u32x2;
 typedef __attribute__((ext_vector_type(2))) short i16x2;
+typedef __attribute__((ext_vector_type(4))) short i16x4;
 // ReLU of two packed bf16 values: as signed 16-bit integers the negative
 // ones (sign bit set) are below zero
 __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t u) {
@@ -1669,8 +1670,13 @@ struct Pair8Layout {
   static constexpr int LDS_BYTES = IN_BYTES + MID_BYTES + 4 * F * 4;  // scale, bias per layer
   static constexpr int NCHUNK = IH * IW * CPP, NLOAD = (NCHUNK + NT - 1) / NT;
   static constexpr int NL1 = NLOAD / 2, NL2 = NLOAD - NL1;
+  // fused first layer: x window (IH + 2) x (IW + 2) as bf16, its scale and bias
+  static constexpr int XH = IH + 2, XW = IW + 2, NX = XH * XW, XQ = (NX + NT - 1) / NT;
+  static constexpr int FIRST_BYTES = NX * 2 + 2 * F * 4;
+  static constexpr int lds_bytes(bool first) { return LDS_BYTES + (first ? FIRST_BYTES : 0); }
 };
-static_assert(Pair8Layout::MW == 32 && Pair8Layout::LDS_BYTES <= 80 * 1024, "e4m3 pair layout");
+static_assert(Pair8Layout::MW == 32 && Pair8Layout::lds_bytes(true) <= 80 * 1024,
+              "e4m3 pair layout: two workgroups per CU");
 // LDS byte offset of pixel p in the padded e4m3 layout
 __device__ __forceinline__ constexpr int p8_off(int p) {
   return (p >> 2) * Pair8Layout::GRP + (p & 3) * Pair8Layout::PIXB;
@@ -1681,8 +1687,14 @@ __device__ __forceinline__ constexpr int p8_off(int p) {
 #endif
 
 // OUT2: storage format of the second layer's output (e4m3, or bf16 when the
-// next layer reads bf16, e.g. the last layer)
-template <int OUT2>
+// next layer reads bf16, e.g. the last layer).  FIRST: the network's first
+// layer (1 -> 64, bf16 weights, e4m3 output) is computed per tile from x
+// into the input window instead of reading its output from memory: each
+// wave takes its 16 channels for every window pixel, one MFMA per 16 pixels
+// (K = the 9 taps padded to 16), then scale, bias, ReLU and e4m3 as the
+// standalone first-layer kernel does; window pixels outside the image are
+// set to zero (the next layer's padding).
+template <int OUT2, bool FIRST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PNP_PAIR8_WPE, PNP_PAIR8_WPE)))
 void conv_pair8_kernel(ConvArgs a) {
   using Lo = Pair8Layout;
@@ -1692,6 +1704,8 @@ void conv_pair8_kernel(ConvArgs a) {
   uint8_t *lds_in = lds;
   uint8_t *lds_mid = lds + Lo::IN_BYTES;
   float *lds_ep = reinterpret_cast<float *>(lds_mid + Lo::MID_BYTES);  // [layer][scale | bias]
+  uint16_t *lds_x = reinterpret_cast<uint16_t *>(lds + Lo::LDS_BYTES);   // FIRST only
+  float *lds_ep0 = reinterpret_cast<float *>(lds_x + Lo::NX);             // FIRST: scale | bias
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1718,6 +1732,21 @@ void conv_pair8_kernel(ConvArgs a) {
   {
     const float *src = tid < 64 ? a.oscale : tid < 128 ? a.bias : tid < 192 ? a.oscale2 : a.bias2;
     lds_ep[tid] = gp(src)[tid & 63];
+    if (FIRST && tid < 128) lds_ep0[tid] = gp(tid < 64 ? a.first_oscale : a.first_bias)[tid & 63];
+  }
+  // fused first layer: this wave's A fragment (rows = its 16 channels, K =
+  // the 9 taps padded to 16: lane group g holds taps 4g .. 4g+3) and the
+  // lane's tap offsets in the x window relative to the pixel's own
+  i16x4 A0;
+  int toff[4];
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int t = 4 * g + e, tt = t < 9 ? t : 8;
+      A0[e] = __builtin_bit_cast(short, f32_to_bf16(t < 9 ? gp(a.first_w)[(16 * wave + l16) * 9 + t]
+                                                         : 0.0f));
+      toff[e] = (tt / 3) * Lo::XW + tt % 3;
+    }
   }
   // the intermediate's columns MW .. IW-1 are read only for the two padding
   // output columns and never written: zero the buffer once
@@ -1745,19 +1774,81 @@ void conv_pair8_kernel(ConvArgs a) {
   };
   static_assert(Lo::NLOAD * 64 >= Lo::IH * Lo::IW && Lo::NLOAD <= 2 * NL2, "window loads");
 
+  // fused first layer: x window rows y0-3 .. y0+TH+2, columns x0-3 ..
+  // x0+TW+2, clamped to the image and its zero ring (positions outside the
+  // image only feed window pixels that are set to zero)
+  auto load_x = [&](const MidTile &c, int i) -> float {
+    int q0 = tid + i * NT;
+    asm volatile("" : "+v"(q0));
+    const int q = q0 < Lo::NX ? q0 : 0;
+    const int r = q / Lo::XW, col = q % Lo::XW;
+    const int Y = min(max(c.y0 - 3 + r, -1), c.ny), X = min(max(c.x0 - 3 + col, -1), c.nx);
+    return c.x[(int64_t)(Y + c.xb) * c.xpitch + (X + c.xb)];
+  };
+  auto put_x = [&](int i, float v) {
+    const int q = tid + i * NT;
+    if (q < Lo::NX) lds_x[q] = f32_to_bf16(v);
+  };
+  auto layer0 = [&](const MidTile &c) {
+    const f32x4 sc0 = *reinterpret_cast<const f32x4 *>(lds_ep0 + 16 * wave + 4 * g);
+    const f32x4 bi0 = *reinterpret_cast<const f32x4 *>(lds_ep0 + Lo::F + 16 * wave + 4 * g);
+    const float is0 = a.first_out_inv_scale;
+    constexpr int NWIN = Lo::IH * IW, NB = (NWIN + 15) / 16;
+    // unrolled by four (four independent read -> MFMA -> write chains), with
+    // an opaque index: the per-lane addresses are the same for every tile and
+    // would otherwise be kept live across the tile loop
+#pragma unroll 4
+    for (int blk = 0; blk < NB; ++blk) {
+      int q0 = 16 * blk + l16;
+      asm volatile("" : "+v"(q0));
+      const int q = q0 < NWIN ? q0 : 0;
+      const int wr = q / IW, wc = q % IW;
+      const uint16_t *xp = lds_x + wr * Lo::XW + wc;
+      i16x4 Bx;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint16_t v = xp[toff[e]];
+        Bx[e] = (short)(4 * g + e < 9 ? v : (uint16_t)0);
+      }
+      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, Bx, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                              0, 0, 0);
+      const bool inside = (unsigned)(c.y0 - 2 + wr) < (unsigned)c.ny &&
+                          (unsigned)(c.x0 - 2 + wc) < (unsigned)c.nx;
+      uint32_t w = pack_e4m3x4_nonan(fmaxf(d[0] * sc0[0] + bi0[0], 0.0f) * is0,
+                                     fmaxf(d[1] * sc0[1] + bi0[1], 0.0f) * is0,
+                                     fmaxf(d[2] * sc0[2] + bi0[2], 0.0f) * is0,
+                                     fmaxf(d[3] * sc0[3] + bi0[3], 0.0f) * is0);
+      w = inside ? w : 0u;
+      // lanes past the window write into the intermediate buffer, which is
+      // rewritten before it is read
+      uint8_t *dst = q0 < NWIN ? lds_in + p8_off(q) : lds_mid;
+      *reinterpret_cast<uint32_t *>(dst + 16 * wave + 4 * g) = w;
+    }
+  };
+
   int ti = t_begin + slot;
   if (ti >= t_end) return;                       // uniform over the workgroup
   MidTile cur = mid_tile(a, ti);
   MidTile nxt = mid_tile(a, ti + per_xcd < t_end ? ti + per_xcd : t_begin);
   u32x4 pre[NL2];
+  float prex[FIRST ? Lo::XQ : 1];
+  if constexpr (FIRST) {
 #pragma unroll
-  for (int i = 0; i < NL1; ++i) pre[i] = load_chunk(cur, i);
+    for (int i = 0; i < Lo::XQ; ++i) prex[i] = load_x(cur, i);
 #pragma unroll
-  for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+    for (int i = 0; i < Lo::XQ; ++i) put_x(i, prex[i]);
+    __syncthreads();
+    layer0(cur);
+  } else {
 #pragma unroll
-  for (int i = 0; i < NL2; ++i) pre[i] = load_chunk(cur, NL1 + i);
+    for (int i = 0; i < NL1; ++i) pre[i] = load_chunk(cur, i);
 #pragma unroll
-  for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+    for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+#pragma unroll
+    for (int i = 0; i < NL2; ++i) pre[i] = load_chunk(cur, NL1 + i);
+#pragma unroll
+    for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+  }
   __syncthreads();
 
   // B fragment of step P at window row ir, block h: this lane's pixel is
@@ -1860,12 +1951,14 @@ void conv_pair8_kernel(ConvArgs a) {
     };
     auto pfA = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
-      if constexpr (stg >= 4 && stg < 4 + NL1) pre[stg - 4] = load_chunk(nxt, stg - 4);
+      if constexpr (!FIRST && stg >= 4 && stg < 4 + NL1) pre[stg - 4] = load_chunk(nxt, stg - 4);
     };
     layer(base_in, WA, std::integral_constant<int, Lo::IH>{}, epA, pfA);
     __syncthreads();                             // intermediate written, window read
+    if constexpr (!FIRST) {
 #pragma unroll
-    for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+      for (int i = 0; i < NL1; ++i) put_chunk(i, pre[i]);
+    }
 
     // layer B: the tile's rows to memory; lanes outside the tile (and the
     // two padding columns) store to the trash pixel.  bf16 output: 128-byte
@@ -1902,16 +1995,30 @@ void conv_pair8_kernel(ConvArgs a) {
     };
     auto pfB = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
-      if constexpr (stg >= 1 && stg < 1 + NL2) pre[stg - 1] = load_chunk(nxt, NL1 + stg - 1);
+      if constexpr (FIRST) {
+        if constexpr (stg >= 1 && stg < 1 + Lo::XQ) prex[stg - 1] = load_x(nxt, stg - 1);
+      } else {
+        if constexpr (stg >= 1 && stg < 1 + NL2) pre[stg - 1] = load_chunk(nxt, NL1 + stg - 1);
+      }
     };
     layer(base_mid, WB, std::integral_constant<int, Lo::MH>{}, epB, pfB);
+    if constexpr (FIRST) {
+      // the x window is read by layer0 only, long done
 #pragma unroll
-    for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+      for (int i = 0; i < Lo::XQ; ++i) put_x(i, prex[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
+    }
     __syncthreads();                             // next window in place, intermediate read
     if (tn >= t_end) break;
     cur = nxt;
     nxt = after;
     ti = tn;
+    if constexpr (FIRST) {
+      layer0(cur);
+      __syncthreads();
+    }
   }
 }
 
@@ -2037,28 +2144,39 @@ bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int ou
 
 int pair8_wg_per_cu() { return PNP_PAIR8_WPE; }
 
-template <int OUT2>
+template <int OUT2, bool FIRST>
 static hipError_t launch_pair8_t(const ConvArgs &a, int n_wg, hipStream_t s) {
+  constexpr int lds = Pair8Layout::lds_bytes(FIRST);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_pair8_kernel<OUT2>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       Pair8Layout::LDS_BYTES);
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&conv_pair8_kernel<OUT2, FIRST>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((conv_pair8_kernel<OUT2>), dim3(n_wg), dim3(256), Pair8Layout::LDS_BYTES, s,
-                     a);
+  hipLaunchKernelGGL((conv_pair8_kernel<OUT2, FIRST>), dim3(n_wg), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, int n_wg, hipStream_t s) {
+hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, int n_wg,
+                             hipStream_t s) {
   if (!a.wblob_rr || !a.wblob2 || !a.bias || !a.bias2 || !a.oscale || !a.oscale2 || n_wg <= 0 ||
       n_wg % 8 != 0)
     return hipErrorInvalidValue;
-  if (out_fmt2 == FMT_E4M3) return launch_pair8_t<FMT_E4M3>(a, n_wg, s);
-  if (out_fmt2 == FMT_BF16) return launch_pair8_t<FMT_BF16>(a, n_wg, s);
+  if (first && (!a.first_w || !a.first_bias || !a.first_oscale)) return hipErrorInvalidValue;
+  if (out_fmt2 == FMT_E4M3)
+    return first ? launch_pair8_t<FMT_E4M3, true>(a, n_wg, s)
+                 : launch_pair8_t<FMT_E4M3, false>(a, n_wg, s);
+  if (out_fmt2 == FMT_BF16)
+    return first ? launch_pair8_t<FMT_BF16, true>(a, n_wg, s)
+                 : launch_pair8_t<FMT_BF16, false>(a, n_wg, s);
   return hipErrorInvalidValue;
+}
+
+bool first_pair8_fusable(int in_fmt0, int out_fmt0, int cin0, int cout0, int relu0) {
+  return PNP_MID_RR && in_fmt0 == FMT_BF16 && out_fmt0 == FMT_E4M3 && cin0 == 1 && cout0 == 64 &&
+         relu0;
 }
 
 bool first_mid_fusable(int in_fmt0, int out_fmt0, int cout0, int relu0, int unit0, int in_fmt1,

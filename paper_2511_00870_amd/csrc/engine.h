@@ -107,8 +107,10 @@ class Engine {
   bool first_mid_fused() const;
   Status launch_first_mid(int64_t tick, bool prof);
   Status launch_mid_last(int k, int in_slot, int64_t tick, bool first, bool prof);
-  Status launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof);
+  Status launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof,
+                     bool first = false);
   bool pair_ok(int k) const;
+  bool first_pair8_ok() const;
   Status launch_g_from_s(int64_t tick, bool prof);
   Status run_fused_denoiser(int64_t tick, bool prof);
   Status launch_layer(int k, int64_t tick, bool prof, int in_slot = -1, int out_slot = -1);

@@ -823,7 +823,20 @@ bool Engine::pair_ok(int k) const {
           A.wblob_rr && B.wblob_rr);
 }
 
-Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof) {
+// the first layer (bf16 -> e4m3) inside the kernel of the first e4m3 pair
+bool Engine::first_pair8_ok() const {
+  if (net.K < 4 || !pair_ok(1) || net.layers[1].in_fmt != FMT_E4M3) return false;
+  if (net.last_fused && net.K - 2 == 2) return false;
+  const LayerPlan &L0 = net.layers[0];
+  if (!first_pair8_fusable(L0.in_fmt, L0.out_fmt, L0.cin, L0.cout, L0.relu)) return false;
+  for (int i = 0; i < 4; ++i)
+    if (i != net.layers[1].in_buf && net.buf_fmt[i] == net.buf_fmt[net.layers[1].in_buf])
+      return true;
+  return false;
+}
+
+Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof,
+                           bool first) {
   const LayerPlan &A = net.layers[k], &B = net.layers[k + 1];
   ConvArgs a{};
   a.jobs = d_jobs;
@@ -847,13 +860,20 @@ Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool 
     a.wblob_rr = A.wblob_rr;
     a.wblob2 = B.wblob_rr;
   }
+  if (first) {
+    const LayerPlan &L0 = net.layers[0];
+    a.first_w = L0.wf32;
+    a.first_bias = L0.bias;
+    a.first_oscale = L0.oscale;
+    a.first_out_inv_scale = L0.out_inv_scale;
+  }
   const int per_cu = e4m3 ? pair8_wg_per_cu() : 1;
   const int need = ((n_pair + 7) / 8) * 8;
   const int n_wg = std::max(8, std::min(n_cu * per_cu, need) / 8 * 8);
   ProfileRec pr;
   if (prof) prof_begin(6, &pr);
   if (e4m3)
-    HIPOK(launch_conv_pair8(a, B.out_fmt, n_wg, stream));
+    HIPOK(launch_conv_pair8(a, B.out_fmt, first, n_wg, stream));
   else
     HIPOK(launch_conv_pair(a, n_wg, stream));
   if (prof) prof_end(&pr);
@@ -896,6 +916,13 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
   if (ff) {
     TRY(launch_first_mid(tick, prof));
     k = 2;
+  } else if (first_pair8_ok()) {
+    // e4m3 networks: the first layer runs inside the first pair's kernel
+    const int in = net.layers[1].in_buf;
+    const int out = net.layers[2].out_fmt == net.buf_fmt[in] ? other(in) : net.layers[2].out_buf;
+    TRY(launch_pair(1, in, out, tick, prof, true));
+    cur = out;
+    k = 3;
   }
   for (; k < K; ++k) {
     const LayerPlan &L = net.layers[k];

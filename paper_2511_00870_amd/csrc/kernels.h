@@ -24,9 +24,12 @@ struct ConvArgs {
   const float *oscale;         // [c_out]: weight scale x input scale
   float in_inv_scale;          // first layer: 1 / scale of its input format
   float out_inv_scale;         // 1 / scale of the next layer's input (e4m3), else 1
-  // first layer fused into the first middle layer: its weights [c][9] and bias
+  // first layer fused into the first middle layer: its weights [c][9], bias,
+  // output scales and 1 / next layer's input scale (the last two: e4m3 pairs)
   const float *first_w;
   const float *first_bias;
+  const float *first_oscale;
+  float first_out_inv_scale;
   // last layer fused into the last middle layer: its weights [c][9]
   const float *last_w;
   // second layer of a fused pair of middle layers: weights (fragment order;
@@ -68,7 +71,11 @@ bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt
 // arguments with wblob_rr; wblob2 / bias2 / oscale2 / out_inv_scale2 the
 // second's); out_fmt2: the second layer's output format (e4m3 or bf16);
 // n_wg a positive multiple of 8, pair8_wg_per_cu() per CU
-hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, int n_wg, hipStream_t s);
+// first: the network's first layer (bf16 -> e4m3) runs inside the kernel
+// from x (first_w / first_bias / first_oscale / first_out_inv_scale)
+hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, int n_wg,
+                             hipStream_t s);
+bool first_pair8_fusable(int in_fmt0, int out_fmt0, int cin0, int cout0, int relu0);
 bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
                    int relu2);
 int pair8_wg_per_cu();
