@@ -832,18 +832,19 @@ void conv_mid_rr_kernel(ConvArgs a) {
     if (FIRST && tid < Lo::F) lds_bias0[tid] = gp(a.first_bias)[tid];
   }
   // fused first layer: A fragments (rows = its 64 output channels in blocks of
-  // 16, K = its 9 taps padded to 32) in LDS, fragment order
+  // 16, K = its 9 taps padded to 16) in LDS, fragment order
   if constexpr (FIRST) {
     if (wave == 0) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        bf16x8 f;
+        i16x4 f;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int t = 8 * g + e;
-          f[e] = (__bf16)(t < 9 ? gp(a.first_w)[(mb * 16 + l16) * 9 + t] : 0.0f);
+        for (int e = 0; e < 4; ++e) {
+          const int t = 4 * g + e;
+          f[e] = __builtin_bit_cast(short, f32_to_bf16(t < 9 ? gp(a.first_w)[(mb * 16 + l16) * 9 + t]
+                                                             : 0.0f));
         }
-        *reinterpret_cast<bf16x8 *>(lds_a0 + (mb * 64 + lane) * 16) = f;
+        *reinterpret_cast<i16x4 *>(lds_a0 + (mb * 64 + lane) * 16) = f;
       }
     }
   }
@@ -928,21 +929,21 @@ void conv_mid_rr_kernel(ConvArgs a) {
       if (blk >= NB0) break;                                  // uniform
       const int q0 = blk * 16 + l16, q = q0 < NWIN ? q0 : 0;
       const int wr = q / IW, wc = q % IW;
-      bf16x8 Bx;
+      i16x4 Bx;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int t = 8 * g + e;
+      for (int e = 0; e < 4; ++e) {
+        const int t = 4 * g + e;
         const int tt = t < 9 ? t : 0;
         const uint16_t v = lds_x[(wr + tt / 3) * Lo::XW + wc + tt % 3];
-        Bx[e] = __builtin_bit_cast(__bf16, t < 9 ? v : (uint16_t)0);
+        Bx[e] = (short)(t < 9 ? v : (uint16_t)0);
       }
       const int Y = c.y0 - 1 + wr, X = c.x0 - 1 + wc;
       const bool inside = Y >= 0 && Y < c.ny && X >= 0 && X < c.nx;
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias0 + mb * 16 + 4 * g);
-        const bf16x8 A0 = *reinterpret_cast<const bf16x8 *>(lds_a0 + (mb * 64 + lane) * 16);
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, Bx, bia, 0, 0, 0);
+        const i16x4 A0 = *reinterpret_cast<const i16x4 *>(lds_a0 + (mb * 64 + lane) * 16);
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, Bx, bia, 0, 0, 0);
         u32x2 w;
         w.x = inside ? relu_bf16x2(pack_bf16x2(d[0], d[1])) : 0u;
         w.y = inside ? relu_bf16x2(pack_bf16x2(d[2], d[3])) : 0u;
