@@ -244,6 +244,35 @@ def test_fp8_layer_pairs_match_per_layer_path(shape, block):
     assert e_f <= 0.125 and e_l <= 0.125
 
 
+@pytest.mark.parametrize("K", [3, 4, 5, 6, 7])
+@pytest.mark.parametrize("prec", [P.PNPULA_BF16, P.PNPULA_FP8_E4M3])
+def test_fused_path_layer_counts(K, prec):
+    """The sampler's denoiser path for every way a network splits into fused
+    first / paired / single / fused last launches (bf16 and e4m3, 3 to 7
+    layers), against the layer-by-layer path on a ragged image: catches a
+    wrong activation buffer or a dropped layer in the launch sequence."""
+    ny, nx = 37, 71
+    say(f"case fused path K={K} precision={prec}")
+    ch, ws, bs = W.denoiser_weights(K, 64, seed=23 + K)
+    x = W.synthetic_image(ny, nx, 43)
+    fmt = W.layer_formats(K, prec)
+    scales = None
+    if prec == P.PNPULA_FP8_E4M3:
+        _, amax = O.denoiser_layers(O.Net(ch, ws, bs), x)
+        scales = [float(2.0 ** np.ceil(np.log2(2 * a / 448))) if f == 2 else 1.0
+                  for a, f in zip(amax, fmt)]
+    wl = W.make_workload("k", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=32, halo=8,
+                         n_layers=K, features=64, precision=prec, iters=1, burn_in=0, seed=5)
+    wl.channels, wl.weights, wl.biases = ch, ws, bs
+    ctx = P.Context(P.Config.from_workload(wl, act_scales=scales))
+    G_fused = ctx.denoise(x.astype(np.float32))
+    G_layers, _ = ctx.denoise(x.astype(np.float32), layers=True)
+    e = rel(G_fused, G_layers)
+    say(f"  fused vs per-layer {e:.2e}")
+    assert np.all(np.isfinite(G_fused))
+    assert e <= (5e-3 if prec == P.PNPULA_BF16 else 1e-2)
+
+
 # -------------------------------------------------------- one iteration
 def _parity_run(wl, n_steps, block=None, label=""):
     say(f"case step parity {label}: {wl.ny}x{wl.nx} L={wl.kernel.shape[0]} "
