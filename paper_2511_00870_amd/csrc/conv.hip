@@ -1675,6 +1675,11 @@ struct Pair8Layout {
   static constexpr int XH = IH + 2, XW = IW + 2, NX = XH * XW, XQ = (NX + NT - 1) / NT;
   static constexpr int FIRST_BYTES = NX * 2 + 2 * F * 4;
   static constexpr int lds_bytes(bool first) { return LDS_BYTES + (first ? FIRST_BYTES : 0); }
+  // fused last layer: per-row partial sums of the 4 waves (2 blocks, lane
+  // groups 0-2 = taps 0..11, 16 bytes per lane) in a ring of 3 rows, placed
+  // in the part of the input window that only the second prefetch half fills
+  static constexpr int STG_ROW = 4 * 2 * 48 * 16, STG_OFF = (NL1 * 64 / 4) * GRP;
+  static_assert(STG_OFF + 3 * STG_ROW <= IN_BYTES, "last-layer ring");
 };
 static_assert(Pair8Layout::MW == 32 && Pair8Layout::lds_bytes(true) <= 80 * 1024,
               "e4m3 pair layout: two workgroups per CU");
@@ -1688,14 +1693,21 @@ __device__ __forceinline__ constexpr int p8_off(int p) {
 #endif
 
 // OUT2: storage format of the second layer's output (e4m3, or bf16 when the
-// next layer reads bf16, e.g. the last layer).  FIRST: the network's first
+// next layer reads bf16, e.g. the last layer).  LAST: the second layer feeds
+// the network's last layer (64 -> 1, bf16), and instead of its activations
+// the kernel writes that layer's per-tap partial sums (JobDesc::S, 12 floats
+// per pixel, zero border of one record), as the bf16 last-middle kernel does:
+// per output row each wave multiplies its 16 channels (rounded to bf16 after
+// ReLU) by the last layer's weights on the matrix core (M = 9 taps padded to
+// 16, K = 16 channels), the four waves' partials meet in LDS, and after a
+// barrier 96 lanes add them and store the records.  FIRST: the network's first
 // layer (1 -> 64, bf16 weights, e4m3 output) is computed per tile from x
 // into the input window instead of reading its output from memory: each
 // wave takes its 16 channels for every window pixel, one MFMA per 16 pixels
 // (K = the 9 taps padded to 16), then scale, bias, ReLU and e4m3 as the
 // standalone first-layer kernel does; window pixels outside the image are
 // set to zero (the next layer's padding).
-template <int OUT2, bool FIRST>
+template <int OUT2, bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PNP_PAIR8_WPE, PNP_PAIR8_WPE)))
 void conv_pair8_kernel(ConvArgs a) {
   using Lo = Pair8Layout;
@@ -1738,6 +1750,15 @@ void conv_pair8_kernel(ConvArgs a) {
   // fused first layer: this wave's A fragment (rows = its 16 channels, K =
   // the 9 taps padded to 16: lane group g holds taps 4g .. 4g+3) and the
   // lane's tap offsets in the x window relative to the pixel's own
+  // fused last layer: this wave's A fragment (rows = the 9 taps padded to
+  // 16, K = its 16 channels: lane group g holds channels 16 wave + 4g ..)
+  i16x4 AL;
+  if constexpr (LAST) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      AL[e] = __builtin_bit_cast(
+          short, f32_to_bf16(l16 < 9 ? gp(a.last_w)[(16 * wave + 4 * g + e) * 9 + l16] : 0.0f));
+  }
   i16x4 A0;
   int toff[4];
   if constexpr (FIRST) {
@@ -1969,12 +1990,43 @@ void conv_pair8_kernel(ConvArgs a) {
     const int64_t trash_b = cur.trash * OPIXB + obyte;
     const int64_t col_b = (int64_t)(cur.x0 + cpos + 1) * OPIXB + obyte;
     const int64_t ok_c = cpos < cur.w ? -1 : 0;
+    const int64_t spitch = cur.nx + 2, strash = (int64_t)(cur.ny + 2) * spitch;
     auto epB = [&](auto oc) {
       constexpr int o = decltype(oc)::value;
       const int64_t ok = (o < cur.h ? -1 : 0) & ok_c;
       const int64_t roff = (int64_t)(cur.y0 + o + 1) * cur.apitch * OPIXB;
       const int64_t bo = ((col_b + roff) & ok) | (trash_b & ~ok);
-      if constexpr (OUT2 == FMT_BF16) {
+      if constexpr (LAST) {
+        const float *ep = lds_ep + 2 * Lo::F;
+        const f32x4 osc = *reinterpret_cast<const f32x4 *>(ep + 16 * wave + 4 * g);
+        const f32x4 bia = *reinterpret_cast<const f32x4 *>(ep + Lo::F + 16 * wave + 4 * g);
+        uint8_t *ring = lds_in + Lo::STG_OFF + (o % 3) * Lo::STG_ROW;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const f32x4 v = acc[o & 3][h];
+          i16x4 bv;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            bv[e] = __builtin_bit_cast(short, f32_to_bf16(fmaxf(fmaf(v[e], osc[e], bia[e]), 0.0f)));
+          // taps 4g .. 4g+3 of pixel l16 of block h, over this wave's channels
+          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(AL, bv, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                  0, 0, 0);
+          if (g < 3)
+            *reinterpret_cast<f32x4 *>(ring + ((wave * 2 + h) * 48 + 16 * g + l16) * 16) = d;
+        }
+        __syncthreads();
+        if (tid < 96) {                          // (block, tap group, pixel) per lane
+          const int h = tid / 48, r = tid % 48, c = 16 * h + (r & 15);
+          f32x4 sum = *reinterpret_cast<const f32x4 *>(ring + (h * 48 + r) * 16);
+#pragma unroll
+          for (int w = 1; w < 4; ++w)
+            sum += *reinterpret_cast<const f32x4 *>(ring + ((w * 2 + h) * 48 + r) * 16);
+          const int64_t rec = (o < cur.h && c < cur.w)
+                                  ? (int64_t)(cur.y0 + o + 1) * spitch + (cur.x0 + c + 1)
+                                  : strash;
+          *reinterpret_cast<PNP_GLOBAL f32x4 *>(cur.S + rec * 12 + 4 * (r >> 4)) = sum;
+        }
+      } else if constexpr (OUT2 == FMT_BF16) {
         const float *ep = lds_ep + 2 * Lo::F;
         const f32x4 osc = *reinterpret_cast<const f32x4 *>(ep + 16 * wave + 4 * g);
         const f32x4 bia = *reinterpret_cast<const f32x4 *>(ep + Lo::F + 16 * wave + 4 * g);
@@ -2003,6 +2055,7 @@ void conv_pair8_kernel(ConvArgs a) {
       }
     };
     layer(base_mid, WB, std::integral_constant<int, Lo::MH>{}, epB, pfB);
+    if constexpr (LAST) __syncthreads();         // the last row's partials are summed
     if constexpr (FIRST) {
       // the x window is read by layer0 only, long done
 #pragma unroll
@@ -2145,34 +2198,44 @@ bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int ou
 
 int pair8_wg_per_cu() { return PNP_PAIR8_WPE; }
 
-template <int OUT2, bool FIRST>
+template <int OUT2, bool FIRST, bool LAST>
 static hipError_t launch_pair8_t(const ConvArgs &a, int n_wg, hipStream_t s) {
   constexpr int lds = Pair8Layout::lds_bytes(FIRST);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&conv_pair8_kernel<OUT2, FIRST>),
+        reinterpret_cast<const void *>(&conv_pair8_kernel<OUT2, FIRST, LAST>),
         hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((conv_pair8_kernel<OUT2, FIRST>), dim3(n_wg), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((conv_pair8_kernel<OUT2, FIRST, LAST>), dim3(n_wg), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, int n_wg,
+hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, bool last, int n_wg,
                              hipStream_t s) {
   if (!a.wblob_rr || !a.wblob2 || !a.bias || !a.bias2 || !a.oscale || !a.oscale2 || n_wg <= 0 ||
       n_wg % 8 != 0)
     return hipErrorInvalidValue;
   if (first && (!a.first_w || !a.first_bias || !a.first_oscale)) return hipErrorInvalidValue;
+  if (last) {
+    if (!a.last_w || out_fmt2 != FMT_BF16) return hipErrorInvalidValue;
+    return first ? launch_pair8_t<FMT_BF16, true, true>(a, n_wg, s)
+                 : launch_pair8_t<FMT_BF16, false, true>(a, n_wg, s);
+  }
   if (out_fmt2 == FMT_E4M3)
-    return first ? launch_pair8_t<FMT_E4M3, true>(a, n_wg, s)
-                 : launch_pair8_t<FMT_E4M3, false>(a, n_wg, s);
+    return first ? launch_pair8_t<FMT_E4M3, true, false>(a, n_wg, s)
+                 : launch_pair8_t<FMT_E4M3, false, false>(a, n_wg, s);
   if (out_fmt2 == FMT_BF16)
-    return first ? launch_pair8_t<FMT_BF16, true>(a, n_wg, s)
-                 : launch_pair8_t<FMT_BF16, false>(a, n_wg, s);
+    return first ? launch_pair8_t<FMT_BF16, true, false>(a, n_wg, s)
+                 : launch_pair8_t<FMT_BF16, false, false>(a, n_wg, s);
   return hipErrorInvalidValue;
+}
+
+bool last_pair8_fusable(int out_fmt2, int last_in_fmt, int last_cin, int last_cout) {
+  return PNP_MID_RR && out_fmt2 == FMT_BF16 && last_in_fmt == FMT_BF16 && last_cin == 64 &&
+         last_cout == 1;
 }
 
 bool first_pair8_fusable(int in_fmt0, int out_fmt0, int cin0, int cout0, int relu0) {

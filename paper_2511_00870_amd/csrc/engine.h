@@ -44,6 +44,7 @@ struct NetPlan {
   std::vector<LayerPlan> layers;
   int buf_fmt[4] = {-1, -1, -1, -1};  // storage format of each activation buffer
   bool last_fused = false;   // the last layer runs inside the last middle layer's kernel
+  bool last_pair8 = false;   // e4m3: the last layer runs inside the last pair's kernel
   std::vector<void *> allocs;
 };
 
@@ -108,7 +109,7 @@ class Engine {
   Status launch_first_mid(int64_t tick, bool prof);
   Status launch_mid_last(int k, int in_slot, int64_t tick, bool first, bool prof);
   Status launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof,
-                     bool first = false);
+                     bool first = false, bool last = false);
   bool pair_ok(int k) const;
   bool first_pair8_ok() const;
   Status launch_g_from_s(int64_t tick, bool prof);

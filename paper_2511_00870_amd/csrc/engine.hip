@@ -313,6 +313,16 @@ Status Engine::set_net(int K, const int32_t *ch, const float *w, const float *b,
                                       Ll.in_fmt, Ll.cin, Ll.cout) &&
                      conv_th == 16;
   }
+  // e4m3 networks whose middle layers pair up exactly: the last pair's second
+  // layer feeds the bf16 last layer, which then runs inside that kernel
+  net.last_pair8 = false;
+  if (K >= 4 && (K - 2) % 2 == 0 && !net.last_fused) {
+    const LayerPlan &A = net.layers[K - 3], &B = net.layers[K - 2], &Ll = net.layers[K - 1];
+    net.last_pair8 = pair8_fusable(A.in_fmt, A.out_fmt, net.F, A.relu, B.in_fmt, B.out_fmt,
+                                   B.relu) &&
+                     A.wblob_rr && B.wblob_rr &&
+                     last_pair8_fusable(B.out_fmt, Ll.in_fmt, Ll.cin, Ll.cout);
+  }
   plan_dirty = true;
   return Status::ok();
 }
@@ -370,7 +380,8 @@ size_t Engine::job_footprint(const pnpula_config *c, const NetPlan &n) {
   for (int b = 0; b < 4; ++b)
     if (n.buf_fmt[b] >= 0) bytes += (size_t)g.arows * g.apitch * n.F * fmt_bytes(n.buf_fmt[b]);
   bytes += N * (sizeof(float) * 3 + sizeof(double) * 2);                // G, Welford
-  if (n.last_fused) bytes += ((size_t)(c->ny + 2) * (c->nx + 2) + 1) * 12 * sizeof(float);
+  if (n.last_fused || n.last_pair8)
+    bytes += ((size_t)(c->ny + 2) * (c->nx + 2) + 1) * 12 * sizeof(float);
   bytes += 4096;
   return bytes;
 }
@@ -473,7 +484,7 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   }
   if (!(s = dalloc(j, &d.G, N * sizeof(float))).good()) return fail(s);
   d.S = nullptr;
-  if (net.last_fused) {
+  if (net.last_fused || net.last_pair8) {
     const size_t sbytes = ((size_t)(ny + 2) * (nx + 2) + 1) * 12 * sizeof(float);
     if (!(s = dalloc(j, &d.S, sbytes)).good()) return fail(s);
     if (hipMemsetAsync(d.S, 0, sbytes, stream) != hipSuccess)
@@ -836,7 +847,7 @@ bool Engine::first_pair8_ok() const {
 }
 
 Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof,
-                           bool first) {
+                           bool first, bool last) {
   const LayerPlan &A = net.layers[k], &B = net.layers[k + 1];
   ConvArgs a{};
   a.jobs = d_jobs;
@@ -860,6 +871,7 @@ Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool 
     a.wblob_rr = A.wblob_rr;
     a.wblob2 = B.wblob_rr;
   }
+  if (last) a.last_w = net.layers[net.K - 1].wf32;
   if (first) {
     const LayerPlan &L0 = net.layers[0];
     a.first_w = L0.wf32;
@@ -873,7 +885,7 @@ Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool 
   ProfileRec pr;
   if (prof) prof_begin(6, &pr);
   if (e4m3)
-    HIPOK(launch_conv_pair8(a, B.out_fmt, first, n_wg, stream));
+    HIPOK(launch_conv_pair8(a, B.out_fmt, first, last, n_wg, stream));
   else
     HIPOK(launch_conv_pair(a, n_wg, stream));
   if (prof) prof_end(&pr);
@@ -920,7 +932,9 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
     // e4m3 networks: the first layer runs inside the first pair's kernel
     const int in = net.layers[1].in_buf;
     const int out = net.layers[2].out_fmt == net.buf_fmt[in] ? other(in) : net.layers[2].out_buf;
-    TRY(launch_pair(1, in, out, tick, prof, true));
+    const bool last = net.last_pair8 && K - 2 == 2;
+    TRY(launch_pair(1, in, out, tick, prof, true, last));
+    if (last) return launch_g_from_s(tick, prof);
     cur = out;
     k = 3;
   }
@@ -938,7 +952,9 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
                              : net.layers[k + 1 < K ? k + 1 : k].out_buf;
     if (pair_ok(k) && !(lf && k + 1 == K - 2) && pair_out >= 0) {
       const int out = pair_out;
-      TRY(launch_pair(k, in, out, tick, prof));
+      const bool last = net.last_pair8 && k + 1 == K - 2;
+      TRY(launch_pair(k, in, out, tick, prof, false, last));
+      if (last) return launch_g_from_s(tick, prof);
       cur = out;
       ++k;
       continue;

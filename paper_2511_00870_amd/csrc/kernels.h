@@ -73,8 +73,11 @@ bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt
 // n_wg a positive multiple of 8, pair8_wg_per_cu() per CU
 // first: the network's first layer (bf16 -> e4m3) runs inside the kernel
 // from x (first_w / first_bias / first_oscale / first_out_inv_scale)
-hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, int n_wg,
+// last: the second layer feeds the last layer, whose per-tap partials go to
+// JobDesc::S (last_w; out_fmt2 must be bf16)
+hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, bool last, int n_wg,
                              hipStream_t s);
+bool last_pair8_fusable(int out_fmt2, int last_in_fmt, int last_cin, int last_cout);
 bool first_pair8_fusable(int in_fmt0, int out_fmt0, int cin0, int cout0, int relu0);
 bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
                    int relu2);
