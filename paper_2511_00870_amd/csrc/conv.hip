@@ -2078,24 +2078,38 @@ void conv_pair8_kernel(ConvArgs a) {
 
 // G from the fused last layer's partials: G(p) = scale * sum over taps of the
 // tap's partial at the neighbour the tap reads, + bias.  The records' zero
-// border supplies the zero padding at the image edge.
+// border supplies the zero padding at the image edge.  A tile's records (its
+// rows and columns plus one on each side) are contiguous per row, so they
+// are staged in LDS with 16-byte loads and the taps are summed from there.
 __global__ __launch_bounds__(256) void g_from_s_kernel(ConvArgs a) {
+  constexpr int RW = kConvTileW + 2, RREC = 12, NCH = RW * RREC / 4;   // 16-byte chunks per row
+  __shared__ __attribute__((aligned(16))) float srec[18 * RW * RREC];
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const PNP_GLOBAL float *S = gp(j.S);
   const int64_t spitch = j.nx + 2;
+  const int rows = tl.h + 2, nch = (tl.w + 2) * RREC / 4;
+  // record (y0 + r, x0 + c) of the bordered record grid holds pixel
+  // (y0 + r - 1, x0 + c - 1); rows y0 .. y0+h+1, columns x0 .. x0+w+1
+  for (int q = threadIdx.x; q < rows * NCH; q += 256) {
+    const int r = q / NCH, k = q % NCH;
+    if (k < nch)
+      *reinterpret_cast<f32x4 *>(srec + r * RW * RREC + 4 * k) = *reinterpret_cast<
+          const PNP_GLOBAL f32x4 *>(S + ((int64_t)(tl.y0 + r) * spitch + tl.x0) * RREC + 4 * k);
+  }
+  __syncthreads();
   const float sc = a.oscale[0], bi = a.bias[0];
   const int npix = tl.h * tl.w;
   for (int pix = threadIdx.x; pix < npix; pix += 256) {
-    const int Y = tl.y0 + pix / tl.w, X = tl.x0 + pix % tl.w;
+    const int r = pix / tl.w, c = pix % tl.w;
     float acc = 0.0f;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      // output (Y, X) reads input (Y + dy - 1, X + dx - 1): record (Y + dy, X + dx)
+      // output (Y, X) reads input (Y + dy - 1, X + dx - 1): record (r + dy, c + dx)
       const int dy = tap / 3, dx = tap % 3;
-      acc += S[((Y + dy) * spitch + (X + dx)) * 12 + tap];
+      acc += srec[((r + dy) * RW + (c + dx)) * RREC + tap];
     }
-    gp(j.G)[(int64_t)Y * j.nx + X] = acc * sc + bi;
+    gp(j.G)[(int64_t)(tl.y0 + r) * j.nx + tl.x0 + c] = acc * sc + bi;
   }
 }
 
@@ -2165,6 +2179,7 @@ hipError_t launch_conv_mid_last(const ConvArgs &a, int n_wg, bool first, hipStre
 }
 
 hipError_t launch_g_from_s(const ConvArgs &a, int n_tiles, hipStream_t s) {
+  if (a.tile_rows < 1 || a.tile_rows > 16) return hipErrorInvalidValue;   // LDS sized for 16
   hipLaunchKernelGGL(g_from_s_kernel, dim3(n_tiles), dim3(256), 0, s, a);
   return hipGetLastError();
 }

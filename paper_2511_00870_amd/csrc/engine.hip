@@ -564,9 +564,12 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   j->t = 0;
   make_tiles(j->conv_tiles, ny, nx, j->block_y, j->block_x, conv_th, kConvTileW);
   make_tiles(j->upd_tiles, ny, nx, j->block_y, j->block_x, kUpdTileH, kUpdTileW);
-  // the two-layer kernel tiles the whole image: every block of one job lives
-  // in one set of activation buffers, so block edges need no tile edge
-  make_tiles(j->pair_tiles, ny, nx, ny, nx, kPairTileH, kPairTileW);
+  // the two-layer kernel tiles the whole image (every block of one job lives
+  // in one set of activation buffers, so block edges need no tile edge), in
+  // column bands 32 tiles wide, top to bottom: the 32 workgroups of an XCD
+  // take one band row at a time, and the next band row's windows overlap the
+  // previous one's while it is still in that XCD's L2
+  make_tiles(j->pair_tiles, ny, nx, ny, 32 * kPairTileW, kPairTileH, kPairTileW);
   if (hipStreamSynchronize(stream) != hipSuccess)
     return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
   *out = j;
