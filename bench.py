@@ -60,8 +60,11 @@ MFMA_CLASSES = {
         1, 2 * 9 * 64),
     5: ("conv_mid_rr_kernel<false,true> (last layer partials fused)",
         "conv_mid_rr_kernel<false, true>", 1, 2 * 9 * 64),
-    6: ("conv_pair_kernel (two middle layers)", "conv_pair_kernel", 2, 0),
+    6: ("conv_pair_ws_kernel (two bf16 middle layers, one per wave group)", "conv_pair_ws_kernel",
+        2, 0),
 }
+# class 6 for e4m3 networks
+PAIR8_CLASS = ("conv_pair8_kernel (two e4m3 middle layers)", "conv_pair8_kernel", 2, 0)
 
 
 def kernel_source_hash():
@@ -245,7 +248,7 @@ def main():
     }
     if busy:
         c = max(busy, key=lambda k: prof[k][0])
-        name, row, layers, extra = MFMA_CLASSES[c]
+        name, row, layers, extra = PAIR8_CLASS if (c == 6 and prec == 2) else MFMA_CLASSES[c]
         avg = prof[c][0] / prof[c][1] / 1e3
         flops_launch = (layers * 2.0 * 9 * F * F + extra) * npx
         ach = flops_launch / avg / 1e12

@@ -44,6 +44,9 @@
 #ifndef PNP_MID_RR
 #define PNP_MID_RR 1
 #endif
+#ifndef PNP_PAIR_WS
+#define PNP_PAIR_WS 1     // bf16 layer pairs: layers on separate waves (conv_pair_ws_kernel)
+#endif
 #ifndef PNP_PAIR_IGLP
 #define PNP_PAIR_IGLP 4   // two-layer kernel: vector ops placed after each MFMA (0: none)
 #endif
@@ -1421,6 +1424,255 @@ void conv_pair_kernel(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------
+// Two bf16 middle layers per kernel with the layers on separate waves.
+// Eight waves per workgroup: waves 0-3 run layer A of tile i (input window
+// -> intermediate) while waves 4-7 run layer B of tile i-1 (intermediate ->
+// memory); the intermediate is double-buffered in LDS.  Each wave keeps the
+// A fragments of one layer only (72 VGPRs), so two waves share a SIMD and
+// the epilogue, loads and barriers of one overlap the MFMAs of the other.
+// Output tiles are 8 x 30 (input window 12 x 34, intermediate 10 x 32): the
+// input window and two intermediates take 139 KB of LDS.  The layer-A waves
+// also load the next tile's window (moving those loads to the layer-B waves,
+// which have fewer MFMAs, spills registers).  Within a layer the
+// row order, B reads, LDS layout and epilogues are those of
+// conv_pair_kernel; wave w & 3 owns output channels 16 (w & 3) .. + 15.
+// ---------------------------------------------------------------------
+struct PairWsLayout {
+  static constexpr int F = 64, PIXB = 128, CPP = 8, NSTEP = 18, NTG = 256;
+  static constexpr int TH = kPairWsTileH, TW = kPairTileW;
+  static constexpr int MH = TH + 2, MW = TW + 2, IH = TH + 4, IW = TW + 4;
+  static constexpr int IN_BYTES = IH * IW * PIXB;
+  static constexpr int MID_BYTES = MH * IW * PIXB;
+  static constexpr int LDS_BYTES = IN_BYTES + 2 * MID_BYTES + 2 * F * 4;
+  static constexpr int NLOAD = IH + 1;          // row loads + one load for columns 32, 33
+};
+static_assert(PairWsLayout::MW == 32 && PairWsLayout::IW == 34 &&
+                  PairWsLayout::LDS_BYTES <= 160 * 1024,
+              "split-layer pair layout");
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void conv_pair_ws_kernel(ConvArgs a) {
+  using Lo = PairWsLayout;
+  constexpr int IW = Lo::IW, NLOAD = Lo::NLOAD;
+  constexpr int NIT = 6, PD = 2;                  // (dx, kh) steps per row; B reads ahead
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  uint8_t *lds_in = lds;
+  uint8_t *lds_mid = lds + Lo::IN_BYTES;          // two buffers of MID_BYTES
+  float *lds_bias = reinterpret_cast<float *>(lds_mid + 2 * Lo::MID_BYTES);   // [layer][64]
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int grp = wave >> 2, wq = wave & 3;       // layer (0: A, 1: B), channel block
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nwg = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3;
+  const int per_xcd = (nwg - xcd + 7) >> 3;
+  const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
+  const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
+
+  bf16x8 W[Lo::NSTEP];
+  {
+    const PNP_GLOBAL bf16x8 *wsrc = gp(reinterpret_cast<const bf16x8 *>(grp ? a.wblob2 : a.wblob));
+#pragma unroll
+    for (int s = 0; s < Lo::NSTEP; ++s) W[s] = wsrc[(s * 4 + wq) * 64 + lane];
+  }
+  if (tid < Lo::F) lds_bias[tid] = gp(a.bias)[tid];
+  else if (tid < 2 * Lo::F) lds_bias[tid] = gp(a.bias2)[tid - Lo::F];
+  // the intermediates' columns MW .. IW-1 are read only for the two padding
+  // output columns and never written: zero both buffers once
+  for (int i = tid; i < 2 * Lo::MID_BYTES / 16; i += 2 * Lo::NTG)
+    reinterpret_cast<u32x4 *>(lds_mid)[i] = u32x4{0u, 0u, 0u, 0u};
+
+  // Window loads by the layer-A waves (256 lanes), 16 bytes per lane: load r
+  // < IH is window row r, lane (c = tid / 8, k = tid % 8) taking chunk k of
+  // column c < 32; the last load takes the pixels of columns 32 and 33
+  // (lanes past them repeat one, storing the bytes its owner stores).
+  // Window pixel (r, c) is image pixel (y0 - 2 + r, x0 - 2 + c); positions
+  // beyond the one-pixel zero border read the border.
+  const int lc = (tid & 255) >> 3, lk = tid & 7;
+  auto lane_col = [&](const MidTile &c) -> uint32_t {
+    const int X = min(max(c.x0 - 2 + lc, -1), c.nx) + 1;
+    return (uint32_t)X * Lo::PIXB + (uint32_t)lk * 16u;
+  };
+  constexpr int NEDGE = 2 * Lo::IH;               // pixels in columns 32 and 33
+  auto load_chunk = [&](const MidTile &c, uint32_t lcol, auto ic) -> u32x4 {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (i < Lo::IH) {
+      const int Y = min(max(c.y0 - 2 + i, -1), c.ny) + 1;
+      return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+          c.in + (int64_t)Y * c.apitch * Lo::PIXB + lcol);
+    } else {
+      const int e0 = (i - Lo::IH) * 32 + lc, e = e0 < NEDGE ? e0 : (lc & 15);
+      const int Y = min(max(c.y0 - 2 + (e >> 1), -1), c.ny) + 1;
+      const int X = min(max(c.x0 + 30 + (e & 1), -1), c.nx) + 1;
+      return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+          c.in + ((int64_t)Y * c.apitch + X) * Lo::PIXB + lk * 16);
+    }
+  };
+  auto put_chunk = [&](auto ic, const u32x4 &v) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (i < Lo::IH) {
+      const int off = (lc << 7) + ((lk ^ ((2 * (i & 3) + lc) & 7)) << 4);
+      *reinterpret_cast<u32x4 *>(lds_in + i * IW * Lo::PIXB + off) = v;
+    } else {
+      const int e0 = (i - Lo::IH) * 32 + lc, e = e0 < NEDGE ? e0 : (lc & 15);
+      *reinterpret_cast<u32x4 *>(lds_in + rr_off((e >> 1) * IW + 32 + (e & 1), lk)) = v;
+    }
+  };
+  static_assert(NEDGE <= 32 && NEDGE >= 16, "edge loads");
+
+  int tA = t_begin + slot;
+  if (tA >= t_end) return;                       // uniform over the workgroup
+  MidTile dA = mid_tile(a, tA), dB = dA;
+  u32x4 pre[NLOAD];
+  if (grp == 0) {
+    const uint32_t lcol = lane_col(dA);
+    static_for<0, NLOAD>([&](auto ic) { pre[decltype(ic)::value] = load_chunk(dA, lcol, ic); });
+    static_for<0, NLOAD>([&](auto ic) { put_chunk(ic, pre[decltype(ic)::value]); });
+  }
+  // base[m][kh]: the lane's part of the swizzled address of chunk 4kh + g of
+  // pixel c + l16 for c = m (mod 8) (see conv_pair_kernel)
+  int bl[8][2];
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+      int v = 128 * l16 + (((4 * kh + g) ^ ((m + l16) & 7)) << 4);
+      asm volatile("" : "+v"(v));
+      bl[m][kh] = v;
+    }
+  __syncthreads();
+
+  const int hb = g & 1, cpos = 16 * hb + l16;     // this lane's pixel after the swap
+  bool haveB = false;
+  int it = 0;
+  while (true) {
+    const bool haveA = tA < t_end;                // uniform
+    const int tAn = tA + per_xcd;
+    const MidTile dAn = mid_tile(a, tAn < t_end ? tAn : t_begin);
+    f32x4 acc[4][2];
+    bf16x8 Bb[PD + 1][2];
+
+    auto layer = [&](const int (&base)[8][2], auto NRc, auto BIc, auto ep, auto pf) {
+      constexpr int NR = decltype(NRc)::value, NO = NR - 2, NSTG = NR * NIT;
+      constexpr int BI = decltype(BIc)::value;
+      auto load_b = [&](auto stc) {
+        constexpr int stg = decltype(stc)::value;
+        constexpr int ir = stg / NIT, it2 = stg % NIT, dx = it2 >> 1, kh = it2 & 1;
+        static_for<0, 2>([&](auto hc) {
+          constexpr int c = ir * IW + 16 * decltype(hc)::value + dx;
+          Bb[stg % (PD + 1)][decltype(hc)::value] =
+              *reinterpret_cast<const bf16x8 *>(lds + base[c & 7][kh] + 128 * c);
+        });
+      };
+      static_for<0, PD>(load_b);
+      static_for<0, NSTG>([&](auto stc) {
+        constexpr int stg = decltype(stc)::value;
+        constexpr int ir = stg / NIT, it2 = stg % NIT, dx = it2 >> 1, kh = it2 & 1;
+        if constexpr (stg + PD < NSTG) load_b(std::integral_constant<int, stg + PD>{});
+        pf(stc);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (it2 == 0 && ir < NO) {
+          const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + BI * Lo::F + 16 * wq + 4 * g);
+          acc[ir & 3][0] = bia;
+          acc[ir & 3][1] = bia;
+        }
+        static_for<0, 3>([&](auto dyc) {
+          constexpr int dy = decltype(dyc)::value, o = ir - dy;
+          if constexpr (o >= 0 && o < NO) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              acc[o & 3][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  W[(3 * dy + dx) * 2 + kh], Bb[stg % (PD + 1)][h], acc[o & 3][h], 0, 0, 0);
+          }
+        });
+        if constexpr (it2 == 1 && ir >= 3 && ir - 3 < NO) ep(std::integral_constant<int, ir - 3>{});
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      static_for<(NR - 3 > 0 ? NR - 3 : 0), NO>(ep);
+    };
+    // bf16, ReLU, then halves swapped between neighbouring 16-lane rows: each
+    // lane holds 8 channels of one pixel (block 0 for even rows, 1 for odd)
+    auto pack_row = [&](auto oc) -> u32x4 {
+      constexpr int o = decltype(oc)::value;
+      u32x2 w[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f32x4 v = acc[o & 3][h];
+        w[h].x = relu_bf16x2(pack_bf16x2(v[0], v[1]));
+        w[h].y = relu_bf16x2(pack_bf16x2(v[2], v[3]));
+      }
+      const auto sx = __builtin_amdgcn_permlane16_swap(w[0].x, w[1].x, false, false);
+      const auto sy = __builtin_amdgcn_permlane16_swap(w[0].y, w[1].y, false, false);
+      return u32x4{sx[0], sy[0], sx[1], sy[1]};
+    };
+
+    if (grp == 0) {
+      if (haveA) {
+        // layer A of tile tA: intermediate rows into buffer it & 1, zero
+        // outside the image; the next tile's window is loaded meanwhile
+        uint8_t *mid = lds_mid + (it & 1) * Lo::MID_BYTES;
+        const uint32_t in_x = (unsigned)(dA.x0 - 1 + cpos) < (unsigned)dA.nx ? ~0u : 0u;
+        const uint32_t lcol_n = lane_col(dAn);
+        auto epA = [&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          const uint32_t in_y = (unsigned)(dA.y0 - 1 + o) < (unsigned)dA.ny ? ~0u : 0u;
+          const uint32_t keep = in_y & in_x;
+          u32x4 q = pack_row(oc);
+          q &= u32x4{keep, keep, keep, keep};
+          *reinterpret_cast<u32x4 *>(mid + rr_off(o * IW + cpos, 2 * wq + (g >> 1))) = q;
+        };
+        auto pfA = [&](auto stc) {
+          constexpr int stg = decltype(stc)::value;
+          if constexpr (stg >= 4 && stg < 4 + NLOAD)
+            pre[stg - 4] = load_chunk(dAn, lcol_n, std::integral_constant<int, stg - 4>{});
+        };
+        layer(bl, std::integral_constant<int, Lo::IH>{}, std::integral_constant<int, 0>{}, epA,
+              pfA);
+      }
+    } else {
+      if (haveB) {
+        // layer B of the previous tile from buffer (it - 1) & 1 to memory;
+        // lanes outside the tile (and the padding columns) store to the trash
+        int bm[8][2];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+          for (int kh = 0; kh < 2; ++kh) {
+            int v = bl[m][kh] + Lo::IN_BYTES + ((it - 1) & 1) * Lo::MID_BYTES;
+            asm volatile("" : "+v"(v));
+            bm[m][kh] = v;
+          }
+        const int64_t lane_b = 32 * wq + 16 * (g >> 1);
+        const int64_t trash_b = dB.trash * Lo::PIXB + lane_b;
+        const int64_t col_b = (int64_t)(dB.x0 + cpos + 1) * Lo::PIXB + lane_b;
+        const int64_t ok_c = cpos < dB.w ? -1 : 0;
+        auto epB = [&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          const int64_t ok = (o < dB.h ? -1 : 0) & ok_c;
+          const int64_t roff = (int64_t)(dB.y0 + o + 1) * dB.apitch * Lo::PIXB;
+          const u32x4 q = pack_row(oc);
+          const int64_t bo = ((col_b + roff) & ok) | (trash_b & ~ok);
+          *reinterpret_cast<PNP_GLOBAL u32x4 *>(dB.out + bo) = q;
+        };
+        auto pfB = [&](auto) {};
+        layer(bm, std::integral_constant<int, Lo::MH>{}, std::integral_constant<int, 1>{}, epB,
+              pfB);
+      }
+    }
+    __syncthreads();                             // intermediate written / read, window read
+    if (!haveA) break;                           // uniform: the last tile's layer B is done
+    if (grp == 0) static_for<0, NLOAD>([&](auto ic) { put_chunk(ic, pre[decltype(ic)::value]); });
+    __syncthreads();                             // next window in place
+    dB = dA;
+    haveB = true;
+    dA = dAn;
+    tA = tAn;
+    ++it;
+  }
+}
+
+// ---------------------------------------------------------------------
 // Middle layers, row-reuse form for e4m3 input (F = 64; output e4m3 or
 // bf16).  v_mfma_scale_f32_16x16x128_f8f6f4 takes K = 128 = two taps of 64
 // channels: lane groups 0-1 carry one tap, groups 2-3 another.  Pairing the
@@ -2184,10 +2436,27 @@ hipError_t launch_g_from_s(const ConvArgs &a, int n_tiles, hipStream_t s) {
   return hipGetLastError();
 }
 
+bool pair_ws_enabled() { return PNP_PAIR_WS; }
+
 bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt2, int out_fmt2,
                   int relu2, int unit2) {
   return PNP_MID_RR && in_fmt == FMT_BF16 && out_fmt == FMT_BF16 && F == 64 && relu && unit &&
          in_fmt2 == FMT_BF16 && out_fmt2 == FMT_BF16 && relu2 && unit2;
+}
+
+hipError_t launch_conv_pair_ws(const ConvArgs &a, int n_wg, hipStream_t s) {
+  if (!a.wblob || !a.wblob2 || !a.bias || !a.bias2 || n_wg <= 0 || n_wg % 8 != 0)
+    return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_pair_ws_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       PairWsLayout::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(conv_pair_ws_kernel, dim3(n_wg), dim3(512), PairWsLayout::LDS_BYTES, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_conv_pair(const ConvArgs &a, int n_wg, hipStream_t s) {

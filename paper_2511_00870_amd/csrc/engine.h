@@ -59,6 +59,7 @@ struct Job {
   std::vector<void *> allocs;
   std::vector<TileRef> conv_tiles, upd_tiles;   // job field = 0 (set at planning)
   std::vector<TileRef> pair_tiles;              // two-layer kernel: whole-image tiling
+  std::vector<TileRef> pair_ws_tiles;           // split-layer pair kernel (bf16)
 };
 
 struct ProfileRec {
@@ -116,9 +117,9 @@ class Engine {
   Status run_fused_denoiser(int64_t tick, bool prof);
   Status launch_layer(int k, int64_t tick, bool prof, int in_slot = -1, int out_slot = -1);
   JobDesc *d_jobs = nullptr;
-  TileRef *d_conv = nullptr, *d_upd = nullptr, *d_pair = nullptr;
-  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0, cap_pair = 0;
-  int n_conv = 0, n_upd = 0, n_pair = 0, max_r = 0;
+  TileRef *d_conv = nullptr, *d_upd = nullptr, *d_pair = nullptr, *d_pair_ws = nullptr;
+  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0, cap_pair = 0, cap_pair_ws = 0;
+  int n_conv = 0, n_upd = 0, n_pair = 0, n_pair_ws = 0, max_r = 0;
   bool uniform_r = true;      // every resident job has blur half-width max_r
   int conv_th = 16;
   bool profiling = false;

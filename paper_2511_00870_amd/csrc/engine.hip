@@ -83,6 +83,7 @@ Engine::~Engine() {
   hipFree(d_conv);
   hipFree(d_upd);
   hipFree(d_pair);
+  hipFree(d_pair_ws);
   for (auto &r : prof_pending) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
@@ -570,6 +571,7 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   // take one band row at a time, and the next band row's windows overlap the
   // previous one's while it is still in that XCD's L2
   make_tiles(j->pair_tiles, ny, nx, ny, 32 * kPairTileW, kPairTileH, kPairTileW);
+  make_tiles(j->pair_ws_tiles, ny, nx, ny, 32 * kPairTileW, kPairWsTileH, kPairTileW);
   if (hipStreamSynchronize(stream) != hipSuccess)
     return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
   *out = j;
@@ -586,7 +588,7 @@ void Engine::free_job(Job *j) {
 // plans
 // ---------------------------------------------------------------------
 Status Engine::rebuild_plan() {
-  std::vector<TileRef> conv, upd, pair;
+  std::vector<TileRef> conv, upd, pair, pair_ws;
   max_r = 0;
   uniform_r = true;
   for (size_t ji = 0; ji < resident.size(); ++ji) {
@@ -602,6 +604,10 @@ Status Engine::rebuild_plan() {
     for (TileRef t : j->pair_tiles) {
       t.job = (int)ji;
       pair.push_back(t);
+    }
+    for (TileRef t : j->pair_ws_tiles) {
+      t.job = (int)ji;
+      pair_ws.push_back(t);
     }
     if (ji > 0 && j->d.r != max_r) uniform_r = false;
     max_r = std::max(max_r, j->d.r);
@@ -623,6 +629,7 @@ Status Engine::rebuild_plan() {
   TRY(grow(&d_conv, cap_conv, std::max<size_t>(conv.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_upd, cap_upd, std::max<size_t>(upd.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_pair, cap_pair, std::max<size_t>(pair.size(), 1), sizeof(TileRef)));
+  TRY(grow(&d_pair_ws, cap_pair_ws, std::max<size_t>(pair_ws.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_jobs, cap_jobs, std::max<size_t>(resident.size(), 1), sizeof(JobDesc)));
   if (!conv.empty())
     HIPOK(hipMemcpyAsync(d_conv, conv.data(), conv.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
@@ -630,8 +637,11 @@ Status Engine::rebuild_plan() {
     HIPOK(hipMemcpyAsync(d_upd, upd.data(), upd.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
   if (!pair.empty())
     HIPOK(hipMemcpyAsync(d_pair, pair.data(), pair.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
+  if (!pair_ws.empty())
+    HIPOK(hipMemcpyAsync(d_pair_ws, pair_ws.data(), pair_ws.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
   n_conv = (int)conv.size();
   n_pair = (int)pair.size();
+  n_pair_ws = (int)pair_ws.size();
   n_upd = (int)upd.size();
   plan_dirty = false;
   return upload_descs();
@@ -887,10 +897,16 @@ Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool 
   const int n_wg = std::max(8, std::min(n_cu * per_cu, need) / 8 * 8);
   ProfileRec pr;
   if (prof) prof_begin(6, &pr);
-  if (e4m3)
+  if (e4m3) {
     HIPOK(launch_conv_pair8(a, B.out_fmt, first, last, n_wg, stream));
-  else
+  } else if (pair_ws_enabled()) {
+    a.tiles = d_pair_ws;
+    a.n_tiles = n_pair_ws;
+    const int need_ws = ((n_pair_ws + 7) / 8) * 8;
+    HIPOK(launch_conv_pair_ws(a, std::max(8, std::min(n_cu, need_ws) / 8 * 8), stream));
+  } else {
     HIPOK(launch_conv_pair(a, n_wg, stream));
+  }
   if (prof) prof_end(&pr);
   return Status::ok();
 }
