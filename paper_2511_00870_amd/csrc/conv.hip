@@ -1430,8 +1430,8 @@ void conv_pair_kernel(ConvArgs a) {
 // memory); the intermediate is double-buffered in LDS.  Each wave keeps the
 // A fragments of one layer only (72 VGPRs), so two waves share a SIMD and
 // the epilogue, loads and barriers of one overlap the MFMAs of the other.
-// Output tiles are 8 x 30 (input window 12 x 34, intermediate 10 x 32): the
-// input window and two intermediates take 139 KB of LDS.  The layer-A waves
+// Output tiles are 9 x 30 (input window 13 x 34, intermediate 11 x 32): the
+// input window and two intermediates take 153 KB of LDS.  The layer-A waves
 // also load the next tile's window (moving those loads to the layer-B waves,
 // which have fewer MFMAs, spills registers).  Within a layer the
 // row order, B reads, LDS layout and epilogues are those of

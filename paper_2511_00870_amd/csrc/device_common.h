@@ -16,7 +16,7 @@ constexpr int kUpdThreads = 512;
 constexpr int kConvTileW = 32;     // convolution tiles are TH x 32 pixels
 constexpr int kPairTileH = 14;     // two-layer middle kernel: output tiles of 14 x 30
 constexpr int kPairTileW = 30;
-constexpr int kPairWsTileH = 8;   // split-layer pair kernel: output tiles of 8 x 30
+constexpr int kPairWsTileH = 9;   // split-layer pair kernel: output tiles of 9 x 30
 
 // One chain resident on the device.  All images live in padded row-major
 // buffers whose zero border is never written, so stencils read it as the
