@@ -153,7 +153,9 @@ pnpula_status pnpula_calibrate(pnpula_ctx *ctx, const float *x, float *amax);
  * the first middle layer, 5 = last middle layer writing the last layer's
  * per-tap partials (both bf16 networks; class 2 then times the kernel that
  * sums the partials into G), 6 = two consecutive middle layers in one
- * kernel (bf16 networks).  Enabling resets totals. */
+ * kernel (bf16 and e4m3 networks; for e4m3 the first pair also runs the first
+ * layer and the last pair the last layer's partials, class 2 again timing the
+ * sums).  Enabling resets totals. */
 pnpula_status pnpula_profile(pnpula_ctx *ctx, int32_t enable);
 pnpula_status pnpula_profile_read(pnpula_ctx *ctx, int32_t kernel_class, double *total_ms,
                                   int64_t *launches);
