@@ -42,8 +42,10 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
   float *sx = smem;                                  // WH x WW
   float *sh = sx + WH * WW;                          // WH x RW  (row pass of x)
   float *sres = sh + WH * RW;                        // RH x RW
-  float *shr = sres + RH * RW;                       // RH x TW  (row pass of res)
-  float *sxi = shr + RH * TW;                        // TH x TW
+  float *sxi = sres + RH * RW;                       // TH x TW
+  // RH x TW (row pass of the residual): reuses the row pass of x, whose last
+  // reader (the residual pass) ends at the barrier before it is written
+  float *shr = sh;
   const int tid = threadIdx.x;
   const PNP_GLOBAL float *xin = gp(j.x[t & 1]);
   const int B = j.xborder;
@@ -277,8 +279,9 @@ hipError_t launch_amax(const float *p, size_t n, uint32_t *out, hipStream_t s) {
 size_t update_lds_bytes(int r) {
   const int TH = kUpdTileH, TW = kUpdTileW;
   const int WH = TH + 4 * r, WW = TW + 4 * r, RH = TH + 2 * r, RW = TW + 2 * r;
+  // the residual's row pass shares the x row pass's buffer (RH x TW <= WH x RW)
   return sizeof(float) * ((size_t)WH * WW + (size_t)WH * RW + (size_t)RH * RW +
-                          (size_t)RH * TW + (size_t)TH * TW);
+                          (size_t)TH * TW);
 }
 
 template <int RT>
