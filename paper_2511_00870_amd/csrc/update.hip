@@ -22,6 +22,8 @@
 
 namespace pnp {
 
+typedef float upd_f32x4 __attribute__((ext_vector_type(4)));
+
 // RT > 0: every tile's blur half-width is RT (window sizes, divisions and
 // tap loops become compile-time constants); RT = 0: read per job.
 template <int RT>
@@ -37,6 +39,10 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
   constexpr int RQ = ((TH + 2 * RM) * (TW + 2 * RM) + NT - 1) / NT;
   constexpr int CQ = TH * TW / NT;
   constexpr int XQ = ((TH + 4 * RM) * (TW + 4 * RM) + NT - 1) / NT;
+  // 16-byte slots of the x window (fixed widths: its rows are TW + 4r wide,
+  // a multiple of 4) and the registers holding either form of the window
+  constexpr int XQ4 = ((TH + 4 * RM) * (TW + 4 * RM) / 4 + NT - 1) / NT;
+  constexpr int XS = XQ > 4 * XQ4 ? XQ : 4 * XQ4;
   const int WH = TH + 4 * r, WW = TW + 4 * r;       // x window
   const int RH = TH + 2 * r, RW = TW + 2 * r;       // K x / residual region
   float *sx = smem;                                  // WH x WW
@@ -79,12 +85,30 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
   //    ignore the value, so the waits fall where the values are used)
   const int wy = tl.y0 - 2 * r, wx = tl.x0 - 2 * r;
   const int64_t xpitch = j.xpitch;
-  float xv[XQ];
+  // 16-byte loads when the window's rows start 16-byte aligned (uniform:
+  // the tile's first column, the border and the pitch decide it)
+  const bool xvec = RT > 0 && ((wx + B) & 3) == 0 && (xpitch & 3) == 0;
+  float xv[XS];
+  if (xvec) {
+    constexpr int WW4 = RT > 0 ? (TW + 4 * RT) / 4 : 1;
 #pragma unroll
-  for (int k = 0; k < XQ; ++k) {
-    const int q0 = tid + NT * k, q = q0 < WH * WW ? q0 : 0;
-    const int i = q / WW, c = q % WW;
-    xv[k] = xin[(wy + i + B) * xpitch + (wx + c + B)];
+    for (int k = 0; k < XQ4; ++k) {
+      const int q0 = tid + NT * k, q = q0 < WH * WW4 ? q0 : 0;
+      const int i = q / WW4, c4 = q % WW4;
+      const upd_f32x4 v = *reinterpret_cast<const PNP_GLOBAL upd_f32x4 *>(
+          xin + (wy + i + B) * xpitch + (wx + B + 4 * c4));
+      xv[4 * k] = v.x;
+      xv[4 * k + 1] = v.y;
+      xv[4 * k + 2] = v.z;
+      xv[4 * k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < XQ; ++k) {
+      const int q0 = tid + NT * k, q = q0 < WH * WW ? q0 : 0;
+      const int i = q / WW, c = q % WW;
+      xv[k] = xin[(wy + i + B) * xpitch + (wx + c + B)];
+    }
   }
   const PNP_GLOBAL float *yb = gp(j.y);
   const PNP_GLOBAL uint8_t *mk = gp(j.has_mask ? j.mask : reinterpret_cast<const uint8_t *>(j.y));
@@ -122,10 +146,20 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
     if (tid < nk) skern[tid] = tap0;
     if (tid + NT < nk) skern[tid + NT] = tap1;
   }
+  if (xvec) {
 #pragma unroll
-  for (int k = 0; k < XQ; ++k) {
-    const int q = tid + NT * k;
-    if (NT * k < WH * WW && q < WH * WW) sx[q] = xv[k];
+    for (int k = 0; k < XQ4; ++k) {
+      const int q = tid + NT * k;
+      if (4 * q < WH * WW)
+        *reinterpret_cast<upd_f32x4 *>(sx + 4 * q) =
+            upd_f32x4{xv[4 * k], xv[4 * k + 1], xv[4 * k + 2], xv[4 * k + 3]};
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < XQ; ++k) {
+      const int q = tid + NT * k;
+      if (NT * k < WH * WW && q < WH * WW) sx[q] = xv[k];
+    }
   }
   __syncthreads();
 
