@@ -200,7 +200,7 @@ def serving(a, stream):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the sampler runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2511_00870_amd import workloads as W
