@@ -17,7 +17,7 @@
  * denoiser D_eps = Id - G (DnCNN form, Sec. II-B1 Example 2: a stack of
  * 3x3 convolutions with zero "half" padding, ReLU on all but the last
  * layer), and online Welford mean / variance of the samples after burn-in
- * (the MMSE estimate and the pixel-wise variance map, Sec. IV-C).
+ * (the MMSE estimate and the pixel-wise variance map, Sec. III-C).
  *
  * The image is split into blocks of block_y x block_x pixels with a halo
  * of `halo` pixels (Sec. II-A Defs. 1-2; Sec. II-B2): every block is

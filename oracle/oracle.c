@@ -12,7 +12,7 @@
  *   - posterior and splitting: Sec. II-C, Eq. (general_posterior_l2_axda),
  *     conditionals (sgs:marginal_x), (sgs:marginal_z);
  *   - PnP-ULA x-transition: Eq. (sgs_pnp_ula_psgla:pnp_ula), Algorithm 1;
- *   - Gaussian likelihood, mask and blur operators: Sec. IV-A1, IV-A2,
+ *   - Gaussian likelihood, mask and blur operators: Sec. III-A1, III-A2,
  *     Eq. (likelihood:gaussian_inpainting), (potential_gaussian_likelihood);
  *   - CNN denoiser: Sec. II-B1 Eqs. (feedforward_cnn), (cnn:convolution),
  *     Example 2 (DnCNN: D = Id - G, ReLU except on the last layer);
@@ -513,7 +513,7 @@ static void grad_window(const grad_ctx *gc, const double *win, int oy, int ox, i
             draw_pixel(gc->seed, p, t, gc->chain, &xi_unused, &zeta);
             z = (gc->rho * gc->y[p] + sig2 * (m * kx[q])) / (gc->rho + sig2) + zsd * zeta;
           } else {
-            z = 0.0;  /* z^(0) = 0 (Sec. IV-B) */
+            z = 0.0;  /* z^(0) = 0 (Sec. III-B) */
           }
           v = z;
         } else {

@@ -29,38 +29,10 @@
 #include "device_common.h"
 #include "kernels.h"
 
-// Implementation choices of the middle-layer kernels (all compute the same
-// result): register pipeline across K steps, LDS-staged epilogue, the
-// row-reuse kernel for bf16 with 64 channels, and the XCD-aware tile order.
-#ifndef PNP_MID_PIPE
-#define PNP_MID_PIPE 1
-#endif
-#ifndef PNP_MID_STAGE
-#define PNP_MID_STAGE 1
-#endif
-#ifndef PNP_NW_LOWP
-#define PNP_NW_LOWP 8
-#endif
-#ifndef PNP_MID_RR
-#define PNP_MID_RR 1
-#endif
-#ifndef PNP_PAIR_WS
-#define PNP_PAIR_WS 1     // bf16 layer pairs: layers on separate waves (conv_pair_ws_kernel)
-#endif
-#ifndef PNP_PAIR_IGLP
-#define PNP_PAIR_IGLP 4   // two-layer kernel: vector ops placed after each MFMA (0: none)
-#endif
-#ifndef PNP_RR_PD
-#define PNP_RR_PD 3
-#endif
-#ifndef PNP_RR_LPS
-#define PNP_RR_LPS 1
-#endif
-#ifndef PNP_XCD_MAP
-#define PNP_XCD_MAP 1
-#endif
-
 namespace pnp {
+
+constexpr int kNwLowp = 8;      // waves of the generic middle-layer kernel for bf16 / e4m3 input
+constexpr int kPair8Wpe = 2;    // waves per SIMD the e4m3 pair kernel is compiled for
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -490,7 +462,7 @@ struct MidLayout {
   static constexpr int OPIXB = F * OB;               // bytes of one output pixel
   static constexpr int OSTR = OPIXB + 16;            // LDS stride of staged outputs
   static constexpr int IN_BYTES = IH * IW * C::PSTR;
-  static constexpr int OUT_BYTES = PNP_MID_STAGE ? TH * TW * OSTR : 0;
+  static constexpr int OUT_BYTES = TH * TW * OSTR;
   static constexpr int TILE_BYTES = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
   static constexpr int LDS_BYTES = TILE_BYTES + C::WBYTES + 2 * F * 4;   // + scale, bias
   static_assert(LDS_BYTES <= 160 * 1024, "LDS");
@@ -522,14 +494,10 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
   // contiguous tile ranges per XCD (workgroups are dispatched round-robin
   // over the 8 XCDs): neighbouring tiles share their halo rows in one L2
   const int nwg = gridDim.x, b = blockIdx.x;
-#if PNP_XCD_MAP
   const int xcd = b & 7, slot = b >> 3;
   const int per_xcd = (nwg - xcd + 7) >> 3;
   const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
   const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
-#else
-  const int slot = b, per_xcd = nwg, t_begin = 0, t_end = a.n_tiles;
-#endif
 
   auto load_weights = [&](int chunk) {
     const PNP_GLOBAL u32x4 *src = gp(reinterpret_cast<const u32x4 *>(
@@ -656,7 +624,6 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
         load_weights(ch);
         __syncthreads();
       }
-#if PNP_MID_PIPE
       // two-stage register pipeline: the next step's LDS reads are issued
       // before the current step's MFMAs
       AT A0[MB], B0[4], A1[MB], B1[4];
@@ -671,17 +638,8 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
           mma_step(A1, B1, acc);
         }
       }
-#else
-#pragma unroll 1
-      for (int sl = 0; sl < C::STEPS_PER_CH; ++sl) {
-        AT A0[MB], B0[4];
-        load_step(ch * C::STEPS_PER_CH + sl, sl, A0, B0);
-        mma_step(A0, B0, acc);
-      }
-#endif
     }
 
-#if PNP_MID_STAGE
     // epilogue: scale, bias, ReLU, round to the next layer's format, stage
     // the tile in LDS (over the consumed input tile), then store whole
     // pixels with 16-byte lanes
@@ -724,33 +682,6 @@ __global__ __launch_bounds__(NW * 64) void conv_mid_kernel(ConvArgs a) {
         }
       }
     }
-#else
-    // epilogue: scale, bias, ReLU, round to the next layer's format, store
-    // 4 consecutive channels of one pixel per lane
-    {
-      PNP_GLOBAL uint8_t *out = tl.out;
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int r = 2 * wave + (nb >> 1), c = (nb & 1) * 16 + l16;
-        if (r < tl.h && c < tl.w) {
-          PNP_GLOBAL uint8_t *dst = out + ((int64_t)(tl.y0 + r + 1) * tl.apitch + (tl.x0 + c + 1)) * Lo::OPIXB;
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) {
-            const f32x4 osc = *reinterpret_cast<const f32x4 *>(lds_osc + mb * 16 + 4 * g);
-            const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + mb * 16 + 4 * g);
-            f32x4 v;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              float o = acc[mb][nb][e] * osc[e] + bia[e];
-              if (a.relu) o = fmaxf(o, 0.0f);
-              v[e] = o;
-            }
-            store4<OUT_FMT>(dst + (mb * 16 + 4 * g) * OB, v, a.out_inv_scale);
-          }
-        }
-      }
-    }
-#endif
     tl = nxt;
     nxt = after;
     ti = tn;
@@ -818,14 +749,10 @@ void conv_mid_rr_kernel(ConvArgs a) {
   const int g = lane >> 4, l16 = lane & 15;
 
   const int nwg = gridDim.x, b = blockIdx.x;
-#if PNP_XCD_MAP
   const int xcd = b & 7, slot = b >> 3;
   const int per_xcd = (nwg - xcd + 7) >> 3;
   const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
   const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
-#else
-  const int slot = b, per_xcd = nwg, t_begin = 0, t_end = a.n_tiles;
-#endif
 
   {
     const PNP_GLOBAL u32x4 *src = gp(reinterpret_cast<const u32x4 *>(a.wblob));
@@ -1002,7 +929,7 @@ void conv_mid_rr_kernel(ConvArgs a) {
     // rows): the B fragments of the stage PD ahead and the next iteration's
     // A fragments are read from LDS while this stage's MFMAs run.
     // Scheduling barriers keep each stage's reads ahead of its MFMAs.
-    constexpr int NIT = 6, NR = ROWS + 2, NSTG = NIT * NR, PD = PNP_RR_PD;
+    constexpr int NIT = 6, NR = ROWS + 2, NSTG = NIT * NR, PD = 3;
     bf16x8 Ab[2][3][MB], Bb[PD + 1][2];
     auto load_a = [&](int it, int dy) {
       const int dx = it >> 1, kh = it & 1;
@@ -1028,7 +955,7 @@ void conv_mid_rr_kernel(ConvArgs a) {
       if (stg + PD < NSTG) load_b(stg + PD);
       if (it + 1 < NIT && ir >= 2 && ir <= 4) load_a(it + 1, ir - 2);
       if constexpr (!FIRST) {
-        constexpr int LPS = PNP_RR_LPS;                  // global loads per stage
+        constexpr int LPS = 1;                  // global loads per stage
 #pragma unroll
         for (int i = stg * LPS; i < (stg + 1) * LPS; ++i)
           if (i < NLOAD) issue_load(nxt, i);
@@ -1124,25 +1051,6 @@ void conv_mid_rr_kernel(ConvArgs a) {
   }
 }
 
-// ---------------------------------------------------------------------
-// Two consecutive bf16 middle layers (F = 64, ReLU, unit output scales) in
-// one persistent kernel, so that the activation between them never goes to
-// memory.  Per output tile of 14 x 30 pixels: layer A computes the 16 x 32
-// intermediate activation (the tile and a one-pixel ring, plus two padding
-// columns) from the 18 x 34 input window into LDS -- bf16, ReLU, and zero at
-// positions outside the image, which is layer B's zero padding -- and layer B
-// computes the tile from it.
-//
-// Wave w owns output channels 16w .. 16w+15 of both layers and keeps their A
-// fragments (18 K steps each) in registers for the whole kernel, so LDS holds
-// activations only; every wave reads every B fragment.  Work runs input row
-// by input row: the B fragment of input row ir serves output rows ir, ir-1
-// and ir-2 (taps dy = 0, 1, 2), so output row o is complete after input row
-// o + 2 and four accumulator row slots suffice.  The next tile's window is
-// loaded into registers in two halves, one issued during layer A and one at
-// the start of layer B, and each is copied into the input buffer once layer
-// A has finished reading it: three barriers per tile.
-// ---------------------------------------------------------------------
 // calls fn(std::integral_constant<int, i>) for i = I .. N-1 in order (a loop
 // unrolled by construction, whatever its body's size)
 template <int I, int N, class Fn>
@@ -1150,276 +1058,6 @@ __device__ __forceinline__ void static_for(Fn &&fn) {
   if constexpr (I < N) {
     fn(std::integral_constant<int, I>{});
     static_for<I + 1, N>(fn);
-  }
-}
-
-struct PairLayout {
-  static constexpr int F = 64, PIXB = 128, CPP = 8, NSTEP = 18, NT = 256;
-  static constexpr int TH = kPairTileH, TW = kPairTileW;   // output tile
-  static constexpr int MH = TH + 2, MW = TW + 2;            // intermediate rows x columns
-  static constexpr int IH = TH + 4, IW = TW + 4;            // input window
-  static constexpr int IN_BYTES = IH * IW * PIXB;
-  static constexpr int MID_BYTES = MH * IW * PIXB;          // row pitch IW, like the window
-  static constexpr int LDS_BYTES = IN_BYTES + MID_BYTES + 2 * F * 4;
-  static constexpr int NCHUNK = IH * IW * CPP, NLOAD = (NCHUNK + NT - 1) / NT;
-  static constexpr int NL1 = NLOAD / 2, NL2 = NLOAD - NL1;  // the two prefetch halves
-};
-static_assert(PairLayout::MW == 32 && PairLayout::LDS_BYTES <= 160 * 1024, "pair layout");
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void conv_pair_kernel(ConvArgs a) {
-  using Lo = PairLayout;
-  constexpr int NT = Lo::NT, IW = Lo::IW, NL1 = Lo::NL1, NL2 = Lo::NL2;
-  constexpr int NIT = 6, PD = 2;                  // (dx, kh) steps per row; B reads ahead
-  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-  uint8_t *lds_in = lds;
-  uint8_t *lds_mid = lds + Lo::IN_BYTES;
-  float *lds_bias = reinterpret_cast<float *>(lds_mid + Lo::MID_BYTES);   // [layer][64]
-
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = lane >> 4, l16 = lane & 15;
-  const int nwg = gridDim.x, b = blockIdx.x;
-  const int xcd = b & 7, slot = b >> 3;
-  const int per_xcd = (nwg - xcd + 7) >> 3;
-  const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
-  const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
-
-  // this wave's A fragments of both layers: fragment (step s, block wave)
-  bf16x8 WA[Lo::NSTEP], WB[Lo::NSTEP];
-  {
-    const PNP_GLOBAL bf16x8 *wa = gp(reinterpret_cast<const bf16x8 *>(a.wblob));
-    const PNP_GLOBAL bf16x8 *wb = gp(reinterpret_cast<const bf16x8 *>(a.wblob2));
-#pragma unroll
-    for (int s = 0; s < Lo::NSTEP; ++s) {
-      WA[s] = wa[(s * 4 + wave) * 64 + lane];
-      WB[s] = wb[(s * 4 + wave) * 64 + lane];
-    }
-  }
-  if (tid < Lo::F) lds_bias[tid] = gp(a.bias)[tid];
-  else if (tid < 2 * Lo::F) lds_bias[tid] = gp(a.bias2)[tid - Lo::F];
-  // the intermediate's columns MW .. IW-1 are read only for the two padding
-  // output columns and never written: zero them once
-  for (int i = tid; i < Lo::MID_BYTES / 16; i += NT)
-    reinterpret_cast<u32x4 *>(lds_mid)[i] = u32x4{0u, 0u, 0u, 0u};
-
-  // Window loads, 16 bytes per lane: load r < IH is window row r, lane
-  // (c = tid / 8, k = tid % 8) taking chunk k of column c < 32; the last two
-  // loads take the 36 pixels of columns 32 and 33 (lanes past them repeat
-  // one, storing the bytes its owner stores).  Window pixel (r, c) is image
-  // pixel (y0 - 2 + r, x0 - 2 + c); positions beyond the one-pixel zero
-  // border read the border.  A row load's address is a scalar row part plus
-  // a per-tile lane part (lane_col).
-  const int lc = tid >> 3, lk = tid & 7;
-  auto lane_col = [&](const MidTile &c) -> uint32_t {
-    const int X = min(max(c.x0 - 2 + lc, -1), c.nx) + 1;
-    return (uint32_t)X * Lo::PIXB + (uint32_t)lk * 16u;
-  };
-  auto load_chunk = [&](const MidTile &c, uint32_t lcol, auto ic) -> u32x4 {
-    constexpr int i = decltype(ic)::value;
-    if constexpr (i < Lo::IH) {
-      const int Y = min(max(c.y0 - 2 + i, -1), c.ny) + 1;
-      return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
-          c.in + (int64_t)Y * c.apitch * Lo::PIXB + lcol);
-    } else {
-      const int e = i == Lo::IH ? lc : 32 + (lc & 3);
-      const int Y = min(max(c.y0 - 2 + (e >> 1), -1), c.ny) + 1;
-      const int X = min(max(c.x0 + 30 + (e & 1), -1), c.nx) + 1;
-      return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
-          c.in + ((int64_t)Y * c.apitch + X) * Lo::PIXB + lk * 16);
-    }
-  };
-  auto put_chunk = [&](auto ic, const u32x4 &v) {
-    constexpr int i = decltype(ic)::value;
-    if constexpr (i < Lo::IH) {
-      // pixel i*IW + lc: its low three bits are (2i + lc) mod 8
-      const int off = (lc << 7) + ((lk ^ ((2 * (i & 3) + lc) & 7)) << 4);
-      *reinterpret_cast<u32x4 *>(lds_in + i * IW * Lo::PIXB + off) = v;
-    } else {
-      const int e = i == Lo::IH ? lc : 32 + (lc & 3);
-      *reinterpret_cast<u32x4 *>(lds_in + rr_off((e >> 1) * IW + 32 + (e & 1), lk)) = v;
-    }
-  };
-  static_assert(Lo::IW == 34 && Lo::NLOAD == Lo::IH + 2, "window load mapping");
-
-  int ti = t_begin + slot;
-  if (ti >= t_end) return;                       // uniform over the workgroup
-  MidTile cur = mid_tile(a, ti);
-  MidTile nxt = mid_tile(a, ti + per_xcd < t_end ? ti + per_xcd : t_begin);
-  u32x4 pre[NL2];
-  {
-    const uint32_t lcol = lane_col(cur);
-    static_for<0, NL1>([&](auto ic) { pre[decltype(ic)::value] = load_chunk(cur, lcol, ic); });
-    static_for<0, NL1>([&](auto ic) { put_chunk(ic, pre[decltype(ic)::value]); });
-    static_for<0, NL2>([&](auto ic) {
-      pre[decltype(ic)::value] =
-          load_chunk(cur, lcol, std::integral_constant<int, NL1 + decltype(ic)::value>{});
-    });
-    static_for<0, NL2>([&](auto ic) {
-      put_chunk(std::integral_constant<int, NL1 + decltype(ic)::value>{}, pre[decltype(ic)::value]);
-    });
-  }
-  __syncthreads();
-  int base_in[8][2], base_mid[8][2];
-#pragma unroll
-  for (int m = 0; m < 8; ++m)
-#pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-      // opaque registers: folded back into the immediates, the intermediate's
-      // offsets would exceed the 16-bit LDS offset field
-      int v = 128 * l16 + (((4 * kh + g) ^ ((m + l16) & 7)) << 4), u = v + Lo::IN_BYTES;
-      asm volatile("" : "+v"(v), "+v"(u));
-      base_in[m][kh] = v;
-      base_mid[m][kh] = u;
-    }
-
-  while (true) {
-    const int tn = ti + per_xcd, tnn = tn + per_xcd;
-    const MidTile after = mid_tile(a, tnn < t_end ? tnn : t_begin);
-    const uint32_t lcol_n = lane_col(nxt);
-    f32x4 acc[4][2];
-    bf16x8 Bb[PD + 1][2];
-
-    // one layer over NR input rows of src (pitch IW) into NO = NR - 2 output
-    // rows; ep(o) takes output row o's finished accumulators.  pf(stage)
-    // issues the global loads placed at that stage.
-    // base[m][kh]: the lane's part of the swizzled address of chunk 4kh + g
-    // of window pixel c + l16 for any c = m (mod 8): rr_off(c + l16, 4kh + g)
-    // = 128 c + base[m][kh], so every B read is a base plus an immediate
-    auto layer = [&](const int (&base)[8][2], const bf16x8 *W, auto NRc, auto BIc, auto ep,
-                     auto pf) {
-      constexpr int NR = decltype(NRc)::value, NO = NR - 2, NSTG = NR * NIT;
-      constexpr int BI = decltype(BIc)::value;          // bias row in LDS
-      auto load_b = [&](auto stc) {
-        constexpr int stg = decltype(stc)::value;
-        constexpr int ir = stg / NIT, it = stg % NIT, dx = it >> 1, kh = it & 1;
-        static_for<0, 2>([&](auto hc) {
-          constexpr int c = ir * IW + 16 * decltype(hc)::value + dx;
-          Bb[stg % (PD + 1)][decltype(hc)::value] =
-              *reinterpret_cast<const bf16x8 *>(lds + base[c & 7][kh] + 128 * c);
-        });
-      };
-      static_for<0, PD>(load_b);
-      static_for<0, NSTG>([&](auto stc) {
-        constexpr int stg = decltype(stc)::value;
-        constexpr int ir = stg / NIT, it = stg % NIT, dx = it >> 1, kh = it & 1;
-        if constexpr (stg + PD < NSTG) load_b(std::integral_constant<int, stg + PD>{});
-        pf(stc);
-#if !PNP_PAIR_IGLP
-        __builtin_amdgcn_sched_barrier(0);
-#endif
-        if constexpr (it == 0 && ir < NO) {
-          const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias + BI * Lo::F + 16 * wave + 4 * g);
-          acc[ir & 3][0] = bia;
-          acc[ir & 3][1] = bia;
-        }
-        static_for<0, 3>([&](auto dyc) {
-          constexpr int dy = decltype(dyc)::value, o = ir - dy;
-          if constexpr (o >= 0 && o < NO) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-              acc[o & 3][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  W[(3 * dy + dx) * 2 + kh], Bb[stg % (PD + 1)][h], acc[o & 3][h], 0, 0, 0);
-          }
-        });
-        // output row ir - 3 finished one input row ago
-        if constexpr (it == 1 && ir >= 3 && ir - 3 < NO) ep(std::integral_constant<int, ir - 3>{});
-#if PNP_PAIR_IGLP
-        // one wave per SIMD issues in order: place the stage's LDS reads, the
-        // global load and the epilogue's vector work between its MFMAs, where
-        // they issue while the matrix core is busy
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global load
-        static_for<0, 4>([&](auto) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x002, PNP_PAIR_IGLP, 0);   // VALU
-          __builtin_amdgcn_sched_group_barrier(0x240, 1, 0); // LDS write / global store
-        });
-#endif
-        __builtin_amdgcn_sched_barrier(0);
-      });
-      static_for<(NR - 3 > 0 ? NR - 3 : 0), NO>(ep);
-    };
-
-    // Both layers' epilogues round a row's two blocks to bf16 with ReLU and
-    // then swap halves between neighbouring 16-lane rows (v_permlane16_swap):
-    // lanes of even rows end up with 8 channels of a block-0 pixel, lanes of
-    // odd rows with 8 channels of a block-1 pixel, so each lane stores one
-    // whole 16-byte chunk (half as many stores as 8-byte pieces).
-    auto pack_row = [&](auto oc) -> u32x4 {
-      constexpr int o = decltype(oc)::value;
-      u32x2 w[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const f32x4 v = acc[o & 3][h];
-        w[h].x = relu_bf16x2(pack_bf16x2(v[0], v[1]));
-        w[h].y = relu_bf16x2(pack_bf16x2(v[2], v[3]));
-      }
-      const auto sx = __builtin_amdgcn_permlane16_swap(w[0].x, w[1].x, false, false);
-      const auto sy = __builtin_amdgcn_permlane16_swap(w[0].y, w[1].y, false, false);
-      return u32x4{sx[0], sy[0], sx[1], sy[1]};
-    };
-    const int hb = g & 1;                        // block of this lane's pixel after the swap
-    const int cpos = 16 * hb + l16;              // its column in the tile
-
-    // Epilogue selections are bit masks, not branches: a branch would end
-    // the scheduling region and leave the epilogue's dependent chain with no
-    // MFMAs to issue beside it.
-    // layer A: intermediate rows into LDS (zero outside the image)
-    const uint32_t in_x = (unsigned)(cur.x0 - 1 + cpos) < (unsigned)cur.nx ? ~0u : 0u;
-    auto epA = [&](auto oc) {
-      constexpr int o = decltype(oc)::value;
-      const uint32_t in_y = (unsigned)(cur.y0 - 1 + o) < (unsigned)cur.ny ? ~0u : 0u;  // uniform
-      const uint32_t keep = in_y & in_x;
-      u32x4 q = pack_row(oc);
-      q &= u32x4{keep, keep, keep, keep};
-      // pixel o*IW + cpos: o*IW = 2o (mod 8) moves the swizzle by the row
-      *reinterpret_cast<u32x4 *>(lds_mid + rr_off(o * IW + cpos, 2 * wave + (g >> 1))) = q;
-    };
-    // first half of the next tile's window, a load per stage from stage 6
-    auto pfA = [&](auto stc) {
-      constexpr int stg = decltype(stc)::value;
-      if constexpr (stg >= 6 && stg < 6 + NL1)
-        pre[stg - 6] = load_chunk(nxt, lcol_n, std::integral_constant<int, stg - 6>{});
-    };
-    layer(base_in, WA, std::integral_constant<int, Lo::IH>{}, std::integral_constant<int, 0>{}, epA,
-          pfA);
-    __syncthreads();                             // intermediate written, window read
-    static_for<0, NL1>([&](auto ic) { put_chunk(ic, pre[decltype(ic)::value]); });
-
-    // layer B: the tile's rows to memory; lanes outside the tile (and the
-    // two padding columns) store to the trash pixel
-    // byte offsets from cur.out: the lane's column in row o, or the trash pixel
-    const int64_t lane_b = 32 * wave + 16 * (g >> 1);
-    const int64_t trash_b = cur.trash * Lo::PIXB + lane_b;
-    const int64_t col_b = (int64_t)(cur.x0 + cpos + 1) * Lo::PIXB + lane_b;
-    const int64_t ok_c = cpos < cur.w ? -1 : 0;
-    auto epB = [&](auto oc) {
-      constexpr int o = decltype(oc)::value;
-      const int64_t ok = (o < cur.h ? -1 : 0) & ok_c;
-      const int64_t roff = (int64_t)(cur.y0 + o + 1) * cur.apitch * Lo::PIXB;
-      const u32x4 q = pack_row(oc);
-      const int64_t b = ((col_b + roff) & ok) | (trash_b & ~ok);
-      *reinterpret_cast<PNP_GLOBAL u32x4 *>(cur.out + b) = q;
-    };
-    auto pfB = [&](auto stc) {
-      constexpr int stg = decltype(stc)::value;
-      if constexpr (stg >= 1 && stg < 1 + NL2)
-        pre[stg - 1] = load_chunk(nxt, lcol_n, std::integral_constant<int, NL1 + stg - 1>{});
-    };
-    layer(base_mid, WB, std::integral_constant<int, Lo::MH>{}, std::integral_constant<int, 1>{}, epB,
-          pfB);
-    static_for<0, NL2>([&](auto ic) {
-      put_chunk(std::integral_constant<int, NL1 + decltype(ic)::value>{}, pre[decltype(ic)::value]);
-    });
-    __syncthreads();                             // next window in place, intermediate read
-    if (tn >= t_end) break;
-    cur = nxt;
-    nxt = after;
-    ti = tn;
   }
 }
 
@@ -1433,9 +1071,17 @@ void conv_pair_kernel(ConvArgs a) {
 // Output tiles are 9 x 30 (input window 13 x 34, intermediate 11 x 32): the
 // input window and two intermediates take 153 KB of LDS.  The layer-A waves
 // also load the next tile's window (moving those loads to the layer-B waves,
-// which have fewer MFMAs, spills registers).  Within a layer the
-// row order, B reads, LDS layout and epilogues are those of
-// conv_pair_kernel; wave w & 3 owns output channels 16 (w & 3) .. + 15.
+// which have fewer MFMAs, spills registers).  Wave w & 3 owns output
+// channels 16 (w & 3) .. + 15 of its layer and keeps their A fragments in
+// registers for the whole kernel, so LDS holds activations only.
+//
+// Within a layer, work runs input row by input row: the B fragment of input
+// row ir serves output rows ir, ir-1 and ir-2 (taps dy = 0, 1, 2), so output
+// row o is complete after input row o + 2 and four accumulator row slots
+// suffice.  The intermediate holds the tile plus a one-pixel ring (bf16,
+// ReLU, and zero at positions outside the image, which is layer B's zero
+// padding), computed from the input window; window positions beyond the
+// one-pixel zero border of the activation buffer read the border.
 // ---------------------------------------------------------------------
 struct PairWsLayout {
   static constexpr int F = 64, PIXB = 128, CPP = 8, NSTEP = 18, NTG = 256;
@@ -1532,7 +1178,7 @@ void conv_pair_ws_kernel(ConvArgs a) {
     static_for<0, NLOAD>([&](auto ic) { put_chunk(ic, pre[decltype(ic)::value]); });
   }
   // base[m][kh]: the lane's part of the swizzled address of chunk 4kh + g of
-  // pixel c + l16 for c = m (mod 8) (see conv_pair_kernel)
+  // pixel c + l16 for c = m (mod 8)
   int bl[8][2];
 #pragma unroll
   for (int m = 0; m < 8; ++m)
@@ -1718,14 +1364,10 @@ void conv_mid_rr8_kernel(ConvArgs a) {
   const int g = lane >> 4, l16 = lane & 15;
 
   const int nwg = gridDim.x, b = blockIdx.x;
-#if PNP_XCD_MAP
   const int xcd = b & 7, slot = b >> 3;
   const int per_xcd = (nwg - xcd + 7) >> 3;
   const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
   const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
-#else
-  const int slot = b, per_xcd = nwg, t_begin = 0, t_end = a.n_tiles;
-#endif
 
   {
     const PNP_GLOBAL u32x4 *src = gp(reinterpret_cast<const u32x4 *>(a.wblob_rr));
@@ -1941,9 +1583,6 @@ __device__ __forceinline__ constexpr int p8_off(int p) {
   return (p >> 2) * Pair8Layout::GRP + (p & 3) * Pair8Layout::PIXB;
 }
 
-#ifndef PNP_PAIR8_WPE
-#define PNP_PAIR8_WPE 2   // waves per SIMD the e4m3 pair kernel is compiled for
-#endif
 
 // OUT2: storage format of the second layer's output (e4m3, or bf16 when the
 // next layer reads bf16, e.g. the last layer).  LAST: the second layer feeds
@@ -1961,7 +1600,7 @@ __device__ __forceinline__ constexpr int p8_off(int p) {
 // standalone first-layer kernel does; window pixels outside the image are
 // set to zero (the next layer's padding).
 template <int OUT2, bool FIRST, bool LAST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PNP_PAIR8_WPE, PNP_PAIR8_WPE)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPair8Wpe, kPair8Wpe)))
 void conv_pair8_kernel(ConvArgs a) {
   using Lo = Pair8Layout;
   constexpr int NT = Lo::NT, IW = Lo::IW, NL1 = Lo::NL1, NL2 = Lo::NL2;
@@ -2385,7 +2024,7 @@ static hipError_t launch_mid_t(const ConvArgs &a, int n_wg, hipStream_t s) {
   return hipGetLastError();
 }
 
-static_assert(!PNP_MID_RR || 2 * PNP_NW_LOWP == RrLayout::TH, "bf16 tile rows");
+static_assert(2 * kNwLowp == RrLayout::TH, "bf16 tile rows");
 template <int OUT_FMT>
 static hipError_t launch_rr8_t(const ConvArgs &a, int n_wg, hipStream_t s) {
   constexpr int lds = Rr8Layout<OUT_FMT>::LDS_BYTES;
@@ -2420,7 +2059,7 @@ static hipError_t launch_rr(const ConvArgs &a, int n_wg, hipStream_t s) {
 
 bool mid_last_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int last_in_fmt,
                       int last_cin, int last_cout) {
-  return PNP_MID_RR && in_fmt == FMT_BF16 && out_fmt == FMT_BF16 && F == 64 && relu && unit &&
+  return in_fmt == FMT_BF16 && out_fmt == FMT_BF16 && F == 64 && relu && unit &&
          last_in_fmt == FMT_BF16 && last_cin == 64 && last_cout == 1;
 }
 
@@ -2437,11 +2076,10 @@ hipError_t launch_g_from_s(const ConvArgs &a, int n_tiles, hipStream_t s) {
   return hipGetLastError();
 }
 
-bool pair_ws_enabled() { return PNP_PAIR_WS; }
 
 bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt2, int out_fmt2,
                   int relu2, int unit2) {
-  return PNP_MID_RR && in_fmt == FMT_BF16 && out_fmt == FMT_BF16 && F == 64 && relu && unit &&
+  return in_fmt == FMT_BF16 && out_fmt == FMT_BF16 && F == 64 && relu && unit &&
          in_fmt2 == FMT_BF16 && out_fmt2 == FMT_BF16 && relu2 && unit2;
 }
 
@@ -2460,28 +2098,8 @@ hipError_t launch_conv_pair_ws(const ConvArgs &a, int n_wg, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_conv_pair(const ConvArgs &a, int n_wg, hipStream_t s) {
-  if (!a.wblob || !a.wblob2 || !a.bias || !a.bias2 || n_wg <= 0 || n_wg % 8 != 0)
-    return hipErrorInvalidValue;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_pair_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       PairLayout::LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(conv_pair_kernel, dim3(n_wg), dim3(256), PairLayout::LDS_BYTES, s, a);
-  return hipGetLastError();
-}
 
-bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
-                   int relu2) {
-  return PNP_MID_RR && in_fmt == FMT_E4M3 && out_fmt == FMT_E4M3 && F == 64 && relu &&
-         in_fmt2 == FMT_E4M3 && (out_fmt2 == FMT_E4M3 || out_fmt2 == FMT_BF16) && relu2;
-}
-
-int pair8_wg_per_cu() { return PNP_PAIR8_WPE; }
+int pair8_wg_per_cu() { return kPair8Wpe; }
 
 template <int OUT2, bool FIRST, bool LAST>
 static hipError_t launch_pair8_t(const ConvArgs &a, int n_wg, hipStream_t s) {
@@ -2519,18 +2137,18 @@ hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, bool l
 }
 
 bool last_pair8_fusable(int out_fmt2, int last_in_fmt, int last_cin, int last_cout) {
-  return PNP_MID_RR && out_fmt2 == FMT_BF16 && last_in_fmt == FMT_BF16 && last_cin == 64 &&
+  return out_fmt2 == FMT_BF16 && last_in_fmt == FMT_BF16 && last_cin == 64 &&
          last_cout == 1;
 }
 
 bool first_pair8_fusable(int in_fmt0, int out_fmt0, int cin0, int cout0, int relu0) {
-  return PNP_MID_RR && in_fmt0 == FMT_BF16 && out_fmt0 == FMT_E4M3 && cin0 == 1 && cout0 == 64 &&
+  return in_fmt0 == FMT_BF16 && out_fmt0 == FMT_E4M3 && cin0 == 1 && cout0 == 64 &&
          relu0;
 }
 
 bool first_mid_fusable(int in_fmt0, int out_fmt0, int cout0, int relu0, int unit0, int in_fmt1,
                        int out_fmt1, int F, int relu1, int unit1) {
-  return PNP_MID_RR && in_fmt0 == FMT_BF16 && out_fmt0 == FMT_BF16 && cout0 == 64 && relu0 &&
+  return in_fmt0 == FMT_BF16 && out_fmt0 == FMT_BF16 && cout0 == 64 && relu0 &&
          unit0 && in_fmt1 == FMT_BF16 && out_fmt1 == FMT_BF16 && F == 64 && relu1 && unit1;
 }
 
@@ -2542,15 +2160,15 @@ hipError_t launch_conv_first_mid(const ConvArgs &a, int n_wg, hipStream_t s) {
 // tile rows of the middle-layer kernel for an input format
 int mid_tile_rows(int in_fmt) {
   if (in_fmt == FMT_F32) return 8;
-  return 2 * PNP_NW_LOWP;
+  return 2 * kNwLowp;
 }
 
 size_t mid_lds_bytes(int in_fmt, int F) {
-  if (PNP_MID_RR && in_fmt == FMT_BF16 && F == 64) return RrLayout::LDS_BYTES;
+  if (in_fmt == FMT_BF16 && F == 64) return RrLayout::LDS_BYTES;
   const int TH = mid_tile_rows(in_fmt);
   const int ib = in_fmt == FMT_F32 ? 4 : (in_fmt == FMT_BF16 ? 2 : 1);
   const int ob = in_fmt == FMT_E4M3 ? 2 : ib;          // widest output format
-  const int pstr = F * ib + 16, ostr = PNP_MID_STAGE ? F * ob + 16 : 0;
+  const int pstr = F * ib + 16, ostr = F * ob + 16;
   int nstep = in_fmt == FMT_E4M3 ? 5 : 9 * (in_fmt == FMT_F32 ? F / 16 : F / 32);
   int nch = (in_fmt == FMT_F32 && F == 64) ? 3 : 1;
   int fragb = in_fmt == FMT_E4M3 ? 32 : 16;
@@ -2566,16 +2184,16 @@ hipError_t launch_conv_mid(int in_fmt, int out_fmt, int F, const ConvArgs &a, in
     if (F == 32) return launch_mid_t<FMT_F32, FMT_F32, 32, 4>(a, n_wg, s);
     if (F == 64) return launch_mid_t<FMT_F32, FMT_F32, 64, 4>(a, n_wg, s);
   } else if (in_fmt == FMT_BF16 && out_fmt == FMT_BF16) {
-    if (F == 64 && PNP_MID_RR && a.relu && a.unit_scale) return launch_rr(a, n_wg, s);
-    if (F == 32) return launch_mid_t<FMT_BF16, FMT_BF16, 32, PNP_NW_LOWP>(a, n_wg, s);
-    if (F == 64) return launch_mid_t<FMT_BF16, FMT_BF16, 64, PNP_NW_LOWP>(a, n_wg, s);
+    if (F == 64 && a.relu && a.unit_scale) return launch_rr(a, n_wg, s);
+    if (F == 32) return launch_mid_t<FMT_BF16, FMT_BF16, 32, kNwLowp>(a, n_wg, s);
+    if (F == 64) return launch_mid_t<FMT_BF16, FMT_BF16, 64, kNwLowp>(a, n_wg, s);
   } else if (in_fmt == FMT_E4M3 && F == 64) {
-    if (PNP_MID_RR && a.relu && a.wblob_rr) {
+    if (a.relu && a.wblob_rr) {
       if (out_fmt == FMT_E4M3) return launch_rr8_t<FMT_E4M3>(a, n_wg, s);
       if (out_fmt == FMT_BF16) return launch_rr8_t<FMT_BF16>(a, n_wg, s);
     }
-    if (out_fmt == FMT_E4M3) return launch_mid_t<FMT_E4M3, FMT_E4M3, 64, PNP_NW_LOWP>(a, n_wg, s);
-    if (out_fmt == FMT_BF16) return launch_mid_t<FMT_E4M3, FMT_BF16, 64, PNP_NW_LOWP>(a, n_wg, s);
+    if (out_fmt == FMT_E4M3) return launch_mid_t<FMT_E4M3, FMT_E4M3, 64, kNwLowp>(a, n_wg, s);
+    if (out_fmt == FMT_BF16) return launch_mid_t<FMT_E4M3, FMT_BF16, 64, kNwLowp>(a, n_wg, s);
   }
   return hipErrorInvalidValue;
 }

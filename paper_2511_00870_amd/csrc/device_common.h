@@ -14,7 +14,7 @@ constexpr int kUpdTileH = 32;      // fused-update tile (rows x cols) and workgr
 constexpr int kUpdTileW = 64;
 constexpr int kUpdThreads = 512;
 constexpr int kConvTileW = 32;     // convolution tiles are TH x 32 pixels
-constexpr int kPairTileH = 14;     // two-layer middle kernel: output tiles of 14 x 30
+constexpr int kPairTileH = 14;     // e4m3 pair kernel: output tiles of 14 x 30
 constexpr int kPairTileW = 30;
 constexpr int kPairWsTileH = 9;   // split-layer pair kernel: output tiles of 9 x 30
 

@@ -58,7 +58,7 @@ struct Job {
   size_t footprint = 0;
   std::vector<void *> allocs;
   std::vector<TileRef> conv_tiles, upd_tiles;   // job field = 0 (set at planning)
-  std::vector<TileRef> pair_tiles;              // two-layer kernel: whole-image tiling
+  std::vector<TileRef> pair_tiles;              // e4m3 pair kernel: whole-image tiling
   std::vector<TileRef> pair_ws_tiles;           // split-layer pair kernel (bf16)
 };
 

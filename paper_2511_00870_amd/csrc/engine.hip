@@ -899,13 +899,11 @@ Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool 
   if (prof) prof_begin(6, &pr);
   if (e4m3) {
     HIPOK(launch_conv_pair8(a, B.out_fmt, first, last, n_wg, stream));
-  } else if (pair_ws_enabled()) {
+  } else {
     a.tiles = d_pair_ws;
     a.n_tiles = n_pair_ws;
     const int need_ws = ((n_pair_ws + 7) / 8) * 8;
     HIPOK(launch_conv_pair_ws(a, std::max(8, std::min(n_cu, need_ws) / 8 * 8), stream));
-  } else {
-    HIPOK(launch_conv_pair(a, n_wg, stream));
   }
   if (prof) prof_end(&pr);
   return Status::ok();

@@ -61,14 +61,11 @@ hipError_t launch_conv_first_mid(const ConvArgs &a, int n_wg, hipStream_t s);
 // must be false: a middle layer with both fusions is not built)
 hipError_t launch_conv_mid_last(const ConvArgs &a, int n_wg, bool first, hipStream_t s);
 // G = sum over taps of the partials at the tap's neighbour, plus the bias
-// two consecutive bf16 middle layers in one kernel (a: the first layer's
-// arguments plus wblob2 / bias2; tiles of kPairTileH x kPairTileW); n_wg a
-// positive multiple of 8
-hipError_t launch_conv_pair(const ConvArgs &a, int n_wg, hipStream_t s);
-// the same with the two layers on separate waves (8 per workgroup; tiles of
-// kPairWsTileH x kPairTileW)
+// two consecutive bf16 middle layers in one kernel, the two layers on
+// separate waves (a: the first layer's arguments plus wblob2 / bias2; 8
+// waves per workgroup; tiles of kPairWsTileH x kPairTileW); n_wg a positive
+// multiple of 8
 hipError_t launch_conv_pair_ws(const ConvArgs &a, int n_wg, hipStream_t s);
-bool pair_ws_enabled();
 bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt2, int out_fmt2,
                   int relu2, int unit2);
 // two consecutive e4m3 middle layers in one kernel (a: the first layer's

@@ -1,6 +1,6 @@
 // update.hip -- the fused memory-bound part of one PnP-ULA iteration.
 //
-// For every 16 x 64 tile of a block (arXiv 2511.00870, Algorithm 1, the
+// For every 32 x 64 tile of a block (arXiv 2511.00870, Algorithm 1, the
 // x-update lines, with the z-update folded in):
 //   1. read the tile's window x^(t) on [core +- 2r] from the previous iterate
 //      (the block's ghost region is an overlapping read of device memory);

@@ -6,7 +6,7 @@ contains none of the sampler's arithmetic (no Langevin step, no denoiser
 forward pass, no random draws of the chain) and imports nothing from the
 product library or from the oracle, so both sides can be fed from it.
 
-Paper context (Sec. IV-A, "Application setting"): ground-truth images are
+Paper context (Sec. III-A, "Application setting"): ground-truth images are
 normalised to [0, 1]; observations follow the Gaussian likelihood
 y | x ~ N(H x, sigma^2 I) with H a normalised blur and/or a {0,1} diagonal
 mask; the chain runs T samples with a 10% burn-in.  The photographs, the
@@ -19,8 +19,8 @@ structure:
   constant-intensity rectangles (sides U[side/32, side/8], level U[0, 0.4]),
   clipped to [0, 1];
 * blur: an isotropic Gaussian, normalised to unit sum ("normalised blur",
-  Sec. IV-A2), applied as a same-size linear convolution with zero boundary;
-* mask: i.i.d. Bernoulli(p) observed pixels (inpainting, Sec. IV-A1);
+  Sec. III-A2), applied as a same-size linear convolution with zero boundary;
+* mask: i.i.d. Bernoulli(p) observed pixels (inpainting, Sec. III-A1);
 * noise: y = m * (K xbar + sigma w), w ~ N(0, I);
 * denoiser: DnCNN-style residual CNN (Example 2 of Sec. II-B), He-normal
   weights rescaled so that every layer's 3x3 convolution has spectral norm

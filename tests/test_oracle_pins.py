@@ -2,7 +2,7 @@
 library routines (numpy's Philox4x64, rocRAND's Philox4x32 header, scipy's
 FFT convolution, torch's float64 conv2d and its bf16/e4m3 casts), closed
 forms (adjoint identity, finite differences, Gaussian moments) and the
-paper's own statements (blocked == monolithic, Sec. IV-C; Example 1 sizes).
+paper's own statements (blocked == monolithic, Sec. IV-B; Example 1 sizes).
 """
 import json
 import os
@@ -262,7 +262,7 @@ def test_weight_scales_are_powers_of_two_covering_amax():
     assert np.all(O.weight_scales(net, 0) == 1.0)
 
 
-# ------------------------------------- blocked == monolithic (Sec. IV-C)
+# ------------------------------------- blocked == monolithic (Sec. IV-B)
 def _chain(wl, block, **kw):
     return O.Chain.from_workload(wl, block=block, **kw)
 
