@@ -2099,6 +2099,12 @@ hipError_t launch_conv_pair_ws(const ConvArgs &a, int n_wg, hipStream_t s) {
 }
 
 
+bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
+                   int relu2) {
+  return in_fmt == FMT_E4M3 && out_fmt == FMT_E4M3 && F == 64 && relu &&
+         in_fmt2 == FMT_E4M3 && (out_fmt2 == FMT_E4M3 || out_fmt2 == FMT_BF16) && relu2;
+}
+
 int pair8_wg_per_cu() { return kPair8Wpe; }
 
 template <int OUT2, bool FIRST, bool LAST>
