@@ -435,6 +435,27 @@ int oracle_denoiser(const oracle_net *n, const double *x, int32_t ny, int32_t nx
   return 0;
 }
 
+/* G(x) on the region [y0, y0+h) x [x0, x0+w) of an ny x nx image, from the
+ * region's extended window of half-width K (zeros outside the image): the
+ * same window computation as a block, so sampled outputs of very large
+ * images can be checked one region at a time. */
+int oracle_denoise_region(const oracle_net *n, const double *x, int32_t ny, int32_t nx,
+                          int32_t y0, int32_t x0, int32_t h, int32_t w, double *G) {
+  if (y0 < 0 || x0 < 0 || h < 1 || w < 1 || y0 + h > ny || x0 + w > nx) return -1;
+  int K = n->n_layers;
+  prepared_net p;
+  prepare_net(n, &p);
+  int H = h + 2 * K, W = w + 2 * K;
+  double *win = xmalloc((size_t)H * W * sizeof(double));
+  extract_window(x, 1, ny, nx, y0 - K, x0 - K, H, W, win);
+  double *res = denoise_window(n, &p, win, ny, nx, y0 - K, x0 - K, H, W, 0, NULL, NULL);
+  memcpy(G, res, (size_t)h * w * sizeof(double));
+  free(res);
+  free(win);
+  free_net(&p);
+  return 0;
+}
+
 /* all layer outputs of the monolithic denoiser (layer k: channels[k+1]
  * planes), and the max |input| of every layer before its quantisation */
 int oracle_denoiser_layers(const oracle_net *n, const double *x, int32_t ny, int32_t nx,

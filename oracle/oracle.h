@@ -94,6 +94,8 @@ double oracle_quantize(double v, int32_t fmt);
 void oracle_weight_scales(const oracle_net *net, int32_t layer, double *scales);
 int  oracle_denoiser(const oracle_net *net, const double *x, int32_t ny, int32_t nx,
                      int32_t block_y, int32_t block_x, int32_t halo, double *G);
+int  oracle_denoise_region(const oracle_net *net, const double *x, int32_t ny, int32_t nx,
+                           int32_t y0, int32_t x0, int32_t h, int32_t w, double *G);
 int  oracle_denoiser_layers(const oracle_net *net, const double *x, int32_t ny,
                             int32_t nx, double *acts, double *amax);
 int  oracle_data_grad(const oracle_config *cfg, const double *x, int64_t t, double *g);

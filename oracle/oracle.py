@@ -87,6 +87,8 @@ def _declare(L):
     L.oracle_weight_scales.argtypes = [C.POINTER(OracleNet), C.c_int32, _dp]
     L.oracle_denoiser.argtypes = [C.POINTER(OracleNet), _dp, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int32, _dp]
+    L.oracle_denoise_region.argtypes = [C.POINTER(OracleNet), _dp, C.c_int32, C.c_int32,
+                                        C.c_int32, C.c_int32, C.c_int32, C.c_int32, _dp]
     L.oracle_denoiser_layers.argtypes = [C.POINTER(OracleNet), _dp, C.c_int32, C.c_int32,
                                          _dp, _dp]
     L.oracle_data_grad.argtypes = [C.POINTER(OracleConfig), _dp, C.c_int64, _dp]
@@ -197,6 +199,18 @@ def denoiser(net: Net, x, block: int = 0, halo: int = 0, block_x: Optional[int] 
     if rc != 0:
         raise ValueError("halo smaller than the receptive field of the denoiser")
     return G
+
+
+def denoise_region(net: Net, x, y0: int, x0: int, h: int, w: int) -> np.ndarray:
+    """G(x) on the region [y0, y0+h) x [x0, x0+w) of the full image x (cost ~
+    region size: the region's K-halo window only)."""
+    x = _f64(x)
+    out = np.empty((h, w))
+    rc = lib().oracle_denoise_region(C.byref(net.struct), _d(x), x.shape[0], x.shape[1], y0, x0,
+                                     h, w, _d(out))
+    if rc != 0:
+        raise ValueError("region outside the image")
+    return out
 
 
 def denoiser_layers(net: Net, x):

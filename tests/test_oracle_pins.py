@@ -398,3 +398,126 @@ def test_step_region_equals_full_step_bitwise():
         assert np.array_equal(reg, full[y0:y0 + h, x0:x0 + w])
     with pytest.raises(ValueError):
         ch.step_region(x, 3, 35, 0, 10, 10)
+
+
+# ------------------------------------- quantised layers, composed (Eq. (cnn:convolution))
+def _torch_round(t, dtype):
+    """Round float64 values to `dtype` (bf16 or e4m3fn) to nearest, ties to
+    even, using torch's casts only.  torch converts float64 through float32
+    first, which can double-round a float64 value that lies just off a tie
+    of the target format; such values are detected (the float32 value is an
+    exact tie) and resolved towards the float64 value's side."""
+    import torch
+    q = t.to(torch.float32)
+    base = q.to(dtype).to(torch.float64)
+    up = torch.nextafter(q, torch.tensor(float("inf"))).to(dtype).to(torch.float64)
+    dn = torch.nextafter(q, torch.tensor(float("-inf"))).to(dtype).to(torch.float64)
+    q64 = q.to(torch.float64)
+    tie = (up != dn) & ((q64 - dn) == (up - q64))
+    fixed = torch.where(t > q64, up, torch.where(t < q64, dn, base))
+    return torch.where(tie, fixed, base)
+
+
+def test_torch_round_helper_single_rounding():
+    import torch
+    # 1 + 2^-8 is a bf16 tie; a float64 value just above it must round up
+    t = torch.tensor([1 + 2 ** -8 + 2 ** -30, 1 + 2 ** -8 - 2 ** -30, 1 + 2 ** -8,
+                      1 + 3 * 2 ** -8], dtype=torch.float64)
+    got = _torch_round(t, torch.bfloat16).numpy()
+    assert list(got) == [1 + 2 ** -7, 1.0, 1.0, 1 + 2 ** -6]
+    # the same for e4m3 (step 2^-3 at 1): tie at 1 + 2^-4
+    t = torch.tensor([1 + 2 ** -4 + 2 ** -40, 1 + 2 ** -4 - 2 ** -40], dtype=torch.float64)
+    assert list(_torch_round(t, torch.float8_e4m3fn).numpy()) == [1.125, 1.0]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_quantised_denoiser_matches_torch_composition(seed):
+    """The oracle's quantisation-emulation mode against a float64 torch
+    reference built from torch's own casts: layer k rounds its input divided
+    by its activation scale s_a and its weights divided by a per-output-channel
+    power-of-two scale s_w to its format, convolves exactly, multiplies by
+    s_w s_a, adds the bias and applies ReLU (all but the last layer).  Four
+    layers mix bf16 and e4m3, with non-unit power-of-two activation scales."""
+    import torch
+    ch, ws, bs = W.denoiser_weights(4, 16, seed=40 + seed, bias_scale=0.05)
+    fmt = [O.FMT_BF16, O.FMT_E4M3, O.FMT_E4M3, O.FMT_BF16]
+    x = W.synthetic_image(23, 29, 50 + seed)
+    # activation scales: powers of two from the exact network's input ranges,
+    # with the bf16 layers given non-unit scales too (they must ignore them)
+    _, amax = O.denoiser_layers(O.Net(ch, ws, bs), x)
+    sa = [0.25, float(2.0 ** np.ceil(np.log2(2 * amax[1] / 448))),
+          float(2.0 ** np.ceil(np.log2(2 * amax[2] / 448))), 4.0]
+    assert sa[1] != 1.0 and sa[2] != 1.0
+    acts, _ = O.denoiser_layers(O.Net(ch, ws, bs, fmt, sa), x)
+    tdt = {O.FMT_BF16: torch.bfloat16, O.FMT_E4M3: torch.float8_e4m3fn}
+    v = torch.tensor(x, dtype=torch.float64)[None, None]
+    for k in range(4):
+        w = torch.tensor(ws[k], dtype=torch.float64)
+        b = torch.tensor(bs[k], dtype=torch.float64)
+        if fmt[k] == O.FMT_E4M3:
+            amax_w = w.abs().reshape(w.shape[0], -1).max(1).values.numpy()
+            s_w = torch.tensor(2.0 ** np.ceil(np.log2(amax_w / 448.0)))
+            s_a = sa[k]
+        else:
+            s_w = torch.ones(w.shape[0], dtype=torch.float64)
+            s_a = 1.0
+        vq = _torch_round(v / s_a, tdt[fmt[k]])
+        wq = _torch_round(w / s_w[:, None, None, None], tdt[fmt[k]])
+        v = torch.nn.functional.conv2d(vq, wq, padding=1) * (s_w * s_a)[None, :, None, None] \
+            + b[None, :, None, None]
+        if k < 3:
+            v = torch.relu(v)
+        got = acts[k]
+        ref = v[0].numpy()
+        err = np.abs(got - ref).max()
+        assert err <= 1e-13 * max(1.0, np.abs(ref).max()), (k, err)
+        v = torch.tensor(got)[None]       # both sides continue from the same values
+
+
+def test_projection_term_is_moreau_gradient():
+    """The term delta/lambda (clip_[0,1](x) - x) of Eq. (sgs_pnp_ula_psgla:pnp_ula)
+    is -delta times the gradient of d_C(x)^2 / (2 lambda), C = [0,1]^N: one
+    oracle step with H = I, G = 0 and no splitting, minus its data, noise and
+    identity parts, against central finite differences of d_C^2/(2 lambda) at
+    points below 0, inside [0,1] and above 1."""
+    ny, nx = 6, 7
+    rng = np.random.default_rng(12)
+    x = rng.uniform(-0.8, 1.8, (ny, nx))
+    x[0, 0], x[0, 1], x[0, 2] = -0.3, 0.5, 1.4
+    y = rng.uniform(0, 1, (ny, nx))
+    sigma, delta, inv_lambda, seed, t = 0.1, 1e-3, 37.0, 77, 5
+    ch = [1, 4, 1]
+    ws = [np.zeros((4, 1, 3, 3), np.float32), np.zeros((1, 4, 3, 3), np.float32)]
+    bs = [np.zeros(4, np.float32), np.zeros(1, np.float32)]
+    oc = O.Chain(y=y, kernel=np.ones((1, 1)), sigma=sigma, eps=sigma ** 2, delta=delta,
+                 inv_lambda=inv_lambda, channels=ch, weights=ws, biases=bs, seed=seed)
+    oc.set_state(x, t)
+    oc.step(1)
+    x1, _ = oc.get_state()
+    xi, _ = O.noise(ny, nx, seed, t)
+    proj_term = x1 - x + delta * (x - y) / sigma ** 2 - np.sqrt(2 * delta) * xi
+
+    def moreau(v):
+        d = v - np.clip(v, 0.0, 1.0)
+        return inv_lambda * np.sum(d * d) / 2.0
+
+    h = 1e-5
+    for (i, j) in [(0, 0), (0, 1), (0, 2), (3, 4), (5, 6)]:
+        e = np.zeros_like(x)
+        e[i, j] = h
+        fd = (moreau(x + e) - moreau(x - e)) / (2 * h)
+        assert proj_term[i, j] == pytest.approx(-delta * fd, rel=1e-6, abs=1e-12)
+    assert abs(proj_term[0, 1]) <= 1e-15 and proj_term[0, 0] > 0 and proj_term[0, 2] < 0
+
+
+def test_denoise_region_equals_full_denoiser_bitwise():
+    """The region form of the denoiser (used to check full-size GPU runs) is
+    the monolithic denoiser restricted to the region, bit for bit."""
+    ch, ws, bs = W.denoiser_weights(4, 8, seed=5, bias_scale=0.05)
+    net = O.Net(ch, ws, bs)
+    x = np.random.default_rng(3).random((31, 45))
+    full = O.denoiser(net, x)
+    for (y0, x0, h, w) in [(0, 0, 31, 45), (3, 9, 10, 20), (0, 40, 5, 5), (27, 0, 4, 13)]:
+        assert np.array_equal(O.denoise_region(net, x, y0, x0, h, w), full[y0:y0 + h, x0:x0 + w])
+    with pytest.raises(ValueError):
+        O.denoise_region(net, x, 30, 0, 4, 4)
