@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--jobs", type=int, default=64)
     ap.add_argument("--iters-scale", type=float, default=0.1,
                     help="serving: fraction of the 1000-5000 iterations each job runs")
+    ap.add_argument("--no-serving-leg", action="store_true",
+                    help="skip the bounded serving pass of the default run")
+    ap.add_argument("--leg-jobs", type=int, default=32)
+    ap.add_argument("--leg-iters-scale", type=float, default=0.05)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (three times): the "
@@ -146,13 +150,15 @@ def cpu_baseline(wl, region):
                       f"max(2r,K) halo) of the same workload, {dt:.1f} s"}
 
 
-def serving(a, stream):
+def serving(a, stream, n_jobs=None, iters_scale=None):
     """Jobs arrive by a Poisson process (20/s); each is submitted at its
     arrival, the server ticks continuously, latency = completion - arrival."""
     from paper_2511_00870_amd import pnpula as P
     from paper_2511_00870_amd import workloads as W
-    lo, hi = max(1, int(1000 * a.iters_scale)), max(1, int(5000 * a.iters_scale))
-    jobs = W.serving_jobs(n_jobs=a.jobs, iters=(lo, hi))
+    n_jobs = a.jobs if n_jobs is None else n_jobs
+    iters_scale = a.iters_scale if iters_scale is None else iters_scale
+    lo, hi = max(1, int(1000 * iters_scale)), max(1, int(5000 * iters_scale))
+    jobs = W.serving_jobs(n_jobs=n_jobs, iters=(lo, hi))
     net = jobs[0].workload
     srv = P.Server(net.channels, net.weights, net.biases, precision=P.PNPULA_BF16,
                    max_slots=a.slots, stream=stream)
@@ -191,7 +197,7 @@ def serving(a, stream):
         "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
         "makespan_s": round(span, 2), "higher_is_better": True, "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"serving: {a.jobs} jobs, Poisson 20/s, sides 256-2048, "
+        "config": {"workload": f"serving: {n_jobs} jobs, Poisson 20/s, sides 256-2048, "
                                f"blur 5-9 (+50% mask), iterations {lo}-{hi}, 8x64 bf16 "
                                f"denoiser, {a.slots} slots"},
     }
@@ -292,6 +298,16 @@ def main():
             except Exception as e:  # report, do not hide
                 comp[DTYPE[p]] = f"error: {e}"
         out["compare_precisions"] = comp
+    if not a.no_serving_leg:
+        # a bounded continuous-batching pass: latency percentiles and the
+        # aggregate rate of a Poisson job stream (fewer, shorter jobs than the
+        # full 256-job serving workload, which bench.py --serving runs)
+        sv = serving(a, stream, a.leg_jobs, a.leg_iters_scale)
+        out["p50_latency_s"] = sv["p50_latency_s"]
+        out["p99_latency_s"] = sv["p99_latency_s"]
+        out["serving"] = {k: sv[k] for k in ("value", "unit", "p50_latency_s", "p99_latency_s",
+                                             "makespan_s")}
+        out["serving"]["workload"] = sv["config"]["workload"]
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_region)
     print(json.dumps(out), flush=True)

@@ -143,6 +143,20 @@ pnpula_status pnpula_restore(pnpula_ctx *ctx, const float *x, int64_t t, const d
  * to FP32, as channels[k+1] planes of ny*nx per layer (CHW), concatenated. */
 pnpula_status pnpula_denoise(pnpula_ctx *ctx, const float *x, float *G, float *layers);
 
+/* The sampler's own (fused) denoiser path applied to an ny*nx image x, with
+ * the activation written to memory by each of its launches returned for
+ * inspection (Sec. II-B1, Eq. (cnn:convolution): each launch computes one
+ * layer or two consecutive layers; the first and last layers may run inside
+ * the launches next to them).  G receives x - D_eps(x) (FP32, may be NULL).
+ * *n_stages receives the number of launches that wrote an activation;
+ * stage_layer[i] the index (0-based) of the last layer launch i computed;
+ * stage_acts + i * F * ny * nx its output dequantised to FP32 (value = code x
+ * the next layer's activation scale), F planes of ny*nx (CHW).  stage_layer
+ * needs n_layers entries and stage_acts (n_layers - 1) * F * ny * nx floats;
+ * either may be NULL. */
+pnpula_status pnpula_denoise_stages(pnpula_ctx *ctx, const float *x, float *G, int32_t *n_stages,
+                                    int32_t *stage_layer, float *stage_acts);
+
 /* Largest |input| of every layer when the denoiser (in FP32) is applied to
  * x: the data for choosing e4m3 activation scales. */
 pnpula_status pnpula_calibrate(pnpula_ctx *ctx, const float *x, float *amax);

@@ -100,6 +100,20 @@ static void draw_pixel(uint64_t seed, int64_t p, int64_t t, uint32_t chain,
   oracle_gauss_pair(w[0], w[1], xi, zeta);
 }
 
+/* Three Gaussian draws of pixel p at counter t: the pair above from words
+ * (w0, w1) and the cosine branch of a second Box-Muller pair from (w2, w3):
+ * xi, the first z block's zeta and the second z block's zeta2. */
+static void draw_pixel3(uint64_t seed, int64_t p, int64_t t, uint32_t chain, double *xi,
+                        double *zeta, double *zeta2) {
+  uint32_t ctr[4] = {(uint32_t)p, (uint32_t)t, chain, (uint32_t)((uint64_t)p >> 32)};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  double unused;
+  oracle_philox4x32_10(ctr, key, w);
+  oracle_gauss_pair(w[0], w[1], xi, zeta);
+  oracle_gauss_pair(w[2], w[3], zeta2, &unused);
+}
+
 void oracle_noise(int32_t ny, int32_t nx, uint64_t seed, uint32_t t, uint32_t chain,
                   double *xi, double *zeta) {
 #pragma omp parallel for schedule(static)
@@ -460,11 +474,20 @@ int oracle_denoise_region(const oracle_net *n, const double *x, int32_t ny, int3
  * planes), and the max |input| of every layer before its quantisation */
 int oracle_denoiser_layers(const oracle_net *n, const double *x, int32_t ny, int32_t nx,
                            double *acts, double *amax) {
+  return oracle_layers_from(n, x, ny, nx, 0, n->n_layers, acts, amax);
+}
+
+/* layers k0 .. k1-1 of the monolithic denoiser applied to `in` (the input of
+ * layer k0: channels[k0] planes of ny x nx); acts receives their outputs as
+ * in oracle_denoiser_layers, amax (optional) the max |input| of each */
+int oracle_layers_from(const oracle_net *n, const double *in, int32_t ny, int32_t nx,
+                       int32_t k0, int32_t k1, double *acts, double *amax) {
   int K = n->n_layers;
+  if (k0 < 0 || k1 > K || k0 >= k1) return -1;
   prepared_net p;
   prepare_net(n, &p);
-  const double *cur = x;
-  for (int k = 0; k < K; ++k) {
+  const double *cur = in;
+  for (int k = k0; k < k1; ++k) {
     int cin = n->channels[k], cout = n->channels[k + 1], fmt = layer_fmt(n, k);
     double sa = (fmt == OR_FMT_E4M3 && n->act_scales) ? n->act_scales[k] : 1.0;
     int H = ny + 2, W = nx + 2;
@@ -474,7 +497,7 @@ int oracle_denoiser_layers(const oracle_net *n, const double *x, int32_t ny, int
     if (amax) {
       double m = 0.0;
       for (size_t i = 0; i < nin; ++i) m = fmax(m, fabs(pad[i]));
-      amax[k] = m;
+      amax[k - k0] = m;
     }
     if (fmt != OR_FMT_EXACT)
       for (size_t i = 0; i < nin; ++i) pad[i] = oracle_quantize(pad[i] / sa, fmt);
@@ -590,14 +613,229 @@ int oracle_data_grad(const oracle_config *c, const double *x, int64_t t, double 
 }
 
 /* ======================================================================
+ * Proximity operators of the z-steps (Eq. (sgs_pnp_ula_psgla:psgla)):
+ *   prox_{kappa f}(v) = argmin_u kappa f(u) + |u - v|^2 / 2.
+ * ==================================================================== */
+
+/* f(u) = KL(y || u) = u - y log u (+ const), u >= 0 (Poisson data term,
+ * Eq. (poisson:f2)): the stationarity condition u^2 - (v - kappa) u -
+ * kappa y = 0 has one non-negative root. */
+double oracle_prox_kl(double v, double y, double kappa) {
+  double b = v - kappa;
+  return 0.5 * (b + sqrt(b * b + 4.0 * kappa * y));
+}
+
+/* f(u) = (y - u)^2 / (2 sigma^2) (Gaussian data term as f2): the weighted
+ * mean of v and y. */
+double oracle_prox_gauss(double v, double y, double sigma, double kappa) {
+  double s2 = sigma * sigma;
+  return (s2 * v + kappa * y) / (s2 + kappa);
+}
+
+/* f(u) = ||u||_2 for one pixel's two differences (the l_{2,1} norm of the TV
+ * prior, Sec. III-B2), scaled by tau: block soft thresholding. */
+void oracle_prox_l21(double *vh, double *vv, double tau) {
+  double nrm = sqrt(*vh * *vh + *vv * *vv);
+  double f = nrm > tau ? 1.0 - tau / nrm : 0.0;
+  *vh *= f;
+  *vv *= f;
+}
+
+/* ======================================================================
+ * 2-D discrete gradient D (Sec. III-B2): forward differences, zero in the
+ * last column (horizontal) and last row (vertical); D^T its adjoint.
+ * ==================================================================== */
+void oracle_grad2d(const double *x, int32_t ny, int32_t nx, double *dh, double *dv) {
+  for (int i = 0; i < ny; ++i)
+    for (int j = 0; j < nx; ++j) {
+      size_t p = (size_t)i * nx + j;
+      dh[p] = j + 1 < nx ? x[p + 1] - x[p] : 0.0;
+      dv[p] = i + 1 < ny ? x[p + nx] - x[p] : 0.0;
+    }
+}
+
+void oracle_grad2d_adjoint(const double *dh, const double *dv, int32_t ny, int32_t nx,
+                           double *out) {
+  for (int i = 0; i < ny; ++i)
+    for (int j = 0; j < nx; ++j) {
+      size_t p = (size_t)i * nx + j;
+      double v = 0.0;
+      if (j >= 1) v += dh[p - 1];
+      if (j + 1 < nx) v -= dh[p];
+      if (i >= 1) v += dv[p - nx];
+      if (i + 1 < ny) v -= dv[p];
+      out[p] = v;
+    }
+}
+
+/* ======================================================================
+ * DDFB denoiser (Sec. II-B1 Example 3, Eqs. (ddfb_operator), (dfb_operator:T)):
+ *   u_0 = W_K v,
+ *   u_k = HT(u_{k-1} + gamma_k W_k P(v - W_k^* u_{k-1})),  k = 1 .. K-1,
+ *   D(v) = P(v - gamma_K W_K^* u_{K-1}),
+ * with W_k the 1 -> F zero-padded 3x3 cross-correlation, W_k^* its adjoint,
+ * P the projection onto [0,1] and HT the clip to [-thresh, thresh].
+ * On a window (origin (oy, ox), H x W) every map is zeroed outside the
+ * image, the zero padding of each convolution of the whole-image operator;
+ * each convolution shrinks the valid region by one pixel per side.
+ * ==================================================================== */
+
+/* out[c][i][j] = sum_{a,b} w[c][a][b] in[i+a][j+b]: in H x W -> F x (H-2) x (W-2) */
+static void ddfb_fwd(const double *in, int H, int W, const double *w, int F, double *out) {
+  int Ho = H - 2, Wo = W - 2;
+  for (int c = 0; c < F; ++c)
+    for (int i = 0; i < Ho; ++i)
+      for (int j = 0; j < Wo; ++j) {
+        double acc = 0.0;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) acc += w[c * 9 + a * 3 + b] * in[(size_t)(i + a) * W + j + b];
+        out[((size_t)c * Ho + i) * Wo + j] = acc;
+      }
+}
+
+/* adjoint: out[i][j] = sum_c sum_{a,b} w[c][a][b] u[c][i+2-a][j+2-b]:
+ * F x H x W -> (H-2) x (W-2) */
+static void ddfb_adj(const double *u, int H, int W, const double *w, int F, double *out) {
+  int Ho = H - 2, Wo = W - 2;
+  for (int i = 0; i < Ho; ++i)
+    for (int j = 0; j < Wo; ++j) {
+      double acc = 0.0;
+      for (int c = 0; c < F; ++c)
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b)
+            acc += w[c * 9 + a * 3 + b] * u[((size_t)c * H + i + 2 - a) * W + j + 2 - b];
+      out[(size_t)i * Wo + j] = acc;
+    }
+}
+
+static double clip01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+/* sub-window of C planes: rows/cols shrink by `d` on each side */
+static double *crop(const double *in, int C, int H, int W, int d) {
+  int Ho = H - 2 * d, Wo = W - 2 * d;
+  double *out = xmalloc((size_t)C * Ho * Wo * sizeof(double));
+  for (int c = 0; c < C; ++c)
+    for (int i = 0; i < Ho; ++i)
+      memcpy(out + ((size_t)c * Ho + i) * Wo, in + ((size_t)c * H + i + d) * W + d,
+             (size_t)Wo * sizeof(double));
+  return out;
+}
+
+/* D(v) on the window's region shrunk by 2K per side */
+static double *ddfb_window(const oracle_config *cf, const double *win, int ny, int nx, int oy,
+                           int ox, int H, int W) {
+  const int K = cf->ddfb_layers, F = cf->ddfb_features;
+  const double *WK = cf->ddfb_weights + (size_t)(K - 1) * F * 9;
+  const double th = cf->ddfb_thresh;
+  /* u_0 = W_K v on (H-2) x (W-2), origin (oy+1, ox+1) */
+  int Hu = H - 2, Wu = W - 2, uy = oy + 1, ux = ox + 1;
+  double *u = xmalloc((size_t)F * Hu * Wu * sizeof(double));
+  ddfb_fwd(win, H, W, WK, F, u);
+  zero_outside(u, F, ny, nx, uy, ux, Hu, Wu);
+  for (int k = 1; k < K; ++k) {
+    const double *Wk = cf->ddfb_weights + (size_t)(k - 1) * F * 9;
+    const double gk = cf->ddfb_gamma[k - 1];
+    /* b = P(v - W_k^* u) on (Hu-2) x (Wu-2), origin (uy+1, ux+1) */
+    int Hb = Hu - 2, Wb = Wu - 2, by = uy + 1, bx = ux + 1;
+    double *b = xmalloc((size_t)Hb * Wb * sizeof(double));
+    ddfb_adj(u, Hu, Wu, Wk, F, b);
+    for (int i = 0; i < Hb; ++i)
+      for (int j = 0; j < Wb; ++j) {
+        double v = win[(size_t)(by - oy + i) * W + (bx - ox + j)];
+        b[(size_t)i * Wb + j] = clip01(v - b[(size_t)i * Wb + j]);
+      }
+    zero_outside(b, 1, ny, nx, by, bx, Hb, Wb);
+    /* u <- HT(u + gamma_k W_k b) on (Hb-2) x (Wb-2), origin (by+1, bx+1) */
+    int Hn = Hb - 2, Wn = Wb - 2, ny0 = by + 1, nx0 = bx + 1;
+    double *wb = xmalloc((size_t)F * Hn * Wn * sizeof(double));
+    ddfb_fwd(b, Hb, Wb, Wk, F, wb);
+    double *un = crop(u, F, Hu, Wu, 2);
+    for (size_t q = 0; q < (size_t)F * Hn * Wn; ++q) {
+      double v = un[q] + gk * wb[q];
+      un[q] = v < -th ? -th : (v > th ? th : v);
+    }
+    zero_outside(un, F, ny, nx, ny0, nx0, Hn, Wn);
+    free(u);
+    free(b);
+    free(wb);
+    u = un;
+    Hu = Hn; Wu = Wn; uy = ny0; ux = nx0;
+  }
+  /* D(v) = P(v - gamma_K W_K^* u_{K-1}) on (Hu-2) x (Wu-2) */
+  int Ho = Hu - 2, Wo = Wu - 2, oy2 = uy + 1, ox2 = ux + 1;
+  double *out = xmalloc((size_t)Ho * Wo * sizeof(double));
+  ddfb_adj(u, Hu, Wu, WK, F, out);
+  const double gK = cf->ddfb_gamma[K - 1];
+  for (int i = 0; i < Ho; ++i)
+    for (int j = 0; j < Wo; ++j) {
+      double v = win[(size_t)(oy2 - oy + i) * W + (ox2 - ox + j)];
+      out[(size_t)i * Wo + j] = clip01(v - gK * out[(size_t)i * Wo + j]);
+    }
+  free(u);
+  return out;
+}
+
+int oracle_ddfb(const oracle_config *cf, const double *v, int32_t ny, int32_t nx, double *out) {
+  if (cf->ddfb_layers < 1 || cf->ddfb_features < 1 || !cf->ddfb_weights || !cf->ddfb_gamma)
+    return -1;
+  int R = 2 * cf->ddfb_layers;
+  int H = ny + 2 * R, W = nx + 2 * R;
+  double *win = xmalloc((size_t)H * W * sizeof(double));
+  extract_window(v, 1, ny, nx, -R, -R, H, W, win);
+  double *res = ddfb_window(cf, win, ny, nx, -R, -R, H, W);
+  memcpy(out, res, (size_t)ny * nx * sizeof(double));
+  free(res);
+  free(win);
+  return 0;
+}
+
+/* Data-term gradient with the splitting variable z1 held as chain state
+ * (PSGLA z-steps): with A = eta diag(m) K,
+ *   g = A^T (A x - z1) / rho = eta K^T (m (eta K x - z1)) / rho
+ * on the window's region shrunk by 2r per side.  zwin holds z1 on the region
+ * shrunk by r (origin (oy + r, ox + r)). */
+static void grad_window_state(const oracle_config *c, const double *win, const double *zwin,
+                              int oy, int ox, int H, int W, double *g) {
+  int L = c->ksize, r = L / 2;
+  int H1 = H - 2 * r, W1 = W - 2 * r;
+  const double eta = c->eta > 0 ? c->eta : 1.0;
+  double *kx = xmalloc((size_t)H1 * W1 * sizeof(double));
+  valid_conv(win, H, W, c->kernel, L, kx);
+  for (int i = 0; i < H1; ++i)
+    for (int j = 0; j < W1; ++j) {
+      int gi = oy + r + i, gj = ox + r + j;
+      size_t q = (size_t)i * W1 + j;
+      double res = 0.0;
+      if (gi >= 0 && gi < c->ny && gj >= 0 && gj < c->nx) {
+        int64_t p = (int64_t)gi * c->nx + gj;
+        double m = c->mask ? (double)c->mask[p] : 1.0;
+        res = m * (eta * (m * kx[q]) - zwin[q]);
+      }
+      kx[q] = res;
+    }
+  valid_xcorr(kx, H1, W1, c->kernel, L, g);
+  int n2 = (H1 - 2 * r) * (W1 - 2 * r);
+  for (int i = 0; i < n2; ++i) g[i] = eta * g[i] / c->rho;
+  free(kx);
+}
+
+/* Prior radius of one iteration: the receptive field of the prior term. */
+static int prior_radius(const oracle_config *c) {
+  if (c->prior == 1) return 1;
+  if (c->prior == 2) return 2 * c->ddfb_layers;
+  return c->net.n_layers;
+}
+
+/* ======================================================================
  * The chain
  * ==================================================================== */
 struct oracle_chain {
   oracle_config cfg;       /* pointers below are owned copies */
-  double *y, *kernel, *w, *b, *act_scales;
+  double *y, *kernel, *w, *b, *act_scales, *dw, *dg;
   int32_t *channels, *fmt;
   uint8_t *mask;
   double *x, *z;
+  double *z1, *z2;         /* PSGLA / TV state z^(t) (z^(0) = 0) */
   int64_t t;
   int64_t n;               /* Welford count */
   int record_z;
@@ -624,13 +862,28 @@ oracle_chain *oracle_create(const oracle_config *cfg, char *err, int errlen) {
       !(cfg->alpha >= 0) || !(cfg->inv_lambda >= 0))
     FAIL("sigma, eps, delta must be > 0; rho, alpha, inv_lambda >= 0");
   const oracle_net *n = &cfg->net;
-  if (n->n_layers < 1 || !n->channels || n->channels[0] != 1 ||
-      n->channels[n->n_layers] != 1 || !n->weights || !n->biases)
+  if (cfg->prior < 0 || cfg->prior > 2) FAIL("unknown prior");
+  if (cfg->prior == 0 &&
+      (n->n_layers < 1 || !n->channels || n->channels[0] != 1 ||
+       n->channels[n->n_layers] != 1 || !n->weights || !n->biases))
     FAIL("denoiser must map 1 channel to 1 channel");
+  if (cfg->prior == 2 && (cfg->ddfb_layers < 1 || cfg->ddfb_features < 1 || !cfg->ddfb_weights ||
+                          !cfg->ddfb_gamma || !(cfg->ddfb_thresh >= 0)))
+    FAIL("DDFB needs layers, features, weights, step sizes and a threshold");
+  if (cfg->likelihood < 0 || cfg->likelihood > 1 || cfg->z_step < 0 || cfg->z_step > 1)
+    FAIL("unknown likelihood or z-step");
+  if (cfg->likelihood == 1 && cfg->z_step != 1) FAIL("the Poisson likelihood needs the PSGLA z-step");
+  if ((cfg->z_step == 1 || cfg->prior == 1) && !(cfg->rho > 0 && cfg->kappa > 0))
+    FAIL("PSGLA needs rho > 0 and kappa > 0");
+  if (cfg->prior == 1 && (cfg->z_step != 0 || cfg->likelihood != 0 || cfg->rho2 > 0))
+    FAIL("the TV prior runs with the unsplit Gaussian likelihood");
+  if (cfg->rho2 > 0 && !(cfg->kappa2 > 0)) FAIL("the second z block needs kappa2 > 0");
+  if (!(cfg->rho2 >= 0) || !(cfg->beta >= 0) || !(cfg->eta >= 0)) FAIL("negative parameter");
   int r = cfg->ksize / 2;
   int blocked = cfg->block_y > 0 && cfg->block_x > 0 &&
                 !(cfg->block_y >= cfg->ny && cfg->block_x >= cfg->nx);
-  if (blocked && cfg->halo < (2 * r > n->n_layers ? 2 * r : n->n_layers))
+  int pr = prior_radius(cfg);
+  if (blocked && cfg->halo < (2 * r > pr ? 2 * r : pr))
     FAIL("halo must be >= max(2r, K)");
   oracle_chain *c = calloc(1, sizeof *c);
   if (!c) FAIL("out of memory");
@@ -639,11 +892,17 @@ oracle_chain *oracle_create(const oracle_config *cfg, char *err, int errlen) {
   c->y = dup(cfg->y, N * sizeof(double));
   c->kernel = dup(cfg->kernel, (size_t)cfg->ksize * cfg->ksize * sizeof(double));
   c->mask = dup(cfg->mask, N);
-  c->channels = dup(n->channels, (n->n_layers + 1) * sizeof(int32_t));
-  c->w = dup(n->weights, weight_offset(n, n->n_layers) * sizeof(double));
-  c->b = dup(n->biases, bias_offset(n, n->n_layers) * sizeof(double));
-  c->fmt = dup(n->layer_fmt, n->n_layers * sizeof(int32_t));
-  c->act_scales = dup(n->act_scales, n->n_layers * sizeof(double));
+  if (cfg->prior == 0) {
+    c->channels = dup(n->channels, (n->n_layers + 1) * sizeof(int32_t));
+    c->w = dup(n->weights, weight_offset(n, n->n_layers) * sizeof(double));
+    c->b = dup(n->biases, bias_offset(n, n->n_layers) * sizeof(double));
+    c->fmt = dup(n->layer_fmt, n->n_layers * sizeof(int32_t));
+    c->act_scales = dup(n->act_scales, n->n_layers * sizeof(double));
+  }
+  if (cfg->prior == 2) {
+    c->dw = dup(cfg->ddfb_weights, (size_t)cfg->ddfb_layers * cfg->ddfb_features * 9 * sizeof(double));
+    c->dg = dup(cfg->ddfb_gamma, (size_t)cfg->ddfb_layers * sizeof(double));
+  }
   c->cfg.y = c->y;
   c->cfg.kernel = c->kernel;
   c->cfg.mask = c->mask;
@@ -652,9 +911,13 @@ oracle_chain *oracle_create(const oracle_config *cfg, char *err, int errlen) {
   c->cfg.net.biases = c->b;
   c->cfg.net.layer_fmt = c->fmt;
   c->cfg.net.act_scales = c->act_scales;
+  c->cfg.ddfb_weights = c->dw;
+  c->cfg.ddfb_gamma = c->dg;
   c->cfg.x0 = NULL;
   c->x = xmalloc(N * sizeof(double));
   c->z = calloc(N, sizeof(double));
+  c->z1 = calloc(N, sizeof(double));
+  c->z2 = calloc(N, sizeof(double));
   c->mean = calloc(N, sizeof(double));
   c->m2 = calloc(N, sizeof(double));
   if (cfg->x0) memcpy(c->x, cfg->x0, N * sizeof(double));
@@ -665,7 +928,136 @@ oracle_chain *oracle_create(const oracle_config *cfg, char *err, int errlen) {
 #undef FAIL
 }
 
-/* x^(t) -> x^(t+1) (Eq. (sgs_pnp_ula_psgla:pnp_ula), Algorithm 1) */
+/* Data-term gradient with z1 held as state, on the whole image (blocked
+ * like oracle_data_grad when the configuration has several blocks), plus
+ * the second block's (x - z2) / rho2. */
+static int data_grad_state(const oracle_config *c, const double *x, const double *z1,
+                           const double *z2, double *g) {
+  int ny = c->ny, nx = c->nx, r = c->ksize / 2;
+  int blocked = c->block_y > 0 && c->block_x > 0 && !(c->block_y >= ny && c->block_x >= nx);
+  int by0 = blocked ? c->block_y : ny, bx0 = blocked ? c->block_x : nx;
+  int h = blocked ? c->halo : 2 * r;
+  if (h < 2 * r) return -1;
+  for (int by = 0; by < ny; by += by0)
+    for (int bx = 0; bx < nx; bx += bx0) {
+      int cy = (by + by0 <= ny) ? by0 : ny - by;
+      int cx = (bx + bx0 <= nx) ? bx0 : nx - bx;
+      int H = cy + 2 * h, W = cx + 2 * h;
+      double *win = xmalloc((size_t)H * W * sizeof(double));
+      double *zw = xmalloc((size_t)(H - 2 * r) * (W - 2 * r) * sizeof(double));
+      extract_window(x, 1, ny, nx, by - h, bx - h, H, W, win);
+      extract_window(z1, 1, ny, nx, by - h + r, bx - h + r, H - 2 * r, W - 2 * r, zw);
+      int Hg = H - 4 * r, Wg = W - 4 * r, off = h - 2 * r;
+      double *gw = xmalloc((size_t)Hg * Wg * sizeof(double));
+      grad_window_state(c, win, zw, by - h, bx - h, H, W, gw);
+      for (int i = 0; i < cy; ++i)
+        for (int j = 0; j < cx; ++j)
+          g[(size_t)(by + i) * nx + bx + j] = gw[(size_t)(i + off) * Wg + j + off];
+      free(gw);
+      free(zw);
+      free(win);
+    }
+  if (c->rho2 > 0)
+    for (size_t p = 0; p < (size_t)ny * nx; ++p) g[p] += (x[p] - z2[p]) / c->rho2;
+  return 0;
+}
+
+/* D(x) of the DDFB prior on the whole image, blocked like oracle_denoiser */
+static int ddfb_blocked(const oracle_config *c, const double *x, double *D) {
+  int ny = c->ny, nx = c->nx, R = 2 * c->ddfb_layers;
+  int blocked = c->block_y > 0 && c->block_x > 0 && !(c->block_y >= ny && c->block_x >= nx);
+  if (!blocked) return oracle_ddfb(c, x, ny, nx, D);
+  int h = c->halo;
+  if (h < R) return -1;
+  for (int by = 0; by < ny; by += c->block_y)
+    for (int bx = 0; bx < nx; bx += c->block_x) {
+      int cy = (by + c->block_y <= ny) ? c->block_y : ny - by;
+      int cx = (bx + c->block_x <= nx) ? c->block_x : nx - bx;
+      int H = cy + 2 * h, W = cx + 2 * h;
+      double *win = xmalloc((size_t)H * W * sizeof(double));
+      extract_window(x, 1, ny, nx, by - h, bx - h, H, W, win);
+      double *res = ddfb_window(c, win, ny, nx, by - h, bx - h, H, W);
+      int Wr = W - 2 * R, off = h - R;
+      for (int i = 0; i < cy; ++i)
+        for (int j = 0; j < cx; ++j)
+          D[(size_t)(by + i) * nx + bx + j] = res[(size_t)(i + off) * Wr + j + off];
+      free(res);
+      free(win);
+    }
+  return 0;
+}
+
+/* (1/rho) D^T (D x - z) of the TV prior's coupling term at pixel (i, j),
+ * from x and the two difference planes of z (Sec. III-B2) */
+static double tv_coupling(const oracle_config *c, const double *x, const double *zh,
+                          const double *zv, int i, int j) {
+  int ny = c->ny, nx = c->nx;
+  size_t p = (size_t)i * nx + j;
+  /* residual r = D x - z at pixel q, both components */
+#define RH(q, jj) ((jj) + 1 < nx ? (x[(q) + 1] - x[q]) - zh[q] : -zh[q])
+#define RV(q, ii) ((ii) + 1 < ny ? (x[(q) + nx] - x[q]) - zv[q] : -zv[q])
+  double v = 0.0;
+  if (j >= 1) v += RH(p - 1, j - 1);
+  if (j + 1 < nx) v -= RH(p, j);
+  if (i >= 1) v += RV(p - nx, i - 1);
+  if (i + 1 < ny) v -= RV(p, i);
+#undef RH
+#undef RV
+  return v / c->rho;
+}
+
+/* z^(t) -> z^(t+1) from x^(t+1) (Eq. (sgs_pnp_ula_psgla:psgla) and the
+ * z-update of Algorithm 1; Sec. III-B2 for TV), noise from counter t+1 */
+static void z_step(oracle_chain *c) {
+  const oracle_config *cf = &c->cfg;
+  int ny = cf->ny, nx = cf->nx;
+  size_t N = (size_t)ny * nx;
+  const int64_t tz = c->t;                 /* c->t already holds t+1 */
+  if (cf->prior == 1) {                    /* TV: z ~ D x, f2 = beta ||.||_{2,1} */
+    double *dh = xmalloc(N * sizeof(double)), *dv = xmalloc(N * sizeof(double));
+    oracle_grad2d(c->x, ny, nx, dh, dv);
+    const double a = cf->kappa / cf->rho, sq = sqrt(2.0 * cf->kappa), tau = cf->kappa * cf->beta;
+    for (int i = 0; i < ny; ++i)
+      for (int j = 0; j < nx; ++j) {
+        int64_t p = (int64_t)i * nx + j;
+        double xi_u, zh, zv;
+        draw_pixel3(cf->seed, p, tz, cf->chain, &xi_u, &zh, &zv);
+        double vh = c->z1[p] - a * (c->z1[p] - dh[p]) + sq * zh;
+        double vv = c->z2[p] - a * (c->z2[p] - dv[p]) + sq * zv;
+        oracle_prox_l21(&vh, &vv, tau);
+        c->z1[p] = vh;
+        c->z2[p] = vv;
+      }
+    free(dh);
+    free(dv);
+    return;
+  }
+  /* z1 ~ eta diag(m) K x with the likelihood as f; z2 ~ x with f = indicator of R+ */
+  const double eta = cf->eta > 0 ? cf->eta : 1.0;
+  double *kx = xmalloc(N * sizeof(double));
+  oracle_blur(c->x, ny, nx, cf->kernel, cf->ksize, kx);
+  const double a1 = cf->kappa / cf->rho, s1 = sqrt(2.0 * cf->kappa);
+  const double a2 = cf->rho2 > 0 ? cf->kappa2 / cf->rho2 : 0.0, s2 = sqrt(2.0 * cf->kappa2);
+  for (size_t p = 0; p < N; ++p) {
+    double xi_u, ze1, ze2;
+    draw_pixel3(cf->seed, (int64_t)p, tz, cf->chain, &xi_u, &ze1, &ze2);
+    double m = cf->mask ? (double)cf->mask[p] : 1.0;
+    double v = c->z1[p] - a1 * (c->z1[p] - eta * m * kx[p]) + s1 * ze1;
+    if (m != 0.0)   /* unobserved entries carry no data term: prox = identity */
+      v = cf->likelihood == 1 ? oracle_prox_kl(v, c->y[p], cf->kappa)
+                              : oracle_prox_gauss(v, c->y[p], cf->sigma, cf->kappa);
+    c->z1[p] = v;
+    if (cf->rho2 > 0) {
+      double w = c->z2[p] - a2 * (c->z2[p] - c->x[p]) + s2 * ze2;
+      c->z2[p] = w > 0.0 ? w : 0.0;
+    }
+  }
+  free(kx);
+}
+
+/* x^(t) -> x^(t+1) (Eq. (sgs_pnp_ula_psgla:pnp_ula), Algorithm 1; PSGLA
+ * x-transition with the indicator of R+ for the TV prior, Sec. III-B2),
+ * then z^(t+1) for the PSGLA and TV chains */
 static int one_step(oracle_chain *c) {
   const oracle_config *cfg = &c->cfg;
   int ny = cfg->ny, nx = cfg->nx;
@@ -673,9 +1065,17 @@ static int one_step(oracle_chain *c) {
   double *g = xmalloc(N * sizeof(double));
   double *G = xmalloc(N * sizeof(double));
   /* data term (blocked when the configuration has several blocks) */
-  oracle_data_grad(cfg, c->x, c->t, g);
+  if (cfg->prior == 1) {
+    oracle_config cg = *cfg;
+    cg.rho = 0.0;                          /* TV: the likelihood is not split */
+    oracle_data_grad(&cg, c->x, c->t, g);
+  } else if (cfg->z_step == 1) {
+    data_grad_state(cfg, c->x, c->z1, c->z2, g);
+  } else {
+    oracle_data_grad(cfg, c->x, c->t, g);
+  }
   /* record z for inspection (monolithic draw, identical values) */
-  if (cfg->rho > 0 && c->record_z) {
+  if (cfg->z_step == 0 && cfg->prior != 1 && cfg->rho > 0 && c->record_z) {
     int r = cfg->ksize / 2;
     int H = ny + 4 * r, W = nx + 4 * r;
     double *win = xmalloc((size_t)H * W * sizeof(double));
@@ -691,8 +1091,13 @@ static int one_step(oracle_chain *c) {
     free(gtmp);
     free(win);
   }
-  /* prior term: G = Id - D_eps */
-  oracle_denoiser(&cfg->net, c->x, ny, nx, cfg->block_y, cfg->block_x, cfg->halo, G);
+  /* prior term: G = Id - D_eps (residual CNN or DDFB) */
+  if (cfg->prior == 0) {
+    oracle_denoiser(&cfg->net, c->x, ny, nx, cfg->block_y, cfg->block_x, cfg->halo, G);
+  } else if (cfg->prior == 2) {
+    ddfb_blocked(cfg, c->x, G);
+    for (size_t p = 0; p < N; ++p) G[p] = c->x[p] - G[p];
+  }
   const double d = cfg->delta;
   const double cprior = cfg->alpha * d / cfg->eps;
   const double cproj = d * cfg->inv_lambda;
@@ -705,13 +1110,20 @@ static int one_step(oracle_chain *c) {
       double xi, zeta_unused;
       draw_pixel(cfg->seed, p, c->t, cfg->chain, &xi, &zeta_unused);
       double x = c->x[p];
-      double proj = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
-      double xn = x - d * g[p] - cprior * G[p] + cproj * (proj - x) + sq * xi;
+      double xn;
+      if (cfg->prior == 1) {
+        double v = x - d * g[p] - d * tv_coupling(cfg, c->x, c->z1, c->z2, i, j) + sq * xi;
+        xn = v > 0.0 ? v : 0.0;            /* prox of the indicator of R+ */
+      } else {
+        double proj = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+        xn = x - d * g[p] - cprior * G[p] + cproj * (proj - x) + sq * xi;
+      }
       if (!isfinite(xn)) bad = 1;
       g[p] = xn;  /* x^(t+1) staged in g so every pixel reads x^(t) */
     }
   memcpy(c->x, g, N * sizeof(double));
   c->t += 1;
+  if (cfg->z_step == 1 || cfg->prior == 1) z_step(c);
   /* online mean / variance of the samples after burn-in (Welford) */
   if (c->t > cfg->burn_in) {
     c->n += 1;
@@ -728,26 +1140,48 @@ static int one_step(oracle_chain *c) {
 }
 
 /* x^(t+1) on the region [y0, y0+h) x [x0, x0+w) of the image described by
- * cfg, from the full x^(t): every operator is evaluated on the region's
- * extended window of half-width max(2r, K) only (the same window
+ * cfg, from the full x^(t) (and, for the PSGLA and TV chains, the full
+ * z^(t) planes z1, z2): every operator is evaluated on the region's extended
+ * window of half-width max(2r, prior radius) only (the same window
  * computation as a block), so sampled outputs of very large images can be
  * checked one region at a time. */
-int oracle_step_region(const oracle_config *c, const double *x, int64_t t, int32_t y0,
-                       int32_t x0, int32_t h, int32_t w, double *xnew) {
-  int ny = c->ny, nx = c->nx, r = c->ksize / 2, K = c->net.n_layers;
+int oracle_step_region_z(const oracle_config *c, const double *x, const double *z1,
+                         const double *z2, int64_t t, int32_t y0, int32_t x0, int32_t h,
+                         int32_t w, double *xnew) {
+  int ny = c->ny, nx = c->nx, r = c->ksize / 2, pr = prior_radius(c);
   if (y0 < 0 || x0 < 0 || h < 1 || w < 1 || y0 + h > ny || x0 + w > nx) return -1;
-  int hh = 2 * r > K ? 2 * r : K;
+  if ((c->z_step == 1 || c->prior == 1) && (!z1 || (!z2 && (c->rho2 > 0 || c->prior == 1))))
+    return -2;
+  int hh = 2 * r > pr ? 2 * r : pr;
   int H = h + 2 * hh, W = w + 2 * hh;
   double *win = xmalloc((size_t)H * W * sizeof(double));
   extract_window(x, 1, ny, nx, y0 - hh, x0 - hh, H, W, win);
-  grad_ctx gc = make_grad_ctx(c);
   int Hg = H - 4 * r, Wg = W - 4 * r, og = hh - 2 * r;
   double *g = xmalloc((size_t)Hg * Wg * sizeof(double));
-  grad_window(&gc, win, y0 - hh, x0 - hh, H, W, t, g, NULL);
-  prepared_net pn;
-  prepare_net(&c->net, &pn);
-  double *res = denoise_window(&c->net, &pn, win, ny, nx, y0 - hh, x0 - hh, H, W, 0, NULL, NULL);
-  int Wd = W - 2 * K, od = hh - K;
+  if (c->z_step == 1 && c->prior != 1) {
+    double *zw = xmalloc((size_t)(H - 2 * r) * (W - 2 * r) * sizeof(double));
+    extract_window(z1, 1, ny, nx, y0 - hh + r, x0 - hh + r, H - 2 * r, W - 2 * r, zw);
+    grad_window_state(c, win, zw, y0 - hh, x0 - hh, H, W, g);
+    free(zw);
+  } else {
+    grad_ctx gc = make_grad_ctx(c);
+    if (c->prior == 1) gc.rho = 0.0;
+    grad_window(&gc, win, y0 - hh, x0 - hh, H, W, t, g, NULL);
+  }
+  double *res = NULL;
+  int Wd = 0, od = 0;
+  if (c->prior == 0) {
+    prepared_net pn;
+    prepare_net(&c->net, &pn);
+    res = denoise_window(&c->net, &pn, win, ny, nx, y0 - hh, x0 - hh, H, W, 0, NULL, NULL);
+    free_net(&pn);
+    Wd = W - 2 * pr;
+    od = hh - pr;
+  } else if (c->prior == 2) {
+    res = ddfb_window(c, win, ny, nx, y0 - hh, x0 - hh, H, W);
+    Wd = W - 2 * pr;
+    od = hh - pr;
+  }
   const double d = c->delta, cprior = c->alpha * d / c->eps, cproj = d * c->inv_lambda;
   const double sq = sqrt(2.0 * d);
   for (int i = 0; i < h; ++i)
@@ -756,16 +1190,27 @@ int oracle_step_region(const oracle_config *c, const double *x, int64_t t, int32
       double xi, zeta_unused;
       draw_pixel(c->seed, p, t, c->chain, &xi, &zeta_unused);
       double xv = x[p];
-      double proj = xv < 0.0 ? 0.0 : (xv > 1.0 ? 1.0 : xv);
       double gv = g[(size_t)(i + og) * Wg + j + og];
+      if (c->z_step == 1 && c->prior != 1 && c->rho2 > 0) gv += (xv - z2[p]) / c->rho2;
+      if (c->prior == 1) {
+        double v = xv - d * gv - d * tv_coupling(c, x, z1, z2, y0 + i, x0 + j) + sq * xi;
+        xnew[(size_t)i * w + j] = v > 0.0 ? v : 0.0;
+        continue;
+      }
+      double proj = xv < 0.0 ? 0.0 : (xv > 1.0 ? 1.0 : xv);
       double Gv = res[(size_t)(i + od) * Wd + j + od];
+      if (c->prior == 2) Gv = xv - Gv;
       xnew[(size_t)i * w + j] = xv - d * gv - cprior * Gv + cproj * (proj - xv) + sq * xi;
     }
   free(res);
-  free_net(&pn);
   free(g);
   free(win);
   return 0;
+}
+
+int oracle_step_region(const oracle_config *c, const double *x, int64_t t, int32_t y0,
+                       int32_t x0, int32_t h, int32_t w, double *xnew) {
+  return oracle_step_region_z(c, x, NULL, NULL, t, y0, x0, h, w, xnew);
 }
 
 int oracle_step(oracle_chain *c, int32_t n_iters) {
@@ -799,10 +1244,23 @@ void oracle_last_z(const oracle_chain *c, double *z) {
 
 void oracle_record_z(oracle_chain *c, int32_t on) { c->record_z = on; }
 
+void oracle_get_z(const oracle_chain *c, double *z1, double *z2) {
+  size_t N = (size_t)c->cfg.ny * c->cfg.nx;
+  if (z1) memcpy(z1, c->z1, N * sizeof(double));
+  if (z2) memcpy(z2, c->z2, N * sizeof(double));
+}
+
+void oracle_set_z(oracle_chain *c, const double *z1, const double *z2) {
+  size_t N = (size_t)c->cfg.ny * c->cfg.nx;
+  if (z1) memcpy(c->z1, z1, N * sizeof(double));
+  if (z2) memcpy(c->z2, z2, N * sizeof(double));
+}
+
 void oracle_destroy(oracle_chain *c) {
   if (!c) return;
   free(c->y); free(c->kernel); free(c->mask); free(c->channels); free(c->w); free(c->b);
-  free(c->fmt); free(c->act_scales); free(c->x); free(c->z); free(c->mean); free(c->m2);
+  free(c->fmt); free(c->act_scales); free(c->dw); free(c->dg); free(c->x); free(c->z);
+  free(c->z1); free(c->z2); free(c->mean); free(c->m2);
   free(c);
 }
 

@@ -62,6 +62,19 @@ typedef struct {
   uint32_t chain;
   int32_t burn_in;
   const double *x0;          /* NULL: zeros */
+  /* likelihood and splitting variable (Sec. III-A, Eq. (sgs_pnp_ula_psgla:psgla)) */
+  int32_t likelihood;        /* 0 Gaussian, 1 Poisson: f = KL(y || .) */
+  int32_t z_step;            /* 0 exact Gaussian conditional draw, 1 PSGLA */
+  double eta;                /* operator eta diag(m) K (0 is taken as 1) */
+  double kappa;              /* PSGLA step of the z block coupled to the operator */
+  double rho2, kappa2;       /* second block z2 ~ x, f = indicator of R+ (rho2 = 0: none) */
+  /* prior (Sec. II-B1 Examples 2-3, Sec. III-B2) */
+  int32_t prior;             /* 0 residual CNN, 1 TV (PSGLA), 2 DDFB */
+  double beta;               /* TV weight */
+  int32_t ddfb_layers, ddfb_features;
+  const double *ddfb_weights;  /* K blocks of [F][3][3]: W_k maps 1 -> F channels */
+  const double *ddfb_gamma;    /* K step sizes gamma_k */
+  double ddfb_thresh;          /* hard-tanh level */
 } oracle_config;
 
 typedef struct oracle_chain oracle_chain;
@@ -74,6 +87,11 @@ void oracle_set_state(oracle_chain *c, const double *x, int64_t t);
 void oracle_stats(const oracle_chain *c, double *mean, double *m2, int64_t *n);
 void oracle_record_z(oracle_chain *c, int32_t on);           /* keep z of each step */
 void oracle_last_z(const oracle_chain *c, double *z);        /* z used by last step */
+/* state z^(t) of the PSGLA and TV chains (z1: the block coupled to the
+ * operator, or the horizontal differences for TV; z2: the second block, or
+ * the vertical differences); either may be NULL */
+void oracle_get_z(const oracle_chain *c, double *z1, double *z2);
+void oracle_set_z(oracle_chain *c, const double *z1, const double *z2);
 void oracle_destroy(oracle_chain *c);
 int  oracle_num_threads(void);
 
@@ -98,9 +116,25 @@ int  oracle_denoise_region(const oracle_net *net, const double *x, int32_t ny, i
                            int32_t y0, int32_t x0, int32_t h, int32_t w, double *G);
 int  oracle_denoiser_layers(const oracle_net *net, const double *x, int32_t ny,
                             int32_t nx, double *acts, double *amax);
+int  oracle_layers_from(const oracle_net *net, const double *in, int32_t ny, int32_t nx,
+                        int32_t k0, int32_t k1, double *acts, double *amax);
 int  oracle_data_grad(const oracle_config *cfg, const double *x, int64_t t, double *g);
 int  oracle_step_region(const oracle_config *cfg, const double *x, int64_t t, int32_t y0,
                         int32_t x0, int32_t h, int32_t w, double *xnew);
+int  oracle_step_region_z(const oracle_config *cfg, const double *x, const double *z1,
+                          const double *z2, int64_t t, int32_t y0, int32_t x0, int32_t h,
+                          int32_t w, double *xnew);
+/* the DDFB denoiser D(v) of Eq. (ddfb_operator) on a whole image */
+int  oracle_ddfb(const oracle_config *cfg, const double *v, int32_t ny, int32_t nx,
+                 double *out);
+/* the 2-D forward-difference operator D and its adjoint */
+void oracle_grad2d(const double *x, int32_t ny, int32_t nx, double *dh, double *dv);
+void oracle_grad2d_adjoint(const double *dh, const double *dv, int32_t ny, int32_t nx,
+                           double *out);
+/* proximity operators used by the z-steps (elementwise / per pixel) */
+double oracle_prox_kl(double v, double y, double kappa);
+double oracle_prox_gauss(double v, double y, double sigma, double kappa);
+void oracle_prox_l21(double *vh, double *vv, double tau);
 
 #ifdef __cplusplus
 }

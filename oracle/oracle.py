@@ -60,7 +60,12 @@ class OracleConfig(C.Structure):
                 ("alpha", C.c_double), ("delta", C.c_double), ("rho", C.c_double),
                 ("inv_lambda", C.c_double), ("block_y", C.c_int32), ("block_x", C.c_int32),
                 ("halo", C.c_int32), ("net", OracleNet), ("seed", C.c_uint64),
-                ("chain", C.c_uint32), ("burn_in", C.c_int32), ("x0", _dp)]
+                ("chain", C.c_uint32), ("burn_in", C.c_int32), ("x0", _dp),
+                ("likelihood", C.c_int32), ("z_step", C.c_int32), ("eta", C.c_double),
+                ("kappa", C.c_double), ("rho2", C.c_double), ("kappa2", C.c_double),
+                ("prior", C.c_int32), ("beta", C.c_double), ("ddfb_layers", C.c_int32),
+                ("ddfb_features", C.c_int32), ("ddfb_weights", _dp), ("ddfb_gamma", _dp),
+                ("ddfb_thresh", C.c_double)]
 
 
 def _declare(L):
@@ -91,10 +96,24 @@ def _declare(L):
                                         C.c_int32, C.c_int32, C.c_int32, C.c_int32, _dp]
     L.oracle_denoiser_layers.argtypes = [C.POINTER(OracleNet), _dp, C.c_int32, C.c_int32,
                                          _dp, _dp]
+    L.oracle_layers_from.argtypes = [C.POINTER(OracleNet), _dp, C.c_int32, C.c_int32,
+                                     C.c_int32, C.c_int32, _dp, _dp]
     L.oracle_data_grad.argtypes = [C.POINTER(OracleConfig), _dp, C.c_int64, _dp]
     L.oracle_num_threads.restype = C.c_int
     L.oracle_step_region.argtypes = [C.POINTER(OracleConfig), _dp, C.c_int64, C.c_int32,
                                      C.c_int32, C.c_int32, C.c_int32, _dp]
+    L.oracle_step_region_z.argtypes = [C.POINTER(OracleConfig), _dp, _dp, _dp, C.c_int64,
+                                       C.c_int32, C.c_int32, C.c_int32, C.c_int32, _dp]
+    L.oracle_get_z.argtypes = [C.c_void_p, _dp, _dp]
+    L.oracle_set_z.argtypes = [C.c_void_p, _dp, _dp]
+    L.oracle_ddfb.argtypes = [C.POINTER(OracleConfig), _dp, C.c_int32, C.c_int32, _dp]
+    L.oracle_grad2d.argtypes = [_dp, C.c_int32, C.c_int32, _dp, _dp]
+    L.oracle_grad2d_adjoint.argtypes = [_dp, _dp, C.c_int32, C.c_int32, _dp]
+    L.oracle_prox_kl.restype = C.c_double
+    L.oracle_prox_kl.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.oracle_prox_gauss.restype = C.c_double
+    L.oracle_prox_gauss.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+    L.oracle_prox_l21.argtypes = [_dp, _dp, C.c_double]
 
 
 def _d(a: np.ndarray):
@@ -201,6 +220,63 @@ def denoiser(net: Net, x, block: int = 0, halo: int = 0, block_x: Optional[int] 
     return G
 
 
+def grad2d(x):
+    """(D_h x, D_v x): forward differences, zero in the last column / row."""
+    x = _f64(x)
+    dh, dv = np.empty_like(x), np.empty_like(x)
+    lib().oracle_grad2d(_d(x), x.shape[0], x.shape[1], _d(dh), _d(dv))
+    return dh, dv
+
+
+def grad2d_adjoint(dh, dv):
+    dh, dv = _f64(dh), _f64(dv)
+    out = np.empty_like(dh)
+    lib().oracle_grad2d_adjoint(_d(dh), _d(dv), dh.shape[0], dh.shape[1], _d(out))
+    return out
+
+
+def prox_kl(v, y, kappa):
+    return lib().oracle_prox_kl(float(v), float(y), float(kappa))
+
+
+def prox_gauss(v, y, sigma, kappa):
+    return lib().oracle_prox_gauss(float(v), float(y), float(sigma), float(kappa))
+
+
+def prox_l21(vh, vv, tau):
+    a, b = C.c_double(vh), C.c_double(vv)
+    lib().oracle_prox_l21(C.byref(a), C.byref(b), float(tau))
+    return a.value, b.value
+
+
+class Ddfb:
+    """DDFB parameters: K layers of 1 -> F 3x3 weights, step sizes, threshold."""
+
+    def __init__(self, weights, gammas, thresh):
+        self.w = _f64(np.asarray(weights, np.float64).ravel())
+        self.K = len(gammas)
+        self.F = self.w.size // (9 * self.K)
+        self.g = _f64(gammas)
+        self.thresh = float(thresh)
+
+    def fill(self, cfg):
+        cfg.prior = 2
+        cfg.ddfb_layers, cfg.ddfb_features = self.K, self.F
+        cfg.ddfb_weights, cfg.ddfb_gamma = _d(self.w), _d(self.g)
+        cfg.ddfb_thresh = self.thresh
+
+
+def ddfb(params: Ddfb, v) -> np.ndarray:
+    """D(v) of the DDFB denoiser on a whole image."""
+    v = _f64(v)
+    cfg = OracleConfig()
+    params.fill(cfg)
+    out = np.empty_like(v)
+    if lib().oracle_ddfb(C.byref(cfg), _d(v), v.shape[0], v.shape[1], _d(out)) != 0:
+        raise ValueError("bad DDFB parameters")
+    return out
+
+
 def denoise_region(net: Net, x, y0: int, x0: int, h: int, w: int) -> np.ndarray:
     """G(x) on the region [y0, y0+h) x [x0, x0+w) of the full image x (cost ~
     region size: the region's K-halo window only)."""
@@ -228,6 +304,25 @@ def denoiser_layers(net: Net, x):
     return out, amax
 
 
+def layers_from(net: Net, inp, k0: int, k1: int):
+    """Outputs of layers k0 .. k1-1 applied to `inp` (layer k0's input,
+    (channels[k0], ny, nx)): list of (C, ny, nx) arrays."""
+    inp = _f64(inp)
+    if inp.ndim == 2:
+        inp = inp[None]
+    _, ny, nx = inp.shape
+    sizes = [int(c) * ny * nx for c in net.channels[k0 + 1:k1 + 1]]
+    acts = np.empty(sum(sizes))
+    rc = lib().oracle_layers_from(C.byref(net.struct), _d(inp), ny, nx, k0, k1, _d(acts), None)
+    if rc != 0:
+        raise ValueError("layer range outside the network")
+    out, off = [], 0
+    for c, s in zip(net.channels[k0 + 1:k1 + 1], sizes):
+        out.append(acts[off:off + s].reshape(int(c), ny, nx))
+        off += s
+    return out
+
+
 # --------------------------------------------------------------------------
 # chain
 # --------------------------------------------------------------------------
@@ -235,20 +330,28 @@ class Chain:
     """One FP64 PnP-ULA chain (mirrors the product's create/step/stats)."""
 
     def __init__(self, *, y, kernel, sigma, eps, delta, rho=0.0, alpha=1.0, inv_lambda=0.0,
-                 mask=None, block_y=0, block_x=0, halo=0, channels, weights, biases,
-                 layer_fmt=None, act_scales=None, seed=0, chain=0, burn_in=0, x0=None):
+                 mask=None, block_y=0, block_x=0, halo=0, channels=(1, 1),
+                 weights=(np.zeros((1, 1, 3, 3)),), biases=(np.zeros(1),),
+                 layer_fmt=None, act_scales=None, seed=0, chain=0, burn_in=0, x0=None,
+                 likelihood=0, z_step=0, eta=0.0, kappa=0.0, rho2=0.0, kappa2=0.0,
+                 prior=0, beta=0.0, ddfb: Optional[Ddfb] = None):
         self.y = _f64(y)
         self.ny, self.nx = self.y.shape
         self.kernel = _f64(kernel)
         self.mask = None if mask is None else np.ascontiguousarray(mask, np.uint8)
         self.x0 = None if x0 is None else _f64(x0)
         self.net = Net(channels, weights, biases, layer_fmt, act_scales)
+        self.ddfb = ddfb
         self.cfg = OracleConfig(
             self.ny, self.nx, _d(self.y), self.kernel.shape[0], _d(self.kernel),
             self.mask.ctypes.data_as(_u8p) if self.mask is not None else None,
             sigma, eps, alpha, delta, rho, inv_lambda, block_y, block_x, halo,
             self.net.struct, seed, chain, burn_in,
-            _d(self.x0) if self.x0 is not None else None)
+            _d(self.x0) if self.x0 is not None else None,
+            likelihood, z_step, eta, kappa, rho2, kappa2, prior, beta)
+        if ddfb is not None:
+            ddfb.fill(self.cfg)
+            self.cfg.prior = prior if prior else 2
         err = C.create_string_buffer(256)
         h = lib().oracle_create(C.byref(self.cfg), err, 256)
         if not h:
@@ -264,7 +367,13 @@ class Chain:
                   block_x=wl.block_x if block is None else block, halo=wl.halo,
                   channels=wl.channels, weights=wl.weights, biases=wl.biases,
                   layer_fmt=wl.layer_fmt if quantized else None,
-                  act_scales=act_scales, seed=wl.seed, chain=chain, burn_in=wl.burn_in)
+                  act_scales=act_scales, seed=wl.seed, chain=chain, burn_in=wl.burn_in,
+                  likelihood=getattr(wl, "likelihood", 0), z_step=getattr(wl, "z_step", 0),
+                  eta=getattr(wl, "eta", 0.0), kappa=getattr(wl, "kappa", 0.0),
+                  rho2=getattr(wl, "rho2", 0.0), kappa2=getattr(wl, "kappa2", 0.0),
+                  prior=getattr(wl, "prior", 0), beta=getattr(wl, "beta", 0.0))
+        if getattr(wl, "prior", 0) == 2:
+            kw["ddfb"] = Ddfb(wl.ddfb_weights, wl.ddfb_gamma, wl.ddfb_thresh)
         kw.update(over)
         return cls(**kw)
 
@@ -286,6 +395,17 @@ class Chain:
         lib().oracle_stats(self.h, _d(mean), _d(m2), C.byref(n))
         return mean, m2, n.value
 
+    def get_z(self):
+        """z^(t) of the PSGLA / TV chains: (z1, z2)."""
+        z1 = np.empty((self.ny, self.nx)); z2 = np.empty((self.ny, self.nx))
+        lib().oracle_get_z(self.h, _d(z1), _d(z2))
+        return z1, z2
+
+    def set_z(self, z1, z2=None):
+        z1 = _f64(z1)
+        z2 = None if z2 is None else _f64(z2)
+        lib().oracle_set_z(self.h, _d(z1), _d(z2) if z2 is not None else None)
+
     def record_z(self, on: bool = True):
         lib().oracle_record_z(self.h, int(on))
 
@@ -302,13 +422,21 @@ class Chain:
             raise ValueError("halo smaller than 2r")
         return g
 
-    def step_region(self, x, t: int, y0: int, x0: int, h: int, w: int):
-        """x^(t+1) on a region, from the full x^(t) (cost ~ region size)."""
+    def step_region(self, x, t: int, y0: int, x0: int, h: int, w: int, z=None):
+        """x^(t+1) on a region, from the full x^(t) (and z^(t) = (z1, z2) for
+        the PSGLA and TV chains); cost ~ region size."""
         x = _f64(x)
         out = np.empty((h, w))
-        rc = lib().oracle_step_region(C.byref(self.cfg), _d(x), t, y0, x0, h, w, _d(out))
+        z1 = z2 = None
+        if z is not None:
+            z1 = _f64(z[0])
+            z2 = None if z[1] is None else _f64(z[1])
+        rc = lib().oracle_step_region_z(C.byref(self.cfg), _d(x),
+                                        _d(z1) if z1 is not None else None,
+                                        _d(z2) if z2 is not None else None, t, y0, x0, h, w,
+                                        _d(out))
         if rc != 0:
-            raise ValueError("region outside the image")
+            raise ValueError("region outside the image or z missing")
         return out
 
     def close(self):

@@ -139,6 +139,13 @@ pnpula_status pnpula_denoise(pnpula_ctx *c, const float *x, float *G, float *lay
   return report(c, c->eng.denoise(c->job, x, G, layers, nullptr));
 }
 
+pnpula_status pnpula_denoise_stages(pnpula_ctx *c, const float *x, float *G, int32_t *n_stages,
+                                    int32_t *stage_layer, float *stage_acts) {
+  GUARD(c);
+  if (!x) return report(c, Status::fail(PNPULA_EINVAL, "x is required"));
+  return report(c, c->eng.denoise_stages(c->job, x, G, n_stages, stage_layer, stage_acts));
+}
+
 pnpula_status pnpula_calibrate(pnpula_ctx *c, const float *x, float *amax) {
   GUARD(c);
   if (!x || !amax) return report(c, Status::fail(PNPULA_EINVAL, "x and amax are required"));

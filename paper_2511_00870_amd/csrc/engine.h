@@ -5,6 +5,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -91,6 +92,9 @@ class Engine {
   Status read_stats(Job *j, double *mean, double *m2, int64_t *n);
   Status restore_stats(Job *j, const double *mean, const double *m2, int64_t n);
   Status denoise(Job *j, const float *x, float *G, float *layers, float *amax);
+  Status denoise_stages(Job *j, const float *x, float *G, int32_t *n_stages,
+                        int32_t *stage_layer, float *stage_acts);
+  Status read_act(Job *j, int k, int slot, float *dst);
 
   void profile_enable(bool on);
   Status profile_read(int cls, double *ms, int64_t *launches);
@@ -114,7 +118,10 @@ class Engine {
   bool pair_ok(int k) const;
   bool first_pair8_ok() const;
   Status launch_g_from_s(int64_t tick, bool prof);
-  Status run_fused_denoiser(int64_t tick, bool prof);
+  // called after each launch of the fused path that writes an activation
+  // buffer: (index of the last layer it computed, buffer)
+  using StageFn = std::function<Status(int, int)>;
+  Status run_fused_denoiser(int64_t tick, bool prof, const StageFn *on_stage = nullptr);
   Status launch_layer(int k, int64_t tick, bool prof, int in_slot = -1, int out_slot = -1);
   JobDesc *d_jobs = nullptr;
   TileRef *d_conv = nullptr, *d_upd = nullptr, *d_pair = nullptr, *d_pair_ws = nullptr;

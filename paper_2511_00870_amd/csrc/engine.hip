@@ -929,7 +929,7 @@ Status Engine::launch_g_from_s(int64_t tick, bool prof) {
 // the denoiser as the sampler runs it: first layer inside the first middle
 // layer's kernel and last layer inside the last middle layer's (when the
 // network allows), the rest layer by layer
-Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
+Status Engine::run_fused_denoiser(int64_t tick, bool prof, const StageFn *on_stage) {
   const int K = net.K;
   const bool ff = first_mid_fused(), lf = net.last_fused;
   // cur: the activation buffer holding the latest layer's output once a
@@ -942,8 +942,12 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
     return -1;
   };
   int k = 0;
+  auto stage = [&](int layer, int slot) -> Status {
+    return on_stage ? (*on_stage)(layer, slot) : Status::ok();
+  };
   if (ff) {
     TRY(launch_first_mid(tick, prof));
+    TRY(stage(1, net.layers[1].out_buf));
     k = 2;
   } else if (first_pair8_ok()) {
     // e4m3 networks: the first layer runs inside the first pair's kernel
@@ -952,6 +956,7 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
     const bool last = net.last_pair8 && K - 2 == 2;
     TRY(launch_pair(1, in, out, tick, prof, true, last));
     if (last) return launch_g_from_s(tick, prof);
+    TRY(stage(2, out));
     cur = out;
     k = 3;
   }
@@ -972,16 +977,19 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof) {
       const bool last = net.last_pair8 && k + 1 == K - 2;
       TRY(launch_pair(k, in, out, tick, prof, false, last));
       if (last) return launch_g_from_s(tick, prof);
+      TRY(stage(k + 1, out));
       cur = out;
       ++k;
       continue;
     }
     if (cur < 0) {
       TRY(launch_layer(k, tick, prof));
+      if (k + 1 < K) TRY(stage(k, L.out_buf));
       continue;
     }
     const int out = (k + 1 < K && L.out_fmt == net.buf_fmt[cur]) ? other(cur) : L.out_buf;
     TRY(launch_layer(k, tick, prof, in, out));
+    if (k + 1 < K) TRY(stage(k, out));
     cur = k + 1 < K ? out : -1;
   }
   return Status::ok();
@@ -1093,6 +1101,66 @@ Status Engine::restore_stats(Job *j, const double *mean, const double *m2, int64
   return Status::ok();
 }
 
+// Output of layer k (k < K - 1) held in activation buffer `slot`,
+// dequantised to FP32 (value = code x the next layer's input scale), as
+// channels planes of ny*nx (CHW).
+Status Engine::read_act(Job *j, int k, int slot, float *dst) {
+  const JobDesc &d = j->d;
+  const LayerPlan &L = net.layers[k];
+  const int ob = fmt_bytes(L.out_fmt), C = L.cout;
+  const size_t pixb = (size_t)net.F * ob, N = (size_t)d.ny * d.nx;
+  HIPOK(hipStreamSynchronize(stream));
+  std::vector<uint8_t> buf((size_t)d.ny * d.nx * C * ob);
+  const uint8_t *src = reinterpret_cast<const uint8_t *>(d.act[slot]);
+  HIPOK(hipMemcpy2D(buf.data(), (size_t)d.nx * C * ob, src + ((size_t)d.apitch + 1) * pixb,
+                    (size_t)d.apitch * pixb, (size_t)d.nx * C * ob, d.ny, hipMemcpyDeviceToHost));
+  const float sc = net.act_scales[k + 1];
+  for (size_t p = 0; p < N; ++p)
+    for (int c = 0; c < C; ++c) {
+      const uint8_t *e = &buf[(p * C + c) * ob];
+      float v;
+      if (L.out_fmt == FMT_F32) {
+        std::memcpy(&v, e, 4);
+      } else if (L.out_fmt == FMT_BF16) {
+        uint32_t u = (uint32_t)(e[0] | (e[1] << 8)) << 16;
+        std::memcpy(&v, &u, 4);
+      } else {
+        v = host_e4m3_to_f32(e[0]) * sc;
+      }
+      dst[(size_t)c * N + p] = v;
+    }
+  return Status::ok();
+}
+
+// The sampler's denoiser path on x, recording the activation each launch
+// writes: stage i is the output of layer stage_layer[i], dequantised, as
+// channels planes (CHW) at stage_acts + i * F * ny * nx.
+Status Engine::denoise_stages(Job *j, const float *x, float *G, int32_t *n_stages,
+                              int32_t *stage_layer, float *stage_acts) {
+  if (plan_dirty) TRY(rebuild_plan());
+  if (resident.size() != 1 || resident[0] != j)
+    return Status::fail(PNPULA_ESTATE, "denoise needs a single-job engine");
+  JobDesc &d = j->d;
+  const size_t origin = (size_t)d.xborder * d.xpitch + d.xborder;
+  const int64_t alt = j->t + 1;
+  HIPOK(hipMemcpy2DAsync(d.x[alt & 1] + origin, (size_t)d.xpitch * sizeof(float), x,
+                         (size_t)d.nx * sizeof(float), (size_t)d.nx * sizeof(float), d.ny,
+                         hipMemcpyHostToDevice, stream));
+  const size_t plane = (size_t)net.F * d.ny * d.nx;
+  int n = 0;
+  StageFn fn = [&](int layer, int slot) -> Status {
+    if (stage_layer) stage_layer[n] = layer;
+    if (stage_acts) TRY(read_act(j, layer, slot, stage_acts + (size_t)n * plane));
+    ++n;
+    return Status::ok();
+  };
+  TRY(run_fused_denoiser(ticks + 1, false, &fn));
+  HIPOK(hipStreamSynchronize(stream));
+  if (G) HIPOK(hipMemcpy(G, d.G, (size_t)d.ny * d.nx * sizeof(float), hipMemcpyDeviceToHost));
+  if (n_stages) *n_stages = n;
+  return Status::ok();
+}
+
 // Run the denoiser of job j on a given image (placed in the ping-pong
 // buffer that does not hold x^(t)); optionally read back every layer
 // (dequantised) or the largest |input| of every layer.
@@ -1131,8 +1199,7 @@ Status Engine::denoise(Job *j, const float *x, float *G, float *layers, float *a
     const LayerPlan &L = net.layers[k];
     TRY(launch_layer(k, tick_alt, false));
     if (k == K - 1) break;
-    const int ob = fmt_bytes(L.out_fmt), C = L.cout;
-    const size_t pixb = (size_t)net.F * ob;
+    const int C = L.cout;
     if (d_amax) {
       if (L.out_fmt != FMT_F32)
         return Status::fail(PNPULA_ESTATE, "calibration runs on an FP32 denoiser");
@@ -1140,28 +1207,7 @@ Status Engine::denoise(Job *j, const float *x, float *G, float *layers, float *a
                         (size_t)(d.ny + 2 + 16) * d.apitch * net.F, d_amax + k + 1, stream));
     }
     if (lp) {
-      HIPOK(hipStreamSynchronize(stream));
-      // dequantise the stored output: value = code * scale of the next layer's input
-      std::vector<uint8_t> buf((size_t)d.ny * d.nx * C * ob);
-      const uint8_t *src = reinterpret_cast<const uint8_t *>(d.act[L.out_buf]);
-      HIPOK(hipMemcpy2D(buf.data(), (size_t)d.nx * C * ob, src + ((size_t)d.apitch + 1) * pixb,
-                        (size_t)d.apitch * pixb, (size_t)d.nx * C * ob, d.ny,
-                        hipMemcpyDeviceToHost));
-      const float sc = net.act_scales[k + 1];
-      for (size_t p = 0; p < N; ++p)
-        for (int c = 0; c < C; ++c) {
-          const uint8_t *e = &buf[(p * C + c) * ob];
-          float v;
-          if (L.out_fmt == FMT_F32) {
-            std::memcpy(&v, e, 4);
-          } else if (L.out_fmt == FMT_BF16) {
-            uint32_t u = (uint32_t)(e[0] | (e[1] << 8)) << 16;
-            std::memcpy(&v, &u, 4);
-          } else {
-            v = host_e4m3_to_f32(e[0]) * sc;
-          }
-          lp[(size_t)c * N + p] = v;
-        }
+      TRY(read_act(j, k, L.out_buf, lp));
       lp += (size_t)C * N;
     }
   }

@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE"
 EXPORTS = [
     "pnpula_create", "pnpula_step", "pnpula_sync", "pnpula_stats", "pnpula_stats_f64",
     "pnpula_get_state", "pnpula_set_state", "pnpula_restore", "pnpula_denoise",
+    "pnpula_denoise_stages",
     "pnpula_calibrate", "pnpula_profile", "pnpula_profile_read", "pnpula_state_device",
     "pnpula_destroy", "pnpula_last_error", "pnpula_create_error", "pnpula_footprint",
     "pnpula_server_create", "pnpula_server_submit", "pnpula_server_tick", "pnpula_server_poll",
@@ -86,6 +87,7 @@ def _declare(L):
     L.pnpula_set_state.argtypes = [vp, _fp, C.c_int64]
     L.pnpula_restore.argtypes = [vp, _fp, C.c_int64, _dp, _dp, C.c_int64]
     L.pnpula_denoise.argtypes = [vp, _fp, _fp, _fp]
+    L.pnpula_denoise_stages.argtypes = [vp, _fp, _fp, _ip, _ip, _fp]
     L.pnpula_calibrate.argtypes = [vp, _fp, _fp]
     L.pnpula_profile.argtypes = [vp, C.c_int32]
     L.pnpula_profile_read.argtypes = [vp, C.c_int32, _dp, _i64p]
@@ -237,6 +239,22 @@ class Context:
             out.append(lay[off:off + n].reshape(int(c), self.ny, self.nx))
             off += n
         return G, out
+
+    def denoise_stages(self, x):
+        """The fused denoiser path on x: (G, [(layer, activation (F, ny, nx))]) with one
+        entry per launch that wrote an activation to memory."""
+        x = _f32(x)
+        K = len(self.cfg.channels) - 1
+        F = int(self.cfg.channels[1]) if K > 1 else 1
+        G = np.empty((self.ny, self.nx), np.float32)
+        n = C.c_int32()
+        lay = np.zeros(max(K, 1), np.int32)
+        acts = np.empty(max(K - 1, 1) * F * self.ny * self.nx, np.float32)
+        _check(lib().pnpula_denoise_stages(self.h, _fptr(x), _fptr(G), C.byref(n),
+                                           lay.ctypes.data_as(_ip), _fptr(acts)), self._err)
+        plane = F * self.ny * self.nx
+        return G, [(int(lay[i]), acts[i * plane:(i + 1) * plane].reshape(F, self.ny, self.nx))
+                   for i in range(n.value)]
 
     def calibrate(self, x):
         x = _f32(x)

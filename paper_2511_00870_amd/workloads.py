@@ -202,6 +202,21 @@ class Workload:
     iters: int
     burn_in: int
     welford_window: int = 256
+    # likelihood and splitting variable: 0 Gaussian / 1 Poisson (KL);
+    # z-step 0 exact Gaussian draw / 1 PSGLA; operator eta diag(m) K; second
+    # block z2 ~ x with the indicator of R+ when rho2 > 0
+    likelihood: int = 0
+    z_step: int = 0
+    eta: float = 0.0
+    kappa: float = 0.0
+    rho2: float = 0.0
+    kappa2: float = 0.0
+    # prior: 0 residual CNN (PnP-ULA), 1 TV (PSGLA), 2 DDFB (PnP-ULA)
+    prior: int = 0
+    beta: float = 0.0
+    ddfb_weights: Optional[np.ndarray] = None   # (K, F, 3, 3) float32
+    ddfb_gamma: Optional[np.ndarray] = None     # (K,)
+    ddfb_thresh: float = 0.0
 
     @property
     def n_layers(self) -> int:
@@ -269,6 +284,134 @@ def config(n: int, **over) -> Workload:
     base.update(over)
     base.setdefault("seed", 1000 * n)
     return make_workload(**base)
+
+
+# --------------------------------------------------------------------------
+# the paper's other applications and priors (Sec. III-A3, III-B)
+# --------------------------------------------------------------------------
+def motion_blur_kernel(L: int, seed: int, length: Optional[float] = None,
+                       substeps: int = 8) -> np.ndarray:
+    """Seeded L x L motion-blur kernel (the paper's kernels are not
+    available): a random camera trajectory -- a walk whose direction drifts
+    with inertia and random turns -- of total length `length` pixels
+    (default 0.6 L), centred, rasterised with bilinear splatting and
+    normalised to unit sum.  Non-negative, non-separable, sparse."""
+    if L % 2 != 1:
+        raise ValueError("blur size must be odd")
+    rng = np.random.default_rng(seed)
+    length = 0.6 * L if length is None else length
+    n = max(int(length * substeps), 2)
+    ang = rng.uniform(0, 2 * math.pi)
+    turn = 0.0
+    pts = np.zeros((n, 2))
+    for i in range(1, n):
+        turn = 0.9 * turn + rng.normal(0, 0.35 / substeps)
+        ang += turn
+        pts[i] = pts[i - 1] + np.array([math.sin(ang), math.cos(ang)]) / substeps
+    pts -= (pts.max(0) + pts.min(0)) / 2           # centre the trajectory
+    r = L // 2
+    span = np.abs(pts).max()
+    if span > r - 1:
+        pts *= (r - 1) / span
+    k = np.zeros((L, L))
+    for (py, px) in pts + r:
+        iy, ix = int(math.floor(py)), int(math.floor(px))
+        fy, fx = py - iy, px - ix
+        for dy, wy in ((0, 1 - fy), (1, fy)):
+            for dx, wx in ((0, 1 - fx), (1, fx)):
+                k[iy + dy, ix + dx] += wy * wx
+    return k / k.sum()
+
+
+def poisson_workload(name: str, ny: int, nx: int, kernel: np.ndarray, block: int, halo: int,
+                     n_layers: int, features: int, precision: int, iters: int, burn_in: int,
+                     seed: int, eta: float = 250.0, eps_std: float = 0.05,
+                     rho1: float = 10.0, rho2: float = 1e-3, bias_scale: float = 0.0,
+                     mask_p: Optional[float] = None) -> Workload:
+    """Deconvolution with Poisson noise (Sec. III-A3): y ~ P(eta K xbar), the
+    likelihood KL(y || eta K x) on z1 and the indicator of R+ on z2 ~ x, both
+    through AXDA and sampled by PSGLA (Sec. III-B1 (ii)): alpha = 1,
+    eps = 0.05 (standard deviation), rho1 = 10, rho2 = 1e-3, kappa_i = 0.99
+    rho_i, lambda = 0.99 / (4 ||eta H||^2/rho1 + 4/rho2 + 2 alpha L_eps/eps^2),
+    gamma = 0.99 / (alpha L_eps/eps^2 + ||eta H||^2/rho1 + 1/rho2 + 1/lambda) / 3,
+    with ||H|| <= 1 and L_eps <= 0.9^K."""
+    xbar = synthetic_image(ny, nx, seed)
+    mask = bernoulli_mask(ny, nx, mask_p, seed + 2) if mask_p is not None else None
+    from scipy.signal import fftconvolve
+    rng = np.random.default_rng(seed + 1)
+    hx = np.maximum(fftconvolve(xbar, kernel, mode="same"), 0.0)
+    y = rng.poisson(eta * hx).astype(np.float64)
+    if mask is not None:
+        y = y * mask
+    ch, ws, bs = denoiser_weights(n_layers, features, 7, 0.9, bias_scale)
+    alpha, l_eps = 1.0, 0.9 ** n_layers
+    eps_var = eps_std ** 2
+    nh2 = eta ** 2
+    lam = 0.99 / (4 * nh2 / rho1 + 4 / rho2 + 2 * alpha * l_eps / eps_var)
+    gamma = 0.99 / (alpha * l_eps / eps_var + nh2 / rho1 + 1 / rho2 + 1 / lam) / 3
+    return Workload(name=name, ny=ny, nx=nx, xbar=xbar, y=y, kernel=np.asarray(kernel, np.float64),
+                    mask=mask, sigma=1.0, eps=eps_var, alpha=alpha, delta=gamma, rho=rho1,
+                    inv_lambda=1.0 / lam, block_y=block, block_x=block, halo=halo, channels=ch,
+                    weights=ws, biases=bs, precision=precision,
+                    layer_fmt=layer_formats(len(ws), precision),
+                    seed=seed + 3, iters=iters, burn_in=burn_in, likelihood=1, z_step=1,
+                    eta=eta, kappa=0.99 * rho1, rho2=rho2, kappa2=0.99 * rho2)
+
+
+def tv_workload(name: str, ny: int, nx: int, kernel: np.ndarray, sigma: float, block: int,
+                halo: int, iters: int, burn_in: int, seed: int, beta: float = 40.0,
+                rho: float = 1e-5, mask_p: Optional[float] = None) -> Workload:
+    """Isotropic TV prior with Gaussian noise (Sec. III-B2 (i)): p = indicator
+    of R+, f2 = beta ||.||_{2,1} on z ~ D x through AXDA, x and z sampled by
+    PSGLA with rho = 1e-5, beta = 40, gamma = 0.99 (||H||^2/sigma^2 +
+    ||D||^2/rho)^-1, kappa = 0.99 rho ||D||^-2, with ||H|| <= 1 and the bound
+    ||D||^2 <= 8 of the 2-D forward differences."""
+    xbar = synthetic_image(ny, nx, seed)
+    mask = bernoulli_mask(ny, nx, mask_p, seed + 2) if mask_p is not None else None
+    y = observe(xbar, kernel, sigma, mask, seed + 1)
+    d2 = 8.0
+    gamma = 0.99 / (1.0 / sigma ** 2 + d2 / rho)
+    return Workload(name=name, ny=ny, nx=nx, xbar=xbar, y=y, kernel=np.asarray(kernel, np.float64),
+                    mask=mask, sigma=sigma, eps=1.0, alpha=0.0, delta=gamma, rho=rho,
+                    inv_lambda=0.0, block_y=block, block_x=block, halo=halo, channels=[1, 1],
+                    weights=[np.zeros((1, 1, 3, 3), np.float32)], biases=[np.zeros(1, np.float32)],
+                    precision=FMT_FP32, layer_fmt=[FMT_FP32], seed=seed + 3, iters=iters,
+                    burn_in=burn_in, kappa=0.99 * rho / d2, prior=1, beta=beta)
+
+
+def ddfb_params(n_layers: int = 4, features: int = 64, seed: int = 11, thresh: float = 0.05,
+                gamma_frac: float = 1.8):
+    """Random DDFB parameters (trained weights are not available): K
+    weights W_k mapping 1 -> F channels with 3x3 kernels, He-normal then
+    rescaled to operator norm 1 (maximum over a frequency grid of the
+    per-frequency norm of the F x 1 symbol), step sizes gamma_k = gamma_frac
+    / ||W_k||^2 inside (0, 2/||W_k||^2) (Example 3), hard-tanh level thresh."""
+    rng = np.random.default_rng(seed)
+    ws = []
+    for _ in range(n_layers):
+        w = rng.standard_normal((features, 1, 3, 3)) * math.sqrt(2.0 / 9.0)
+        w /= conv_spectral_norm(w)
+        ws.append(w[:, 0].astype(np.float32))
+    gam = np.full(n_layers, gamma_frac, np.float64)
+    return np.stack(ws), gam, float(thresh)
+
+
+def ddfb_workload(name: str, ny: int, nx: int, L: int, sigma_k: float, sigma: float,
+                  block: int, halo: int, iters: int, burn_in: int, seed: int,
+                  n_layers: int = 4, features: int = 64, eps_std: Optional[float] = None,
+                  mask_p: Optional[float] = None, split: bool = True) -> Workload:
+    """PnP-ULA with the DDFB denoiser (Sec. II-B1 Example 3; Sec. III-B1):
+    Gaussian blur (+ optional mask), eps = sigma^2 (variance convention),
+    delta = 0.9 / L with L_eps <= 1 (D is firmly nonexpansive in the paper's
+    setting; 1 bounds the Lipschitz constant of Id - D used here)."""
+    wl = make_workload(name, ny, nx, L=L, sigma_k=sigma_k, sigma=sigma, block=block, halo=halo,
+                       n_layers=1, features=1, precision=FMT_FP32, iters=iters, burn_in=burn_in,
+                       seed=seed, mask_p=mask_p, split=split)
+    w, g, th = ddfb_params(n_layers, features, 11, 0.05 if eps_std is None else eps_std)
+    wl.prior = 2
+    wl.ddfb_weights, wl.ddfb_gamma, wl.ddfb_thresh = w, g, th
+    wl.delta = step_size(wl.sigma, wl.eps, wl.rho, 1, l_eps=1.0)
+    return wl
 
 
 # --------------------------------------------------------------------------

@@ -580,3 +580,56 @@ def test_serving_budget_admission_and_rejection():
     with pytest.raises(P.PnpulaError) as e:
         srv.result(ic)
     assert e.value.code == P.PNPULA_ENOMEM
+
+
+def test_serving_bf16_alone_equals_mix():
+    """The configured 8-layer 64-channel bf16 network serving three jobs of
+    sides 256-512 at once (the layer-pair and fused first / last kernels then
+    run over several jobs' tiles in one launch): each job's statistics are
+    bitwise those of the same job run alone."""
+    ch, ws, bs = W.denoiser_weights(8, 64, seed=7, bias_scale=0.05)
+    specs = [(256, 256, 5, False, 0.02, 1100, 12), (384, 320, 7, True, 0.01, 1200, 9),
+             (512, 512, 9, False, 0.03, 1300, 15)]
+    jobs = []
+    for ny, nx, L, masked, sigma, seed, iters in specs:
+        wl = W.make_workload(f"b{seed}", ny, nx, L=L, sigma_k=L / 4.5, sigma=sigma, block=256,
+                             halo=8, n_layers=8, features=64, precision=P.PNPULA_BF16,
+                             iters=iters, burn_in=iters // 3, seed=seed,
+                             mask_p=0.5 if masked else None)
+        wl.channels, wl.weights, wl.biases = ch, ws, bs
+        jobs.append(wl)
+    say("case serving bf16 8x64 alone vs mix")
+    srv = P.Server(ch, ws, bs, precision=P.PNPULA_BF16, max_slots=3)
+    ids = [srv.submit(P.Config.from_workload(wl), wl.iters) for wl in jobs]
+    while srv.tick() > 0:
+        pass
+    for wl, i in zip(jobs, ids):
+        m, v, n = srv.result(i)
+        ctx = P.Context(P.Config.from_workload(wl))
+        ctx.step(wl.iters)
+        ma, va, na = ctx.stats()
+        say(f"  job {wl.ny}x{wl.nx}: n={n}, max |mean diff| {np.abs(m - ma).max():.1e}")
+        assert n == na == wl.iters - wl.burn_in
+        assert np.array_equal(m, ma) and np.array_equal(v, va)
+
+
+def test_served_job_tracks_oracle():
+    """A job served beside two others follows the FP64 oracle chain with the
+    same noise: final state through the statistics, as the free-running
+    single-chain test (mean 1e-3, variance 2e-2 relative)."""
+    ch, ws, bs = _small_net()
+    target = _job(48, 5, True, 0.02, 500, 120)
+    others = [_job(64, 7, False, 0.01, 600, 80), _job(40, 9, True, 0.03, 700, 150)]
+    say("case served job vs oracle")
+    srv = P.Server(ch, ws, bs, precision=P.PNPULA_FP32, max_slots=3)
+    ids = [srv.submit(P.Config.from_workload(wl), wl.iters) for wl in [others[0], target, others[1]]]
+    while srv.tick() > 0:
+        pass
+    m, v, n = srv.result(ids[1])
+    oc = O.Chain.from_workload(target, block=0)
+    oc.step(target.iters)
+    mo, m2o, no = oc.stats()
+    vo = m2o / (no - 1)
+    say(f"  mean rel {rel(m, mo):.2e}; var rel {rel(v, vo):.2e}")
+    assert n == no == target.iters - target.burn_in
+    assert rel(m, mo) <= 1e-3 and rel(v, vo) <= 2e-2

@@ -521,3 +521,22 @@ def test_denoise_region_equals_full_denoiser_bitwise():
         assert np.array_equal(O.denoise_region(net, x, y0, x0, h, w), full[y0:y0 + h, x0:x0 + w])
     with pytest.raises(ValueError):
         O.denoise_region(net, x, 30, 0, 4, 4)
+
+
+@pytest.mark.parametrize("quantised", [False, True])
+def test_layers_from_continues_the_network_bitwise(quantised):
+    """Running layers k0..K-1 from layer k0's input (used to check each fused
+    GPU launch from the GPU's own input activation) equals the tail of the
+    whole network's layer outputs, bit for bit."""
+    ch, ws, bs = W.denoiser_weights(5, 8, seed=9, bias_scale=0.05)
+    fmt = [1, 2, 2, 2, 1] if quantised else None
+    sc = [1.0, 2.0 ** -6, 2.0 ** -7, 2.0 ** -7, 1.0] if quantised else None
+    net = O.Net(ch, ws, bs, fmt, sc)
+    x = np.random.default_rng(8).random((17, 22))
+    acts, _ = O.denoiser_layers(net, x)
+    assert all(np.array_equal(a, b) for a, b in zip(O.layers_from(net, x, 0, 5), acts))
+    for k0 in (1, 3):
+        tail = O.layers_from(net, acts[k0 - 1], k0, 5)
+        assert all(np.array_equal(a, b) for a, b in zip(tail, acts[k0:]))
+    with pytest.raises(ValueError):
+        O.layers_from(net, x, 3, 2)
