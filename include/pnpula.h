@@ -72,10 +72,23 @@ typedef enum {
                              last layer bf16; FP32 accumulation */
 } pnpula_precision;
 
+/* data terms (Sec. III-A) */
+typedef enum { PNPULA_LIK_GAUSSIAN = 0, PNPULA_LIK_POISSON = 1 } pnpula_likelihood;
+
+/* priors (Sec. II-B1, III-B): the residual CNN D = Id - G (Example 2); the
+ * TV prior through AXDA with the x-chain kept in R+ (Sec. III-B2): the
+ * x-step's prior term is (1/rho) D^T (D x - z), z = (zh, zv) held as state
+ * and moved by the PSGLA step with the block soft threshold, and the
+ * x-update ends with max(., 0) (the data term is not split; kappa, rho and
+ * beta parameterise z); the DDFB denoiser (Example 3, Eqs. (ddfb_operator),
+ * (dfb_operator:T)) with G = x - D(x). */
+typedef enum { PNPULA_PRIOR_CNN = 0, PNPULA_PRIOR_TV = 1, PNPULA_PRIOR_DDFB = 2 } pnpula_prior;
+
 typedef struct {
   int32_t ny, nx;                 /* image size (pixels) */
   const float *y;                 /* ny*nx observation, zero where mask == 0 */
-  int32_t ksize;                  /* odd blur size L, 1 <= L <= 17 */
+  int32_t ksize;                  /* odd blur size L, 1 <= L <= 129 (above 17: the
+                                     large-blur path, Sec. III-A2 motion blurs) */
   const float *kernel;            /* L*L blur, row-major; applied as a same-size
                                      linear convolution with zero boundary */
   const uint8_t *mask;            /* ny*nx of {0,1} applied after the blur; NULL:
@@ -89,10 +102,12 @@ typedef struct {
   double inv_lambda;              /* 1/lambda of the [0,1] projection term (>= 0) */
   int32_t block_y, block_x;       /* block size (>= 1); blocks tile the image,
                                      the last row/column of blocks may be smaller */
-  int32_t halo;                   /* ghost-region width, >= max(2 r, n_layers) with
-                                     r = ksize/2, and < min(block_y, block_x) unless
-                                     a single block covers the image */
-  int32_t n_layers;               /* denoiser depth K >= 1 */
+  int32_t halo;                   /* ghost-region width, >= max(2 r, prior radius)
+                                     with r = ksize/2 (prior radius: n_layers for the
+                                     CNN, 1 for TV, 2 ddfb_layers for DDFB), and
+                                     < min(block_y, block_x) unless a single block
+                                     covers the image */
+  int32_t n_layers;               /* denoiser depth K >= 1 (CNN prior only) */
   const int32_t *channels;        /* K+1 entries, channels[0] = channels[K] = 1,
                                      inner entries equal F in {16, 32, 64}
                                      (FP32) or {32, 64} (BF16) or 64 (FP8) */
@@ -110,6 +125,32 @@ typedef struct {
                                      (1..65536; 0: 256) */
   const float *x0;                /* ny*nx initial state; NULL: zeros */
   void *stream;                   /* hipStream_t to run on; NULL: a new stream */
+  /* ---- the paper's other data terms and priors (all zero: the chain above).
+   * PSGLA z-steps (Eq. (sgs_pnp_ula_psgla:psgla), Algorithm 1): z1 ~ eta m K x
+   * carries the data term f, optionally z2 ~ x carries the indicator of R+;
+   * both are chain state (z^(0) = 0) and move after each x-update by
+   *   z <- prox_{kappa f}(z - (kappa/rho)(z - A x) + sqrt(2 kappa) zeta);
+   * the x-step's data gradient is eta K^T m (eta m K x - z1)/rho
+   * + (x - z2)/rho2. ---- */
+  int32_t likelihood;             /* PNPULA_LIK_GAUSSIAN: f = (y - .)^2/(2 sigma^2);
+                                     PNPULA_LIK_POISSON: y holds counts and
+                                     f = KL(y || .) (Sec. III-A3); needs z_step 1 */
+  int32_t z_step;                 /* 0: exact conditional draw of z (rho > 0) or no
+                                     z (rho = 0); 1: PSGLA, z held as state */
+  double eta;                     /* operator scale of z1 (Poisson: photon level;
+                                     0 is taken as 1) */
+  double kappa;                   /* PSGLA step of z1 (TV: of z), 0 < kappa <= rho */
+  double rho2, kappa2;            /* second block (rho2 = 0: none) and its step */
+  int32_t prior;                  /* pnpula_prior */
+  double beta;                    /* TV weight: f = beta ||.||_{2,1} on z ~ D x */
+  int32_t ddfb_layers;            /* DDFB iterations K (1..8) */
+  int32_t ddfb_features;          /* DDFB feature maps F (1..256) */
+  const float *ddfb_weights;      /* K blocks of [F][3][3]: W_k maps 1 -> F channels
+                                     (cross-correlation, zero padding) */
+  const float *ddfb_gamma;        /* K step sizes gamma_k */
+  double ddfb_thresh;             /* hard-tanh level of the dual variables (>= 0) */
+  int32_t inputs_on_device;       /* 1: y, kernel, mask and x0 are device pointers
+                                     (read once at create); 0: host pointers */
 } pnpula_config;
 
 /* Validate cfg, allocate device memory, upload inputs and repack weights.
@@ -137,6 +178,19 @@ pnpula_status pnpula_set_state(pnpula_ctx *ctx, const float *x, int64_t t);
 /* Replace x, t and the FP64 statistics (mean, m2 of n samples). */
 pnpula_status pnpula_restore(pnpula_ctx *ctx, const float *x, int64_t t, const double *mean,
                              const double *m2, int64_t n_samples);
+
+/* Splitting variables held as chain state (PSGLA z-steps, Eq.
+ * (sgs_pnp_ula_psgla:psgla); TV: z = (zh, zv) ~ D x, Sec. III-B2): z1 and z2
+ * (ny*nx each; either may be NULL) of the current iterate.  PNPULA_ESTATE
+ * when the chain holds no z (z_step 0 and prior not TV). */
+pnpula_status pnpula_get_z(pnpula_ctx *ctx, float *z1, float *z2);
+/* Replace z1 and z2 (either may be NULL: kept). */
+pnpula_status pnpula_set_z(pnpula_ctx *ctx, const float *z1, const float *z2);
+
+/* pnpula_stats with DEVICE outputs: mean and var (ny*nx floats each, either
+ * may be NULL) are device pointers written on the context's stream, which
+ * is synchronised before return. */
+pnpula_status pnpula_stats_device(pnpula_ctx *ctx, float *mean, float *var, int64_t *n_samples);
 
 /* Apply the context's denoiser to an ny*nx image: G = x - D_eps(x) (FP32
  * output).  layers (optional) receives every layer's output, dequantised

@@ -157,6 +157,12 @@ double oracle_quantize(double v, int32_t fmt) {
   return q;
 }
 
+/* out[i] = quantize(v[i] / scale) * scale for n values (the array form of
+ * the rounding above, for checks over whole activation maps) */
+void oracle_quantize_n(const double *v, int64_t n, int32_t fmt, double scale, double *out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = oracle_quantize(v[i] / scale, fmt) * scale;
+}
+
 /* smallest power of two s with amax / s <= 448 (1 when amax == 0) */
 static double pow2_scale(double amax) {
   if (!(amax > 0.0)) return 1.0;

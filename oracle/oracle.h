@@ -109,6 +109,7 @@ void oracle_conv3x3(const double *in, int32_t cin, int32_t ny, int32_t nx,
                     const double *w, const double *b, int32_t cout, int32_t relu,
                     double *out);
 double oracle_quantize(double v, int32_t fmt);
+void oracle_quantize_n(const double *v, int64_t n, int32_t fmt, double scale, double *out);
 void oracle_weight_scales(const oracle_net *net, int32_t layer, double *scales);
 int  oracle_denoiser(const oracle_net *net, const double *x, int32_t ny, int32_t nx,
                      int32_t block_y, int32_t block_x, int32_t halo, double *G);

@@ -89,6 +89,7 @@ def _declare(L):
                                  C.c_int32, _dp]
     L.oracle_quantize.restype = C.c_double
     L.oracle_quantize.argtypes = [C.c_double, C.c_int32]
+    L.oracle_quantize_n.argtypes = [_dp, C.c_int64, C.c_int32, C.c_double, _dp]
     L.oracle_weight_scales.argtypes = [C.POINTER(OracleNet), C.c_int32, _dp]
     L.oracle_denoiser.argtypes = [C.POINTER(OracleNet), _dp, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int32, _dp]
@@ -182,6 +183,14 @@ def conv3x3(inp, w, b, relu: bool) -> np.ndarray:
 def quantize(v, fmt: int):
     f = lib().oracle_quantize
     return np.vectorize(lambda a: f(float(a), fmt), otypes=[np.float64])(np.asarray(v))
+
+
+def quantize_scaled(v, fmt: int, scale: float = 1.0):
+    """quantize(v / scale) * scale over a whole array (one C call)"""
+    v = _f64(v)
+    out = np.empty_like(v)
+    lib().oracle_quantize_n(_d(v), v.size, fmt, float(scale), _d(out))
+    return out
 
 
 class Net:

@@ -39,12 +39,14 @@ pnpula_status pnpula_create(const pnpula_config *cfg, pnpula_ctx **out) {
   pnpula_ctx *c = new (std::nothrow) pnpula_ctx();
   if (!c) return PNPULA_ENOMEM;
   Status s = Engine::validate_job(cfg, cfg->n_layers, {});
-  if (s.good() && (cfg->n_layers < 1 || !cfg->channels))
+  const bool cnn = cfg->prior == PNPULA_PRIOR_CNN;
+  if (s.good() && cnn && (cfg->n_layers < 1 || !cfg->channels))
     s = Status::fail(PNPULA_EINVAL, "denoiser missing");
   if (s.good()) s = c->eng.init(cfg->stream);
   if (s.good())
-    s = c->eng.set_net(cfg->n_layers, cfg->channels, cfg->weights, cfg->biases, cfg->precision,
-                       cfg->act_scales);
+    s = cnn ? c->eng.set_net(cfg->n_layers, cfg->channels, cfg->weights, cfg->biases,
+                             cfg->precision, cfg->act_scales)
+            : c->eng.set_prior(cfg);
   if (s.good()) s = c->eng.make_job(cfg, &c->job);
   if (s.good()) {
     c->eng.resident.push_back(c->job);
@@ -133,6 +135,21 @@ pnpula_status pnpula_restore(pnpula_ctx *c, const float *x, int64_t t, const dou
   return report(c, s);
 }
 
+pnpula_status pnpula_get_z(pnpula_ctx *c, float *z1, float *z2) {
+  GUARD(c);
+  return report(c, c->eng.get_z(c->job, z1, z2));
+}
+
+pnpula_status pnpula_set_z(pnpula_ctx *c, const float *z1, const float *z2) {
+  GUARD(c);
+  return report(c, c->eng.set_z(c->job, z1, z2));
+}
+
+pnpula_status pnpula_stats_device(pnpula_ctx *c, float *mean, float *var, int64_t *n_samples) {
+  GUARD(c);
+  return report(c, c->eng.stats_device(c->job, mean, var, n_samples));
+}
+
 pnpula_status pnpula_denoise(pnpula_ctx *c, const float *x, float *G, float *layers) {
   GUARD(c);
   if (!x) return report(c, Status::fail(PNPULA_EINVAL, "x is required"));
@@ -211,8 +228,8 @@ pnpula_status pnpula_footprint(const pnpula_config *cfg, size_t *bytes) {
     return s.code;
   }
   pnp::NetPlan n;
-  n.K = cfg->n_layers;
-  n.F = (cfg->n_layers > 1 && cfg->channels) ? cfg->channels[1] : 1;
+  n.K = cfg->prior == PNPULA_PRIOR_CNN ? cfg->n_layers : 0;
+  n.F = (n.K > 1 && cfg->channels) ? cfg->channels[1] : 1;
   // activation buffers as the engine assigns them (see Engine::set_net)
   if (n.K > 1) {
     if (cfg->precision == PNPULA_FP8_E4M3) {

@@ -17,6 +17,9 @@ constexpr int kConvTileW = 32;     // convolution tiles are TH x 32 pixels
 constexpr int kPairTileH = 14;     // e4m3 pair kernel: output tiles of 14 x 30
 constexpr int kPairTileW = 30;
 constexpr int kPairWsTileH = 9;   // split-layer pair kernel: output tiles of 9 x 30
+constexpr int kDdTile = 30;        // DDFB stage kernel: output tiles of 30 x 30
+constexpr int kMaxDdfbLayers = 8;  // DDFB iterations K
+constexpr int kMaxRBig = 64;       // largest blur half-width (L <= 129)
 
 // One chain resident on the device.  All images live in padded row-major
 // buffers whose zero border is never written, so stencils read it as the
@@ -63,6 +66,40 @@ struct JobDesc {
   float zsd;               // sqrt(rho sigma^2 / (rho + sigma^2))
   float pad1;
   uint32_t key0, key1, chain, pad2;
+  // ---- splitting variables held as chain state, and the other priors ----
+  // zmode 1: PSGLA z-steps (Eq. (sgs_pnp_ula_psgla:psgla)): z1 ~ eta m K x with
+  //   the data term (Gaussian, or Poisson KL(y || .)) as f, and optionally z2 ~ x
+  //   with the indicator of R+; the x-step's data gradient is
+  //   eta K^T m (eta m K x - z1)/rho + (x - z2)/rho2.
+  // zmode 2: TV prior through AXDA (Sec. III-B2): z = (zh, zv) ~ D x with
+  //   beta ||.||_{2,1}; the x-step adds (1/rho) D^T (D x - z) (held in G) and
+  //   ends with the projection onto R+.
+  int32_t zmode;
+  int32_t poisson;         // z1's data term is KL(y || .) (else Gaussian)
+  int32_t has_z2;          // second block z2
+  int32_t xpos;            // the x-update ends with max(., 0)
+  float *z1, *z2;          // padded like x (zero border); TV: zh, zv
+  float eta;               // operator scale of the PSGLA residual
+  float za1, zs1;          // z1 (TV: z) step: kappa/rho and sqrt(2 kappa)
+  float za2, zs2;          // z2 step: kappa2/rho2 and sqrt(2 kappa2)
+  float zkappa;            // prox parameter: kappa (TV: kappa beta)
+  float zsig2;             // Gaussian data term of z1: sigma^2
+  float inv_rho2;          // 1/rho2
+  float inv_rho;           // TV: 1/rho of the coupling term
+  float pad3;
+  // large blur (half-width above kMaxR): the residual m (K x - v) on the whole
+  // image, padded with a zero border of width r (row pitch rpitch floats)
+  float *res;
+  int64_t rpitch;
+  float *gdat;             // large blur: the data gradient K^T res / s2 (compact)
+  const float *kbig[2];    // large blur: [0] the kernel flipped, [1] as is; rows of
+                           // kpitch floats (a multiple of 8, zero padded)
+  int32_t kpitch;
+  int32_t big;             // blur half-width above kMaxR
+  // DDFB prior: maps b_1 .. b_{K-1} of the unrolled dual forward-backward
+  // iterations, padded like x (zero border), dstride floats apart
+  float *dmaps;
+  int64_t dstride;
 };
 
 // A rectangle of one job's image: rows [y0, y0+h), cols [x0, x0+w).
@@ -134,6 +171,25 @@ __device__ __forceinline__ void gauss_pair(uint32_t key0, uint32_t key1, uint32_
   const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
   xi = rad * __builtin_amdgcn_cosf(u2);
   zeta = rad * __builtin_amdgcn_sinf(u2);
+}
+
+// Three standard normals of pixel p at counter t (the z-steps): the cosine
+// and sine branches of the pair above from words (w0, w1), and the cosine
+// branch of a second Box-Muller pair from (w2, w3).
+__device__ __forceinline__ void gauss_triple(uint32_t key0, uint32_t key1, uint32_t chain,
+                                             int64_t p, int64_t t, float &g0, float &g1,
+                                             float &g2) {
+  uint4 c = make_uint4((uint32_t)p, (uint32_t)t, chain, (uint32_t)((uint64_t)p >> 32));
+  uint4 w = philox4x32_10(c, key0, key1);
+  const float u1 = (float)((w.x >> 8) + 1u) * 5.9604644775390625e-8f;
+  const float u2 = (float)(w.y >> 8) * 5.9604644775390625e-8f;
+  const float u3 = (float)((w.z >> 8) + 1u) * 5.9604644775390625e-8f;
+  const float u4 = (float)(w.w >> 8) * 5.9604644775390625e-8f;
+  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+  const float rad2 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u3));
+  g0 = rad * __builtin_amdgcn_cosf(u2);
+  g1 = rad * __builtin_amdgcn_sinf(u2);
+  g2 = rad2 * __builtin_amdgcn_cosf(u4);
 }
 
 // --------------------------------------------------------------------

@@ -47,6 +47,12 @@ struct NetPlan {
   bool last_fused = false;   // the last layer runs inside the last middle layer's kernel
   bool last_pair8 = false;   // e4m3: the last layer runs inside the last pair's kernel
   std::vector<void *> allocs;
+  // prior of the chain: PNPULA_PRIOR_CNN (the layers above), _TV or _DDFB
+  int prior = PNPULA_PRIOR_CNN;
+  int ddfb_K = 0, ddfb_F = 0;
+  float ddfb_thresh = 0.f;
+  std::vector<float> ddfb_gamma;
+  float *ddfb_w = nullptr;   // device: K x F x 9
 };
 
 struct Job {
@@ -61,6 +67,7 @@ struct Job {
   std::vector<TileRef> conv_tiles, upd_tiles;   // job field = 0 (set at planning)
   std::vector<TileRef> pair_tiles;              // e4m3 pair kernel: whole-image tiling
   std::vector<TileRef> pair_ws_tiles;           // split-layer pair kernel (bf16)
+  std::vector<TileRef> ddfb_tiles;              // DDFB stages: whole-image tiling
 };
 
 struct ProfileRec {
@@ -74,7 +81,11 @@ class Engine {
   Status init(void *stream);
   Status set_net(int K, const int32_t *channels, const float *w, const float *b, int precision,
                  const float *act_scales);
+  // TV or DDFB prior in place of the CNN (cfg's prior fields)
+  Status set_prior(const pnpula_config *cfg);
   static Status validate_job(const pnpula_config *cfg, int K, const std::vector<int> &ch);
+  // receptive-field radius of the prior term for cfg
+  static int prior_radius(const pnpula_config *cfg);
   static size_t job_footprint(const pnpula_config *cfg, const NetPlan &net);
   Status make_job(const pnpula_config *cfg, Job **out);
   void free_job(Job *j);
@@ -95,6 +106,9 @@ class Engine {
   Status denoise_stages(Job *j, const float *x, float *G, int32_t *n_stages,
                         int32_t *stage_layer, float *stage_acts);
   Status read_act(Job *j, int k, int slot, float *dst);
+  Status get_z(Job *j, float *z1, float *z2);
+  Status set_z(Job *j, const float *z1, const float *z2);
+  Status stats_device(Job *j, float *mean, float *var, int64_t *n);
 
   void profile_enable(bool on);
   Status profile_read(int cls, double *ms, int64_t *launches);
@@ -123,16 +137,21 @@ class Engine {
   using StageFn = std::function<Status(int, int)>;
   Status run_fused_denoiser(int64_t tick, bool prof, const StageFn *on_stage = nullptr);
   Status launch_layer(int k, int64_t tick, bool prof, int in_slot = -1, int out_slot = -1);
+  Status run_prior_other(int64_t tick);
   JobDesc *d_jobs = nullptr;
-  TileRef *d_conv = nullptr, *d_upd = nullptr, *d_pair = nullptr, *d_pair_ws = nullptr;
-  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0, cap_pair = 0, cap_pair_ws = 0;
-  int n_conv = 0, n_upd = 0, n_pair = 0, n_pair_ws = 0, max_r = 0;
+  TileRef *d_conv = nullptr, *d_upd = nullptr, *d_pair = nullptr, *d_pair_ws = nullptr,
+          *d_ddfb = nullptr;
+  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0, cap_pair = 0, cap_pair_ws = 0, cap_ddfb = 0;
+  int n_conv = 0, n_upd = 0, n_pair = 0, n_pair_ws = 0, n_ddfb = 0, max_r = 0;
   bool uniform_r = true;      // every resident job has blur half-width max_r
+  int zmode = 0;              // JobDesc::zmode of the resident jobs (all equal)
+  bool big = false;           // the resident jobs take the large-blur path
+  int max_kpitch = 8;
   int conv_th = 16;
   bool profiling = false;
   std::vector<ProfileRec> prof_pending;
   std::vector<hipEvent_t> prof_free;
-  static constexpr int kProfClasses = 7;
+  static constexpr int kProfClasses = 10;
   double prof_ms[kProfClasses] = {};
   int64_t prof_n[kProfClasses] = {};
   void prof_begin(int cls, ProfileRec *r);

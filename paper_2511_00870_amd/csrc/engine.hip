@@ -84,6 +84,7 @@ Engine::~Engine() {
   hipFree(d_upd);
   hipFree(d_pair);
   hipFree(d_pair_ws);
+  hipFree(d_ddfb);
   for (auto &r : prof_pending) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
@@ -328,16 +329,66 @@ Status Engine::set_net(int K, const int32_t *ch, const float *w, const float *b,
   return Status::ok();
 }
 
+Status Engine::set_prior(const pnpula_config *c) {
+  net = NetPlan();
+  net.prior = c->prior;
+  if (c->prior == PNPULA_PRIOR_DDFB) {
+    const int K = c->ddfb_layers, F = c->ddfb_features;
+    const size_t nw = (size_t)K * F * 9;
+    for (size_t i = 0; i < nw; ++i)
+      if (!std::isfinite(c->ddfb_weights[i])) return Status::fail(PNPULA_EINVAL, "non-finite weight");
+    for (int k = 0; k < K; ++k)
+      if (!std::isfinite(c->ddfb_gamma[k])) return Status::fail(PNPULA_EINVAL, "non-finite step size");
+    net.ddfb_K = K;
+    net.ddfb_F = F;
+    net.ddfb_thresh = (float)c->ddfb_thresh;
+    net.ddfb_gamma.assign(c->ddfb_gamma, c->ddfb_gamma + K);
+    HIPOK(hipMalloc(&net.ddfb_w, nw * sizeof(float)));
+    net.allocs.push_back(net.ddfb_w);
+    HIPOK(hipMemcpy(net.ddfb_w, c->ddfb_weights, nw * sizeof(float), hipMemcpyHostToDevice));
+  }
+  plan_dirty = true;
+  return Status::ok();
+}
+
 // ---------------------------------------------------------------------
 // jobs
 // ---------------------------------------------------------------------
-Status Engine::validate_job(const pnpula_config *c, int K, const std::vector<int> &) {
+int Engine::prior_radius(const pnpula_config *c) {
+  if (c->prior == PNPULA_PRIOR_TV) return 1;
+  if (c->prior == PNPULA_PRIOR_DDFB) return 2 * c->ddfb_layers;
+  return c->n_layers;
+}
+
+Status Engine::validate_job(const pnpula_config *c, int, const std::vector<int> &) {
   if (!c) return Status::fail(PNPULA_EINVAL, "null config");
   if (c->ny < 1 || c->nx < 1) return Status::fail(PNPULA_EINVAL, "image size must be positive");
   if ((int64_t)c->ny * c->nx > (int64_t)1 << 40) return Status::fail(PNPULA_EINVAL, "image too large");
   if (!c->y) return Status::fail(PNPULA_EINVAL, "y is required");
-  if (c->ksize < 1 || c->ksize % 2 == 0 || c->ksize > 2 * kMaxR + 1 || !c->kernel)
-    return Status::fail(PNPULA_EINVAL, "blur size must be odd and at most 17");
+  if (c->ksize < 1 || c->ksize % 2 == 0 || c->ksize > 2 * kMaxRBig + 1 || !c->kernel)
+    return Status::fail(PNPULA_EINVAL, "blur size must be odd and at most 129");
+  if (c->prior < PNPULA_PRIOR_CNN || c->prior > PNPULA_PRIOR_DDFB)
+    return Status::fail(PNPULA_EINVAL, "unknown prior");
+  if (c->likelihood < PNPULA_LIK_GAUSSIAN || c->likelihood > PNPULA_LIK_POISSON ||
+      c->z_step < 0 || c->z_step > 1)
+    return Status::fail(PNPULA_EINVAL, "unknown likelihood or z-step");
+  if (c->likelihood == PNPULA_LIK_POISSON && c->z_step != 1)
+    return Status::fail(PNPULA_EINVAL, "the Poisson likelihood needs the PSGLA z-step");
+  if (!(c->eta >= 0) || !(c->rho2 >= 0) || !(c->beta >= 0) || !(c->kappa >= 0) ||
+      !(c->kappa2 >= 0) || !std::isfinite(c->eta) || !std::isfinite(c->rho2) ||
+      !std::isfinite(c->beta) || !std::isfinite(c->kappa) || !std::isfinite(c->kappa2))
+    return Status::fail(PNPULA_EINVAL, "eta, kappa, rho2, kappa2, beta must be finite and >= 0");
+  if ((c->z_step == 1 || c->prior == PNPULA_PRIOR_TV) && !(c->rho > 0 && c->kappa > 0))
+    return Status::fail(PNPULA_EINVAL, "PSGLA needs rho > 0 and kappa > 0");
+  if (c->rho2 > 0 && (c->z_step != 1 || !(c->kappa2 > 0)))
+    return Status::fail(PNPULA_EINVAL, "the second z block needs the PSGLA z-step and kappa2 > 0");
+  if (c->prior == PNPULA_PRIOR_TV && (c->z_step != 0 || c->likelihood != PNPULA_LIK_GAUSSIAN))
+    return Status::fail(PNPULA_EINVAL, "the TV prior runs with the unsplit Gaussian likelihood");
+  if (c->prior == PNPULA_PRIOR_DDFB &&
+      (c->ddfb_layers < 1 || c->ddfb_layers > kMaxDdfbLayers || c->ddfb_features < 1 ||
+       c->ddfb_features > 256 || !c->ddfb_weights || !c->ddfb_gamma || !(c->ddfb_thresh >= 0)))
+    return Status::fail(PNPULA_EINVAL,
+                        "DDFB needs 1..8 layers, 1..256 features, weights, step sizes, thresh >= 0");
   if (!(c->sigma > 0) || !(c->eps > 0) || !(c->delta > 0) || !(c->rho >= 0) ||
       !(c->alpha >= 0) || !(c->inv_lambda >= 0) || !std::isfinite(c->sigma) ||
       !std::isfinite(c->eps) || !std::isfinite(c->delta) || !std::isfinite(c->rho) ||
@@ -347,8 +398,8 @@ Status Engine::validate_job(const pnpula_config *c, int K, const std::vector<int
   const int r = c->ksize / 2;
   const bool single = c->block_y >= c->ny && c->block_x >= c->nx;
   if (!single) {
-    if (c->halo < std::max(2 * r, K))
-      return Status::fail(PNPULA_EINVAL, "halo must be >= max(2r, n_layers)");
+    if (c->halo < std::max(2 * r, prior_radius(c)))
+      return Status::fail(PNPULA_EINVAL, "halo must be >= max(2r, prior radius)");
     if (c->halo >= std::min(c->block_y, c->block_x))
       return Status::fail(PNPULA_EINVAL, "halo must be smaller than the blocks");
   }
@@ -373,11 +424,26 @@ static Geometry geometry(int ny, int nx, int r) {
   return g;
 }
 
+// large blur: residual buffer with a zero border of r, and kernel rows
+// padded to a multiple of 8 taps
+static int64_t res_pitch(int nx, int r) { return ((int64_t)nx + 2 * r + kUpdTileW + 63) / 64 * 64; }
+static int64_t res_rows(int ny, int r) { return (int64_t)ny + 2 * r + kUpdTileH; }
+static int kbig_pitch(int L) { return (L + 7) / 8 * 8; }
+
 size_t Engine::job_footprint(const pnpula_config *c, const NetPlan &n) {
-  const Geometry g = geometry(c->ny, c->nx, c->ksize / 2);
+  const int r = c->ksize / 2;
+  const Geometry g = geometry(c->ny, c->nx, r);
   const size_t N = (size_t)c->ny * c->nx;
-  size_t bytes = 3 * (size_t)g.rows * g.pitch * sizeof(float);          // x[2], y
+  const size_t xbytes = (size_t)g.rows * g.pitch * sizeof(float);
+  size_t bytes = 3 * xbytes;                                            // x[2], y
   if (c->mask) bytes += (size_t)g.rows * g.pitch;
+  if (c->z_step == 1) bytes += (c->rho2 > 0 ? 2 : 1) * xbytes;          // z1 (, z2)
+  if (c->prior == PNPULA_PRIOR_TV) bytes += 2 * xbytes;                 // zh, zv
+  if (c->prior == PNPULA_PRIOR_DDFB && c->ddfb_layers > 1)
+    bytes += (size_t)(c->ddfb_layers - 1) * xbytes;                     // b_1 .. b_{K-1}
+  if (r > kMaxR)
+    bytes += (size_t)res_rows(c->ny, r) * res_pitch(c->nx, r) * sizeof(float) + N * sizeof(float) +
+             2 * (size_t)c->ksize * kbig_pitch(c->ksize) * sizeof(float);
   for (int b = 0; b < 4; ++b)
     if (n.buf_fmt[b] >= 0) bytes += (size_t)g.arows * g.apitch * n.F * fmt_bytes(n.buf_fmt[b]);
   bytes += N * (sizeof(float) * 3 + sizeof(double) * 2);                // G, Welford
@@ -441,6 +507,12 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   d.r = r;
   d.has_mask = c->mask != nullptr;
   d.split = c->rho > 0;
+  d.zmode = c->z_step == 1 ? 1 : (c->prior == PNPULA_PRIOR_TV ? 2 : 0);
+  d.poisson = c->likelihood == PNPULA_LIK_POISSON;
+  d.has_z2 = (d.zmode == 1 && c->rho2 > 0) || d.zmode == 2;
+  d.xpos = c->prior == PNPULA_PRIOR_TV;
+  d.big = r > kMaxR;
+  if (d.zmode != 0) d.split = 0;          // z is chain state, not drawn in the update
   d.burn_in = c->burn_in;
   d.wwin = c->welford_window > 0 ? c->welford_window : 256;
   j->block_y = std::min(c->block_y, ny);
@@ -448,6 +520,8 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   j->halo = c->halo;
   j->footprint = job_footprint(c, net);
   const size_t xbytes = (size_t)g.rows * g.pitch * sizeof(float);
+  // inputs_on_device: y, kernel, mask and x0 are device pointers
+  const hipMemcpyKind in_kind = c->inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   Status s;
   if (!(s = dalloc(j, &d.x[0], xbytes)).good()) return fail(s);
   if (!(s = dalloc(j, &d.x[1], xbytes)).good()) return fail(s);
@@ -461,17 +535,30 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   const size_t hpitch = (size_t)nx * sizeof(float), dpitch = (size_t)g.pitch * sizeof(float);
   const size_t origin = (size_t)g.B * g.pitch + g.B;
   if (e == hipSuccess)
-    e = hipMemcpy2DAsync(yb + origin, dpitch, c->y, hpitch, hpitch, ny, hipMemcpyHostToDevice, stream);
+    e = hipMemcpy2DAsync(yb + origin, dpitch, c->y, hpitch, hpitch, ny, in_kind, stream);
   if (e == hipSuccess && c->x0)
-    e = hipMemcpy2DAsync(d.x[0] + origin, dpitch, c->x0, hpitch, hpitch, ny, hipMemcpyHostToDevice,
-                         stream);
+    e = hipMemcpy2DAsync(d.x[0] + origin, dpitch, c->x0, hpitch, hpitch, ny, in_kind, stream);
   if (e == hipSuccess && c->mask) {
     uint8_t *mb = nullptr;
     if (!(s = dalloc(j, &mb, (size_t)g.rows * g.pitch)).good()) return fail(s);
     e = hipMemsetAsync(mb, 0, (size_t)g.rows * g.pitch, stream);
     if (e == hipSuccess)
-      e = hipMemcpy2DAsync(mb + origin, g.pitch, c->mask, nx, nx, ny, hipMemcpyHostToDevice, stream);
+      e = hipMemcpy2DAsync(mb + origin, g.pitch, c->mask, nx, nx, ny, in_kind, stream);
     d.mask = mb;
+  }
+  // splitting variables held as state (z^(0) = 0) and the DDFB maps: padded
+  // like x, zero border never written
+  float **zb[2] = {&d.z1, &d.z2};
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    if (d.zmode == 0 || (i == 1 && !d.has_z2)) continue;
+    if (!(s = dalloc(j, zb[i], xbytes)).good()) return fail(s);
+    e = hipMemsetAsync(*zb[i], 0, xbytes, stream);
+  }
+  if (e == hipSuccess && c->prior == PNPULA_PRIOR_DDFB && c->ddfb_layers > 1) {
+    const size_t mbytes = (size_t)(c->ddfb_layers - 1) * xbytes;
+    if (!(s = dalloc(j, &d.dmaps, mbytes)).good()) return fail(s);
+    e = hipMemsetAsync(d.dmaps, 0, mbytes, stream);
+    d.dstride = (int64_t)g.rows * g.pitch;
   }
   if (e != hipSuccess) return fail(Status::fail(PNPULA_EDEVICE, hipGetErrorString(e)));
   for (int b = 0; b < 4; ++b) {
@@ -501,7 +588,14 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
       hipMemsetAsync(d.m2, 0, N * sizeof(double), stream) != hipSuccess)
     return fail(Status::fail(PNPULA_EDEVICE, "memset"));
   // blur: full kernel, and its rank-1 factors when it is separable
-  std::vector<float> kern(c->kernel, c->kernel + L * L);
+  std::vector<float> kern(L * L);
+  if (c->inputs_on_device) {
+    if (hipMemcpy(kern.data(), c->kernel, (size_t)L * L * sizeof(float), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return fail(Status::fail(PNPULA_EDEVICE, "kernel read from device failed"));
+  } else {
+    std::copy(c->kernel, c->kernel + L * L, kern.begin());
+  }
   std::vector<float> ku(L, 0.f), kv(L, 0.f);
   {
     int pa = 0, pc = 0;
@@ -548,6 +642,34 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   d.kern = kd;
   d.ku = kd + L * L;
   d.kv = kd + 2 * L * L;
+  if (d.big) {
+    // correlation kernels of the whole-image passes: flip(k) for K x, k for
+    // K^T r; residual buffer with a zero border of r; the gradient
+    const int Lp = kbig_pitch(L);
+    std::vector<float> kb((size_t)2 * L * Lp, 0.f);
+    for (int a = 0; a < L; ++a)
+      for (int b = 0; b < L; ++b) {
+        kb[(size_t)a * Lp + b] = kern[(size_t)(L - 1 - a) * L + (L - 1 - b)];
+        kb[(size_t)L * Lp + (size_t)a * Lp + b] = kern[(size_t)a * L + b];
+      }
+    float *kbd = nullptr;
+    if (!(s = dalloc(j, &kbd, kb.size() * sizeof(float))).good()) return fail(s);
+    if (hipMemcpyAsync(kbd, kb.data(), kb.size() * sizeof(float), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+      return fail(Status::fail(PNPULA_EDEVICE, "kernel upload"));
+    d.kbig[0] = kbd;
+    d.kbig[1] = kbd + (size_t)L * Lp;
+    d.kpitch = Lp;
+    d.rpitch = res_pitch(nx, r);
+    const size_t rbytes = (size_t)res_rows(ny, r) * d.rpitch * sizeof(float);
+    if (!(s = dalloc(j, &d.res, rbytes)).good()) return fail(s);
+    if (hipMemsetAsync(d.res, 0, rbytes, stream) != hipSuccess)
+      return fail(Status::fail(PNPULA_EDEVICE, "memset"));
+    if (!(s = dalloc(j, &d.gdat, N * sizeof(float))).good()) return fail(s);
+    // the host copy kb must outlive the asynchronous upload
+    if (hipStreamSynchronize(stream) != hipSuccess)
+      return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
+  }
   // coefficients (FP64, rounded once)
   const double sig2 = c->sigma * c->sigma;
   d.delta = (float)c->delta;
@@ -557,6 +679,28 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   d.inv_s2 = (float)(c->rho > 0 ? 1.0 / c->rho : 1.0 / sig2);
   d.zmix = (float)(c->rho > 0 ? c->rho / (c->rho + sig2) : 0.0);
   d.zsd = (float)(c->rho > 0 ? std::sqrt(c->rho * sig2 / (c->rho + sig2)) : 0.0);
+  const double eta = c->eta > 0 ? c->eta : 1.0;
+  if (d.zmode == 1) {                     // PSGLA: g = eta K^T m (eta m K x - z1)/rho + ...
+    d.inv_s2 = (float)(eta / c->rho);
+    d.eta = (float)eta;
+    d.za1 = (float)(c->kappa / c->rho);
+    d.zs1 = (float)std::sqrt(2.0 * c->kappa);
+    d.zkappa = (float)c->kappa;
+    d.zsig2 = (float)sig2;
+    if (c->rho2 > 0) {
+      d.za2 = (float)(c->kappa2 / c->rho2);
+      d.zs2 = (float)std::sqrt(2.0 * c->kappa2);
+      d.inv_rho2 = (float)(1.0 / c->rho2);
+    }
+  } else if (d.zmode == 2) {              // TV: unsplit data term, prior term delta G
+    d.inv_s2 = (float)(1.0 / sig2);
+    d.cprior = (float)c->delta;
+    d.cproj = 0.0f;
+    d.za1 = (float)(c->kappa / c->rho);
+    d.zs1 = (float)std::sqrt(2.0 * c->kappa);
+    d.zkappa = (float)(c->kappa * c->beta);
+    d.inv_rho = (float)(1.0 / c->rho);
+  }
   d.key0 = (uint32_t)c->seed;
   d.key1 = (uint32_t)(c->seed >> 32);
   d.chain = c->chain;
@@ -572,6 +716,7 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   // previous one's while it is still in that XCD's L2
   make_tiles(j->pair_tiles, ny, nx, ny, 32 * kPairTileW, kPairTileH, kPairTileW);
   make_tiles(j->pair_ws_tiles, ny, nx, ny, 32 * kPairTileW, kPairWsTileH, kPairTileW);
+  if (c->prior == PNPULA_PRIOR_DDFB) make_tiles(j->ddfb_tiles, ny, nx, ny, nx, kDdTile, kDdTile);
   if (hipStreamSynchronize(stream) != hipSuccess)
     return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
   *out = j;
@@ -588,11 +733,23 @@ void Engine::free_job(Job *j) {
 // plans
 // ---------------------------------------------------------------------
 Status Engine::rebuild_plan() {
-  std::vector<TileRef> conv, upd, pair, pair_ws;
+  std::vector<TileRef> conv, upd, pair, pair_ws, ddfb;
   max_r = 0;
   uniform_r = true;
+  max_kpitch = 8;
   for (size_t ji = 0; ji < resident.size(); ++ji) {
     Job *j = resident[ji];
+    if (ji == 0) {
+      zmode = j->d.zmode;
+      big = j->d.big;
+    } else if (j->d.zmode != zmode || (bool)j->d.big != big) {
+      return Status::fail(PNPULA_EINVAL, "resident jobs must share the z-step and blur path");
+    }
+    max_kpitch = std::max(max_kpitch, (int)j->d.kpitch);
+    for (TileRef t : j->ddfb_tiles) {
+      t.job = (int)ji;
+      ddfb.push_back(t);
+    }
     for (TileRef t : j->conv_tiles) {
       t.job = (int)ji;
       conv.push_back(t);
@@ -631,6 +788,10 @@ Status Engine::rebuild_plan() {
   TRY(grow(&d_pair, cap_pair, std::max<size_t>(pair.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_pair_ws, cap_pair_ws, std::max<size_t>(pair_ws.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_jobs, cap_jobs, std::max<size_t>(resident.size(), 1), sizeof(JobDesc)));
+  TRY(grow(&d_ddfb, cap_ddfb, std::max<size_t>(ddfb.size(), 1), sizeof(TileRef)));
+  if (!ddfb.empty())
+    HIPOK(hipMemcpyAsync(d_ddfb, ddfb.data(), ddfb.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
+  n_ddfb = (int)ddfb.size();
   if (!conv.empty())
     HIPOK(hipMemcpyAsync(d_conv, conv.data(), conv.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
   if (!upd.empty())
@@ -997,19 +1158,95 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof, const StageFn *on_sta
 
 Status Engine::run_denoiser(int64_t tick) { return run_fused_denoiser(tick, true); }
 
+// Prior term other than the residual CNN into JobDesc::G: the TV coupling
+// term (1/rho) D^T (D x - z), or G = x - D(x) of the DDFB denoiser (one
+// launch per stage).
+Status Engine::run_prior_other(int64_t tick) {
+  ProfileRec pr;
+  if (net.prior == PNPULA_PRIOR_TV) {
+    UpdateArgs u{};
+    u.jobs = d_jobs;
+    u.tiles = d_upd;
+    u.n_tiles = n_upd;
+    u.tick = tick;
+    prof_begin(7, &pr);
+    HIPOK(launch_tv_prior(u, n_upd, stream));
+    prof_end(&pr);
+    return Status::ok();
+  }
+  DdfbArgs a{};
+  a.jobs = d_jobs;
+  a.tiles = d_ddfb;
+  a.n_tiles = n_ddfb;
+  a.K = net.ddfb_K;
+  a.F = net.ddfb_F;
+  a.tick = tick;
+  a.w = net.ddfb_w;
+  a.thresh = net.ddfb_thresh;
+  for (int k = 0; k < net.ddfb_K; ++k) a.gamma[k] = net.ddfb_gamma[k];
+  for (int k = 1; k <= net.ddfb_K; ++k) {
+    a.stage = k;
+    prof_begin(7, &pr);
+    HIPOK(launch_ddfb_stage(a, n_ddfb, stream));
+    prof_end(&pr);
+  }
+  return Status::ok();
+}
+
 Status Engine::tick() {
   if (plan_dirty) TRY(rebuild_plan());
   if (resident.empty()) return Status::ok();
-  TRY(run_denoiser(ticks));
+  if (net.prior == PNPULA_PRIOR_CNN) TRY(run_denoiser(ticks));
+  else TRY(run_prior_other(ticks));
   UpdateArgs u{};
   u.jobs = d_jobs;
   u.tiles = d_upd;
   u.n_tiles = n_upd;
   u.tick = ticks;
   ProfileRec pr;
-  prof_begin(3, &pr);
-  HIPOK(launch_fused_update(u, n_upd, max_r, uniform_r, stream));
-  prof_end(&pr);
+  if (big) {
+    // large blur: residual and adjoint as whole-image passes, then the update
+    BlurArgs b{};
+    b.jobs = d_jobs;
+    b.tiles = d_upd;
+    b.n_tiles = n_upd;
+    b.tick = ticks;
+    b.epi = EPI_RESIDUAL;
+    prof_begin(9, &pr);
+    HIPOK(launch_blur_big(b, n_upd, max_r, max_kpitch, stream));
+    prof_end(&pr);
+    b.epi = EPI_GRAD;
+    prof_begin(9, &pr);
+    HIPOK(launch_blur_big(b, n_upd, max_r, max_kpitch, stream));
+    prof_end(&pr);
+    prof_begin(3, &pr);
+    HIPOK(launch_update_pointwise(u, n_upd, stream));
+    prof_end(&pr);
+  } else {
+    prof_begin(3, &pr);
+    HIPOK(launch_fused_update(u, n_upd, max_r, uniform_r, zmode == 1 ? 1 : 0, stream));
+    prof_end(&pr);
+  }
+  if (zmode != 0) {
+    // z-step from x^(t+1), noise at counter t+1
+    UpdateArgs z = u;
+    z.tick = ticks + 1;
+    if (zmode == 1 && big) {
+      BlurArgs b{};
+      b.jobs = d_jobs;
+      b.tiles = d_upd;
+      b.n_tiles = n_upd;
+      b.tick = ticks + 1;
+      b.epi = EPI_KX;
+      prof_begin(9, &pr);
+      HIPOK(launch_blur_big(b, n_upd, max_r, max_kpitch, stream));
+      prof_end(&pr);
+    }
+    prof_begin(8, &pr);
+    if (zmode == 1) HIPOK(launch_zstep_psgla(z, n_upd, big ? 0 : max_r, stream));
+    else HIPOK(launch_zstep_tv(z, n_upd, stream));
+    prof_end(&pr);
+  }
   ticks += 1;
   for (Job *j : resident) j->t += 1;
   return Status::ok();
@@ -1101,6 +1338,51 @@ Status Engine::restore_stats(Job *j, const double *mean, const double *m2, int64
   return Status::ok();
 }
 
+Status Engine::get_z(Job *j, float *z1, float *z2) {
+  const JobDesc &d = j->d;
+  if (d.zmode == 0) return Status::fail(PNPULA_ESTATE, "the chain holds no z");
+  HIPOK(hipStreamSynchronize(stream));
+  const size_t origin = (size_t)d.xborder * d.xpitch + d.xborder;
+  float *dst[2] = {z1, z2};
+  const float *src[2] = {d.z1, d.z2};
+  for (int i = 0; i < 2; ++i) {
+    if (!dst[i]) continue;
+    if (!src[i]) {
+      std::fill(dst[i], dst[i] + (size_t)d.ny * d.nx, 0.0f);
+      continue;
+    }
+    HIPOK(hipMemcpy2D(dst[i], (size_t)d.nx * sizeof(float), src[i] + origin,
+                      (size_t)d.xpitch * sizeof(float), (size_t)d.nx * sizeof(float), d.ny,
+                      hipMemcpyDeviceToHost));
+  }
+  return Status::ok();
+}
+
+Status Engine::set_z(Job *j, const float *z1, const float *z2) {
+  const JobDesc &d = j->d;
+  if (d.zmode == 0) return Status::fail(PNPULA_ESTATE, "the chain holds no z");
+  const size_t origin = (size_t)d.xborder * d.xpitch + d.xborder;
+  const float *src[2] = {z1, z2};
+  float *dst[2] = {d.z1, d.z2};
+  for (int i = 0; i < 2; ++i) {
+    if (!src[i] || !dst[i]) continue;
+    HIPOK(hipMemcpy2DAsync(dst[i] + origin, (size_t)d.xpitch * sizeof(float), src[i],
+                           (size_t)d.nx * sizeof(float), (size_t)d.nx * sizeof(float), d.ny,
+                           hipMemcpyHostToDevice, stream));
+  }
+  HIPOK(hipStreamSynchronize(stream));
+  return Status::ok();
+}
+
+Status Engine::stats_device(Job *j, float *mean, float *var, int64_t *n) {
+  int64_t total = 0;
+  TRY(flush_stats(j, &total));
+  HIPOK(launch_stats_out(j->d, total, mean, var, stream));
+  HIPOK(hipStreamSynchronize(stream));
+  if (n) *n = total;
+  return Status::ok();
+}
+
 // Output of layer k (k < K - 1) held in activation buffer `slot`,
 // dequantised to FP32 (value = code x the next layer's input scale), as
 // channels planes of ny*nx (CHW).
@@ -1175,6 +1457,14 @@ Status Engine::denoise(Job *j, const float *x, float *G, float *layers, float *a
                          (size_t)d.nx * sizeof(float), (size_t)d.nx * sizeof(float), d.ny,
                          hipMemcpyHostToDevice, stream));
   const int64_t tick_alt = ticks + 1;  // t = tick + t_offset = j->t + 1
+  if (net.prior != PNPULA_PRIOR_CNN) {
+    if (net.prior != PNPULA_PRIOR_DDFB || layers || amax)
+      return Status::fail(PNPULA_ESTATE, "this prior has no denoiser to apply");
+    TRY(run_prior_other(tick_alt));
+    HIPOK(hipStreamSynchronize(stream));
+    if (G) HIPOK(hipMemcpy(G, d.G, (size_t)d.ny * d.nx * sizeof(float), hipMemcpyDeviceToHost));
+    return Status::ok();
+  }
   const int K = net.K;
   const size_t N = (size_t)d.ny * d.nx;
   if (amax) {

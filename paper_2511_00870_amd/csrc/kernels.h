@@ -40,6 +40,33 @@ struct ConvArgs {
   float out_inv_scale2;
 };
 
+// one stage of the DDFB denoiser (stage k = 1 .. K writes b_k, or G at K)
+struct DdfbArgs {
+  const JobDesc *jobs;
+  const TileRef *tiles;        // kDdTile x kDdTile tiles over the whole image
+  int32_t n_tiles;
+  int32_t stage, K, F;
+  int64_t tick;
+  const float *w;              // K blocks of [F][3][3]: W_k maps 1 -> F channels
+  float thresh;                // hard-tanh level
+  float gamma[kMaxDdfbLayers]; // step sizes gamma_1 .. gamma_K
+};
+
+// large blur: one correlation of an image with an L x L kernel per output
+// tile (the update tiles); epi selects input and epilogue
+enum BlurEpi : int {
+  EPI_RESIDUAL = 0,  // input x^(t), kernel flipped: residual m (K x - v) into JobDesc::res
+  EPI_GRAD = 1,      // input JobDesc::res, kernel as is: K^T res / s2 into JobDesc::gdat
+  EPI_KX = 2         // input x^(t), kernel flipped: K x into JobDesc::res (z-step)
+};
+struct BlurArgs {
+  const JobDesc *jobs;
+  const TileRef *tiles;
+  int32_t n_tiles;
+  int32_t epi;
+  int64_t tick;
+};
+
 struct UpdateArgs {
   const JobDesc *jobs;
   const TileRef *tiles;
@@ -95,9 +122,23 @@ hipError_t launch_conv_first(int in_fmt, int out_fmt, int F, const ConvArgs &a, 
 hipError_t launch_conv_last(int in_fmt, int F, const ConvArgs &a, int n_tiles, hipStream_t s);
 hipError_t launch_conv_single(const ConvArgs &a, int n_tiles, hipStream_t s);
 // uniform_r: every resident job's blur half-width equals max_r
+// mode: 0 (y or the exact z draw in the residual) or 1 (PSGLA: z1 and z2 held
+// as state); every resident job must have that mode
 hipError_t launch_fused_update(const UpdateArgs &a, int n_tiles, int max_r, bool uniform_r,
-                               hipStream_t s);
+                               int mode, hipStream_t s);
+// update with a precomputed data gradient (JobDesc::gdat)
+hipError_t launch_update_pointwise(const UpdateArgs &a, int n_tiles, hipStream_t s);
+// PSGLA z-step (after the x-update; tick such that t is the new iterate's)
+hipError_t launch_zstep_psgla(const UpdateArgs &a, int n_tiles, int max_r, hipStream_t s);
+// TV prior term G = (1/rho) D^T (D x - z) at x^(t), and the TV z-step
+hipError_t launch_tv_prior(const UpdateArgs &a, int n_tiles, hipStream_t s);
+hipError_t launch_zstep_tv(const UpdateArgs &a, int n_tiles, hipStream_t s);
+hipError_t launch_ddfb_stage(const DdfbArgs &a, int n_tiles, hipStream_t s);
+// large blur (half-width max_r > kMaxR)
+hipError_t launch_blur_big(const BlurArgs &a, int n_tiles, int max_r, int kpitch, hipStream_t s);
+size_t blur_big_lds_bytes(int r, int kpitch);
 hipError_t launch_amax(const float *p, size_t n, uint32_t *out, hipStream_t s);
+hipError_t launch_stats_out(const JobDesc &j, int64_t n, float *mean, float *var, hipStream_t s);
 hipError_t launch_welford_flush(const JobDesc &j, double n_a, double n_b, hipStream_t s);
 
 }  // namespace pnp

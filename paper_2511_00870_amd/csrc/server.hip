@@ -157,6 +157,13 @@ pnpula_status pnpula_server_submit(pnpula_server *s, const pnpula_config *cfg, i
   if (n_iters < 1) return sreport(s, Status::fail(PNPULA_EINVAL, "n_iters must be >= 1"));
   Status st = Engine::validate_job(cfg, s->eng.net.K, s->eng.net.channels);
   if (!st.good()) return sreport(s, st);
+  // jobs share one launch per kernel: the server's CNN denoiser, the exact z
+  // draw (or none) and the fused blur path; inputs are copied from the host
+  if (cfg->prior != PNPULA_PRIOR_CNN || cfg->z_step != 0 || cfg->ksize > 2 * pnp::kMaxR + 1 ||
+      cfg->inputs_on_device)
+    return sreport(s, Status::fail(PNPULA_EINVAL,
+                                   "served jobs use the CNN prior, no PSGLA z-step, blurs up to "
+                                   "17 x 17 and host inputs"));
   Pending p;
   p.id = s->next_id++;
   p.n_iters = n_iters;

@@ -17,6 +17,8 @@
 //                + sqrt(2 delta) xi,   g = K^T res / s2;
 //   6. after burn-in, Welford update of the FP32 window mean / M2 and, when
 //      the window is full, the Chan-Golub-LeVeque merge into the FP64 maps.
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -26,7 +28,11 @@ typedef float upd_f32x4 __attribute__((ext_vector_type(4)));
 
 // RT > 0: every tile's blur half-width is RT (window sizes, divisions and
 // tap loops become compile-time constants); RT = 0: read per job.
-template <int RT>
+// MODE 0: the residual uses y (rho = 0) or the exact z draw (rho > 0);
+// MODE 1: PSGLA chains, z1 and z2 held as state (JobDesc::zmode 1): the
+// residual is m (eta m K x - z1), read in place of y, and the data gradient
+// gains (x - z2)/rho2 on the core.
+template <int RT, int MODE>
 __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
       xv[k] = xin[(wy + i + B) * xpitch + (wx + c + B)];
     }
   }
-  const PNP_GLOBAL float *yb = gp(j.y);
+  const PNP_GLOBAL float *yb = gp(MODE == 1 ? j.z1 : j.y);
   const PNP_GLOBAL uint8_t *mk = gp(j.has_mask ? j.mask : reinterpret_cast<const uint8_t *>(j.y));
   float yv[RQ];
   uint32_t mraw[RQ];
@@ -123,12 +129,18 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
     mraw[k] = mk[pidx];
   }
   float gv[CQ], wmv[CQ], wm2v[CQ];
+  float z2v[MODE == 1 ? CQ : 1];
+  const bool z2on = MODE == 1 && j.has_z2;
 #pragma unroll
   for (int k = 0; k < CQ; ++k) {
     const int q = tid + NT * k;
     const int i = q / TW, c = q % TW;
     const int64_t p = (i < tl.h && c < tl.w) ? (int64_t)(tl.y0 + i) * j.nx + tl.x0 + c : 0;
     gv[k] = gp(j.G)[p];
+    if (MODE == 1) {
+      const int ii = i < tl.h ? i : 0, cc = c < tl.w ? c : 0;
+      z2v[k] = z2on ? gp(j.z2)[(int64_t)(tl.y0 + ii + B) * xpitch + (tl.x0 + cc + B)] : 0.0f;
+    }
     wmv[k] = wm2v[k] = 0.0f;
     if (stats && nw > 1) {                           // uniform
       wmv[k] = gp(j.wmean)[p];
@@ -194,7 +206,9 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
     const float mv = j.has_mask ? (float)mraw[k] : 1.0f;
     float res = 0.0f;
     if (Y >= 0 && Y < j.ny && X >= 0 && X < j.nx) {
-      if (!split) {
+      if (MODE == 1) {
+        res = mv * (j.eta * (mv * kx) - yv[k]);             // yv holds z1
+      } else if (!split) {
         res = mv * (kx - yv[k]);
       } else if (!draw) {
         res = mv * kx;                                      // z^(0) = 0
@@ -252,9 +266,11 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
     }
     const float xo = sx[(i + 2 * r) * WW + (c + 2 * r)];
     const float proj = fminf(fmaxf(xo, 0.0f), 1.0f);
-    const float xn = xo - j.delta * (ktr * j.inv_s2) - j.cprior * gv[k] +
-                     j.cproj * (proj - xo) + j.sq2d * xi;
+    float gdat = ktr * j.inv_s2;
+    if (MODE == 1 && z2on) gdat += (xo - z2v[k]) * j.inv_rho2;
+    float xn = xo - j.delta * gdat - j.cprior * gv[k] + j.cproj * (proj - xo) + j.sq2d * xi;
     bad |= !isfinite(xn);
+    if (j.xpos) xn = fmaxf(xn, 0.0f);                      // prox of the indicator of R+
     xout[(int64_t)(Y + B) * j.xpitch + (X + B)] = xn;
     if (stats) {
       float m = wmv[k], M = wm2v[k];                       // zero when the window starts
@@ -277,6 +293,71 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
   if (bad) gp(j.flag)[0] = 1;
 }
 
+// The update and statistics of step 5./6. when the data gradient comes
+// precomputed (JobDesc::gdat: large blurs, whose blur and adjoint run as
+// separate whole-image passes).  One workgroup per 32 x 64 tile.
+__global__ __launch_bounds__(256) void update_pointwise_kernel(UpdateArgs a) {
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+  const int64_t t = a.tick + j.t_offset;
+  const int B = j.xborder;
+  const int64_t xpitch = j.xpitch;
+  const int64_t s = t + 1 - j.burn_in;
+  const bool stats = s >= 1;
+  int nw = 0;
+  bool merge = false;
+  if (stats) {
+    nw = (int)((s - j.wbase - 1) % j.wwin) + 1;
+    merge = nw == j.wwin;
+  }
+  const float inv_nw = stats ? 1.0f / (float)nw : 0.0f;
+  const int64_t na_i = j.nbase + (s - j.wbase - nw);
+  const double n_a = (double)na_i, n_b = (double)nw;
+  const PNP_GLOBAL float *xin = gp(j.x[t & 1]);
+  PNP_GLOBAL float *xout = gp(j.x[(t + 1) & 1]);
+  const bool z2on = j.zmode == 1 && j.has_z2;
+  bool bad = false;
+  for (int q = threadIdx.x; q < kUpdTileH * kUpdTileW; q += 256) {
+    const int i = q / kUpdTileW, c = q % kUpdTileW;
+    if (i >= tl.h || c >= tl.w) continue;
+    const int Y = tl.y0 + i, X = tl.x0 + c;
+    const int64_t p = (int64_t)Y * j.nx + X, pp = (int64_t)(Y + B) * xpitch + (X + B);
+    const float xo = xin[pp];
+    float gdat = gp(j.gdat)[p];
+    if (z2on) gdat += (xo - gp(j.z2)[pp]) * j.inv_rho2;
+    float xi, zeta_unused;
+    gauss_pair(j.key0, j.key1, j.chain, p, t, xi, zeta_unused);
+    const float proj = fminf(fmaxf(xo, 0.0f), 1.0f);
+    float xn = xo - j.delta * gdat - j.cprior * gp(j.G)[p] + j.cproj * (proj - xo) + j.sq2d * xi;
+    bad |= !isfinite(xn);
+    if (j.xpos) xn = fmaxf(xn, 0.0f);
+    xout[pp] = xn;
+    if (stats) {
+      float m = nw > 1 ? gp(j.wmean)[p] : 0.0f, M = nw > 1 ? gp(j.wm2)[p] : 0.0f;
+      const float d = xn - m;
+      m = fmaf(d, inv_nw, m);
+      M = fmaf(d, xn - m, M);
+      if (merge) {
+        const double n = n_a + n_b;
+        const double ma = na_i > 0 ? gp(j.mean)[p] : 0.0;
+        const double Ma = na_i > 0 ? gp(j.m2)[p] : 0.0;
+        const double dl = (double)m - ma;
+        gp(j.mean)[p] = ma + dl * (n_b / n);
+        gp(j.m2)[p] = Ma + (double)M + dl * dl * (n_a * n_b / n);
+      } else {
+        gp(j.wmean)[p] = m;
+        gp(j.wm2)[p] = M;
+      }
+    }
+  }
+  if (bad) gp(j.flag)[0] = 1;
+}
+
+hipError_t launch_update_pointwise(const UpdateArgs &a, int n_tiles, hipStream_t s) {
+  hipLaunchKernelGGL(update_pointwise_kernel, dim3(n_tiles), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // Merge a partially filled FP32 window (nw samples on top of n_a merged
 // ones) into the FP64 statistics of one job.
 __global__ __launch_bounds__(256) void welford_flush_kernel(JobDesc j, double n_a, double n_b) {
@@ -290,6 +371,26 @@ __global__ __launch_bounds__(256) void welford_flush_kernel(JobDesc j, double n_
     gp(j.mean)[p] = ma + dl * (n_b / n);
     gp(j.m2)[p] = Ma + (double)gp(j.wm2)[p] + dl * dl * (n_a * n_b / n);
   }
+}
+
+// MMSE estimate and pixel variance of one job into FP32 device arrays
+// (either may be null): mean = mu, var = M2 / (n - 1) (0 when n < 2)
+__global__ __launch_bounds__(256) void stats_out_kernel(JobDesc j, int64_t n, float *mean,
+                                                        float *var) {
+  const int64_t n_pix = (int64_t)j.ny * j.nx;
+  const double inv = n >= 2 ? 1.0 / (double)(n - 1) : 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n_pix;
+       p += (int64_t)gridDim.x * 256) {
+    if (mean) mean[p] = n >= 1 ? (float)gp(j.mean)[p] : 0.0f;
+    if (var) var[p] = (float)(gp(j.m2)[p] * inv);
+  }
+}
+
+hipError_t launch_stats_out(const JobDesc &j, int64_t n, float *mean, float *var, hipStream_t s) {
+  const int64_t n_pix = (int64_t)j.ny * j.nx;
+  int blocks = (int)std::min<int64_t>((n_pix + 255) / 256, 8192);
+  hipLaunchKernelGGL(stats_out_kernel, dim3(blocks), dim3(256), 0, s, j, n, mean, var);
+  return hipGetLastError();
 }
 
 // max |p[i]| over n floats into *out (float bits; all values >= 0 so the
@@ -318,31 +419,37 @@ size_t update_lds_bytes(int r) {
                           (size_t)TH * TW);
 }
 
-template <int RT>
+template <int RT, int MODE>
 static hipError_t launch_update_t(const UpdateArgs &a, int n_tiles, int max_r, hipStream_t s) {
   const size_t lds = update_lds_bytes(max_r);
   static size_t attr = 0;
   if (lds > attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_update_kernel<RT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&fused_update_kernel<RT, MODE>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = lds;
   }
-  hipLaunchKernelGGL((fused_update_kernel<RT>), dim3(n_tiles), dim3(kUpdThreads), lds, s, a);
+  hipLaunchKernelGGL((fused_update_kernel<RT, MODE>), dim3(n_tiles), dim3(kUpdThreads), lds, s,
+                     a);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_update(const UpdateArgs &a, int n_tiles, int max_r, bool uniform_r,
-                               hipStream_t s) {
+                               int mode, hipStream_t s) {
+  if (mode == 1) {
+    if (uniform_r && max_r == 4) return launch_update_t<4, 1>(a, n_tiles, max_r, s);
+    return launch_update_t<0, 1>(a, n_tiles, max_r, s);
+  }
   if (uniform_r) {
     switch (max_r) {                             // the blur sizes 5, 7 and 9
-      case 2: return launch_update_t<2>(a, n_tiles, max_r, s);
-      case 3: return launch_update_t<3>(a, n_tiles, max_r, s);
-      case 4: return launch_update_t<4>(a, n_tiles, max_r, s);
+      case 2: return launch_update_t<2, 0>(a, n_tiles, max_r, s);
+      case 3: return launch_update_t<3, 0>(a, n_tiles, max_r, s);
+      case 4: return launch_update_t<4, 0>(a, n_tiles, max_r, s);
       default: break;
     }
   }
-  return launch_update_t<0>(a, n_tiles, max_r, s);
+  return launch_update_t<0, 0>(a, n_tiles, max_r, s);
 }
 
 hipError_t launch_welford_flush(const JobDesc &j, double n_a, double n_b, hipStream_t s) {

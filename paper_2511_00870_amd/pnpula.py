@@ -19,13 +19,16 @@ LIB_PATH = os.path.join(HERE, "libpnpula.so")
 PNPULA_OK, PNPULA_EINVAL, PNPULA_ENOMEM, PNPULA_EDEVICE, PNPULA_ESTATE, PNPULA_EDIVERGED = \
     0, -1, -2, -3, -4, -5
 PNPULA_FP32, PNPULA_BF16, PNPULA_FP8_E4M3 = 0, 1, 2
+PNPULA_LIK_GAUSSIAN, PNPULA_LIK_POISSON = 0, 1
+PNPULA_PRIOR_CNN, PNPULA_PRIOR_TV, PNPULA_PRIOR_DDFB = 0, 1, 2
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE",
                 -5: "EDIVERGED"}
 
 # every symbol include/pnpula.h declares
 EXPORTS = [
     "pnpula_create", "pnpula_step", "pnpula_sync", "pnpula_stats", "pnpula_stats_f64",
-    "pnpula_get_state", "pnpula_set_state", "pnpula_restore", "pnpula_denoise",
+    "pnpula_get_state", "pnpula_set_state", "pnpula_restore", "pnpula_get_z", "pnpula_set_z",
+    "pnpula_stats_device", "pnpula_denoise",
     "pnpula_denoise_stages",
     "pnpula_calibrate", "pnpula_profile", "pnpula_profile_read", "pnpula_state_device",
     "pnpula_destroy", "pnpula_last_error", "pnpula_create_error", "pnpula_footprint",
@@ -57,7 +60,12 @@ class pnpula_config(C.Structure):
                 ("weights", _fp), ("biases", _fp), ("precision", C.c_int32),
                 ("act_scales", _fp), ("seed", C.c_uint64), ("chain", C.c_uint32),
                 ("burn_in", C.c_int32), ("welford_window", C.c_int32), ("x0", _fp),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("likelihood", C.c_int32), ("z_step", C.c_int32),
+                ("eta", C.c_double), ("kappa", C.c_double), ("rho2", C.c_double),
+                ("kappa2", C.c_double), ("prior", C.c_int32), ("beta", C.c_double),
+                ("ddfb_layers", C.c_int32), ("ddfb_features", C.c_int32),
+                ("ddfb_weights", _fp), ("ddfb_gamma", _fp), ("ddfb_thresh", C.c_double),
+                ("inputs_on_device", C.c_int32)]
 
 
 _lib = None
@@ -86,6 +94,9 @@ def _declare(L):
     L.pnpula_get_state.argtypes = [vp, _fp, _i64p]
     L.pnpula_set_state.argtypes = [vp, _fp, C.c_int64]
     L.pnpula_restore.argtypes = [vp, _fp, C.c_int64, _dp, _dp, C.c_int64]
+    L.pnpula_get_z.argtypes = [vp, _fp, _fp]
+    L.pnpula_set_z.argtypes = [vp, _fp, _fp]
+    L.pnpula_stats_device.argtypes = [vp, vp, vp, _i64p]
     L.pnpula_denoise.argtypes = [vp, _fp, _fp, _fp]
     L.pnpula_denoise_stages.argtypes = [vp, _fp, _fp, _ip, _ip, _fp]
     L.pnpula_calibrate.argtypes = [vp, _fp, _fp]
@@ -123,30 +134,61 @@ def _fptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(_fp)
 
 
+def _is_device(a) -> bool:
+    """a torch tensor on a GPU (torch is imported only when one is passed)"""
+    return type(a).__module__.startswith("torch") and getattr(a, "is_cuda", False)
+
+
 class Config:
     """Owns the arrays a pnpula_config points to."""
 
     def __init__(self, *, y, kernel, sigma, eps, delta, channels, weights, biases,
                  rho=0.0, alpha=1.0, inv_lambda=0.0, mask=None, block_y=None, block_x=None,
                  halo=0, precision=PNPULA_FP32, act_scales=None, seed=0, chain=0, burn_in=0,
-                 welford_window=0, x0=None, stream=None):
-        self.y = _f32(y)
-        ny, nx = self.y.shape
-        self.kernel = _f32(kernel)
-        self.mask = None if mask is None else np.ascontiguousarray(mask, np.uint8)
+                 welford_window=0, x0=None, stream=None, likelihood=PNPULA_LIK_GAUSSIAN,
+                 z_step=0, eta=0.0, kappa=0.0, rho2=0.0, kappa2=0.0, prior=PNPULA_PRIOR_CNN,
+                 beta=0.0, ddfb_weights=None, ddfb_gamma=None, ddfb_thresh=0.0):
+        """Host arrays (numpy), or torch device tensors for y, kernel, mask
+        and x0 together (then inputs_on_device = 1 and the tensors must stay
+        alive until the context is created)."""
+        dev = _is_device(y)
+        if dev:
+            ny, nx = (int(v) for v in y.shape)
+            self._keep = [v for v in (y, kernel, mask, x0) if v is not None]
+            for v in self._keep:
+                if not _is_device(v) or not v.is_contiguous():
+                    raise ValueError("device inputs: y, kernel, mask and x0 must all be "
+                                     "contiguous device tensors")
+            ksize = int(kernel.shape[0])
+            yp, kp = C.cast(y.data_ptr(), _fp), C.cast(kernel.data_ptr(), _fp)
+            mp = None if mask is None else C.cast(mask.data_ptr(), _u8p)
+            xp = None if x0 is None else C.cast(x0.data_ptr(), _fp)
+        else:
+            self.y = _f32(y)
+            ny, nx = self.y.shape
+            self.kernel = _f32(kernel)
+            ksize = self.kernel.shape[0]
+            self.mask = None if mask is None else np.ascontiguousarray(mask, np.uint8)
+            self.x0 = None if x0 is None else _f32(x0)
+            yp, kp = _fptr(self.y), _fptr(self.kernel)
+            mp = self.mask.ctypes.data_as(_u8p) if self.mask is not None else None
+            xp = _fptr(self.x0)
         self.channels = np.ascontiguousarray(channels, np.int32)
         self.weights = _f32(np.concatenate([np.asarray(w, np.float32).ravel() for w in weights]))
         self.biases = _f32(np.concatenate([np.asarray(b, np.float32).ravel() for b in biases]))
         self.act_scales = None if act_scales is None else _f32(act_scales)
-        self.x0 = None if x0 is None else _f32(x0)
+        self.ddfb_weights = None if ddfb_weights is None else _f32(ddfb_weights)
+        self.ddfb_gamma = None if ddfb_gamma is None else _f32(ddfb_gamma)
+        dK = 0 if self.ddfb_weights is None else int(self.ddfb_weights.shape[0])
+        dF = 0 if self.ddfb_weights is None else int(self.ddfb_weights.shape[1])
         self.c = pnpula_config(
-            ny, nx, _fptr(self.y), self.kernel.shape[0], _fptr(self.kernel),
-            self.mask.ctypes.data_as(_u8p) if self.mask is not None else None,
-            sigma, eps, alpha, delta, rho, inv_lambda,
+            ny, nx, yp, ksize, kp, mp, sigma, eps, alpha, delta, rho, inv_lambda,
             ny if block_y is None else block_y, nx if block_x is None else block_x, halo,
             len(self.channels) - 1, self.channels.ctypes.data_as(_ip), _fptr(self.weights),
             _fptr(self.biases), precision, _fptr(self.act_scales), seed, chain, burn_in,
-            welford_window, _fptr(self.x0), stream)
+            welford_window, xp, stream, likelihood, z_step, eta, kappa, rho2, kappa2, prior,
+            beta, dK, dF, _fptr(self.ddfb_weights), _fptr(self.ddfb_gamma), ddfb_thresh,
+            1 if dev else 0)
 
     @classmethod
     def from_workload(cls, wl, *, precision=None, act_scales=None, block=None, x0=None,
@@ -158,7 +200,11 @@ class Config:
                   channels=wl.channels, weights=wl.weights, biases=wl.biases,
                   precision=wl.precision if precision is None else precision,
                   act_scales=act_scales, seed=wl.seed, chain=chain, burn_in=wl.burn_in,
-                  welford_window=wl.welford_window, x0=x0, stream=stream)
+                  welford_window=wl.welford_window, x0=x0, stream=stream,
+                  likelihood=wl.likelihood, z_step=wl.z_step, eta=wl.eta, kappa=wl.kappa,
+                  rho2=wl.rho2, kappa2=wl.kappa2, prior=wl.prior, beta=wl.beta,
+                  ddfb_weights=wl.ddfb_weights, ddfb_gamma=wl.ddfb_gamma,
+                  ddfb_thresh=wl.ddfb_thresh)
         kw.update(over)
         return cls(**kw)
 
@@ -215,6 +261,31 @@ class Context:
     def set_state(self, x, t: int):
         x = _f32(x)
         _check(lib().pnpula_set_state(self.h, _fptr(x), t), self._err)
+
+    def get_z(self):
+        """(z1, z2) of a chain that holds its splitting variables (PSGLA, TV)"""
+        z1 = np.empty((self.ny, self.nx), np.float32)
+        z2 = np.empty((self.ny, self.nx), np.float32)
+        _check(lib().pnpula_get_z(self.h, _fptr(z1), _fptr(z2)), self._err)
+        return z1, z2
+
+    def set_z(self, z1=None, z2=None):
+        z1 = None if z1 is None else _f32(z1)
+        z2 = None if z2 is None else _f32(z2)
+        _check(lib().pnpula_set_z(self.h, _fptr(z1), _fptr(z2)), self._err)
+
+    def stats_device(self, mean, var):
+        """pnpula_stats into torch device tensors (float32, ny x nx each,
+        either may be None); returns the sample count"""
+        n = C.c_int64()
+        for v in (mean, var):
+            if v is not None and (not _is_device(v) or not v.is_contiguous() or
+                                  v.numel() != self.ny * self.nx):
+                raise ValueError("mean / var must be contiguous device tensors of ny*nx floats")
+        _check(lib().pnpula_stats_device(
+            self.h, None if mean is None else C.c_void_p(mean.data_ptr()),
+            None if var is None else C.c_void_p(var.data_ptr()), C.byref(n)), self._err)
+        return n.value
 
     def restore(self, x, t, mean, m2, n):
         x = _f32(x)

@@ -41,7 +41,14 @@ def _cfg(**over):
 
 @pytest.mark.parametrize("over,needle", [
     (dict(kernel=np.ones((4, 4)) / 16), "odd"),
-    (dict(kernel=np.ones((19, 19)) / 361), "odd"),
+    (dict(kernel=np.ones((131, 131)) / 131 ** 2), "odd"),
+    (dict(likelihood=P.PNPULA_LIK_POISSON), "Poisson"),
+    (dict(z_step=1, rho=1e-3), "PSGLA"),
+    (dict(z_step=1, rho=1e-3, kappa=1e-3, rho2=1e-3), "second z block"),
+    (dict(prior=P.PNPULA_PRIOR_TV, rho=1e-5, kappa=1e-6, z_step=1), "TV"),
+    (dict(prior=P.PNPULA_PRIOR_TV), "PSGLA"),
+    (dict(prior=P.PNPULA_PRIOR_DDFB), "DDFB"),
+    (dict(prior=7), "prior"),
     (dict(halo=3), "halo"),
     (dict(halo=16), "smaller"),
     (dict(sigma=0.0), "sigma"),

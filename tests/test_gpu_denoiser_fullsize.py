@@ -30,10 +30,11 @@ def say(*a):
 
 
 def _q(v, fmt, scale=1.0):
-    return O.quantize(np.asarray(v) / scale, fmt) * scale
+    return O.quantize_scaled(v, fmt, scale)
 
 
 def _ulp(v, fmt, scale=1.0):
+    """one code step of the format at |v| (after dividing by the scale)"""
     a = np.abs(np.asarray(v, np.float64)) / scale
     e = np.floor(np.log2(np.maximum(a, 1e-300)))
     if fmt == 1:
@@ -41,29 +42,40 @@ def _ulp(v, fmt, scale=1.0):
     return 2.0 ** (np.maximum(e, -6) - 3) * scale
 
 
-def _near_tie(v, fmt, scale, slack):
-    """pixels (any channel) whose exact value lies within `slack` of a
-    rounding boundary of the format: FP32 accumulation may round them the
-    other way"""
+# FP32 accumulation slack of one layer's output, relative to the value: the
+# GPU sums 9 F exact products (bf16 x bf16 and e4m3 x e4m3 products are exact
+# in FP32) in its own order, so its pre-rounding value differs from the exact
+# one by a few units in the 24th bit; 1e-5 leaves a wide margin
+ACC_REL = 1e-5
+
+
+def _abs_layer(ws, fmt, net, j):
+    """|W_j| as the layer multiplies it (rounded to its format with its
+    per-output-channel scales), for propagating error bounds"""
+    w = np.asarray(ws[j], np.float64)
+    if fmt[j] == 0:
+        return np.abs(w)
+    s = O.weight_scales(net, j).reshape(-1, 1, 1, 1)
+    return np.abs(_q(w / s, fmt[j]) * s)
+
+
+def _propagate(F, wabs):
+    """upper bound of how far a layer's pre-activation output can move when
+    its input moves by at most F (per channel and pixel): |W| * F"""
+    cout, cin = wabs.shape[:2]
+    ch = np.array([cin, cout], np.int32)
+    net = O.Net(ch, [wabs], [np.zeros(cout)])
+    return O.layers_from(net, F, 0, 1)[0]
+
+
+def _flip_bound(v, fmt, scale, e):
+    """how far the rounded value of v can move when v itself is only known
+    within e: one code step (or 2e, when larger) where v lies within e of a
+    rounding boundary, zero elsewhere; returns (bound, possibly-flipped)"""
     q = _q(v, fmt, scale)
-    half = _ulp(v, fmt, scale) / 2
-    return (np.abs(np.abs(v - q) - half) <= slack).any(axis=0)
-
-
-def _dilate(m, n=1):
-    for _ in range(n):
-        out = m.copy()
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
-                sh = np.zeros_like(m)
-                ys = slice(max(dy, 0), m.shape[0] + min(dy, 0))
-                yd = slice(max(-dy, 0), m.shape[0] + min(-dy, 0))
-                xs = slice(max(dx, 0), m.shape[1] + min(dx, 0))
-                xd = slice(max(-dx, 0), m.shape[1] + min(-dx, 0))
-                sh[yd, xd] = m[ys, xs]
-                out |= sh
-        m = out
-    return m
+    step = _ulp(v, fmt, scale)
+    near = np.abs(np.abs(v - q) - step / 2) <= e
+    return np.where(near, np.maximum(step, 2 * e), 0.0), near
 
 
 def _scales(ch, ws, bs, fmt, x):
@@ -85,11 +97,15 @@ def _ctx(ch, ws, bs, prec, ny, nx, scales, block=None):
 @pytest.mark.parametrize("shape", [(37, 71), (48, 2000)])
 def test_fused_launches_teacher_forced(prec, K, shape):
     """Each launch of the sampler's denoiser path against the emulating
-    oracle run from that launch's GPU input.  Stored codes must lie within one
-    code step of the exact value (plus the FP32 accumulation slack) except
-    at pixels whose inputs inside the launch sat on a rounding boundary (and
-    their 3x3 neighbourhoods per later layer); at most 2e-3 of the codes may
-    round the other way.  The last launch's G is compared the same way."""
+    oracle run from that launch's GPU input (teacher forcing).
+
+    Error model: every layer's GPU value before rounding lies within
+    ACC_REL |v| of the exact one, plus what rounding flips of earlier layers
+    inside the same launch can add (|W| times one code step at every value
+    that sat within its own bound of a rounding boundary).  A stored code
+    must equal the exact rounding wherever that bound keeps the value off a
+    boundary, and lie within one code step elsewhere; G must lie within its
+    bound everywhere.  At most 2e-3 of the stored codes may differ at all."""
     ny, nx = shape
     say(f"case teacher-forced fused launches precision={prec} K={K} {ny}x{nx}")
     ch, ws, bs = W.denoiser_weights(K, 64, seed=61 + K, bias_scale=0.05)
@@ -104,29 +120,32 @@ def test_fused_launches_teacher_forced(prec, K, shape):
     inp, k0 = x, 0
     for (k1, act) in stages + [(K - 1, None)]:
         outs = O.layers_from(net, inp, k0, k1 + 1)
-        excl = np.zeros((ny, nx), bool)
-        for j in range(k0, k1):          # intermediate layers inside the launch
+        F = None                          # bound on the quantised input's movement
+        for j in range(k0, k1 + 1):
             v = outs[j - k0]
-            excl = _dilate(excl) | _near_tie(v, fmt[j + 1], scales[j + 1],
-                                              1e-5 * np.abs(v).max())
-        excl = _dilate(excl)
+            e = ACC_REL * np.abs(v)
+            if F is not None:
+                e = e + _propagate(F, _abs_layer(ws, fmt, net, j))
+            if j < k1:                    # rounded inside the launch
+                F, _ = _flip_bound(v, fmt[j + 1], scales[j + 1], e)
         ref = outs[-1]
-        if act is None:                  # the last launch: G in FP32
+        if act is None:                   # the last launch: G in FP32
             g = G.astype(np.float64)
-            err = np.abs(g - ref[0])[~excl].max()
+            err = np.abs(g - ref[0])
             rel = float(np.linalg.norm(g - ref[0]) / np.linalg.norm(ref[0]))
-            say(f"  layers {k0}..{k1} -> G: max err off flips {err:.2e} "
-                f"(|G| max {np.abs(ref).max():.2e}), rel {rel:.2e}, {excl.mean():.1e} excluded")
-            assert err <= 1e-5 * np.abs(ref).max()
+            say(f"  layers {k0}..{k1} -> G: max err {err.max():.2e}, max bound "
+                f"{e.max():.2e} (|G| max {np.abs(ref).max():.2e}), rel {rel:.2e}")
+            assert (err <= e[0] + 1e-12).all(), np.argwhere(err > e[0])[:5]
             assert rel <= (5e-3 if prec == P.PNPULA_BF16 else 5e-2)
             break
         f, s = fmt[k1 + 1], scales[k1 + 1]
         refq = _q(ref, f, s)
-        diff = act.astype(np.float64) != refq
-        slack = 1e-5 * np.abs(ref).max()
-        bad = (np.abs(act - ref) > _ulp(ref, f, s) + slack) & ~excl[None]
-        say(f"  layers {k0}..{k1}: {diff.mean():.2e} codes differ, {excl.mean():.1e} pixels "
-            f"excluded, {int(bad.sum())} beyond one code step")
+        bound, near = _flip_bound(ref, f, s, e)
+        dev = np.abs(act.astype(np.float64) - refq)
+        diff = dev > 0
+        bad = dev > bound
+        say(f"  layers {k0}..{k1}: {diff.mean():.2e} codes differ, {near.mean():.1e} of the "
+            f"values within their bound of a boundary, {int(bad.sum())} outside the bound")
         assert not bad.any(), (np.argwhere(bad)[:5])
         assert diff.mean() <= 2e-3
         inp, k0 = act.astype(np.float64), k1 + 1

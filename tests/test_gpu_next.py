@@ -1,0 +1,220 @@
+"""GPU parity of the paper's other data terms and priors against the FP64
+oracle, step by step (the GPU step applied to the oracle's state):
+
+* PSGLA z-steps with the Gaussian data term and the second block on R+, and
+  Poisson deconvolution (Eq. (sgs_pnp_ula_psgla:psgla); Sec. III-A3 and
+  III-B1 (ii) parameters: rho1 = 10, rho2 = 1e-3, kappa_i = 0.99 rho_i,
+  eta = 250);
+* the TV prior through AXDA with PSGLA (Sec. III-B2, Eq. (tv_prior));
+* the DDFB denoiser (Sec. II-B1 Example 3, Eqs. (ddfb_operator),
+  (dfb_operator:T)), alone and inside the chain;
+* large non-separable motion blurs, 33^2 to 129^2 (Sec. III-A2), with the
+  exact z draw, without splitting and with the Poisson PSGLA chain;
+* inputs given as device tensors and statistics written to device memory.
+
+Bar: 1e-5 relative per step on x (and on the z blocks) for FP32.
+"""
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+from paper_2511_00870_amd import pnpula as P
+from paper_2511_00870_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    nb = float(np.linalg.norm(b))
+    d = float(np.linalg.norm(np.asarray(a, np.float64) - b))
+    return d / nb if nb > 0 else d
+
+
+def _parity(wl, n_steps, label, zstate=False, block=None, x0=None):
+    """Teacher-forced per-step comparison; returns the worst x and z errors."""
+    say(f"case {label}: {wl.ny}x{wl.nx} L={wl.kernel.shape[0]} prior={wl.prior} "
+        f"z_step={wl.z_step} likelihood={wl.likelihood} steps={n_steps}")
+    oc = O.Chain.from_workload(wl, block=0)
+    if x0 is not None:
+        oc.set_state(x0, 0)
+    ctx = P.Context(P.Config.from_workload(wl, block=block))
+    worst_x = worst_z = 0.0
+    for t in range(n_steps):
+        x_t, tt = oc.get_state()
+        assert tt == t
+        ctx.set_state(x_t.astype(np.float32), t)
+        if zstate:
+            z1, z2 = oc.get_z()
+            ctx.set_z(z1.astype(np.float32), z2.astype(np.float32))
+        ctx.step(1)
+        assert ctx.sync() == P.PNPULA_OK
+        xg, tg = ctx.get_state()
+        oc.step(1)
+        x1, _ = oc.get_state()
+        assert tg == t + 1
+        worst_x = max(worst_x, rel(xg, x1))
+        if zstate:
+            g1, g2 = ctx.get_z()
+            o1, o2 = oc.get_z()
+            worst_z = max(worst_z, rel(g1, o1), rel(g2, o2))
+    say(f"  worst per-step rel: x {worst_x:.2e}, z {worst_z:.2e}")
+    assert worst_x <= TOL and worst_z <= TOL
+    return ctx, oc
+
+
+# ------------------------------------------------------------------ PSGLA
+@pytest.mark.parametrize("sep", [True, False])
+def test_psgla_gaussian_step_parity(sep):
+    wl = W.make_workload("g", 45, 70, L=5, sigma_k=1.0, sigma=0.05, block=24, halo=5,
+                         n_layers=4, features=16, precision=0, iters=12, burn_in=3, seed=5,
+                         bias_scale=0.05, mask_p=0.7)
+    if not sep:
+        rng = np.random.default_rng(3)
+        wl.kernel = rng.random((5, 5))
+        wl.kernel /= wl.kernel.sum()
+    wl.z_step, wl.kappa = 1, 0.9 * wl.rho
+    wl.rho2, wl.kappa2 = 0.5 * wl.rho, 0.45 * wl.rho
+    x0 = np.random.default_rng(2).random((45, 70))
+    _parity(wl, 12, f"PSGLA Gaussian {'separable' if sep else '2-D'} blur", zstate=True, x0=x0)
+
+
+@pytest.mark.parametrize("mask_p", [None, 0.6])
+def test_poisson_step_parity(mask_p):
+    wl = W.poisson_workload("p", 53, 66, W.gaussian_kernel(7, 1.5), 32, 6, 4, 16, 0, 15, 4, 11,
+                            bias_scale=0.05, mask_p=mask_p)
+    x0 = np.clip(wl.xbar + 0.05 * np.random.default_rng(4).standard_normal(wl.xbar.shape),
+                 0, 1)
+    _parity(wl, 15, f"Poisson deconvolution mask={mask_p}", zstate=True, x0=x0)
+
+
+def test_poisson_free_running_stays_close_and_in_domain():
+    """Both chains from z^(0) = 0 for 40 steps: same Philox stream, so they
+    stay coupled; z1, z2 stay non-negative on the GPU."""
+    wl = W.poisson_workload("p", 40, 48, W.gaussian_kernel(5, 1.0), 40, 8, 4, 16, 0, 40, 10, 13,
+                            bias_scale=0.05)
+    say("case Poisson free-running 40 steps")
+    oc = O.Chain.from_workload(wl, block=0)
+    ctx = P.Context(P.Config.from_workload(wl))
+    oc.step(40)
+    ctx.step(40)
+    assert ctx.sync() == P.PNPULA_OK
+    xg, _ = ctx.get_state()
+    xo, _ = oc.get_state()
+    z1, z2 = ctx.get_z()
+    e = rel(xg, xo)
+    say(f"  free-running rel after 40 steps {e:.2e}")
+    assert z1.min() >= 0 and z2.min() >= 0
+    assert e <= 1e-3
+    mg, vg, n = ctx.stats()
+    mo, m2o, no = oc.stats()
+    assert n == no == 30
+    assert rel(mg, mo) <= 1e-3
+
+
+# --------------------------------------------------------------------- TV
+@pytest.mark.parametrize("mask_p,beta", [(None, 40.0), (0.7, 400.0)])
+def test_tv_step_parity(mask_p, beta):
+    wl = W.tv_workload("t", 47, 75, W.gaussian_kernel(5, 1.0), 0.05, 24, 4, 10, 2, 9,
+                       beta=beta, mask_p=mask_p)
+    x0 = np.clip(wl.xbar + 0.05 * np.random.default_rng(5).standard_normal(wl.xbar.shape),
+                 0, 1)
+    ctx, oc = _parity(wl, 10, f"TV beta={beta} mask={mask_p}", zstate=True, x0=x0)
+    x, _ = ctx.get_state()
+    assert x.min() >= 0.0
+
+
+def test_tv_prox_zeroes_pairs_on_gpu():
+    wl = W.tv_workload("t", 24, 20, W.gaussian_kernel(5, 1.0), 0.05, 24, 4, 30, 5, 9,
+                       beta=4000.0)
+    ctx = P.Context(P.Config.from_workload(wl))
+    ctx.step(30)
+    assert ctx.sync() == P.PNPULA_OK
+    zh, zv = ctx.get_z()
+    x, _ = ctx.get_state()
+    assert x.min() >= 0.0
+    assert np.mean((zh == 0) & (zv == 0)) > 0.1
+
+
+# ------------------------------------------------------------------- DDFB
+@pytest.mark.parametrize("K,F,shape", [(4, 64, (61, 95)), (3, 6, (37, 29)), (8, 16, (64, 64))])
+def test_ddfb_denoiser_matches_oracle(K, F, shape):
+    """G = x - D(x) of the DDFB stages against the oracle's D, FP32 bar."""
+    ny, nx = shape
+    say(f"case DDFB denoiser K={K} F={F} {ny}x{nx}")
+    wl = W.ddfb_workload("d", ny, nx, 5, 1.0, 0.05, max(ny, nx), 2 * K, 1, 0, 5, n_layers=K,
+                         features=F)
+    ctx = P.Context(P.Config.from_workload(wl))
+    rng = np.random.default_rng(K)
+    x = np.clip(wl.xbar + 0.1 * rng.standard_normal(wl.xbar.shape), -0.2, 1.2)
+    G = ctx.denoise(x.astype(np.float32))
+    D = O.ddfb(O.Ddfb(wl.ddfb_weights, wl.ddfb_gamma, wl.ddfb_thresh),
+               x.astype(np.float32).astype(np.float64))
+    ref = x.astype(np.float32).astype(np.float64) - D
+    e = rel(G, ref)
+    say(f"  rel {e:.2e} (|G| {np.linalg.norm(ref):.2e})")
+    assert np.linalg.norm(ref) > 1e-3 * np.linalg.norm(x)
+    assert e <= TOL
+
+
+def test_ddfb_step_parity():
+    wl = W.ddfb_workload("d", 66, 71, 5, 1.0, 0.05, 33, 8, 8, 2, 7, n_layers=4, features=64,
+                         mask_p=0.8)
+    x0 = np.clip(wl.xbar + 0.05 * np.random.default_rng(6).standard_normal(wl.xbar.shape),
+                 0, 1)
+    _parity(wl, 8, "DDFB chain", x0=x0)
+
+
+# ------------------------------------------------------------ large blurs
+@pytest.mark.parametrize("L,split,mask_p", [(65, True, 0.5), (129, False, None),
+                                            (33, True, None)])
+def test_large_blur_step_parity(L, split, mask_p):
+    ny, nx = (150, 170) if L < 129 else (140, 150)
+    wl = W.make_workload("b", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=max(ny, nx),
+                         halo=L - 1, n_layers=4, features=16, precision=0, iters=6, burn_in=1,
+                         seed=17, bias_scale=0.05, mask_p=mask_p, split=split)
+    k = W.motion_blur_kernel(L, seed=L)
+    wl.kernel = k
+    wl.y = W.observe(wl.xbar, k, wl.sigma, wl.mask, 18)
+    x0 = np.clip(wl.xbar + 0.05 * np.random.default_rng(7).standard_normal(wl.xbar.shape),
+                 0, 1)
+    _parity(wl, 4, f"motion blur {L}x{L} split={split} mask={mask_p}", x0=x0)
+
+
+def test_large_blur_poisson_step_parity():
+    k = W.motion_blur_kernel(41, seed=41)
+    wl = W.poisson_workload("p", 96, 110, k, 110, 40, 4, 16, 0, 4, 1, 19, bias_scale=0.05)
+    x0 = np.clip(wl.xbar + 0.05 * np.random.default_rng(8).standard_normal(wl.xbar.shape),
+                 0, 1)
+    _parity(wl, 4, "Poisson with a 41x41 motion blur", zstate=True, x0=x0)
+
+
+# ------------------------------------------------ device inputs and outputs
+def test_device_inputs_and_device_stats():
+    import torch
+    wl = W.config(1, ny=48, nx=40, block=24, halo=8, mask_p=0.5, bias_scale=0.05)
+    x0 = np.random.default_rng(9).random((48, 40)).astype(np.float32)
+    say("case device inputs vs host inputs, device stats")
+    host = P.Context(P.Config.from_workload(wl, x0=x0))
+    dev = torch.device("cuda:0")
+    ty = torch.from_numpy(np.ascontiguousarray(wl.y, np.float32)).to(dev)
+    tk = torch.from_numpy(np.ascontiguousarray(wl.kernel, np.float32)).to(dev)
+    tm = torch.from_numpy(np.ascontiguousarray(wl.mask, np.uint8)).to(dev)
+    tx = torch.from_numpy(x0).to(dev)
+    torch.cuda.synchronize()
+    dctx = P.Context(P.Config.from_workload(wl, y=ty, kernel=tk, mask=tm, x0=tx))
+    host.step(30)
+    dctx.step(30)
+    a, _ = host.get_state()
+    b, _ = dctx.get_state()
+    assert np.array_equal(a, b)
+    mh, vh, nh = host.stats()
+    tmean = torch.empty((48, 40), dtype=torch.float32, device=dev)
+    tvar = torch.empty((48, 40), dtype=torch.float32, device=dev)
+    n = dctx.stats_device(tmean, tvar)
+    assert n == nh
+    assert np.array_equal(tmean.cpu().numpy(), mh) and np.array_equal(tvar.cpu().numpy(), vh)
