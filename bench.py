@@ -49,6 +49,11 @@ def parse():
     ap.add_argument("--leg-jobs", type=int, default=32)
     ap.add_argument("--leg-iters-scale", type=float, default=0.05)
     ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the pass over the paper's other data terms and priors")
+    ap.add_argument("--next-steps", type=int, default=5)
+    ap.add_argument("--only-next", default=None,
+                    help="run only this row of the pass (poisson, tv, ddfb, blur65, blur129)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (three times): the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -114,7 +119,8 @@ def fp8_scales(ctx_fp32, wl, x):
             for a, f in zip(amax, fmt)]
 
 
-def run_gpu(wl, precision, steps, warmup, stream, act_scales=None, profile=True):
+def run_gpu(wl, precision, steps, warmup, stream, act_scales=None, profile=True,
+            classes=range(7)):
     import torch
     from paper_2511_00870_amd import pnpula as P
     cfg = P.Config.from_workload(wl, precision=precision, act_scales=act_scales, stream=stream)
@@ -131,9 +137,108 @@ def run_gpu(wl, precision, steps, warmup, stream, act_scales=None, profile=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rc = ctx.sync()
-    prof = {c: ctx.profile_read(c) for c in range(7)} if profile else None
+    prof = {c: ctx.profile_read(c) for c in classes} if profile else None
     ctx.close()
     return dt, rc, prof
+
+
+# kernels of the other data terms and priors, per profiler class: class 7
+# is the prior other than the CNN (TV coupling term or the DDFB stages),
+# class 8 the z-steps, class 9 the large-blur correlation passes, class 3
+# the update
+def next_workloads(rows=None):
+    """The paper's other data terms and priors at 4096^2 (Sec. III-A2, III-A3,
+    III-B, II-B1 Example 3), each with its own dominant kernel."""
+    from paper_2511_00870_amd import workloads as W
+    n = 4096
+    out = {}
+    want = (lambda k: rows is None or k == rows)
+    if want("poisson"):
+        out["poisson"] = W.poisson_workload("4096x4096 Poisson deconvolution (eta 250, PSGLA z1 KL "
+                                            "+ z2 on R+), blur 9, 8x64 bf16 CNN", n, n,
+                                            W.gaussian_kernel(9, 2.0), 512, 8, 8, 64, 1, 2000,
+                                            200, 6000)
+    if want("tv"):
+        out["tv"] = W.tv_workload("4096x4096 TV prior (AXDA-PSGLA, beta 40), blur 9", n, n,
+                                  W.gaussian_kernel(9, 2.0), 0.02, 512, 8, 2000, 200, 7000)
+    if want("ddfb"):
+        out["ddfb"] = W.ddfb_workload("4096x4096 DDFB denoiser K=4 F=64, blur 9", n, n, 9, 2.0,
+                                      0.02, 512, 8, 2000, 200, 8000, n_layers=4, features=64)
+    for L in (65, 129):
+        key = f"blur{L}"
+        if not want(key):
+            continue
+        wl = W.make_workload(f"4096x4096 motion blur {L}x{L} (non-separable), 8x64 bf16 CNN",
+                             n, n, L=5, sigma_k=1.0, sigma=0.02, block=n, halo=L - 1,
+                             n_layers=8, features=64, precision=1, iters=2000, burn_in=200,
+                             seed=9000 + L)
+        k = W.motion_blur_kernel(L, seed=L)
+        wl.kernel = k
+        wl.y = W.observe(wl.xbar, k, wl.sigma, None, 9001 + L)
+        out[key] = wl
+    return out
+
+
+def next_rows(a, stream):
+    """Throughput of each of the other rows at 4096^2 and the roofline of
+    the kernel class that row adds: HBM for the TV and z-step kernels (their
+    algorithmic bytes per pixel), vector ALU for the DDFB stages and the
+    large-blur correlations (their algorithmic flops per pixel)."""
+    res = {}
+    for key, wl in next_workloads(a.only_next).items():
+        npx = wl.ny * wl.nx
+        try:
+            dt, rc, prof = run_gpu(wl, wl.precision, a.next_steps, 1, stream, None,
+                                   classes=range(10))
+        except Exception as e:  # report, do not hide
+            res[key] = {"error": str(e)}
+            continue
+        r = {"workload": wl.name, "value": round(npx * a.next_steps / dt / 1e6, 2),
+             "unit": "Mpixel*iter/s", "ms_per_step": round(dt / a.next_steps * 1e3, 4),
+             "status": rc,
+             "kernel_ms_per_step": {n: round(prof[c][0] / a.next_steps, 4) for c, n in
+                                    [(3, "update"), (6, "conv_pair"), (4, "conv_first_mid"),
+                                     (5, "conv_mid_last"), (2, "conv_last"),
+                                     (7, "prior"), (8, "z_step"), (9, "blur_passes")]
+                                    if prof[c][1]}}
+        def avg(c):
+            return prof[c][0] / prof[c][1] / 1e3
+        if key == "tv":
+            # prior term: x read 4 + zh, zv read 8 + G write 4; z-step: x 4 + z r/w 16
+            r["roofline"] = {"bound": "hbm", "kernel": "tv_prior_kernel",
+                             "achieved": round(16 * npx / avg(7) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": round(16 * npx / avg(7) / 1e9 / PEAK_HBM_GBS, 4),
+                             "avg_launch_ms": round(avg(7) * 1e3, 4), "bytes_per_launch": 16 * npx}
+            r["roofline_z_step"] = {"bound": "hbm", "kernel": "zstep_tv_kernel",
+                                    "achieved": round(20 * npx / avg(8) / 1e9, 1),
+                                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                    "frac": round(20 * npx / avg(8) / 1e9 / PEAK_HBM_GBS, 4),
+                                    "avg_launch_ms": round(avg(8) * 1e3, 4),
+                                    "bytes_per_launch": 20 * npx}
+        elif key == "poisson":
+            # z-step: x 4 + y 4 + z1, z2 read + write 16
+            r["roofline"] = {"bound": "hbm", "kernel": "zstep_psgla_kernel",
+                             "achieved": round(24 * npx / avg(8) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": round(24 * npx / avg(8) / 1e9 / PEAK_HBM_GBS, 4),
+                             "avg_launch_ms": round(avg(8) * 1e3, 4), "bytes_per_launch": 24 * npx}
+        elif key == "ddfb":
+            K, F = len(wl.ddfb_gamma), wl.ddfb_weights.shape[1]
+            fl = 2.0 * 2 * K * 9 * F * npx        # K forward + K adjoint convolutions
+            per_iter = prof[7][0] / a.next_steps / 1e3
+            r["roofline"] = {"bound": "alu", "kernel": "ddfb_stage_kernel (all K stages)",
+                             "achieved": round(fl / per_iter / 1e12, 2), "peak": 157.3,
+                             "unit": "TFLOP/s", "frac": round(fl / per_iter / 1e12 / 157.3, 4),
+                             "ms_per_iteration": round(per_iter * 1e3, 4),
+                             "flops_per_iteration": fl}
+        else:
+            L = wl.kernel.shape[0]
+            fl = 2.0 * L * L * npx                # one correlation pass
+            r["roofline"] = {"bound": "alu", "kernel": f"blur_big_kernel ({L}x{L})",
+                             "achieved": round(fl / avg(9) / 1e12, 2), "peak": 157.3,
+                             "unit": "TFLOP/s", "frac": round(fl / avg(9) / 1e12 / 157.3, 4),
+                             "avg_launch_ms": round(avg(9) * 1e3, 4), "flops_per_launch": fl}
+        res[key] = r
+    return res
 
 
 def cpu_baseline(wl, region):
@@ -224,6 +329,9 @@ def main():
     if a.serving:
         print(json.dumps(serving(a, stream)), flush=True)
         return
+    if a.only_next:
+        print(json.dumps(next_rows(a, stream)), flush=True)
+        return
     wl = W.config(a.config)
     prec = wl.precision if a.precision is None else a.precision
     npx = wl.ny * wl.nx
@@ -308,6 +416,8 @@ def main():
         out["serving"] = {k: sv[k] for k in ("value", "unit", "p50_latency_s", "p99_latency_s",
                                              "makespan_s")}
         out["serving"]["workload"] = sv["config"]["workload"]
+    if not a.no_next:
+        out["next_rows"] = next_rows(a, stream)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_region)
     print(json.dumps(out), flush=True)

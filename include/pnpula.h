@@ -179,6 +179,16 @@ pnpula_status pnpula_set_state(pnpula_ctx *ctx, const float *x, int64_t t);
 pnpula_status pnpula_restore(pnpula_ctx *ctx, const float *x, int64_t t, const double *mean,
                              const double *m2, int64_t n_samples);
 
+/* Gradient of the Gaussian data-fidelity term at an arbitrary image x:
+ *   g = H^T (H x - y) / sigma^2,   H = diag(m) K
+ * (Eq. (potential_gaussian_likelihood); Sec. III-A1, III-A2) for the
+ * context's observation y, blur K (any size up to 129 x 129) and mask m,
+ * whatever the context's splitting.  x and g: host arrays of ny*nx floats.
+ * Runs as two whole-image correlation passes (residual, then adjoint) on the
+ * context's stream through device buffers allocated for the call; returns
+ * after g is written.  PNPULA_ESTATE for a Poisson chain. */
+pnpula_status pnpula_data_grad(pnpula_ctx *ctx, const float *x, float *g);
+
 /* Splitting variables held as chain state (PSGLA z-steps, Eq.
  * (sgs_pnp_ula_psgla:psgla); TV: z = (zh, zv) ~ D x, Sec. III-B2): z1 and z2
  * (ny*nx each; either may be NULL) of the current iterate.  PNPULA_ESTATE

@@ -135,6 +135,29 @@ pnpula_status pnpula_restore(pnpula_ctx *c, const float *x, int64_t t, const dou
   return report(c, s);
 }
 
+pnpula_status pnpula_data_grad(pnpula_ctx *c, const float *x, float *g) {
+  GUARD(c);
+  if (!x || !g) return report(c, Status::fail(PNPULA_EINVAL, "x and g are required"));
+  const size_t bytes = (size_t)c->job->d.ny * c->job->d.nx * sizeof(float);
+  float *buf = nullptr;                       // x, residual, g
+  if (hipMalloc(&buf, 3 * bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return report(c, Status::fail(PNPULA_ENOMEM, "device allocation failed"));
+  }
+  const size_t n = bytes / sizeof(float);
+  hipStream_t st = c->eng.stream;
+  Status s = Status::ok();
+  if (hipMemcpyAsync(buf, x, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    s = Status::fail(PNPULA_EDEVICE, "copy of x failed");
+  if (s.good()) s = c->eng.data_grad(c->job, buf, buf + 2 * n, buf + n);
+  if (s.good() && (hipMemcpyAsync(g, buf + 2 * n, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                   hipStreamSynchronize(st) != hipSuccess))
+    s = Status::fail(PNPULA_EDEVICE, "data gradient failed");
+  hipStreamSynchronize(st);
+  hipFree(buf);
+  return report(c, s);
+}
+
 pnpula_status pnpula_get_z(pnpula_ctx *c, float *z1, float *z2) {
   GUARD(c);
   return report(c, c->eng.get_z(c->job, z1, z2));

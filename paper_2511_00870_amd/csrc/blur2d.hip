@@ -24,34 +24,24 @@ constexpr int kBThreads = 256;
 typedef float b_f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int blur_ww(int kpitch) { return kUpdTileW + kpitch + 8; }
-}  // namespace
 
-__global__ __launch_bounds__(kBThreads) void blur_big_kernel(BlurArgs a) {
-  extern __shared__ __attribute__((aligned(16))) float sw[];
-  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
-  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
-  const int64_t t = a.tick + j.t_offset;
-  const int r = j.r, L = 2 * r + 1, Lp = j.kpitch;
+// acc[o] = sum_{a,b} kc[a][b] win(ti + a, c0 + o + b), o = 0..7, for the
+// thread's row ti = tid / 8 and columns c0 = 8 (tid % 8) of a 32 x 64 output
+// tile; the window (32 + 2r) x (64 + 2r) starts r rows / columns before the
+// tile and is filled by load(Y, X) (global coordinates), zero beyond it
+template <class Load>
+__device__ __forceinline__ void corr_tile(float *sw, const PNP_CONST TileRef &tl, int r, int Lp,
+                                          const PNP_CONST float *kc, Load load, float acc[8]) {
   constexpr int TH = kUpdTileH, TW = kUpdTileW;
+  const int L = 2 * r + 1;
   const int WH = TH + 2 * r, WWp = blur_ww(Lp), WV = TW + 2 * r;
   const int tid = threadIdx.x;
-  const int epi = a.epi;
-  // window of the input, zero beyond its valid columns
-  {
-    const bool from_res = epi == EPI_GRAD;
-    const PNP_GLOBAL float *src = from_res ? gp(j.res) : gp(j.x[t & 1]);
-    const int64_t pitch = from_res ? j.rpitch : (int64_t)j.xpitch;
-    const int off = from_res ? r : j.xborder;       // zero border of the source
-    for (int q = tid; q < WH * WWp; q += kBThreads) {
-      const int i = q / WWp, c = q % WWp;
-      const int Y = tl.y0 - r + i, X = tl.x0 - r + c;
-      sw[q] = c < WV ? src[(int64_t)(Y + off) * pitch + (X + off)] : 0.0f;
-    }
+  for (int q = tid; q < WH * WWp; q += kBThreads) {
+    const int i = q / WWp, c = q % WWp;
+    sw[q] = c < WV ? load(tl.y0 - r + i, tl.x0 - r + c) : 0.0f;
   }
   __syncthreads();
-  const PNP_CONST float *kc = cp(j.kbig[epi == EPI_GRAD ? 1 : 0]);
   const int ti = tid >> 3, c0 = 8 * (tid & 7);
-  float acc[8];
 #pragma unroll
   for (int o = 0; o < 8; ++o) acc[o] = 0.0f;
   for (int ka = 0; ka < L; ++ka) {
@@ -75,6 +65,27 @@ __global__ __launch_bounds__(kBThreads) void blur_big_kernel(BlurArgs a) {
       }
     }
   }
+}
+}  // namespace
+
+__global__ __launch_bounds__(kBThreads) void blur_big_kernel(BlurArgs a) {
+  extern __shared__ __attribute__((aligned(16))) float sw[];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+  const int64_t t = a.tick + j.t_offset;
+  const int r = j.r;
+  const int epi = a.epi;
+  float acc[8];
+  {
+    // the sources carry a zero border: the residual of r, x of xborder
+    const bool from_res = epi == EPI_GRAD;
+    const PNP_GLOBAL float *src = from_res ? gp(j.res) : gp(j.x[t & 1]);
+    const int64_t pitch = from_res ? j.rpitch : (int64_t)j.xpitch;
+    const int off = from_res ? r : j.xborder;
+    corr_tile(sw, tl, r, j.kpitch, cp(j.kbig[from_res ? 1 : 0]),
+              [&](int Y, int X) { return src[(int64_t)(Y + off) * pitch + (X + off)]; }, acc);
+  }
+  const int ti = threadIdx.x >> 3, c0 = 8 * (threadIdx.x & 7);
   if (ti >= tl.h) return;
   const int Y = tl.y0 + ti;
   const int B = j.xborder;
@@ -107,6 +118,52 @@ __global__ __launch_bounds__(kBThreads) void blur_big_kernel(BlurArgs a) {
       gp(j.res)[pr] = res;
     }
   }
+}
+
+// The data-fidelity gradient of an arbitrary image x (compact ny*nx, zero
+// outside the image): epi 0: res = m (K x - y) into a compact buffer; epi 1:
+// g = K^T res / sigma^2.  One job, its update tiles.
+__global__ __launch_bounds__(kBThreads) void data_grad_kernel(GradArgs a) {
+  extern __shared__ __attribute__((aligned(16))) float sw[];
+  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
+  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+  const int r = j.r, ny = j.ny, nx = j.nx;
+  const PNP_GLOBAL float *src = gp(a.epi == 0 ? a.x : a.res);
+  float acc[8];
+  corr_tile(sw, tl, r, j.kpitch, cp(j.kbig[a.epi == 0 ? 0 : 1]),
+            [&](int Y, int X) {
+              return (Y >= 0 && Y < ny && X >= 0 && X < nx) ? src[(int64_t)Y * nx + X] : 0.0f;
+            },
+            acc);
+  const int ti = threadIdx.x >> 3, c0 = 8 * (threadIdx.x & 7);
+  if (ti >= tl.h) return;
+  const int Y = tl.y0 + ti;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    if (c0 + o >= tl.w) break;
+    const int X = tl.x0 + c0 + o;
+    const int64_t p = (int64_t)Y * nx + X;
+    if (a.epi == 0) {
+      const int64_t pp = (int64_t)(Y + j.xborder) * j.xpitch + (X + j.xborder);
+      const float mv = j.has_mask ? (float)gp(j.mask)[pp] : 1.0f;
+      gp(a.res)[p] = mv * (acc[o] - gp(j.y)[pp]);
+    } else {
+      gp(a.g)[p] = acc[o] * j.inv_sig2;
+    }
+  }
+}
+
+hipError_t launch_data_grad(const GradArgs &a, int n_tiles, int r, int kpitch, hipStream_t s) {
+  const size_t lds = blur_big_lds_bytes(r, kpitch);
+  static size_t attr = 0;
+  if (lds > attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&data_grad_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = lds;
+  }
+  hipLaunchKernelGGL(data_grad_kernel, dim3(n_tiles), dim3(kBThreads), lds, s, a);
+  return hipGetLastError();
 }
 
 size_t blur_big_lds_bytes(int r, int kpitch) {

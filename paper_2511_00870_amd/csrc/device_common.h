@@ -64,7 +64,7 @@ struct JobDesc {
   float inv_s2;            // 1/sigma^2 (rho == 0) or 1/rho
   float zmix;              // rho / (rho + sigma^2): Hx - z = zmix (Hx - y) - zsd zeta
   float zsd;               // sqrt(rho sigma^2 / (rho + sigma^2))
-  float pad1;
+  float inv_sig2;          // 1/sigma^2 (the data-gradient entry point)
   uint32_t key0, key1, chain, pad2;
   // ---- splitting variables held as chain state, and the other priors ----
   // zmode 1: PSGLA z-steps (Eq. (sgs_pnp_ula_psgla:psgla)): z1 ~ eta m K x with

@@ -106,6 +106,7 @@ class Engine {
   Status denoise_stages(Job *j, const float *x, float *G, int32_t *n_stages,
                         int32_t *stage_layer, float *stage_acts);
   Status read_act(Job *j, int k, int slot, float *dst);
+  Status data_grad(Job *j, const float *x, float *g, float *res);
   Status get_z(Job *j, float *z1, float *z2);
   Status set_z(Job *j, const float *z1, const float *z2);
   Status stats_device(Job *j, float *mean, float *var, int64_t *n);

@@ -642,9 +642,9 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   d.kern = kd;
   d.ku = kd + L * L;
   d.kv = kd + 2 * L * L;
-  if (d.big) {
-    // correlation kernels of the whole-image passes: flip(k) for K x, k for
-    // K^T r; residual buffer with a zero border of r; the gradient
+  {
+    // correlation kernels of the whole-image passes (large blurs, the
+    // data-gradient entry point): flip(k) for K x, k for K^T r
     const int Lp = kbig_pitch(L);
     std::vector<float> kb((size_t)2 * L * Lp, 0.f);
     for (int a = 0; a < L; ++a)
@@ -660,15 +660,18 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
     d.kbig[0] = kbd;
     d.kbig[1] = kbd + (size_t)L * Lp;
     d.kpitch = Lp;
+    // the host copy kb must outlive the asynchronous upload
+    if (hipStreamSynchronize(stream) != hipSuccess)
+      return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
+  }
+  if (d.big) {
+    // residual buffer with a zero border of r, and the gradient
     d.rpitch = res_pitch(nx, r);
     const size_t rbytes = (size_t)res_rows(ny, r) * d.rpitch * sizeof(float);
     if (!(s = dalloc(j, &d.res, rbytes)).good()) return fail(s);
     if (hipMemsetAsync(d.res, 0, rbytes, stream) != hipSuccess)
       return fail(Status::fail(PNPULA_EDEVICE, "memset"));
     if (!(s = dalloc(j, &d.gdat, N * sizeof(float))).good()) return fail(s);
-    // the host copy kb must outlive the asynchronous upload
-    if (hipStreamSynchronize(stream) != hipSuccess)
-      return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
   }
   // coefficients (FP64, rounded once)
   const double sig2 = c->sigma * c->sigma;
@@ -677,6 +680,7 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   d.cproj = (float)(c->delta * c->inv_lambda);
   d.sq2d = (float)std::sqrt(2.0 * c->delta);
   d.inv_s2 = (float)(c->rho > 0 ? 1.0 / c->rho : 1.0 / sig2);
+  d.inv_sig2 = (float)(1.0 / sig2);
   d.zmix = (float)(c->rho > 0 ? c->rho / (c->rho + sig2) : 0.0);
   d.zsd = (float)(c->rho > 0 ? std::sqrt(c->rho * sig2 / (c->rho + sig2)) : 0.0);
   const double eta = c->eta > 0 ? c->eta : 1.0;
@@ -1335,6 +1339,26 @@ Status Engine::restore_stats(Job *j, const double *mean, const double *m2, int64
   d.nbase = n;
   d.wbase = samples_at(j, j->t);
   TRY(upload_descs());
+  return Status::ok();
+}
+
+// g = H^T (H x - y) / sigma^2 for device images x, g (ny*nx) through the
+// device residual buffer res (ny*nx); queued on the stream, no allocation.
+Status Engine::data_grad(Job *j, const float *x, float *g, float *res) {
+  if (plan_dirty || resident.size() != 1 || resident[0] != j)
+    return Status::fail(PNPULA_ESTATE, "the data gradient needs a single-job engine");
+  if (j->d.poisson) return Status::fail(PNPULA_ESTATE, "the data term is not Gaussian");
+  GradArgs a{};
+  a.jobs = d_jobs;
+  a.tiles = d_upd;
+  a.n_tiles = n_upd;
+  a.x = x;
+  a.res = res;
+  a.g = g;
+  for (int epi = 0; epi < 2; ++epi) {
+    a.epi = epi;
+    HIPOK(launch_data_grad(a, n_upd, j->d.r, j->d.kpitch, stream));
+  }
   return Status::ok();
 }
 

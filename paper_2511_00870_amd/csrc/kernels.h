@@ -67,6 +67,17 @@ struct BlurArgs {
   int64_t tick;
 };
 
+// data-fidelity gradient of a given image (compact ny x nx buffers)
+struct GradArgs {
+  const JobDesc *jobs;
+  const TileRef *tiles;        // the job's update tiles
+  int32_t n_tiles;
+  int32_t epi;                 // 0: res = m (K x - y); 1: g = K^T res / sigma^2
+  const float *x;
+  float *res;
+  float *g;
+};
+
 struct UpdateArgs {
   const JobDesc *jobs;
   const TileRef *tiles;
@@ -137,6 +148,7 @@ hipError_t launch_ddfb_stage(const DdfbArgs &a, int n_tiles, hipStream_t s);
 // large blur (half-width max_r > kMaxR)
 hipError_t launch_blur_big(const BlurArgs &a, int n_tiles, int max_r, int kpitch, hipStream_t s);
 size_t blur_big_lds_bytes(int r, int kpitch);
+hipError_t launch_data_grad(const GradArgs &a, int n_tiles, int r, int kpitch, hipStream_t s);
 hipError_t launch_amax(const float *p, size_t n, uint32_t *out, hipStream_t s);
 hipError_t launch_stats_out(const JobDesc &j, int64_t n, float *mean, float *var, hipStream_t s);
 hipError_t launch_welford_flush(const JobDesc &j, double n_a, double n_b, hipStream_t s);

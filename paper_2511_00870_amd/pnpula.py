@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE"
 EXPORTS = [
     "pnpula_create", "pnpula_step", "pnpula_sync", "pnpula_stats", "pnpula_stats_f64",
     "pnpula_get_state", "pnpula_set_state", "pnpula_restore", "pnpula_get_z", "pnpula_set_z",
-    "pnpula_stats_device", "pnpula_denoise",
+    "pnpula_stats_device", "pnpula_data_grad", "pnpula_denoise",
     "pnpula_denoise_stages",
     "pnpula_calibrate", "pnpula_profile", "pnpula_profile_read", "pnpula_state_device",
     "pnpula_destroy", "pnpula_last_error", "pnpula_create_error", "pnpula_footprint",
@@ -78,6 +78,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_2511_00870_amd.build`")
+        # torch ships its own HIP runtime.  Whichever runtime a process loads
+        # first serves every later library that asks for it by name, and torch
+        # finds no GPU through another build of the runtime: load torch first
+        # so that the library and torch share torch's runtime (device tensors
+        # and streams then pass between them).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         _declare(L)
         _lib = L
@@ -95,6 +104,7 @@ def _declare(L):
     L.pnpula_set_state.argtypes = [vp, _fp, C.c_int64]
     L.pnpula_restore.argtypes = [vp, _fp, C.c_int64, _dp, _dp, C.c_int64]
     L.pnpula_get_z.argtypes = [vp, _fp, _fp]
+    L.pnpula_data_grad.argtypes = [vp, _fp, _fp]
     L.pnpula_set_z.argtypes = [vp, _fp, _fp]
     L.pnpula_stats_device.argtypes = [vp, vp, vp, _i64p]
     L.pnpula_denoise.argtypes = [vp, _fp, _fp, _fp]
@@ -261,6 +271,13 @@ class Context:
     def set_state(self, x, t: int):
         x = _f32(x)
         _check(lib().pnpula_set_state(self.h, _fptr(x), t), self._err)
+
+    def data_grad(self, x):
+        """H^T (H x - y) / sigma^2 of the context's data term at x"""
+        x = _f32(x)
+        g = np.empty((self.ny, self.nx), np.float32)
+        _check(lib().pnpula_data_grad(self.h, _fptr(x), _fptr(g)), self._err)
+        return g
 
     def get_z(self):
         """(z1, z2) of a chain that holds its splitting variables (PSGLA, TV)"""

@@ -42,10 +42,13 @@ def _ulp(v, fmt, scale=1.0):
     return 2.0 ** (np.maximum(e, -6) - 3) * scale
 
 
-# FP32 accumulation slack of one layer's output, relative to the value: the
-# GPU sums 9 F exact products (bf16 x bf16 and e4m3 x e4m3 products are exact
-# in FP32) in its own order, so its pre-rounding value differs from the exact
-# one by a few units in the 24th bit; 1e-5 leaves a wide margin
+# FP32 accumulation slack of one layer's output, relative to the sum of the
+# absolute values of its terms (|W| |input| + |b|): the GPU sums 9 F exact
+# products (bf16 x bf16 and e4m3 x e4m3 products are exact in FP32) in its own
+# order, so its pre-activation value differs from the exact one by a few units
+# in the 24th bit of that sum; 1e-5 leaves a wide margin.  (Relative to the
+# value itself there is no bound: a sum that cancels to near zero, or a ReLU
+# input near zero, carries the absolute error of its terms.)
 ACC_REL = 1e-5
 
 
@@ -123,9 +126,16 @@ def test_fused_launches_teacher_forced(prec, K, shape):
         F = None                          # bound on the quantised input's movement
         for j in range(k0, k1 + 1):
             v = outs[j - k0]
-            e = ACC_REL * np.abs(v)
+            # the layer's input as it multiplies it (rounded to its format)
+            prev = inp if j == k0 else outs[j - 1 - k0]
+            qin = np.abs(_q(prev, fmt[j], scales[j]))
+            if qin.ndim == 2:
+                qin = qin[None]
+            wabs = _abs_layer(ws, fmt, net, j)
+            S = _propagate(qin, wabs) + np.abs(np.asarray(bs[j], np.float64)).reshape(-1, 1, 1)
+            e = ACC_REL * S
             if F is not None:
-                e = e + _propagate(F, _abs_layer(ws, fmt, net, j))
+                e = e + _propagate(F, wabs)
             if j < k1:                    # rounded inside the launch
                 F, _ = _flip_bound(v, fmt[j + 1], scales[j + 1], e)
         ref = outs[-1]

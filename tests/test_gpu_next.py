@@ -218,3 +218,26 @@ def test_device_inputs_and_device_stats():
     n = dctx.stats_device(tmean, tvar)
     assert n == nh
     assert np.array_equal(tmean.cpu().numpy(), mh) and np.array_equal(tvar.cpu().numpy(), vh)
+
+
+# ------------------------------------------------------- data-term gradient
+@pytest.mark.parametrize("L,mask_p,shape", [(9, None, (70, 130)), (65, 0.5, (100, 90)),
+                                            (1, 0.5, (33, 65))])
+def test_data_grad_matches_oracle(L, mask_p, shape):
+    """pnpula_data_grad: H^T (H x - y) / sigma^2 at an arbitrary x against the
+    oracle's direct sums (unsplit data term, Eq. (potential_gaussian_likelihood))."""
+    ny, nx = shape
+    say(f"case data gradient L={L} mask={mask_p} {ny}x{nx}")
+    wl = W.make_workload("g", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=max(ny, nx),
+                         halo=max(L - 1, 4), n_layers=4, features=16, precision=0, iters=1,
+                         burn_in=0, seed=23, mask_p=mask_p, split=False)
+    k = W.motion_blur_kernel(L, seed=L) if L > 1 else np.ones((1, 1))
+    wl.kernel = k
+    wl.y = W.observe(wl.xbar, k, wl.sigma, wl.mask, 24)
+    x = np.random.default_rng(L).random((ny, nx)).astype(np.float32)
+    ctx = P.Context(P.Config.from_workload(wl))
+    g = ctx.data_grad(x)
+    ref = O.Chain.from_workload(wl, block=0).data_grad(x.astype(np.float64), 0)
+    e = rel(g, ref)
+    say(f"  rel {e:.2e}")
+    assert e <= TOL

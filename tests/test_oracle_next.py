@@ -359,3 +359,106 @@ def test_new_modes_blocked_equal_monolithic_bitwise(mode):
     full, _ = mono.get_state()
     reg = mono.step_region(x, t, 5, 3, 20, 17, z=z)
     assert np.array_equal(reg, full[5:25, 3:20])
+
+
+# ------------------------------ one PSGLA step composed from pinned parts
+def _draws(seed, t, shape):
+    """(xi, zeta1, zeta2) of every pixel at counter t from the pinned
+    Philox4x32-10 and Box-Muller primitives (zeta2: the cosine branch of the
+    pair from words w2, w3)."""
+    ny, nx = shape
+    xi, z1, z2 = (np.empty(shape) for _ in range(3))
+    for i in range(ny):
+        for j in range(nx):
+            p = i * nx + j
+            w = O.philox4x32_10([p & 0xffffffff, t, 0, p >> 32],
+                                [seed & 0xffffffff, seed >> 32])
+            xi[i, j], z1[i, j] = O.gauss_pair(int(w[0]), int(w[1]))
+            z2[i, j], _ = O.gauss_pair(int(w[2]), int(w[3]))
+    return xi, z1, z2
+
+
+def test_poisson_psgla_step_composes_pinned_parts():
+    """One step of the Poisson chain (Sec. III-A3; Eq. (sgs_pnp_ula_psgla:psgla)
+    and the z-update of Algorithm 1) against its parts computed outside the
+    oracle's step: scipy's 2-D convolutions for K and K^T, the pinned
+    Philox / Box-Muller draws and the pinned KL prox.  x-step:
+    x' = x - delta (eta K^T m (eta m K x - z1)/rho1 + (x - z2)/rho2) + sqrt(2 delta) xi
+    (no prior: alpha = 0; x inside [0,1], so the projection term vanishes);
+    z-step from x': z1' = prox_KL(z1 - (kappa/rho1)(z1 - eta m K x') + sqrt(2 kappa) zeta1)
+    where observed (identity elsewhere), z2' = max(z2 - (kappa2/rho2)(z2 - x') +
+    sqrt(2 kappa2) zeta2, 0)."""
+    from scipy.signal import correlate2d
+    wl = W.poisson_workload("p", 11, 13, W.gaussian_kernel(5, 1.0), 13, 4, 2, 4, 0, 1, 0, 3,
+                            mask_p=0.6)
+    wl.alpha = 0.0
+    rng = np.random.default_rng(5)
+    x = 0.1 + 0.8 * rng.random((11, 13))
+    z1 = 250 * 0.5 * rng.random((11, 13))
+    z2 = 0.1 + rng.random((11, 13))
+    t = 7
+    ch = O.Chain.from_workload(wl, block=0)
+    ch.set_state(x, t)
+    ch.set_z(z1, z2)
+    ch.step(1)
+    x1, _ = ch.get_state()
+    z1n, z2n = ch.get_z()
+    k, m, eta = wl.kernel, wl.mask.astype(np.float64), wl.eta
+    K = lambda v: convolve2d(v, k, mode="same")
+    KT = lambda v: correlate2d(v, k, mode="same")
+    xi, _, _ = _draws(wl.seed, t, x.shape)
+    g = eta * KT(m * (eta * m * K(x) - z1)) / wl.rho + (x - z2) / wl.rho2
+    x1_ref = x - wl.delta * g + np.sqrt(2 * wl.delta) * xi
+    assert np.max(np.abs(x1 - x1_ref)) <= 1e-12
+    _, ze1, ze2 = _draws(wl.seed, t + 1, x.shape)
+    v = z1 - wl.kappa / wl.rho * (z1 - eta * m * K(x1)) + np.sqrt(2 * wl.kappa) * ze1
+    z1_ref = np.where(m != 0, np.vectorize(O.prox_kl)(v, wl.y, wl.kappa), v)
+    w = z2 - wl.kappa2 / wl.rho2 * (z2 - x1) + np.sqrt(2 * wl.kappa2) * ze2
+    assert np.max(np.abs(z1n - z1_ref)) <= 1e-9 * np.max(np.abs(z1_ref))
+    assert np.max(np.abs(z2n - np.maximum(w, 0.0))) <= 1e-12
+
+
+def test_tv_step_composes_pinned_parts():
+    """One step of the TV chain (Sec. III-B2) against numpy's differences,
+    scipy's convolutions, the pinned draws and the pinned l21 prox:
+    x' = max(x - delta K^T m (m K x - y)/sigma^2 - (delta/rho) D^T (D x - z) + sqrt(2 delta) xi, 0),
+    z' = prox_{kappa beta ||.||}(z - (kappa/rho)(z - D x') + sqrt(2 kappa) zeta)."""
+    from scipy.signal import correlate2d
+    wl = W.tv_workload("t", 10, 12, W.gaussian_kernel(5, 1.0), 0.05, 12, 4, 1, 0, 4,
+                       beta=200.0, mask_p=0.7)
+    rng = np.random.default_rng(6)
+    x = rng.random((10, 12)) - 0.05
+    zh, zv = 0.3 * rng.standard_normal((2, 10, 12))
+    t = 5
+    ch = O.Chain.from_workload(wl, block=0)
+    ch.set_state(x, t)
+    ch.set_z(zh, zv)
+    ch.step(1)
+    x1, _ = ch.get_state()
+    zh1, zv1 = ch.get_z()
+    k, m = wl.kernel, wl.mask.astype(np.float64)
+
+    def D(v):
+        dh = np.zeros_like(v); dh[:, :-1] = np.diff(v, axis=1)
+        dv = np.zeros_like(v); dv[:-1, :] = np.diff(v, axis=0)
+        return dh, dv
+
+    def DT(ah, av):      # adjoint of D, from its definition column by column
+        out = np.zeros_like(ah)
+        out[:, 1:] += ah[:, :-1]; out[:, :-1] -= ah[:, :-1]
+        out[1:, :] += av[:-1, :]; out[:-1, :] -= av[:-1, :]
+        return out
+
+    xi, ze1, ze2 = _draws(wl.seed, t, x.shape)
+    dh, dv = D(x)
+    g = correlate2d(m * (m * convolve2d(x, k, mode="same") - wl.y), k, mode="same") / wl.sigma ** 2
+    v = x - wl.delta * g - wl.delta / wl.rho * DT(dh - zh, dv - zv) + np.sqrt(2 * wl.delta) * xi
+    assert np.max(np.abs(x1 - np.maximum(v, 0.0))) <= 1e-10
+    _, ze1, ze2 = _draws(wl.seed, t + 1, x.shape)
+    dh1, dv1 = D(x1)
+    a = wl.kappa / wl.rho
+    vh = zh - a * (zh - dh1) + np.sqrt(2 * wl.kappa) * ze1
+    vv = zv - a * (zv - dv1) + np.sqrt(2 * wl.kappa) * ze2
+    ref = [O.prox_l21(h, w_, wl.kappa * wl.beta) for h, w_ in zip(vh.ravel(), vv.ravel())]
+    assert np.max(np.abs(zh1.ravel() - np.array([r[0] for r in ref]))) <= 1e-12
+    assert np.max(np.abs(zv1.ravel() - np.array([r[1] for r in ref]))) <= 1e-12
