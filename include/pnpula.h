@@ -189,6 +189,18 @@ pnpula_status pnpula_restore(pnpula_ctx *ctx, const float *x, int64_t t, const d
  * after g is written.  PNPULA_ESTATE for a Poisson chain. */
 pnpula_status pnpula_data_grad(pnpula_ctx *ctx, const float *x, float *g);
 
+/* pnpula_data_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  x and g are DEVICE pointers of ny*nx floats.  The residual
+ * lives in the library's static device buffer of PNPULA_NOALLOC_MAX_PIXELS
+ * floats (32 MiB), one per GPU, held until the process ends; larger images
+ * return PNPULA_EINVAL.  The call allocates nothing and queues its two
+ * passes on the context's stream without synchronising (pnpula_sync waits).
+ * Every call on one GPU shares that buffer: calls that overlap in time on
+ * one GPU (e.g. on two streams) race; serialise them. */
+#define PNPULA_NOALLOC_MAX_PIXELS (1 << 23)
+pnpula_status pnpula_data_grad_noalloc(pnpula_ctx *ctx, const float *x, float *g);
+
 /* Splitting variables held as chain state (PSGLA z-steps, Eq.
  * (sgs_pnp_ula_psgla:psgla); TV: z = (zh, zv) ~ D x, Sec. III-B2): z1 and z2
  * (ny*nx each; either may be NULL) of the current iterate.  PNPULA_ESTATE

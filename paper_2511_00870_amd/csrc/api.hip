@@ -158,6 +158,18 @@ pnpula_status pnpula_data_grad(pnpula_ctx *c, const float *x, float *g) {
   return report(c, s);
 }
 
+pnpula_status pnpula_data_grad_noalloc(pnpula_ctx *c, const float *x, float *g) {
+  GUARD(c);
+  if (!x || !g) return report(c, Status::fail(PNPULA_EINVAL, "x and g are required"));
+  if ((int64_t)c->job->d.ny * c->job->d.nx > pnp::kNoallocMaxPixels)
+    return report(c, Status::fail(PNPULA_EINVAL, "image larger than the static buffer (" +
+                                                     std::to_string(pnp::kNoallocMaxPixels) +
+                                                     " pixels)"));
+  float *res = pnp::noalloc_scratch(c->eng.device);
+  if (!res) return report(c, Status::fail(PNPULA_EDEVICE, "static buffer not set up"));
+  return report(c, c->eng.data_grad(c->job, x, g, res));
+}
+
 pnpula_status pnpula_get_z(pnpula_ctx *c, float *z1, float *z2) {
   GUARD(c);
   return report(c, c->eng.get_z(c->job, z1, z2));

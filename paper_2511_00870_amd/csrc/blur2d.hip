@@ -14,6 +14,8 @@
 // (32 + 2r) x (64 + 2r) pixels; each thread keeps a row of 8 outputs in
 // registers and walks the kernel in chunks of 8 taps (16 window values read
 // as four 16-byte LDS reads, 8 taps from scalar registers, 64 FMAs).
+#include <mutex>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -181,6 +183,36 @@ hipError_t launch_blur_big(const BlurArgs &a, int n_tiles, int max_r, int kpitch
   }
   hipLaunchKernelGGL(blur_big_kernel, dim3(n_tiles), dim3(kBThreads), lds, s, a);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Allocation-free data gradient: the residual of the first pass lives in a
+// static device buffer instead of memory allocated per call.  Each device
+// the library runs on holds its own copy until the process ends; its device
+// address is looked up once per device at context set-up.
+// ---------------------------------------------------------------------
+static __device__ __align__(256) float scratch[kNoallocMaxPixels];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[device] = static_cast<float *>(p);
+  return hipSuccess;
+}
+
+float *noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch[device] : nullptr;
 }
 
 }  // namespace pnp

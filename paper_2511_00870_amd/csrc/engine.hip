@@ -104,6 +104,7 @@ Status Engine::init(void *user_stream) {
     return Status::fail(PNPULA_EDEVICE,
                         std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
   n_cu = prop.multiProcessorCount;
+  HIPOK(noalloc_scratch_init(device));
   if (user_stream) {
     stream = reinterpret_cast<hipStream_t>(user_stream);
     own_stream = false;

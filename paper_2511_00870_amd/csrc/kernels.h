@@ -149,6 +149,11 @@ hipError_t launch_ddfb_stage(const DdfbArgs &a, int n_tiles, hipStream_t s);
 hipError_t launch_blur_big(const BlurArgs &a, int n_tiles, int max_r, int kpitch, hipStream_t s);
 size_t blur_big_lds_bytes(int r, int kpitch);
 hipError_t launch_data_grad(const GradArgs &a, int n_tiles, int r, int kpitch, hipStream_t s);
+// the static residual buffer of the allocation-free data gradient: look up
+// its address on `device` (current) once; then noalloc_scratch(device)
+constexpr int64_t kNoallocMaxPixels = (int64_t)1 << 23;
+hipError_t noalloc_scratch_init(int device);
+float *noalloc_scratch(int device);
 hipError_t launch_amax(const float *p, size_t n, uint32_t *out, hipStream_t s);
 hipError_t launch_stats_out(const JobDesc &j, int64_t n, float *mean, float *var, hipStream_t s);
 hipError_t launch_welford_flush(const JobDesc &j, double n_a, double n_b, hipStream_t s);

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE"
 EXPORTS = [
     "pnpula_create", "pnpula_step", "pnpula_sync", "pnpula_stats", "pnpula_stats_f64",
     "pnpula_get_state", "pnpula_set_state", "pnpula_restore", "pnpula_get_z", "pnpula_set_z",
-    "pnpula_stats_device", "pnpula_data_grad", "pnpula_denoise",
+    "pnpula_stats_device", "pnpula_data_grad", "pnpula_data_grad_noalloc", "pnpula_denoise",
     "pnpula_denoise_stages",
     "pnpula_calibrate", "pnpula_profile", "pnpula_profile_read", "pnpula_state_device",
     "pnpula_destroy", "pnpula_last_error", "pnpula_create_error", "pnpula_footprint",
@@ -105,6 +105,7 @@ def _declare(L):
     L.pnpula_restore.argtypes = [vp, _fp, C.c_int64, _dp, _dp, C.c_int64]
     L.pnpula_get_z.argtypes = [vp, _fp, _fp]
     L.pnpula_data_grad.argtypes = [vp, _fp, _fp]
+    L.pnpula_data_grad_noalloc.argtypes = [vp, vp, vp]
     L.pnpula_set_z.argtypes = [vp, _fp, _fp]
     L.pnpula_stats_device.argtypes = [vp, vp, vp, _i64p]
     L.pnpula_denoise.argtypes = [vp, _fp, _fp, _fp]
@@ -278,6 +279,15 @@ class Context:
         g = np.empty((self.ny, self.nx), np.float32)
         _check(lib().pnpula_data_grad(self.h, _fptr(x), _fptr(g)), self._err)
         return g
+
+    def data_grad_noalloc(self, x, g):
+        """pnpula_data_grad_noalloc on torch device tensors x, g (float32,
+        ny x nx, contiguous); queued on the context's stream"""
+        for v in (x, g):
+            if not _is_device(v) or not v.is_contiguous() or v.numel() != self.ny * self.nx:
+                raise ValueError("x and g must be contiguous device tensors of ny*nx floats")
+        _check(lib().pnpula_data_grad_noalloc(self.h, C.c_void_p(x.data_ptr()),
+                                              C.c_void_p(g.data_ptr())), self._err)
 
     def get_z(self):
         """(z1, z2) of a chain that holds its splitting variables (PSGLA, TV)"""
