@@ -89,6 +89,26 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def recorded_avg_ms(row):
+    """Average launch duration (ms) of the kernel named `row` in the committed
+    rocprofv3 kernel-trace summary, or None when the kernel sources changed
+    since it was taken."""
+    try:
+        with open(PROFILE_MD) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    import re
+    m = re.search(r"`([0-9a-f]{64})`", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    for line in text.splitlines():
+        if f"pnp::{row}(" in line and line.count("|") == 7:
+            cells = [c.strip() for c in line.strip("|").split("|")]
+            return float(cells[2]) / 1e3
+    return None
+
+
 def recorded_traffic(row):
     """HBM bytes per launch of the kernel named `row` from the committed
     FETCH_SIZE / WRITE_SIZE summary (already scaled by the plain-copy factor),
@@ -375,6 +395,13 @@ def main():
                            "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4),
                            "traffic": traffic, "avg_launch_ms": round(avg * 1e3, 4),
                            "flops_per_launch": flops_launch}
+        # the same kernel's average in the committed rocprofv3 summary, and the
+        # fraction it gives (present while the kernel sources are unchanged)
+        pavg = recorded_avg_ms(row) if (a.config == 3 and prec == 1) else None
+        if pavg is not None:
+            out["roofline"]["profile_avg_launch_ms"] = round(pavg, 4)
+            out["roofline"]["profile_frac"] = round(
+                flops_launch / (pavg / 1e3) / 1e12 / PEAK_TFLOPS[prec], 4)
     if upd_n:
         avg = upd_ms / upd_n / 1e3
         byt = fused_update_bytes_per_pixel(True, wl.mask is not None, wl.welford_window) * npx

@@ -154,24 +154,31 @@ typedef struct {
 } pnpula_config;
 
 /* Validate cfg, allocate device memory, upload inputs and repack weights.
- * On success *out holds a context at t = 0. */
+ * On success *out holds a context at t = 0 (the inputs of Algorithm 1: y,
+ * the operator, the step sizes and splitting parameters, x^(0); z^(0) = 0
+ * as in Sec. III-B). */
 pnpula_status pnpula_create(const pnpula_config *cfg, pnpula_ctx **out);
 
-/* Queue n_iters >= 0 iterations x^(t) -> x^(t+1) on the stream (asynchronous). */
+/* Queue n_iters >= 0 iterations x^(t) -> x^(t+1) on the stream (asynchronous):
+ * each is one pass of Algorithm 1 over every block (Eq.
+ * (sgs_pnp_ula_psgla:pnp_ula) for x, Eq. (sgs:marginal_z) or Eq.
+ * (sgs_pnp_ula_psgla:psgla) for z), followed by the statistics update. */
 pnpula_status pnpula_step(pnpula_ctx *ctx, int32_t n_iters);
 
 /* Wait for queued work; PNPULA_EDIVERGED if any sample so far was non-finite. */
 pnpula_status pnpula_sync(pnpula_ctx *ctx);
 
 /* MMSE estimate and pixel variance M2/(n-1) of the samples after burn-in
- * (FP64 merge of the FP32 windows, rounded to FP32).  mean/var may be NULL.
- * n_samples receives n (var is 0 when n < 2). */
+ * (the Monte Carlo estimates of Sec. III-C; FP64 merge of the FP32 windows,
+ * rounded to FP32).  mean/var may be NULL.  n_samples receives n (var is 0
+ * when n < 2). */
 pnpula_status pnpula_stats(pnpula_ctx *ctx, float *mean, float *var, int64_t *n_samples);
 
 /* Same statistics in FP64: mean and the sum of squared deviations M2. */
 pnpula_status pnpula_stats_f64(pnpula_ctx *ctx, double *mean, double *m2, int64_t *n_samples);
 
-/* Checkpoint: the state is (x^(t), t) plus the statistics. */
+/* State of the chain (not a passage of the paper: parity checks and
+ * restarts).  The state is (x^(t), t) plus the statistics. */
 pnpula_status pnpula_get_state(pnpula_ctx *ctx, float *x, int64_t *t);
 /* Replace x and t (statistics are kept). */
 pnpula_status pnpula_set_state(pnpula_ctx *ctx, const float *x, int64_t t);
@@ -214,8 +221,21 @@ pnpula_status pnpula_set_z(pnpula_ctx *ctx, const float *z1, const float *z2);
  * is synchronised before return. */
 pnpula_status pnpula_stats_device(pnpula_ctx *ctx, float *mean, float *var, int64_t *n_samples);
 
+/* Checkpoint of the whole chain state, for a resume that continues bit for
+ * bit as if the chain had never stopped (the statistics' merge schedule
+ * included): x^(t) and t, the splitting variables held as state, the FP32
+ * Welford window as it stands and the FP64 statistics merged so far, in one
+ * opaque host buffer of pnpula_checkpoint_size bytes.  Taking a checkpoint
+ * does not change the chain. */
+pnpula_status pnpula_checkpoint_size(pnpula_ctx *ctx, size_t *bytes);
+pnpula_status pnpula_checkpoint(pnpula_ctx *ctx, void *buf, size_t bytes);
+/* Load a checkpoint taken from a context of the same configuration (image
+ * size, z-step and prior; PNPULA_EINVAL otherwise). */
+pnpula_status pnpula_resume(pnpula_ctx *ctx, const void *buf, size_t bytes);
+
 /* Apply the context's denoiser to an ny*nx image: G = x - D_eps(x) (FP32
- * output).  layers (optional) receives every layer's output, dequantised
+ * output; Sec. II-B1, Eqs. (feedforward_cnn), (cnn:convolution), Example 2,
+ * or the DDFB denoiser of Example 3).  layers (optional) receives every layer's output, dequantised
  * to FP32, as channels[k+1] planes of ny*nx per layer (CHW), concatenated. */
 pnpula_status pnpula_denoise(pnpula_ctx *ctx, const float *x, float *G, float *layers);
 
@@ -234,10 +254,12 @@ pnpula_status pnpula_denoise_stages(pnpula_ctx *ctx, const float *x, float *G, i
                                     int32_t *stage_layer, float *stage_acts);
 
 /* Largest |input| of every layer when the denoiser (in FP32) is applied to
- * x: the data for choosing e4m3 activation scales. */
+ * x: the data for choosing e4m3 activation scales (not in the paper: the
+ * low-precision form). */
 pnpula_status pnpula_calibrate(pnpula_ctx *ctx, const float *x, float *amax);
 
-/* Per-kernel timing with HIP events on the context's stream.  Classes:
+/* Per-kernel timing with HIP events on the context's stream (measurement,
+ * not in the paper).  Classes:
  * 0 = middle convolution layers, 1 = first layer, 2 = last layer,
  * 3 = fused likelihood/update/statistics kernel, 4 = first layer fused with
  * the first middle layer, 5 = last middle layer writing the last layer's
@@ -245,13 +267,16 @@ pnpula_status pnpula_calibrate(pnpula_ctx *ctx, const float *x, float *amax);
  * sums the partials into G), 6 = two consecutive middle layers in one
  * kernel (bf16 and e4m3 networks; for e4m3 the first pair also runs the first
  * layer and the last pair the last layer's partials, class 2 again timing the
- * sums).  Enabling resets totals. */
+ * sums), 7 = the prior term of the TV and DDFB chains (TV coupling term;
+ * each DDFB stage), 8 = the z-steps held as state (PSGLA, TV), 9 = the
+ * whole-image correlation passes of large blurs.  Enabling resets totals. */
 pnpula_status pnpula_profile(pnpula_ctx *ctx, int32_t enable);
 pnpula_status pnpula_profile_read(pnpula_ctx *ctx, int32_t kernel_class, double *total_ms,
                                   int64_t *launches);
 
 /* Device pointer of the current x^(t) (padded layout: row pitch in floats
- * in *pitch, image origin at element *offset), for zero-copy consumers. */
+ * in *pitch, image origin at element *offset), for zero-copy consumers (not
+ * in the paper). */
 pnpula_status pnpula_state_device(pnpula_ctx *ctx, const float **base, int64_t *pitch,
                                   int64_t *offset);
 
@@ -259,7 +284,8 @@ void pnpula_destroy(pnpula_ctx *ctx);
 const char *pnpula_last_error(const pnpula_ctx *ctx);
 const char *pnpula_create_error(void);
 
-/* Device memory one context of this configuration allocates (bytes). */
+/* Device memory one context of this configuration allocates (bytes); the
+ * serving admission test (not in the paper). */
 pnpula_status pnpula_footprint(const pnpula_config *cfg, size_t *bytes);
 
 /* ------------------------------------------------------------------ *

@@ -170,6 +170,25 @@ pnpula_status pnpula_data_grad_noalloc(pnpula_ctx *c, const float *x, float *g) 
   return report(c, c->eng.data_grad(c->job, x, g, res));
 }
 
+pnpula_status pnpula_checkpoint_size(pnpula_ctx *c, size_t *bytes) {
+  GUARD(c);
+  if (!bytes) return report(c, Status::fail(PNPULA_EINVAL, "bytes is required"));
+  *bytes = c->eng.checkpoint_bytes(c->job);
+  return PNPULA_OK;
+}
+
+pnpula_status pnpula_checkpoint(pnpula_ctx *c, void *buf, size_t bytes) {
+  GUARD(c);
+  if (!buf) return report(c, Status::fail(PNPULA_EINVAL, "buf is required"));
+  return report(c, c->eng.checkpoint(c->job, buf, bytes));
+}
+
+pnpula_status pnpula_resume(pnpula_ctx *c, const void *buf, size_t bytes) {
+  GUARD(c);
+  if (!buf) return report(c, Status::fail(PNPULA_EINVAL, "buf is required"));
+  return report(c, c->eng.resume(c->job, buf, bytes));
+}
+
 pnpula_status pnpula_get_z(pnpula_ctx *c, float *z1, float *z2) {
   GUARD(c);
   return report(c, c->eng.get_z(c->job, z1, z2));

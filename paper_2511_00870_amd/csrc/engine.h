@@ -107,6 +107,9 @@ class Engine {
                         int32_t *stage_layer, float *stage_acts);
   Status read_act(Job *j, int k, int slot, float *dst);
   Status data_grad(Job *j, const float *x, float *g, float *res);
+  size_t checkpoint_bytes(const Job *j) const;
+  Status checkpoint(Job *j, void *buf, size_t bytes);
+  Status resume(Job *j, const void *buf, size_t bytes);
   Status get_z(Job *j, float *z1, float *z2);
   Status set_z(Job *j, const float *z1, const float *z2);
   Status stats_device(Job *j, float *mean, float *var, int64_t *n);

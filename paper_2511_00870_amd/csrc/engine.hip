@@ -866,7 +866,7 @@ void Engine::prof_end(ProfileRec *r) {
 }
 
 Status Engine::profile_read(int cls, double *ms, int64_t *launches) {
-  if (cls < 0 || cls >= kProfClasses) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..6");
+  if (cls < 0 || cls >= kProfClasses) return Status::fail(PNPULA_EINVAL, "kernel class must be 0..9");
   HIPOK(hipStreamSynchronize(stream));
   for (auto &r : prof_pending) {
     float e = 0;
@@ -1360,6 +1360,83 @@ Status Engine::data_grad(Job *j, const float *x, float *g, float *res) {
     a.epi = epi;
     HIPOK(launch_data_grad(a, n_upd, j->d.r, j->d.kpitch, stream));
   }
+  return Status::ok();
+}
+
+// ---------------------------------------------------------------------
+// checkpoint: header, x^(t), z1, z2 (when held), FP32 window mean / M2,
+// FP64 mean / M2, each image compact
+// ---------------------------------------------------------------------
+namespace {
+struct CkptHeader {
+  uint64_t magic;
+  int32_t ny, nx, zmode, has_z2;
+  int64_t t, wbase, nbase;
+};
+constexpr uint64_t kCkptMagic = 0x31544b4350414c55ull;   // "ULAPCKT1"
+}  // namespace
+
+size_t Engine::checkpoint_bytes(const Job *j) const {
+  const JobDesc &d = j->d;
+  const size_t N = (size_t)d.ny * d.nx;
+  const int nz = d.zmode == 0 ? 0 : (d.has_z2 ? 2 : 1);
+  return sizeof(CkptHeader) + N * sizeof(float) * (1 + nz + 2) + N * sizeof(double) * 2;
+}
+
+Status Engine::checkpoint(Job *j, void *buf, size_t bytes) {
+  if (bytes < checkpoint_bytes(j)) return Status::fail(PNPULA_EINVAL, "checkpoint buffer too small");
+  HIPOK(hipStreamSynchronize(stream));
+  const JobDesc &d = j->d;
+  const size_t N = (size_t)d.ny * d.nx;
+  CkptHeader h{kCkptMagic, d.ny, d.nx, d.zmode, d.has_z2, j->t, d.wbase, d.nbase};
+  uint8_t *p = static_cast<uint8_t *>(buf);
+  std::memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  float *f = reinterpret_cast<float *>(p);
+  TRY(get_state(j, f));
+  f += N;
+  if (d.zmode != 0) {
+    TRY(get_z(j, f, d.has_z2 ? f + N : nullptr));
+    f += (d.has_z2 ? 2 : 1) * N;
+  }
+  HIPOK(hipMemcpy(f, d.wmean, N * sizeof(float), hipMemcpyDeviceToHost));
+  HIPOK(hipMemcpy(f + N, d.wm2, N * sizeof(float), hipMemcpyDeviceToHost));
+  double *g = reinterpret_cast<double *>(f + 2 * N);
+  HIPOK(hipMemcpy(g, d.mean, N * sizeof(double), hipMemcpyDeviceToHost));
+  HIPOK(hipMemcpy(g + N, d.m2, N * sizeof(double), hipMemcpyDeviceToHost));
+  return Status::ok();
+}
+
+Status Engine::resume(Job *j, const void *buf, size_t bytes) {
+  JobDesc &d = j->d;
+  const size_t N = (size_t)d.ny * d.nx;
+  CkptHeader h;
+  if (bytes < sizeof h) return Status::fail(PNPULA_EINVAL, "checkpoint buffer too small");
+  std::memcpy(&h, buf, sizeof h);
+  if (h.magic != kCkptMagic || h.ny != d.ny || h.nx != d.nx || h.zmode != d.zmode ||
+      h.has_z2 != d.has_z2 || h.t < 0 || bytes < checkpoint_bytes(j))
+    return Status::fail(PNPULA_EINVAL, "checkpoint does not match this chain");
+  const uint8_t *p = static_cast<const uint8_t *>(buf) + sizeof h;
+  const float *f = reinterpret_cast<const float *>(p);
+  HIPOK(hipStreamSynchronize(stream));
+  const size_t origin = (size_t)d.xborder * d.xpitch + d.xborder;
+  HIPOK(hipMemcpy2D(d.x[h.t & 1] + origin, (size_t)d.xpitch * sizeof(float), f,
+                    (size_t)d.nx * sizeof(float), (size_t)d.nx * sizeof(float), d.ny,
+                    hipMemcpyHostToDevice));
+  f += N;
+  if (d.zmode != 0) {
+    TRY(set_z(j, f, d.has_z2 ? f + N : nullptr));
+    f += (d.has_z2 ? 2 : 1) * N;
+  }
+  HIPOK(hipMemcpy(d.wmean, f, N * sizeof(float), hipMemcpyHostToDevice));
+  HIPOK(hipMemcpy(d.wm2, f + N, N * sizeof(float), hipMemcpyHostToDevice));
+  const double *g = reinterpret_cast<const double *>(f + 2 * N);
+  HIPOK(hipMemcpy(d.mean, g, N * sizeof(double), hipMemcpyHostToDevice));
+  HIPOK(hipMemcpy(d.m2, g + N, N * sizeof(double), hipMemcpyHostToDevice));
+  j->t = h.t;
+  d.wbase = h.wbase;
+  d.nbase = h.nbase;
+  TRY(upload_descs());
   return Status::ok();
 }
 

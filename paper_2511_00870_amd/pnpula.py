@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE"
 # every symbol include/pnpula.h declares
 EXPORTS = [
     "pnpula_create", "pnpula_step", "pnpula_sync", "pnpula_stats", "pnpula_stats_f64",
-    "pnpula_get_state", "pnpula_set_state", "pnpula_restore", "pnpula_get_z", "pnpula_set_z",
+    "pnpula_get_state", "pnpula_set_state", "pnpula_restore", "pnpula_checkpoint_size",
+    "pnpula_checkpoint", "pnpula_resume", "pnpula_get_z", "pnpula_set_z",
     "pnpula_stats_device", "pnpula_data_grad", "pnpula_data_grad_noalloc", "pnpula_denoise",
     "pnpula_denoise_stages",
     "pnpula_calibrate", "pnpula_profile", "pnpula_profile_read", "pnpula_state_device",
@@ -103,6 +104,9 @@ def _declare(L):
     L.pnpula_get_state.argtypes = [vp, _fp, _i64p]
     L.pnpula_set_state.argtypes = [vp, _fp, C.c_int64]
     L.pnpula_restore.argtypes = [vp, _fp, C.c_int64, _dp, _dp, C.c_int64]
+    L.pnpula_checkpoint_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.pnpula_checkpoint.argtypes = [vp, vp, C.c_size_t]
+    L.pnpula_resume.argtypes = [vp, vp, C.c_size_t]
     L.pnpula_get_z.argtypes = [vp, _fp, _fp]
     L.pnpula_data_grad.argtypes = [vp, _fp, _fp]
     L.pnpula_data_grad_noalloc.argtypes = [vp, vp, vp]
@@ -288,6 +292,18 @@ class Context:
                 raise ValueError("x and g must be contiguous device tensors of ny*nx floats")
         _check(lib().pnpula_data_grad_noalloc(self.h, C.c_void_p(x.data_ptr()),
                                               C.c_void_p(g.data_ptr())), self._err)
+
+    def checkpoint(self) -> bytes:
+        """the whole chain state as an opaque byte string"""
+        n = C.c_size_t()
+        _check(lib().pnpula_checkpoint_size(self.h, C.byref(n)), self._err)
+        buf = C.create_string_buffer(n.value)
+        _check(lib().pnpula_checkpoint(self.h, buf, n.value), self._err)
+        return buf.raw
+
+    def resume(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().pnpula_resume(self.h, buf, len(blob)), self._err)
 
     def get_z(self):
         """(z1, z2) of a chain that holds its splitting variables (PSGLA, TV)"""

@@ -420,6 +420,47 @@ def test_checkpoint_resume_bitwise():
     assert np.abs(m2c - m2a).max() <= 1e-5 * np.abs(m2a).max()
 
 
+@pytest.mark.parametrize("mode", ["cnn", "poisson"])
+def test_checkpoint_resume_bitwise_with_statistics(mode):
+    """2N steps == N steps + checkpoint + a fresh context resumed + N steps,
+    bit for bit on x, z and the FP64 statistics (the checkpoint carries the
+    FP32 Welford window, so the merge schedule continues unchanged); the
+    window (7) does not divide the samples at the checkpoint."""
+    if mode == "poisson":
+        wl = W.poisson_workload("p", 40, 48, W.gaussian_kernel(5, 1.0), 40, 8, 4, 16, 0, 40, 3,
+                                13, bias_scale=0.05)
+    else:
+        wl = W.config(1, ny=64, nx=64, bias_scale=0.05)
+        wl.burn_in = 3
+    wl.welford_window = 7
+    say(f"case checkpoint with statistics ({mode})")
+    a = P.Context(P.Config.from_workload(wl))
+    a.step(20)
+    b = P.Context(P.Config.from_workload(wl))
+    b.step(10)
+    blob = b.checkpoint()
+    b.step(10)                                   # taking a checkpoint changes nothing
+    c = P.Context(P.Config.from_workload(wl))
+    c.resume(blob)
+    c.step(10)
+    xa, ta = a.get_state()
+    for other in (b, c):
+        xo, to = other.get_state()
+        assert to == ta == 20 and np.array_equal(xo, xa)
+    sa = a.stats_f64()
+    for other in (b, c):
+        so = other.stats_f64()
+        assert so[2] == sa[2] == 17
+        assert np.array_equal(so[0], sa[0]) and np.array_equal(so[1], sa[1])
+    if mode == "poisson":
+        za, zc = a.get_z(), c.get_z()
+        assert np.array_equal(za[0], zc[0]) and np.array_equal(za[1], zc[1])
+    bad = bytearray(blob)
+    bad[0] ^= 1
+    with pytest.raises(P.PnpulaError):
+        c.resume(bytes(bad))
+
+
 # ---------------------------------------------------------- statistics
 def test_welford_windows_match_two_pass():
     wl = W.config(1, ny=48, nx=40, block=48)
