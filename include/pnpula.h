@@ -144,7 +144,7 @@ typedef struct {
   int32_t prior;                  /* pnpula_prior */
   double beta;                    /* TV weight: f = beta ||.||_{2,1} on z ~ D x */
   int32_t ddfb_layers;            /* DDFB iterations K (1..8) */
-  int32_t ddfb_features;          /* DDFB feature maps F (1..256) */
+  int32_t ddfb_features;          /* DDFB feature maps F (1..64) */
   const float *ddfb_weights;      /* K blocks of [F][3][3]: W_k maps 1 -> F channels
                                      (cross-correlation, zero padding) */
   const float *ddfb_gamma;        /* K step sizes gamma_k */

@@ -13,25 +13,43 @@
 //   u_k[c](p) = HT(u_{k-1}[c](p) + gamma_k (w_k[c] * b_k)(p)),
 // which reads only the 3x3 neighbourhood of p.  So only the maps b_j are
 // kept (4 bytes per pixel each); stage k (one launch) recomputes u_{k-1} on
-// its tile plus a one-pixel ring from v and b_1 .. b_{k-1}, forms the
-// adjoint's per-tap partial sums s_tap(p) = sum_c w_k[c][tap] u_{k-1}[c](p)
-// in registers, exchanges them through LDS and writes b_k (or G for k = K).
-// Recomputing u costs 9 FMAs per channel and layer; storing it would move
-// 2 x 4F bytes per pixel and layer.
+// its 30 x 30 tile plus a one-pixel ring from v and b_1 .. b_{k-1}, forms the
+// adjoint's per-tap partial sums s_tap(p) = sum_c w_k[c][tap] u_{k-1}[c](p),
+// exchanges them through LDS and writes b_k (or G for k = K).  Recomputing u
+// costs 9 multiply-adds per channel and layer; storing it would move 2 x 4F
+// bytes per pixel and layer.  F <= 64.
 #include "device_common.h"
 #include "kernels.h"
 
 namespace pnp {
 
 namespace {
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kDdThreads = 256;
 constexpr int kDdWin = kDdTile + 4;       // v and b maps: core +- 2
 constexpr int kDdReg = kDdTile + 2;       // partial sums: core +- 1
 static_assert(kDdReg * kDdReg == 4 * kDdThreads, "four region pixels per thread");
 }  // namespace
 
-// KM >= K: register budget for the stencils of v and b_1 .. b_{K-1}
-template <int KM>
+// KM >= K: register budget for the A fragments of W_1 .. W_{K-1}
+//
+// Matrix-core form of one stage.  Every contraction of the stage is a small
+// GEMM over 16-pixel groups on v_mfma_f32_16x16x4_f32 (FP32 inputs, FP32
+// accumulation): for the 16 pixels of a group (half a row of the 32 x 32
+// region) and the 64 channels as four 16-row blocks,
+//   u_0 = W_K v:          A = W_K (channels x taps), B = v at the 9 taps (3 K steps
+//                         of 4 taps, the last padded with zero weights);
+//   u_j += gamma_j W_j b_j, then HT: the same, with A = gamma_j W_j, accumulating
+//                         into u, and the clip on the accumulator registers;
+//   s = W_k^* u:          A = the taps x channels transpose (9 taps padded to 16
+//                         rows), B = u itself: the accumulator register r of
+//                         channel block mb holds, in lane group q, channel
+//                         16 mb + 4 q + r, which is exactly a B operand whose
+//                         K index q stands for that channel, so u never moves.
+// Lane layout of the 16x16x4 f32 MFMA: A lane l = (row l % 16, k l / 16),
+// B lane l = (k l / 16, column l % 16), D lane l register r = (row 4 (l / 16)
+// + r, column l % 16).
+template <int KM, int MB>
 __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
   __shared__ float smap[KM][kDdWin * kDdWin];
   __shared__ float spart[9][kDdReg * kDdReg];
@@ -39,10 +57,10 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
   const int k = a.stage, K = a.K, F = a.F;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q4 = lane >> 4, l16 = lane & 15;
   const int B = j.xborder;
   const int64_t P = j.xpitch;
-  // windows of v (map 0) and b_1 .. b_{k-1} (maps 1 .. k-1), zero outside the image
 #pragma unroll
   for (int m = 0; m < KM; ++m) {
     if (m >= k) break;
@@ -52,44 +70,102 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
       smap[m][q] = src[(int64_t)(Y + B) * P + (X + B)];
     }
   }
+  // A fragments: MB blocks of 16 channels (channels from F on have zero
+  // weights, so their u stays zero and adds nothing)
+  const PNP_GLOBAL float *w = gp(a.w);
+  float AK[MB][3], AJ[KM > 1 ? KM - 1 : 1][MB][3], AP[MB][4];
+  int toff[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int tp = 4 * s + q4;
+    toff[s] = tp < 9 ? (tp / 3) * kDdWin + tp % 3 : 0;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int c = 16 * mb + l16;
+      const bool ok = tp < 9 && c < F;
+      AK[mb][s] = ok ? w[((int64_t)(K - 1) * F + c) * 9 + tp] : 0.0f;
+#pragma unroll
+      for (int m = 1; m < KM; ++m)
+        AJ[m - 1][mb][s] = (m < k && ok) ? a.gamma[m - 1] * w[((int64_t)(m - 1) * F + c) * 9 + tp]
+                                         : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 16 * mb + 4 * q4 + r;
+      AP[mb][r] = (l16 < 9 && c < F) ? w[((int64_t)(k - 1) * F + c) * 9 + l16] : 0.0f;
+    }
   __syncthreads();
-  const PNP_CONST float *w = cp(a.w);
-  const PNP_CONST float *wK = w + (size_t)(K - 1) * F * 9;        // W_K: u_0 = W_K v
-  const PNP_CONST float *wa = w + (size_t)(k - 1) * F * 9;        // adjoint of this stage
   const float th = a.thresh;
-  for (int pass = 0; pass < 4; ++pass) {
-    const int q = tid + kDdThreads * pass;
-    const int ri = q / kDdReg, rc = q % kDdReg;
-    const int Y = tl.y0 - 1 + ri, X = tl.x0 - 1 + rc;
-    float s[9];
+  // 64 groups of 16 pixels (row ri, half h) of the 32 x 32 region, 16 per
+  // wave, two at a time (the two halves of one row): two independent chains
+  // for the matrix cores, and the transpose contraction split over MB
+  // accumulators summed at the end instead of one chain of 4 MB steps
+  for (int ri = 8 * wave; ri < 8 * wave + 8; ++ri) {
+    f32x4 acc[2][MB];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) s[i] = 0.0f;
-    if (Y >= 0 && Y < j.ny && X >= 0 && X < j.nx) {      // u is zero outside the image
-      float st[KM][9];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int m = 0; m < KM; ++m)
+      for (int mb = 0; mb < MB; ++mb) acc[h][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int base = ri * kDdWin + l16;            // window position of tap (0, 0), half 0
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-          st[m][i] = m < k ? smap[m][(ri + i / 3) * kDdWin + rc + i % 3] : 0.0f;
-      for (int c = 0; c < F; ++c) {
-        float u = 0.0f;
+    for (int s = 0; s < 3; ++s) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) u = fmaf(wK[c * 9 + i], st[0][i], u);
+      for (int h = 0; h < 2; ++h) {
+        const float bv = (4 * s + q4 < 9) ? smap[0][base + 16 * h + toff[s]] : 0.0f;
 #pragma unroll
-        for (int m = 1; m < KM; ++m) {
-          if (m >= k) break;
-          const PNP_CONST float *wm = w + ((size_t)(m - 1) * F + c) * 9;
-          float acc = 0.0f;
-#pragma unroll
-          for (int i = 0; i < 9; ++i) acc = fmaf(wm[i], st[m][i], acc);
-          u = __builtin_amdgcn_fmed3f(fmaf(a.gamma[m - 1], acc, u), -th, th);
-        }
-#pragma unroll
-        for (int i = 0; i < 9; ++i) s[i] = fmaf(wa[c * 9 + i], u, s[i]);
+        for (int mb = 0; mb < MB; ++mb)
+          acc[h][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(AK[mb][s], bv, acc[h][mb], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) spart[i][q] = s[i];
+    for (int m = 1; m < KM; ++m) {
+      if (m >= k) break;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float bv = (4 * s + q4 < 9) ? smap[m][base + 16 * h + toff[s]] : 0.0f;
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            acc[h][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(AJ[m - 1][mb][s], bv, acc[h][mb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[h][mb][r] = __builtin_amdgcn_fmed3f(acc[h][mb][r], -th, th);
+    }
+    // u is zero outside the image
+    const int Y = tl.y0 - 1 + ri;
+    f32x4 sp[2][MB];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int X = tl.x0 - 1 + 16 * h + l16;
+      const bool inside = Y >= 0 && Y < j.ny && X >= 0 && X < j.nx;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        sp[h][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          sp[h][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(AP[mb][r], inside ? acc[h][mb][r] : 0.0f,
+                                                           sp[h][mb], 0, 0, 0);
+      }
+    }
+    // lane (q4, l16) holds taps 4 q4 .. 4 q4 + 3 of pixel 16 h + l16
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f32x4 tot = sp[h][0];
+#pragma unroll
+      for (int mb = 1; mb < MB; ++mb) tot += sp[h][mb];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * q4 + r < 9) spart[4 * q4 + r][ri * kDdReg + 16 * h + l16] = tot[r];
+    }
   }
   __syncthreads();
   // adjoint on the core: (W^* u)(q) = sum_tap s_tap(q + (1 - dy, 1 - dx))
@@ -112,12 +188,20 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
   }
 }
 
-hipError_t launch_ddfb_stage(const DdfbArgs &a, int n_tiles, hipStream_t s) {
-  if (a.K <= 4)
-    hipLaunchKernelGGL(ddfb_stage_kernel<4>, dim3(n_tiles), dim3(kDdThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(ddfb_stage_kernel<kMaxDdfbLayers>, dim3(n_tiles), dim3(kDdThreads), 0, s, a);
+template <int KM>
+static hipError_t launch_ddfb_km(const DdfbArgs &a, int n_tiles, hipStream_t s) {
+  switch ((a.F + 15) / 16) {
+    case 1: hipLaunchKernelGGL((ddfb_stage_kernel<KM, 1>), dim3(n_tiles), dim3(kDdThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((ddfb_stage_kernel<KM, 2>), dim3(n_tiles), dim3(kDdThreads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((ddfb_stage_kernel<KM, 3>), dim3(n_tiles), dim3(kDdThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((ddfb_stage_kernel<KM, 4>), dim3(n_tiles), dim3(kDdThreads), 0, s, a); break;
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_ddfb_stage(const DdfbArgs &a, int n_tiles, hipStream_t s) {
+  if (a.F < 1 || a.F > 64 || a.K < 1 || a.K > kMaxDdfbLayers) return hipErrorInvalidValue;
+  return a.K <= 4 ? launch_ddfb_km<4>(a, n_tiles, s) : launch_ddfb_km<kMaxDdfbLayers>(a, n_tiles, s);
 }
 
 }  // namespace pnp

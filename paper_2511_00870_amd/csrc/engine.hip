@@ -387,9 +387,9 @@ Status Engine::validate_job(const pnpula_config *c, int, const std::vector<int> 
     return Status::fail(PNPULA_EINVAL, "the TV prior runs with the unsplit Gaussian likelihood");
   if (c->prior == PNPULA_PRIOR_DDFB &&
       (c->ddfb_layers < 1 || c->ddfb_layers > kMaxDdfbLayers || c->ddfb_features < 1 ||
-       c->ddfb_features > 256 || !c->ddfb_weights || !c->ddfb_gamma || !(c->ddfb_thresh >= 0)))
+       c->ddfb_features > 64 || !c->ddfb_weights || !c->ddfb_gamma || !(c->ddfb_thresh >= 0)))
     return Status::fail(PNPULA_EINVAL,
-                        "DDFB needs 1..8 layers, 1..256 features, weights, step sizes, thresh >= 0");
+                        "DDFB needs 1..8 layers, 1..64 features, weights, step sizes, thresh >= 0");
   if (!(c->sigma > 0) || !(c->eps > 0) || !(c->delta > 0) || !(c->rho >= 0) ||
       !(c->alpha >= 0) || !(c->inv_lambda >= 0) || !std::isfinite(c->sigma) ||
       !std::isfinite(c->eps) || !std::isfinite(c->delta) || !std::isfinite(c->rho) ||
