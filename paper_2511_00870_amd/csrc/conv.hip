@@ -1550,19 +1550,23 @@ void conv_mid_rr8_kernel(ConvArgs a) {
 // taps are paired as (dx 0, dx 1) and (dx 2, zero weights), so an input row
 // takes two steps P, each serving the three vertical taps.  Output-channel
 // scales, bias and ReLU apply in the epilogue; each layer's output is rounded
-// to e4m3 with the next layer's activation scale.  LDS pixels are 64 bytes
-// with 16 bytes of padding after every 4 pixels, which keeps the B reads of
-// 16 consecutive pixels conflict-free without a swizzle.  Both windows fit in
-// 80 KB, so two workgroups can share a CU.
+// to e4m3 with the next layer's activation scale.  LDS pixels are 64 bytes,
+// unpadded, and chunk c (16 bytes) of the pixel in window column col sits at
+// c ^ bit 2 of col.  A 16-byte LDS access is served in four passes of 16
+// lanes (lane bit 5 and the parity of lane bits 2..4 pick the pass; the bank
+// is the address mod 256, 64 banks of 4 bytes, as measured with the bank
+// conflict counter).  A pass of a B read holds two lane groups, with chunks c
+// and c + 2, each at columns that share their residue mod 4 in fours (col,
+// col + 4, col + 8, col + 12): the swizzle gives those 16 reads 16 distinct
+// 16-byte slots.  Both windows fit in 80 KB, so two workgroups can share a CU.
 // ---------------------------------------------------------------------
 struct Pair8Layout {
   static constexpr int F = 64, PIXB = 64, CPP = 4, NT = 256;
   static constexpr int TH = kPairTileH, TW = kPairTileW;
   static constexpr int MH = TH + 2, MW = TW + 2;
   static constexpr int IH = TH + 4, IW = TW + 4;
-  static constexpr int GRP = 4 * PIXB + 16;                      // 4 pixels + padding
-  static constexpr int IN_BYTES = (IH * IW + 3) / 4 * GRP;
-  static constexpr int MID_BYTES = (MH * IW + 3) / 4 * GRP;
+  static constexpr int IN_BYTES = IH * IW * PIXB;
+  static constexpr int MID_BYTES = MH * IW * PIXB;
   static constexpr int LDS_BYTES = IN_BYTES + MID_BYTES + 4 * F * 4;  // scale, bias per layer
   static constexpr int NCHUNK = IH * IW * CPP, NLOAD = (NCHUNK + NT - 1) / NT;
   static constexpr int NL1 = NLOAD / 2, NL2 = NLOAD - NL1;
@@ -1573,14 +1577,15 @@ struct Pair8Layout {
   // fused last layer: per-row partial sums of the 4 waves (2 blocks, lane
   // groups 0-2 = taps 0..11, 16 bytes per lane) in a ring of 3 rows, placed
   // in the part of the input window that only the second prefetch half fills
-  static constexpr int STG_ROW = 4 * 2 * 48 * 16, STG_OFF = (NL1 * 64 / 4) * GRP;
+  static constexpr int STG_ROW = 4 * 2 * 48 * 16, STG_OFF = NL1 * 64 * PIXB;
   static_assert(STG_OFF + 3 * STG_ROW <= IN_BYTES, "last-layer ring");
 };
 static_assert(Pair8Layout::MW == 32 && Pair8Layout::lds_bytes(true) <= 80 * 1024,
               "e4m3 pair layout: two workgroups per CU");
-// LDS byte offset of pixel p in the padded e4m3 layout
-__device__ __forceinline__ constexpr int p8_off(int p) {
-  return (p >> 2) * Pair8Layout::GRP + (p & 3) * Pair8Layout::PIXB;
+// LDS byte offset of 16-byte chunk c (channels 16c .. 16c+15) of the pixel
+// in window column col whose row-major window index is p
+__device__ __forceinline__ constexpr int p8_off(int p, int col, int c) {
+  return p * Pair8Layout::PIXB + ((c ^ ((col >> 2) & 1)) << 4);
 }
 
 
@@ -1651,16 +1656,16 @@ void conv_pair8_kernel(ConvArgs a) {
       AL[e] = __builtin_bit_cast(
           short, f32_to_bf16(l16 < 9 ? gp(a.last_w)[(16 * wave + 4 * g + e) * 9 + l16] : 0.0f));
   }
+  // fused first layer: this wave's A fragment, rows = its 16 channels; K slot
+  // 4g + e holds tap (dy, dx) = (g, e) for g, e < 3 and a zero weight
+  // otherwise, so that lane group g reads kernel row g of the x window at the
+  // immediate offsets 0, 1, 2
   i16x4 A0;
-  int toff[4];
   if constexpr (FIRST) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int t = 4 * g + e, tt = t < 9 ? t : 8;
-      A0[e] = __builtin_bit_cast(short, f32_to_bf16(t < 9 ? gp(a.first_w)[(16 * wave + l16) * 9 + t]
-                                                         : 0.0f));
-      toff[e] = (tt / 3) * Lo::XW + tt % 3;
-    }
+    for (int e = 0; e < 4; ++e)
+      A0[e] = __builtin_bit_cast(
+          short, f32_to_bf16(g < 3 && e < 3 ? gp(a.first_w)[(16 * wave + l16) * 9 + 3 * g + e] : 0.0f));
   }
   // the intermediate's columns MW .. IW-1 are read only for the two padding
   // output columns and never written: zero the buffer once
@@ -1684,7 +1689,8 @@ void conv_pair8_kernel(ConvArgs a) {
         c.in + ((int64_t)Y * c.apitch + X) * Lo::PIXB + (tid & 3) * 16);
   };
   auto put_chunk = [&](int i, const u32x4 &v) {
-    *reinterpret_cast<u32x4 *>(lds_in + p8_off(win_pix(i)) + (tid & 3) * 16) = v;
+    const int q = win_pix(i);
+    *reinterpret_cast<u32x4 *>(lds_in + p8_off(q, q % IW, tid & 3)) = v;
   };
   static_assert(Lo::NLOAD * 64 >= Lo::IH * Lo::IW && Lo::NLOAD <= 2 * NL2, "window loads");
 
@@ -1707,36 +1713,42 @@ void conv_pair8_kernel(ConvArgs a) {
     const f32x4 sc0 = *reinterpret_cast<const f32x4 *>(lds_ep0 + 16 * wave + 4 * g);
     const f32x4 bi0 = *reinterpret_cast<const f32x4 *>(lds_ep0 + Lo::F + 16 * wave + 4 * g);
     const float is0 = a.first_out_inv_scale;
-    constexpr int NWIN = Lo::IH * IW, NB = (NWIN + 15) / 16;
-    // unrolled by four (four independent read -> MFMA -> write chains), with
-    // an opaque index: the per-lane addresses are the same for every tile and
-    // would otherwise be kept live across the tile loop
-#pragma unroll 4
-    for (int blk = 0; blk < NB; ++blk) {
-      int q0 = 16 * blk + l16;
-      asm volatile("" : "+v"(q0));
-      const int q = q0 < NWIN ? q0 : 0;
-      const int wr = q / IW, wc = q % IW;
-      const uint16_t *xp = lds_x + wr * Lo::XW + wc;
-      i16x4 Bx;
+    constexpr int NWIN = Lo::IH * IW, NB = (NWIN + 15) / 16, NTAIL = NWIN - 16 * (NB - 1);
+    // Block blk covers window pixels 16 blk .. 16 blk + 15 (row-major); this
+    // lane's pixel (wr, wc) and the x-window element of its tap row, xa, step
+    // by 16 pixels per block.  Starting from an opaque value keeps the
+    // compiler from holding every block's addresses across the tile loop.
+    int wc = l16, wr = 0, xa = (g < 3 ? g : 2) * Lo::XW + l16;
+    asm volatile("" : "+v"(wc), "+v"(wr), "+v"(xa));
+    const int xa0 = xa;                          // the tail's lanes past the window read here
+    const int ys = c.y0 - 2, xs = c.x0 - 2;
+    uint8_t *dst = lds_in + l16 * Lo::PIXB + 4 * g;   // + 16 pixels per block, + chunk
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint16_t v = xp[toff[e]];
-        Bx[e] = (short)(4 * g + e < 9 ? v : (uint16_t)0);
+    for (int blk = 0; blk < NB; ++blk) {
+      if (blk > 0) {
+        wc += 16;
+        const bool wrap = wc >= IW;
+        wc = wrap ? wc - IW : wc;
+        wr += wrap ? 1 : 0;
+        xa += wrap ? 16 + (Lo::XW - IW) : 16;
       }
+      const bool tail_out = blk == NB - 1 && l16 >= NTAIL;
+      const uint16_t *xp = lds_x + (tail_out ? xa0 : xa);
+      i16x4 Bx;
+      Bx[0] = (short)xp[0];
+      Bx[1] = (short)xp[1];
+      Bx[2] = (short)xp[2];
+      Bx[3] = 0;
       const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, Bx, f32x4{0.f, 0.f, 0.f, 0.f},
                                                               0, 0, 0);
-      const bool inside = (unsigned)(c.y0 - 2 + wr) < (unsigned)c.ny &&
-                          (unsigned)(c.x0 - 2 + wc) < (unsigned)c.nx;
+      const bool inside = (unsigned)(ys + wr) < (unsigned)c.ny && (unsigned)(xs + wc) < (unsigned)c.nx;
       uint32_t w = pack_e4m3x4_nonan(fmaxf(d[0] * sc0[0] + bi0[0], 0.0f) * is0,
                                      fmaxf(d[1] * sc0[1] + bi0[1], 0.0f) * is0,
                                      fmaxf(d[2] * sc0[2] + bi0[2], 0.0f) * is0,
                                      fmaxf(d[3] * sc0[3] + bi0[3], 0.0f) * is0);
       w = inside ? w : 0u;
-      // lanes past the window write into the intermediate buffer, which is
-      // rewritten before it is read
-      uint8_t *dst = q0 < NWIN ? lds_in + p8_off(q) : lds_mid;
-      *reinterpret_cast<uint32_t *>(dst + 16 * wave + 4 * g) = w;
+      if (!tail_out)
+        *reinterpret_cast<uint32_t *>(dst + blk * 16 * Lo::PIXB + ((wave ^ ((wc >> 2) & 1)) << 4)) = w;
     }
   };
 
@@ -1765,20 +1777,21 @@ void conv_pair8_kernel(ConvArgs a) {
   }
   __syncthreads();
 
-  // B fragment of step P at window row ir, block h: this lane's pixel is
-  // ir*IW + 16h + dx + l16 with dx = the tap its lane group carries, 32
-  // bytes at channel 32(g&1).  ir*IW + 16h = 4m + 2(ir&1), so the address is
-  // 272m (an immediate) plus base[ir&1][P] (per lane).
-  int base_in[2][NP], base_mid[2][NP];
+  // B fragment of step P at window row ir, block h: this lane's pixel is in
+  // column 16h + q, q = dx + l16 with dx = the tap its lane group carries,
+  // 32 bytes at channel 32(g&1): chunks 2(g&1) (lo) and 2(g&1) + 1 (hi).
+  // Column 16h + q swizzles as column q, so the address is 64 (ir*IW + 16h)
+  // (an immediate) plus base[P][lo/hi] (per lane).
+  int base_in[NP][2], base_mid[NP][2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int P = 0; P < NP; ++P)
 #pragma unroll
-    for (int P = 0; P < NP; ++P) {
-      const int dx = (g < 2) ? (P == 0 ? 0 : 2) : (P == 0 ? 1 : 2);
-      int v = p8_off(2 * s + dx + l16) + 32 * (g & 1), u = v + Lo::IN_BYTES;
+    for (int hl = 0; hl < 2; ++hl) {
+      const int q = ((g < 2) ? (P == 0 ? 0 : 2) : (P == 0 ? 1 : 2)) + l16;
+      int v = p8_off(q, q, 2 * (g & 1) + hl), u = v + Lo::IN_BYTES;
       asm volatile("" : "+v"(v), "+v"(u));
-      base_in[s][P] = v;
-      base_mid[s][P] = u;
+      base_in[P][hl] = v;
+      base_mid[P][hl] = u;
     }
 
   while (true) {
@@ -1787,16 +1800,15 @@ void conv_pair8_kernel(ConvArgs a) {
     f32x4 acc[4][2];
     i32x8 Bb[PD + 1][2];
 
-    auto layer = [&](const int (&base)[2][NP], const i32x8 *W, auto NRc, auto ep, auto pf) {
+    auto layer = [&](const int (&base)[NP][2], const i32x8 *W, auto NRc, auto ep, auto pf) {
       constexpr int NR = decltype(NRc)::value, NO = NR - 2, NSTG = NR * NP;
       auto load_b = [&](auto stc) {
         constexpr int stg = decltype(stc)::value;
         constexpr int ir = stg / NP, P = stg % NP;
         static_for<0, 2>([&](auto hc) {
-          constexpr int c = ir * IW + 16 * decltype(hc)::value;   // = 4m + 2(ir&1)
-          const uint8_t *src = lds + base[ir & 1][P] + (c >> 2) * Lo::GRP;
-          const u32x4 lo = *reinterpret_cast<const u32x4 *>(src);
-          const u32x4 hi = *reinterpret_cast<const u32x4 *>(src + 16);
+          constexpr int c = (ir * IW + 16 * decltype(hc)::value) * Lo::PIXB;
+          const u32x4 lo = *reinterpret_cast<const u32x4 *>(lds + base[P][0] + c);
+          const u32x4 hi = *reinterpret_cast<const u32x4 *>(lds + base[P][1] + c);
           Bb[stg % (PD + 1)][decltype(hc)::value] =
               i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
         });
@@ -1851,6 +1863,8 @@ void conv_pair8_kernel(ConvArgs a) {
     };
     const int cpos = 16 * (g & 1) + l16;         // column of this lane's pixel after the swap
     const int cbyte = 16 * wave + 8 * (g >> 1);  // its 8 channels inside the pixel
+    // the same 8 channels in the swizzled intermediate (+ 64 o IW for row o)
+    const int mid_w = p8_off(cpos, cpos, wave) + 8 * (g >> 1);
 
     // layer A: intermediate rows into LDS (zero outside the image)
     const uint32_t in_x = (unsigned)(cur.x0 - 1 + cpos) < (unsigned)cur.nx ? ~0u : 0u;
@@ -1861,7 +1875,7 @@ void conv_pair8_kernel(ConvArgs a) {
       const uint32_t keep = in_y & in_x;
       u32x2 q = pack_row(oc, 0, isA);
       q &= u32x2{keep, keep};
-      *reinterpret_cast<u32x2 *>(lds_mid + p8_off(o * IW + cpos) + cbyte) = q;
+      *reinterpret_cast<u32x2 *>(lds_mid + o * IW * Lo::PIXB + mid_w) = q;
     };
     auto pfA = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
