@@ -1610,6 +1610,9 @@ void conv_pair8_kernel(ConvArgs a) {
   using Lo = Pair8Layout;
   constexpr int NT = Lo::NT, IW = Lo::IW, NL1 = Lo::NL1, NL2 = Lo::NL2;
   constexpr int NP = 2, PD = 2;                   // steps per input row; B reads ahead
+  // the next tile's first layer runs inside this tile's layer B (with the
+  // fused last layer its partial-sum ring occupies part of the window then)
+  constexpr bool L0_IN_B = FIRST && !LAST;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   uint8_t *lds_in = lds;
   uint8_t *lds_mid = lds + Lo::IN_BYTES;
@@ -1709,47 +1712,54 @@ void conv_pair8_kernel(ConvArgs a) {
     const int q = tid + i * NT;
     if (q < Lo::NX) lds_x[q] = f32_to_bf16(v);
   };
-  auto layer0 = [&](const MidTile &c) {
-    const f32x4 sc0 = *reinterpret_cast<const f32x4 *>(lds_ep0 + 16 * wave + 4 * g);
-    const f32x4 bi0 = *reinterpret_cast<const f32x4 *>(lds_ep0 + Lo::F + 16 * wave + 4 * g);
-    const float is0 = a.first_out_inv_scale;
-    constexpr int NWIN = Lo::IH * IW, NB = (NWIN + 15) / 16, NTAIL = NWIN - 16 * (NB - 1);
-    // Block blk covers window pixels 16 blk .. 16 blk + 15 (row-major); this
-    // lane's pixel (wr, wc) and the x-window element of its tap row, xa, step
-    // by 16 pixels per block.  Starting from an opaque value keeps the
-    // compiler from holding every block's addresses across the tile loop.
-    int wc = l16, wr = 0, xa = (g < 3 ? g : 2) * Lo::XW + l16;
-    asm volatile("" : "+v"(wc), "+v"(wr), "+v"(xa));
-    const int xa0 = xa;                          // the tail's lanes past the window read here
-    const int ys = c.y0 - 2, xs = c.x0 - 2;
-    uint8_t *dst = lds_in + l16 * Lo::PIXB + 4 * g;   // + 16 pixels per block, + chunk
-#pragma unroll
-    for (int blk = 0; blk < NB; ++blk) {
-      if (blk > 0) {
-        wc += 16;
-        const bool wrap = wc >= IW;
-        wc = wrap ? wc - IW : wc;
-        wr += wrap ? 1 : 0;
-        xa += wrap ? 16 + (Lo::XW - IW) : 16;
-      }
-      const bool tail_out = blk == NB - 1 && l16 >= NTAIL;
-      const uint16_t *xp = lds_x + (tail_out ? xa0 : xa);
-      i16x4 Bx;
-      Bx[0] = (short)xp[0];
-      Bx[1] = (short)xp[1];
-      Bx[2] = (short)xp[2];
-      Bx[3] = 0;
-      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, Bx, f32x4{0.f, 0.f, 0.f, 0.f},
-                                                              0, 0, 0);
-      const bool inside = (unsigned)(ys + wr) < (unsigned)c.ny && (unsigned)(xs + wc) < (unsigned)c.nx;
-      uint32_t w = pack_e4m3x4_nonan(fmaxf(d[0] * sc0[0] + bi0[0], 0.0f) * is0,
-                                     fmaxf(d[1] * sc0[1] + bi0[1], 0.0f) * is0,
-                                     fmaxf(d[2] * sc0[2] + bi0[2], 0.0f) * is0,
-                                     fmaxf(d[3] * sc0[3] + bi0[3], 0.0f) * is0);
-      w = inside ? w : 0u;
-      if (!tail_out)
-        *reinterpret_cast<uint32_t *>(dst + blk * 16 * Lo::PIXB + ((wave ^ ((wc >> 2) & 1)) << 4)) = w;
+  // Block blk covers window pixels 16 blk .. 16 blk + 15 (row-major); this
+  // lane's pixel (l0_wr, l0_wc) and the x-window element of its tap row,
+  // l0_xa, step by 16 pixels per block.  l0_reset starts them from an opaque
+  // value, which keeps the compiler from holding every block's addresses
+  // across the tile loop.
+  constexpr int NWIN0 = Lo::IH * IW, NB0 = (NWIN0 + 15) / 16, NTAIL0 = NWIN0 - 16 * (NB0 - 1);
+  int l0_wc = 0, l0_wr = 0, l0_xa = 0, l0_xa0 = 0;
+  f32x4 sc0 = {}, bi0 = {};
+  auto l0_reset = [&]() {
+    l0_wc = l16;
+    l0_wr = 0;
+    l0_xa = (g < 3 ? g : 2) * Lo::XW + l16;
+    asm volatile("" : "+v"(l0_wc), "+v"(l0_wr), "+v"(l0_xa));
+    l0_xa0 = l0_xa;                              // the tail's lanes past the window read here
+  };
+  auto l0_block = [&](const MidTile &c, auto blkc) {
+    constexpr int blk = decltype(blkc)::value;
+    if constexpr (blk > 0) {
+      l0_wc += 16;
+      const bool wrap = l0_wc >= IW;
+      l0_wc = wrap ? l0_wc - IW : l0_wc;
+      l0_wr += wrap ? 1 : 0;
+      l0_xa += wrap ? 16 + (Lo::XW - IW) : 16;
     }
+    const bool tail_out = blk == NB0 - 1 && l16 >= NTAIL0;
+    const uint16_t *xp = lds_x + (tail_out ? l0_xa0 : l0_xa);
+    i16x4 Bx;
+    Bx[0] = (short)xp[0];
+    Bx[1] = (short)xp[1];
+    Bx[2] = (short)xp[2];
+    Bx[3] = 0;
+    const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, Bx, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                            0, 0, 0);
+    const bool inside = (unsigned)(c.y0 - 2 + l0_wr) < (unsigned)c.ny &&
+                        (unsigned)(c.x0 - 2 + l0_wc) < (unsigned)c.nx;
+    const float is0 = a.first_out_inv_scale;
+    uint32_t w = pack_e4m3x4_nonan(fmaxf(d[0] * sc0[0] + bi0[0], 0.0f) * is0,
+                                   fmaxf(d[1] * sc0[1] + bi0[1], 0.0f) * is0,
+                                   fmaxf(d[2] * sc0[2] + bi0[2], 0.0f) * is0,
+                                   fmaxf(d[3] * sc0[3] + bi0[3], 0.0f) * is0);
+    w = inside ? w : 0u;
+    if (!tail_out)
+      *reinterpret_cast<uint32_t *>(lds_in + (16 * blk + l16) * Lo::PIXB + 4 * g +
+                                    ((wave ^ ((l0_wc >> 2) & 1)) << 4)) = w;
+  };
+  auto layer0 = [&](const MidTile &c) {
+    l0_reset();
+    static_for<0, NB0>([&](auto b) { l0_block(c, b); });
   };
 
   int ti = t_begin + slot;
@@ -1764,6 +1774,8 @@ void conv_pair8_kernel(ConvArgs a) {
 #pragma unroll
     for (int i = 0; i < Lo::XQ; ++i) put_x(i, prex[i]);
     __syncthreads();
+    sc0 = *reinterpret_cast<const f32x4 *>(lds_ep0 + 16 * wave + 4 * g);
+    bi0 = *reinterpret_cast<const f32x4 *>(lds_ep0 + Lo::F + 16 * wave + 4 * g);
     layer0(cur);
   } else {
 #pragma unroll
@@ -1880,8 +1892,15 @@ void conv_pair8_kernel(ConvArgs a) {
     auto pfA = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
       if constexpr (!FIRST && stg >= 4 && stg < 4 + NL1) pre[stg - 4] = load_chunk(nxt, stg - 4);
+      if constexpr (L0_IN_B && stg >= 1 && stg < 1 + Lo::XQ) prex[stg - 1] = load_x(nxt, stg - 1);
     };
     layer(base_in, WA, std::integral_constant<int, Lo::IH>{}, epA, pfA);
+    if constexpr (L0_IN_B) {
+      // the x window was last read by the first layer of this tile, during
+      // the previous tile's layer B
+#pragma unroll
+      for (int i = 0; i < Lo::XQ; ++i) put_x(i, prex[i]);
+    }
     __syncthreads();                             // intermediate written, window read
     if constexpr (!FIRST) {
 #pragma unroll
@@ -1952,9 +1971,14 @@ void conv_pair8_kernel(ConvArgs a) {
         *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + bo) = pack_row(oc, 1, isB);
       }
     };
+    if constexpr (L0_IN_B) l0_reset();
     auto pfB = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
-      if constexpr (FIRST) {
+      if constexpr (L0_IN_B) {
+        // the next tile's first layer, NB0 blocks spread over the stages
+        constexpr int NSB = Lo::MH * NP, b0 = NB0 * stg / NSB, b1 = NB0 * (stg + 1) / NSB;
+        static_for<b0, b1>([&](auto b) { l0_block(nxt, b); });
+      } else if constexpr (FIRST) {
         if constexpr (stg >= 1 && stg < 1 + Lo::XQ) prex[stg - 1] = load_x(nxt, stg - 1);
       } else {
         if constexpr (stg >= 1 && stg < 1 + NL2) pre[stg - 1] = load_chunk(nxt, NL1 + stg - 1);
@@ -1962,11 +1986,11 @@ void conv_pair8_kernel(ConvArgs a) {
     };
     layer(base_mid, WB, std::integral_constant<int, Lo::MH>{}, epB, pfB);
     if constexpr (LAST) __syncthreads();         // the last row's partials are summed
-    if constexpr (FIRST) {
+    if constexpr (FIRST && !L0_IN_B) {
       // the x window is read by layer0 only, long done
 #pragma unroll
       for (int i = 0; i < Lo::XQ; ++i) put_x(i, prex[i]);
-    } else {
+    } else if constexpr (!FIRST) {
 #pragma unroll
       for (int i = 0; i < NL2; ++i) put_chunk(NL1 + i, pre[i]);
     }
@@ -1975,7 +1999,7 @@ void conv_pair8_kernel(ConvArgs a) {
     cur = nxt;
     nxt = after;
     ti = tn;
-    if constexpr (FIRST) {
+    if constexpr (FIRST && !L0_IN_B) {
       layer0(cur);
       __syncthreads();
     }
