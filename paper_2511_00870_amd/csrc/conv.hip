@@ -2006,6 +2006,274 @@ void conv_pair8_kernel(ConvArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------
+// Two consecutive e4m3 middle layers on separate waves, with the taps packed
+// without zero slots.  Waves 0-3 run layer A of tile i and waves 4-7 layer B
+// of tile i-1 from the other half of a double-buffered intermediate, as in
+// the bf16 split-layer kernel; each wave holds one layer's A fragments for
+// its 16 output channels.  K = 128 of v_mfma_scale_f32_16x16x128_f8f6f4 is two
+// (tap, 64 channels) units.  The units of the window are numbered row-major,
+// idx = 3 ir + dx (window row ir, horizontal tap dx), and B fragment m
+// carries units 2m (lane groups 0-1) and 2m + 1 (groups 2-3), so no B
+// fragment has an empty half.  Output row o needs units 3o .. 3o + 8: the
+// five fragments floor(3o/2) .. floor((3o + 8)/2), with A fragment
+// j = 2m - 3o + 1, which holds taps j - 1 and j of the 3x3 kernel (zero
+// weights for taps outside 0..8).  Five K steps per row and layer for the
+// nine taps, ten A fragments per layer.  LDS pixels as in the one-group e4m3
+// pair kernel (64 bytes; chunk c at c ^ bit 2 of the column).
+// ---------------------------------------------------------------------
+struct Pair8WsLayout {
+  static constexpr int F = 64, PIXB = 64, CPP = 4, NTG = 256, NA = 10;
+  static constexpr int TH = kPair8WsTileH, TW = kPairTileW;
+  static constexpr int MH = TH + 2, MW = TW + 2, IH = TH + 4, IW = TW + 4;
+  static constexpr int IN_BYTES = IH * IW * PIXB;
+  static constexpr int MID_BYTES = MH * IW * PIXB;
+  static constexpr int LDS_BYTES = IN_BYTES + 2 * MID_BYTES + 4 * F * 4;   // + scale, bias per layer
+  static constexpr int NCHUNK = IH * IW * CPP, NLOAD = (NCHUNK + NTG - 1) / NTG;
+};
+static_assert(Pair8WsLayout::MW == 32 && Pair8WsLayout::IW == 34 && Pair8WsLayout::TH % 2 == 0 &&
+                  Pair8WsLayout::LDS_BYTES <= 160 * 1024 && Pair8WsLayout::PIXB == Pair8Layout::PIXB,
+              "e4m3 split-layer pair layout");
+
+// first and last B fragment of output row o
+__host__ __device__ constexpr int p8s_first(int o) { return (3 * o) / 2; }
+__host__ __device__ constexpr int p8s_last(int o) { return (3 * o + 8) / 2; }
+// row o holds accumulator slot o % NS from its first fragment until its
+// epilogue E fragments after its last: no two rows live at once may share one
+constexpr bool p8s_slots_ok(int NR, int NS, int E) {
+  const int NO = NR - 2, NF = 3 * NR / 2;
+  for (int m = 0; m <= NF + E; ++m)
+    for (int o1 = 0; o1 < NO; ++o1)
+      for (int o2 = o1 + 1; o2 < NO; ++o2)
+        if (o1 % NS == o2 % NS && p8s_first(o1) <= m && m <= p8s_last(o1) + E &&
+            p8s_first(o2) <= m && m <= p8s_last(o2) + E)
+          return false;
+  return true;
+}
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void conv_pair8_ws_kernel(ConvArgs a) {
+  using Lo = Pair8WsLayout;
+  constexpr int IW = Lo::IW, NLOAD = Lo::NLOAD;
+  constexpr int NS = 4, E = 1, PD = 1;            // accumulator slots; epilogue delay; B reads ahead
+  static_assert(p8s_slots_ok(Lo::IH, NS, E) && p8s_slots_ok(Lo::MH, NS, E), "accumulator slots");
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  uint8_t *lds_in = lds;
+  uint8_t *lds_mid = lds + Lo::IN_BYTES;          // two buffers of MID_BYTES
+  float *lds_ep = reinterpret_cast<float *>(lds_mid + 2 * Lo::MID_BYTES);   // [layer][scale | bias]
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int grp = wave >> 2, wq = wave & 3;       // layer (0: A, 1: B), channel block
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nwg = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3;
+  const int per_xcd = (nwg - xcd + 7) >> 3;
+  const int t_begin = (int)(((int64_t)a.n_tiles * xcd) >> 3);
+  const int t_end = (int)(((int64_t)a.n_tiles * (xcd + 1)) >> 3);
+
+  i32x8 W[Lo::NA];
+  {
+    const PNP_GLOBAL u32x4 *w = gp(reinterpret_cast<const u32x4 *>(grp ? a.wblob2 : a.wblob_rr));
+#pragma unroll
+    for (int j = 0; j < Lo::NA; ++j) {
+      const int i = ((j * 4 + wq) * 64 + lane) * 2;
+      const u32x4 w0 = w[i], w1 = w[i + 1];
+      W[j] = i32x8{(int)w0.x, (int)w0.y, (int)w0.z, (int)w0.w, (int)w1.x, (int)w1.y, (int)w1.z, (int)w1.w};
+    }
+  }
+  {
+    const float *src = tid < 64 ? a.oscale : tid < 128 ? a.bias : tid < 192 ? a.oscale2 : a.bias2;
+    if (tid < 256) lds_ep[tid] = gp(src)[tid & 63];
+  }
+  // the intermediates' columns MW .. IW-1 are read only for the two padding
+  // output columns and never written: zero both buffers once
+  for (int i = tid; i < 2 * Lo::MID_BYTES / 16; i += 2 * Lo::NTG)
+    reinterpret_cast<u32x4 *>(lds_mid)[i] = u32x4{0u, 0u, 0u, 0u};
+
+  // Window loads by the layer-A waves (256 lanes): load i takes chunk q =
+  // 256 i + t (t = tid mod 256) of the row-major window, pixel q / 4, chunk
+  // q % 4; lanes past the window repeat chunk t (storing the bytes its owner
+  // stores).  Positions beyond the one-pixel zero border read the border.
+  const int tl = tid & 255;
+  auto win_chunk = [&](int i) {
+    int q = 256 * i + tl;
+    asm volatile("" : "+v"(q));
+    return q < Lo::NCHUNK ? q : tl;
+  };
+  auto load_chunk = [&](const MidTile &c, int i) -> u32x4 {
+    const int q = win_chunk(i), p = q >> 2;
+    const int r = p / IW, col = p % IW;
+    const int Y = min(max(c.y0 - 2 + r, -1), c.ny) + 1, X = min(max(c.x0 - 2 + col, -1), c.nx) + 1;
+    return *reinterpret_cast<const PNP_GLOBAL u32x4 *>(
+        c.in + ((int64_t)Y * c.apitch + X) * Lo::PIXB + (q & 3) * 16);
+  };
+  auto put_chunk = [&](int i, const u32x4 &v) {
+    const int q = win_chunk(i), p = q >> 2;
+    *reinterpret_cast<u32x4 *>(lds_in + p8_off(p, p % IW, q & 3)) = v;
+  };
+
+  int tA = t_begin + slot;
+  if (tA >= t_end) return;                       // uniform over the workgroup
+  MidTile dA = mid_tile(a, tA), dB = dA;
+  u32x4 pre[NLOAD];
+  if (grp == 0) {
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) pre[i] = load_chunk(dA, i);
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) put_chunk(i, pre[i]);
+  }
+  // B fragment m = 3k + tau of a layer: lane group g < 2 reads unit 2m, g >= 2
+  // unit 2m + 1, i.e. (window row, dx) = (2k, 0) | (2k, 1) for tau = 0,
+  // (2k, 2) | (2k + 1, 0) for tau = 1, (2k + 1, 1) | (2k + 1, 2) for tau = 2;
+  // the pixel is in column 16h + dx + l16, chunks 2(g & 1) (lo) and
+  // 2(g & 1) + 1 (hi).  Column 16h + q swizzles as column q, so the address
+  // is 64 (2k IW + 16h) (an immediate) plus bl[tau][lo/hi] (per lane).
+  int bl[3][2];
+#pragma unroll
+  for (int tau = 0; tau < 3; ++tau)
+#pragma unroll
+    for (int hl = 0; hl < 2; ++hl) {
+      const int u = 2 * tau + (g >> 1), drow = u / 3, q = u % 3 + l16;
+      int v = drow * IW * Lo::PIXB + p8_off(q, q, 2 * (g & 1) + hl);
+      asm volatile("" : "+v"(v));
+      bl[tau][hl] = v;
+    }
+  __syncthreads();
+
+  const int cpos = 16 * (g & 1) + l16;           // column of this lane's pixel after the swap
+  const int cbyte = 16 * wq + 8 * (g >> 1);      // its 8 channels inside the pixel
+  const int mid_w = p8_off(cpos, cpos, wq) + 8 * (g >> 1);
+  bool haveB = false;
+  int it = 0;
+  while (true) {
+    const bool haveA = tA < t_end;                // uniform
+    const int tAn = tA + per_xcd;
+    const MidTile dAn = mid_tile(a, tAn < t_end ? tAn : t_begin);
+    f32x4 acc[NS][2];
+    i32x8 Bb[PD + 1][2];
+
+    auto layer = [&](const uint8_t *buf, const int (&base)[3][2], auto NRc, auto ep, auto pf) {
+      constexpr int NR = decltype(NRc)::value, NO = NR - 2, NF = 3 * NR / 2;
+      auto load_b = [&](auto mc) {
+        constexpr int m = decltype(mc)::value, k = m / 3, tau = m % 3;
+        static_for<0, 2>([&](auto hc) {
+          constexpr int c = (2 * k * IW + 16 * decltype(hc)::value) * Lo::PIXB;
+          const u32x4 lo = *reinterpret_cast<const u32x4 *>(buf + base[tau][0] + c);
+          const u32x4 hi = *reinterpret_cast<const u32x4 *>(buf + base[tau][1] + c);
+          Bb[m % (PD + 1)][decltype(hc)::value] =
+              i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        });
+      };
+      static_for<0, PD>(load_b);
+      static_for<0, NF>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        if constexpr (m + PD < NF) load_b(std::integral_constant<int, m + PD>{});
+        pf(mc);
+        static_for<0, NO>([&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          if constexpr (p8s_first(o) == m) {
+            acc[o % NS][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+            acc[o % NS][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+          }
+          if constexpr (p8s_first(o) <= m && m <= p8s_last(o)) {
+            constexpr int j = 2 * m - 3 * o + 1;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              acc[o % NS][h] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                  W[j], Bb[m % (PD + 1)][h], acc[o % NS][h], 0, 0, 0, 0, 0, 0);
+          }
+        });
+        static_for<0, NO>([&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          if constexpr (p8s_last(o) + E == m) ep(oc);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      static_for<0, NO>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        if constexpr (p8s_last(o) + E >= NF) ep(oc);
+      });
+    };
+
+    // scale, bias, ReLU, e4m3 with the next layer's scale, then halves
+    // swapped between neighbouring 16-lane rows: each lane holds 8 channels
+    // (8 bytes) of one pixel, block 0's for even rows, block 1's for odd rows
+    auto pack_row = [&](auto oc, int layer_i, float is) -> u32x2 {
+      constexpr int o = decltype(oc)::value;
+      const float *ep = lds_ep + layer_i * 2 * Lo::F;
+      const f32x4 osc = *reinterpret_cast<const f32x4 *>(ep + 16 * wq + 4 * g);
+      const f32x4 bia = *reinterpret_cast<const f32x4 *>(ep + Lo::F + 16 * wq + 4 * g);
+      uint32_t w[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f32x4 v = acc[o % NS][h];
+        // after the ReLU (fmaxf returns the non-NaN operand) no value is NaN
+        w[h] = pack_e4m3x4_nonan(fmaxf(fmaf(v[0], osc[0], bia[0]), 0.0f) * is,
+                                 fmaxf(fmaf(v[1], osc[1], bia[1]), 0.0f) * is,
+                                 fmaxf(fmaf(v[2], osc[2], bia[2]), 0.0f) * is,
+                                 fmaxf(fmaf(v[3], osc[3], bia[3]), 0.0f) * is);
+      }
+      const auto sw = __builtin_amdgcn_permlane16_swap(w[0], w[1], false, false);
+      return u32x2{sw[0], sw[1]};
+    };
+
+    if (grp == 0) {
+      if (haveA) {
+        // layer A of tile tA: intermediate rows into buffer it & 1, zero
+        // outside the image; the next tile's window is loaded meanwhile
+        uint8_t *mid = lds_mid + (it & 1) * Lo::MID_BYTES;
+        const uint32_t in_x = (unsigned)(dA.x0 - 1 + cpos) < (unsigned)dA.nx ? ~0u : 0u;
+        const float isA = a.out_inv_scale;
+        auto epA = [&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          const uint32_t in_y = (unsigned)(dA.y0 - 1 + o) < (unsigned)dA.ny ? ~0u : 0u;  // uniform
+          const uint32_t keep = in_y & in_x;
+          u32x2 q = pack_row(oc, 0, isA);
+          q &= u32x2{keep, keep};
+          *reinterpret_cast<u32x2 *>(mid + o * IW * Lo::PIXB + mid_w) = q;
+        };
+        auto pfA = [&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          if constexpr (m >= 2 && m < 2 + NLOAD) pre[m - 2] = load_chunk(dAn, m - 2);
+        };
+        layer(lds_in, bl, std::integral_constant<int, Lo::IH>{}, epA, pfA);
+      }
+    } else {
+      if (haveB) {
+        // layer B of the previous tile from buffer (it - 1) & 1 to memory;
+        // lanes outside the tile (and the padding columns) store to the trash
+        const uint8_t *mid = lds_mid + ((it - 1) & 1) * Lo::MID_BYTES;
+        const float isB = a.out_inv_scale2;
+        const int64_t trash_b = dB.trash * Lo::PIXB + cbyte;
+        const int64_t col_b = (int64_t)(dB.x0 + cpos + 1) * Lo::PIXB + cbyte;
+        const int64_t ok_c = cpos < dB.w ? -1 : 0;
+        auto epB = [&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          const int64_t ok = (o < dB.h ? -1 : 0) & ok_c;
+          const int64_t roff = (int64_t)(dB.y0 + o + 1) * dB.apitch * Lo::PIXB;
+          const int64_t bo = ((col_b + roff) & ok) | (trash_b & ~ok);
+          *reinterpret_cast<PNP_GLOBAL u32x2 *>(dB.out + bo) = pack_row(oc, 1, isB);
+        };
+        auto pfB = [&](auto) {};
+        layer(mid, bl, std::integral_constant<int, Lo::MH>{}, epB, pfB);
+      }
+    }
+    __syncthreads();                             // intermediate written / read, window read
+    if (!haveA) break;                           // uniform: the last tile's layer B is done
+    if (grp == 0) {
+#pragma unroll
+      for (int i = 0; i < NLOAD; ++i) put_chunk(i, pre[i]);
+    }
+    __syncthreads();                             // next window in place
+    dB = dA;
+    haveB = true;
+    dA = dAn;
+    tA = tAn;
+    ++it;
+  }
+}
+
 // G from the fused last layer's partials: G(p) = scale * sum over taps of the
 // tap's partial at the neighbour the tap reads, + bias.  The records' zero
 // border supplies the zero padding at the image edge.  A tile's records (its
@@ -2178,6 +2446,22 @@ hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, bool l
     return first ? launch_pair8_t<FMT_BF16, true, false>(a, n_wg, s)
                  : launch_pair8_t<FMT_BF16, false, false>(a, n_wg, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv_pair8_ws(const ConvArgs &a, int n_wg, hipStream_t s) {
+  if (!a.wblob_rr || !a.wblob2 || !a.bias || !a.bias2 || !a.oscale || !a.oscale2 || n_wg <= 0 ||
+      n_wg % 8 != 0)
+    return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&conv_pair8_ws_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       Pair8WsLayout::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(conv_pair8_ws_kernel, dim3(n_wg), dim3(512), Pair8WsLayout::LDS_BYTES, s, a);
+  return hipGetLastError();
 }
 
 bool last_pair8_fusable(int out_fmt2, int last_in_fmt, int last_cin, int last_cout) {

@@ -17,6 +17,7 @@ constexpr int kConvTileW = 32;     // convolution tiles are TH x 32 pixels
 constexpr int kPairTileH = 14;     // e4m3 pair kernel: output tiles of 14 x 30
 constexpr int kPairTileW = 30;
 constexpr int kPairWsTileH = 9;   // split-layer pair kernel: output tiles of 9 x 30
+constexpr int kPair8WsTileH = 20; // e4m3 split-layer pair kernel: output tiles of 20 x 30
 constexpr int kDdTile = 30;        // DDFB stage kernel: output tiles of 30 x 30
 constexpr int kMaxDdfbLayers = 8;  // DDFB iterations K
 constexpr int kMaxRBig = 64;       // largest blur half-width (L <= 129)

@@ -34,6 +34,7 @@ struct LayerPlan {
   int in_buf = 0, out_buf = 0;  // activation buffers read / written
   void *wblob = nullptr;    // middle layers: MFMA fragment order
   void *wblob_rr = nullptr; // e4m3 middle layers: row-reuse kernel's fragment order
+  void *wblob_sl = nullptr; // e4m3 middle layers: sliding tap pairs (split-layer pair kernel)
   float *wf32 = nullptr;    // first / last layer: [c][9]
   float *bias = nullptr, *oscale = nullptr;
 };
@@ -67,6 +68,7 @@ struct Job {
   std::vector<TileRef> conv_tiles, upd_tiles;   // job field = 0 (set at planning)
   std::vector<TileRef> pair_tiles;              // e4m3 pair kernel: whole-image tiling
   std::vector<TileRef> pair_ws_tiles;           // split-layer pair kernel (bf16)
+  std::vector<TileRef> pair8ws_tiles;           // split-layer pair kernel (e4m3)
   std::vector<TileRef> ddfb_tiles;              // DDFB stages: whole-image tiling
 };
 
@@ -144,9 +146,10 @@ class Engine {
   Status run_prior_other(int64_t tick);
   JobDesc *d_jobs = nullptr;
   TileRef *d_conv = nullptr, *d_upd = nullptr, *d_pair = nullptr, *d_pair_ws = nullptr,
-          *d_ddfb = nullptr;
-  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0, cap_pair = 0, cap_pair_ws = 0, cap_ddfb = 0;
-  int n_conv = 0, n_upd = 0, n_pair = 0, n_pair_ws = 0, n_ddfb = 0, max_r = 0;
+          *d_pair8ws = nullptr, *d_ddfb = nullptr;
+  size_t cap_jobs = 0, cap_conv = 0, cap_upd = 0, cap_pair = 0, cap_pair_ws = 0, cap_pair8ws = 0,
+         cap_ddfb = 0;
+  int n_conv = 0, n_upd = 0, n_pair = 0, n_pair_ws = 0, n_pair8ws = 0, n_ddfb = 0, max_r = 0;
   bool uniform_r = true;      // every resident job has blur half-width max_r
   int zmode = 0;              // JobDesc::zmode of the resident jobs (all equal)
   bool big = false;           // the resident jobs take the large-blur path

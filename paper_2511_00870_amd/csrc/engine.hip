@@ -84,6 +84,7 @@ Engine::~Engine() {
   hipFree(d_upd);
   hipFree(d_pair);
   hipFree(d_pair_ws);
+  hipFree(d_pair8ws);
   hipFree(d_ddfb);
   for (auto &r : prof_pending) {
     hipEventDestroy(r.a);
@@ -283,6 +284,22 @@ Status Engine::set_net(int K, const int32_t *ch, const float *w, const float *b,
         HIPOK(hipMalloc(&L.wblob_rr, rr.size()));
         net.allocs.push_back(L.wblob_rr);
         HIPOK(hipMemcpy(L.wblob_rr, rr.data(), rr.size(), hipMemcpyHostToDevice));
+        // split-layer pair kernel: fragment j holds taps j - 1 (lane groups
+        // 0-1) and j (groups 2-3), taps numbered 3 dy + dx, zero outside 0..8
+        std::vector<uint8_t> sl((size_t)10 * MB * 64 * 32, 0);
+        for (int jf = 0; jf < 10; ++jf)
+          for (int mb = 0; mb < MB; ++mb)
+            for (int l = 0; l < 64; ++l) {
+              const int g = l >> 4, tap = g < 2 ? jf - 1 : jf;
+              if (tap < 0 || tap > 8) continue;
+              const int co = mb * 16 + (l & 15);
+              for (int e = 0; e < 32; ++e)
+                sl[(((size_t)jf * MB + mb) * 64 + l) * 32 + e] =
+                    host_f32_to_e4m3(W(co, 32 * (g & 1) + e, tap));
+            }
+        HIPOK(hipMalloc(&L.wblob_sl, sl.size()));
+        net.allocs.push_back(L.wblob_sl);
+        HIPOK(hipMemcpy(L.wblob_sl, sl.data(), sl.size(), hipMemcpyHostToDevice));
       }
     }
     woff += (size_t)L.cin * L.cout * 9;
@@ -721,6 +738,7 @@ Status Engine::make_job(const pnpula_config *c, Job **out) {
   // previous one's while it is still in that XCD's L2
   make_tiles(j->pair_tiles, ny, nx, ny, 32 * kPairTileW, kPairTileH, kPairTileW);
   make_tiles(j->pair_ws_tiles, ny, nx, ny, 32 * kPairTileW, kPairWsTileH, kPairTileW);
+  make_tiles(j->pair8ws_tiles, ny, nx, ny, 32 * kPairTileW, kPair8WsTileH, kPairTileW);
   if (c->prior == PNPULA_PRIOR_DDFB) make_tiles(j->ddfb_tiles, ny, nx, ny, nx, kDdTile, kDdTile);
   if (hipStreamSynchronize(stream) != hipSuccess)
     return fail(Status::fail(PNPULA_EDEVICE, "upload failed"));
@@ -738,7 +756,7 @@ void Engine::free_job(Job *j) {
 // plans
 // ---------------------------------------------------------------------
 Status Engine::rebuild_plan() {
-  std::vector<TileRef> conv, upd, pair, pair_ws, ddfb;
+  std::vector<TileRef> conv, upd, pair, pair_ws, pair8ws, ddfb;
   max_r = 0;
   uniform_r = true;
   max_kpitch = 8;
@@ -771,6 +789,10 @@ Status Engine::rebuild_plan() {
       t.job = (int)ji;
       pair_ws.push_back(t);
     }
+    for (TileRef t : j->pair8ws_tiles) {
+      t.job = (int)ji;
+      pair8ws.push_back(t);
+    }
     if (ji > 0 && j->d.r != max_r) uniform_r = false;
     max_r = std::max(max_r, j->d.r);
   }
@@ -792,6 +814,7 @@ Status Engine::rebuild_plan() {
   TRY(grow(&d_upd, cap_upd, std::max<size_t>(upd.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_pair, cap_pair, std::max<size_t>(pair.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_pair_ws, cap_pair_ws, std::max<size_t>(pair_ws.size(), 1), sizeof(TileRef)));
+  TRY(grow(&d_pair8ws, cap_pair8ws, std::max<size_t>(pair8ws.size(), 1), sizeof(TileRef)));
   TRY(grow(&d_jobs, cap_jobs, std::max<size_t>(resident.size(), 1), sizeof(JobDesc)));
   TRY(grow(&d_ddfb, cap_ddfb, std::max<size_t>(ddfb.size(), 1), sizeof(TileRef)));
   if (!ddfb.empty())
@@ -805,9 +828,12 @@ Status Engine::rebuild_plan() {
     HIPOK(hipMemcpyAsync(d_pair, pair.data(), pair.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
   if (!pair_ws.empty())
     HIPOK(hipMemcpyAsync(d_pair_ws, pair_ws.data(), pair_ws.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
+  if (!pair8ws.empty())
+    HIPOK(hipMemcpyAsync(d_pair8ws, pair8ws.data(), pair8ws.size() * sizeof(TileRef), hipMemcpyHostToDevice, stream));
   n_conv = (int)conv.size();
   n_pair = (int)pair.size();
   n_pair_ws = (int)pair_ws.size();
+  n_pair8ws = (int)pair8ws.size();
   n_upd = (int)upd.size();
   plan_dirty = false;
   return upload_descs();
@@ -1063,7 +1089,15 @@ Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool 
   const int n_wg = std::max(8, std::min(n_cu * per_cu, need) / 8 * 8);
   ProfileRec pr;
   if (prof) prof_begin(6, &pr);
-  if (e4m3) {
+  if (e4m3 && !first && !last && B.out_fmt == FMT_E4M3 && A.wblob_sl && B.wblob_sl) {
+    // the split-layer form: one workgroup of 8 waves per CU
+    a.wblob_rr = A.wblob_sl;
+    a.wblob2 = B.wblob_sl;
+    a.tiles = d_pair8ws;
+    a.n_tiles = n_pair8ws;
+    const int need8 = ((n_pair8ws + 7) / 8) * 8;
+    HIPOK(launch_conv_pair8_ws(a, std::max(8, std::min(n_cu, need8) / 8 * 8), stream));
+  } else if (e4m3) {
     HIPOK(launch_conv_pair8(a, B.out_fmt, first, last, n_wg, stream));
   } else {
     a.tiles = d_pair_ws;

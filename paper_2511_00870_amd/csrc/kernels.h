@@ -116,6 +116,12 @@ bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt
 // JobDesc::S (last_w; out_fmt2 must be bf16)
 hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, bool last, int n_wg,
                              hipStream_t s);
+// two consecutive e4m3 middle layers on separate waves with the taps packed
+// without zero slots (a: as for launch_conv_pair8, with wblob_rr / wblob2 the
+// layers' sliding-pair weights; e4m3 output; 8 waves per workgroup, one
+// workgroup per CU; tiles of kPair8WsTileH x kPairTileW); n_wg a positive
+// multiple of 8
+hipError_t launch_conv_pair8_ws(const ConvArgs &a, int n_wg, hipStream_t s);
 bool last_pair8_fusable(int out_fmt2, int last_in_fmt, int last_cin, int last_cout);
 bool first_pair8_fusable(int in_fmt0, int out_fmt0, int cin0, int cout0, int relu0);
 bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
