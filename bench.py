@@ -73,7 +73,8 @@ MFMA_CLASSES = {
         2, 0),
 }
 # class 6 for e4m3 networks
-PAIR8_CLASS = ("conv_pair8_kernel (two e4m3 middle layers)", "conv_pair8_kernel", 2, 0)
+PAIR8_CLASS = ("e4m3 layer pairs (conv_pair8_ws_kernel; conv_pair8_kernel with the first or last "
+               "layer), averaged over the step's pair launches", "conv_pair8", 2, 0)
 
 
 # sources of the kernels the bf16 step runs (the denoiser layers and the
