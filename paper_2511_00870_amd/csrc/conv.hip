@@ -1642,10 +1642,16 @@ void conv_pair8_kernel(ConvArgs a) {
       WB[s] = i32x8{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
     }
   }
+  // Per-channel scale and bias of each layer.  Where the output is e4m3 they
+  // are stored times the next layer's inverse activation scale, a power of
+  // two, so fma(v, scale, bias) is the scaled value exactly (rounding commutes
+  // with a power-of-two factor) and the epilogue is one fma and one clamp.
   {
     const float *src = tid < 64 ? a.oscale : tid < 128 ? a.bias : tid < 192 ? a.oscale2 : a.bias2;
-    lds_ep[tid] = gp(src)[tid & 63];
-    if (FIRST && tid < 128) lds_ep0[tid] = gp(tid < 64 ? a.first_oscale : a.first_bias)[tid & 63];
+    const float is = tid < 128 ? a.out_inv_scale : (OUT2 == FMT_E4M3 ? a.out_inv_scale2 : 1.0f);
+    lds_ep[tid] = gp(src)[tid & 63] * is;
+    if (FIRST && tid < 128)
+      lds_ep0[tid] = gp(tid < 64 ? a.first_oscale : a.first_bias)[tid & 63] * a.first_out_inv_scale;
   }
   // fused first layer: this wave's A fragment (rows = its 16 channels, K =
   // the 9 taps padded to 16: lane group g holds taps 4g .. 4g+3) and the
@@ -1747,11 +1753,8 @@ void conv_pair8_kernel(ConvArgs a) {
                                                             0, 0, 0);
     const bool inside = (unsigned)(c.y0 - 2 + l0_wr) < (unsigned)c.ny &&
                         (unsigned)(c.x0 - 2 + l0_wc) < (unsigned)c.nx;
-    const float is0 = a.first_out_inv_scale;
-    uint32_t w = pack_e4m3x4_nonan(fmaxf(d[0] * sc0[0] + bi0[0], 0.0f) * is0,
-                                   fmaxf(d[1] * sc0[1] + bi0[1], 0.0f) * is0,
-                                   fmaxf(d[2] * sc0[2] + bi0[2], 0.0f) * is0,
-                                   fmaxf(d[3] * sc0[3] + bi0[3], 0.0f) * is0);
+    uint32_t w = pack_e4m3x4_relu(fmaf(d[0], sc0[0], bi0[0]), fmaf(d[1], sc0[1], bi0[1]),
+                                  fmaf(d[2], sc0[2], bi0[2]), fmaf(d[3], sc0[3], bi0[3]));
     w = inside ? w : 0u;
     if (!tail_out)
       *reinterpret_cast<uint32_t *>(lds_in + (16 * blk + l16) * Lo::PIXB + 4 * g +
@@ -1851,11 +1854,11 @@ void conv_pair8_kernel(ConvArgs a) {
       static_for<(NR - 3 > 0 ? NR - 3 : 0), NO>(ep);
     };
 
-    // Epilogue: scale, bias, ReLU, e4m3 with the next layer's scale; then
-    // halves are swapped between neighbouring 16-lane rows so that each lane
-    // holds 8 channels (8 bytes) of one pixel: block 0's for even rows, block
-    // 1's for odd rows.
-    auto pack_row = [&](auto oc, int layer_i, float is) -> u32x2 {
+    // Epilogue: scale and bias (both already times the next layer's inverse
+    // activation scale), ReLU, e4m3; then halves are swapped between
+    // neighbouring 16-lane rows so that each lane holds 8 channels (8 bytes)
+    // of one pixel: block 0's for even rows, block 1's for odd rows.
+    auto pack_row = [&](auto oc, int layer_i) -> u32x2 {
       constexpr int o = decltype(oc)::value;
       const float *ep = lds_ep + layer_i * 2 * Lo::F;
       const f32x4 osc = *reinterpret_cast<const f32x4 *>(ep + 16 * wave + 4 * g);
@@ -1864,11 +1867,8 @@ void conv_pair8_kernel(ConvArgs a) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const f32x4 v = acc[o & 3][h];
-        // after the ReLU (fmaxf returns the non-NaN operand) no value is NaN
-        w[h] = pack_e4m3x4_nonan(fmaxf(fmaf(v[0], osc[0], bia[0]), 0.0f) * is,
-                           fmaxf(fmaf(v[1], osc[1], bia[1]), 0.0f) * is,
-                           fmaxf(fmaf(v[2], osc[2], bia[2]), 0.0f) * is,
-                           fmaxf(fmaf(v[3], osc[3], bia[3]), 0.0f) * is);
+        w[h] = pack_e4m3x4_relu(fmaf(v[0], osc[0], bia[0]), fmaf(v[1], osc[1], bia[1]),
+                                fmaf(v[2], osc[2], bia[2]), fmaf(v[3], osc[3], bia[3]));
       }
       const auto s = __builtin_amdgcn_permlane16_swap(w[0], w[1], false, false);
       return u32x2{s[0], s[1]};
@@ -1880,12 +1880,11 @@ void conv_pair8_kernel(ConvArgs a) {
 
     // layer A: intermediate rows into LDS (zero outside the image)
     const uint32_t in_x = (unsigned)(cur.x0 - 1 + cpos) < (unsigned)cur.nx ? ~0u : 0u;
-    const float isA = a.out_inv_scale, isB = a.out_inv_scale2;
     auto epA = [&](auto oc) {
       constexpr int o = decltype(oc)::value;
       const uint32_t in_y = (unsigned)(cur.y0 - 1 + o) < (unsigned)cur.ny ? ~0u : 0u;  // uniform
       const uint32_t keep = in_y & in_x;
-      u32x2 q = pack_row(oc, 0, isA);
+      u32x2 q = pack_row(oc, 0);
       q &= u32x2{keep, keep};
       *reinterpret_cast<u32x2 *>(lds_mid + o * IW * Lo::PIXB + mid_w) = q;
     };
@@ -1968,7 +1967,7 @@ void conv_pair8_kernel(ConvArgs a) {
         const auto sy = __builtin_amdgcn_permlane16_swap(w[0].y, w[1].y, false, false);
         *reinterpret_cast<PNP_GLOBAL u32x4 *>(cur.out + bo) = u32x4{sx[0], sy[0], sx[1], sy[1]};
       } else {
-        *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + bo) = pack_row(oc, 1, isB);
+        *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + bo) = pack_row(oc, 1);
       }
     };
     if constexpr (L0_IN_B) l0_reset();
@@ -2082,9 +2081,12 @@ void conv_pair8_ws_kernel(ConvArgs a) {
       W[j] = i32x8{(int)w0.x, (int)w0.y, (int)w0.z, (int)w0.w, (int)w1.x, (int)w1.y, (int)w1.z, (int)w1.w};
     }
   }
-  {
+  // per-channel scale and bias of each layer, times the next layer's inverse
+  // activation scale (a power of two: the fma then gives the scaled value
+  // exactly)
+  if (tid < 256) {
     const float *src = tid < 64 ? a.oscale : tid < 128 ? a.bias : tid < 192 ? a.oscale2 : a.bias2;
-    if (tid < 256) lds_ep[tid] = gp(src)[tid & 63];
+    lds_ep[tid] = gp(src)[tid & 63] * (tid < 128 ? a.out_inv_scale : a.out_inv_scale2);
   }
   // the intermediates' columns MW .. IW-1 are read only for the two padding
   // output columns and never written: zero both buffers once
@@ -2196,10 +2198,11 @@ void conv_pair8_ws_kernel(ConvArgs a) {
       });
     };
 
-    // scale, bias, ReLU, e4m3 with the next layer's scale, then halves
-    // swapped between neighbouring 16-lane rows: each lane holds 8 channels
-    // (8 bytes) of one pixel, block 0's for even rows, block 1's for odd rows
-    auto pack_row = [&](auto oc, int layer_i, float is) -> u32x2 {
+    // scale and bias (times the next layer's inverse activation scale),
+    // ReLU, e4m3, then halves swapped between neighbouring 16-lane rows: each
+    // lane holds 8 channels (8 bytes) of one pixel, block 0's for even rows,
+    // block 1's for odd rows
+    auto pack_row = [&](auto oc, int layer_i) -> u32x2 {
       constexpr int o = decltype(oc)::value;
       const float *ep = lds_ep + layer_i * 2 * Lo::F;
       const f32x4 osc = *reinterpret_cast<const f32x4 *>(ep + 16 * wq + 4 * g);
@@ -2208,11 +2211,8 @@ void conv_pair8_ws_kernel(ConvArgs a) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const f32x4 v = acc[o % NS][h];
-        // after the ReLU (fmaxf returns the non-NaN operand) no value is NaN
-        w[h] = pack_e4m3x4_nonan(fmaxf(fmaf(v[0], osc[0], bia[0]), 0.0f) * is,
-                                 fmaxf(fmaf(v[1], osc[1], bia[1]), 0.0f) * is,
-                                 fmaxf(fmaf(v[2], osc[2], bia[2]), 0.0f) * is,
-                                 fmaxf(fmaf(v[3], osc[3], bia[3]), 0.0f) * is);
+        w[h] = pack_e4m3x4_relu(fmaf(v[0], osc[0], bia[0]), fmaf(v[1], osc[1], bia[1]),
+                                fmaf(v[2], osc[2], bia[2]), fmaf(v[3], osc[3], bia[3]));
       }
       const auto sw = __builtin_amdgcn_permlane16_swap(w[0], w[1], false, false);
       return u32x2{sw[0], sw[1]};
@@ -2224,12 +2224,11 @@ void conv_pair8_ws_kernel(ConvArgs a) {
         // outside the image; the next tile's window is loaded meanwhile
         uint8_t *mid = lds_mid + (it & 1) * Lo::MID_BYTES;
         const uint32_t in_x = (unsigned)(dA.x0 - 1 + cpos) < (unsigned)dA.nx ? ~0u : 0u;
-        const float isA = a.out_inv_scale;
         auto epA = [&](auto oc) {
           constexpr int o = decltype(oc)::value;
           const uint32_t in_y = (unsigned)(dA.y0 - 1 + o) < (unsigned)dA.ny ? ~0u : 0u;  // uniform
           const uint32_t keep = in_y & in_x;
-          u32x2 q = pack_row(oc, 0, isA);
+          u32x2 q = pack_row(oc, 0);
           q &= u32x2{keep, keep};
           *reinterpret_cast<u32x2 *>(mid + o * IW * Lo::PIXB + mid_w) = q;
         };
@@ -2244,7 +2243,6 @@ void conv_pair8_ws_kernel(ConvArgs a) {
         // layer B of the previous tile from buffer (it - 1) & 1 to memory;
         // lanes outside the tile (and the padding columns) store to the trash
         const uint8_t *mid = lds_mid + ((it - 1) & 1) * Lo::MID_BYTES;
-        const float isB = a.out_inv_scale2;
         const int64_t trash_b = dB.trash * Lo::PIXB + cbyte;
         const int64_t col_b = (int64_t)(dB.x0 + cpos + 1) * Lo::PIXB + cbyte;
         const int64_t ok_c = cpos < dB.w ? -1 : 0;
@@ -2253,7 +2251,7 @@ void conv_pair8_ws_kernel(ConvArgs a) {
           const int64_t ok = (o < dB.h ? -1 : 0) & ok_c;
           const int64_t roff = (int64_t)(dB.y0 + o + 1) * dB.apitch * Lo::PIXB;
           const int64_t bo = ((col_b + roff) & ok) | (trash_b & ~ok);
-          *reinterpret_cast<PNP_GLOBAL u32x2 *>(dB.out + bo) = pack_row(oc, 1, isB);
+          *reinterpret_cast<PNP_GLOBAL u32x2 *>(dB.out + bo) = pack_row(oc, 1);
         };
         auto pfB = [&](auto) {};
         layer(mid, bl, std::integral_constant<int, Lo::MH>{}, epB, pfB);

@@ -248,6 +248,14 @@ __device__ __forceinline__ uint32_t pack_e4m3x4(float a, float b, float c, float
 }
 // four values known not to be NaN (e.g. after a ReLU taken with fmaxf,
 // which returns the non-NaN operand): no fallback branch
+// ReLU and e4m3 of four values already multiplied by the activation scale's
+// inverse: the clamp to [0, 448] is the ReLU and the saturation at once
+__device__ __forceinline__ float e4m3_relu_clamp(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 448.0f); }
+__device__ __forceinline__ uint32_t pack_e4m3x4_relu(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_relu_clamp(a), e4m3_relu_clamp(b), 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_relu_clamp(c), e4m3_relu_clamp(d), w, true);
+  return (uint32_t)w;
+}
 __device__ __forceinline__ uint32_t pack_e4m3x4_nonan(float a, float b, float c, float d) {
   int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(a), e4m3_clamp(b), 0, false);
   w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(c), e4m3_clamp(d), w, true);
