@@ -74,11 +74,18 @@ def _propagate(F, wabs):
 def _flip_bound(v, fmt, scale, e):
     """how far the rounded value of v can move when v itself is only known
     within e: one code step (or 2e, when larger) where v lies within e of a
-    rounding boundary, zero elsewhere; returns (bound, possibly-flipped)"""
+    rounding boundary, zero elsewhere; returns (bound, possibly-flipped).
+    The boundaries are the midpoints to the neighbouring codes: the gap away
+    from zero is the code's own step, the gap toward zero the step just inside
+    its magnitude, which is half as large when the code is a power of two (the
+    lower binade's spacing)."""
     q = _q(v, fmt, scale)
-    step = _ulp(v, fmt, scale)
-    near = np.abs(np.abs(v - q) - step / 2) <= e
-    return np.where(near, np.maximum(step, 2 * e), 0.0), near
+    up = _ulp(q, fmt, scale)
+    dn = _ulp(q * (1.0 - 2.0 ** -12), fmt, scale)
+    sgn = np.where(q < 0, -1.0, 1.0)
+    dist = np.minimum(np.abs(v - (q + sgn * up / 2)), np.abs(v - (q - sgn * dn / 2)))
+    near = dist <= e
+    return np.where(near, np.maximum(up, 2 * e), 0.0), near
 
 
 def _scales(ch, ws, bs, fmt, x):
