@@ -116,13 +116,15 @@ def test_denoiser_low_precision_single_mid_layer(prec):
 
 @pytest.mark.parametrize("prec", [P.PNPULA_BF16, P.PNPULA_FP8_E4M3])
 def test_denoiser_low_precision_deep(prec):
-    """K = 8 in bf16 / e4m3 against the emulating oracle: rounding flips
-    propagate, so the bar is a relative error, small against the format's
-    own step (2^-8 bf16, 2^-4 e4m3)."""
+    """K = 8 in bf16 / e4m3 against the emulating oracle, with biases
+    U(-0.05, 0.05) so that the activations keep their size through the
+    layers: rounding flips propagate, so the bar is a relative error, small
+    against the format's own step (2^-8 bf16, 2^-4 e4m3).  Measured 2.4e-4
+    (bf16) and 8.3e-4 (e4m3); the bars are about four times that."""
     say(f"case deep denoiser precision={prec}")
     ny, nx = 64, 96
     K = 8
-    ch, ws, bs = W.denoiser_weights(K, 64, seed=3)
+    ch, ws, bs = W.denoiser_weights(K, 64, seed=3, bias_scale=0.05)
     x = W.synthetic_image(ny, nx, 29)
     fmt = W.layer_formats(K, prec)
     scales = [1.0] * K
@@ -139,7 +141,7 @@ def test_denoiser_low_precision_deep(prec):
     G = ctx.denoise(x.astype(np.float32))
     e = rel(G, ref[-1][0])
     say(f"  G rel {e:.2e}")
-    assert e <= (5e-3 if prec == P.PNPULA_BF16 else 5e-2)
+    assert e <= (1e-3 if prec == P.PNPULA_BF16 else 4e-3)
 
 
 @pytest.mark.parametrize("shape,block", [((53, 83), 32), ((40, 70), 64)])
@@ -202,19 +204,18 @@ def test_layer_pairs_match_per_layer_path(shape, block):
 @pytest.mark.parametrize("shape,block", [((5, 7), 32), ((28, 60), 64), ((53, 83), 32),
                                          ((150, 190), 64), ((403, 371), 128)])
 def test_fp8_layer_pairs_match_per_layer_path(shape, block):
-    """e4m3 middle layers, 8 layers: the sampler's path (layers 1-2 and 3-4
-    two per kernel, e4m3 in and out with per-channel scales) against the
-    layer-by-layer path (tight: both take the same products, summed in a
-    different order) and the emulating oracle.  Against the oracle the bar
-    is two e4m3 steps: per layer a few codes in a thousand round the other
-    way (the single-layer code-match test bounds that at 2e-3), and six e4m3
-    layers compound them; for these seeds both GPU paths land at 7-10%
-    (the deep-network test's 5e-2 holds for its seed), while a wrong tap,
-    channel or scale gives errors of order one."""
+    """e4m3 middle layers, 8 layers, biases U(-0.05, 0.05): the sampler's
+    path (pairs of layers per kernel, e4m3 in and out with per-channel
+    scales) against the layer-by-layer path (tight: both take the same
+    products, summed in a different order; measured below 5e-8) and the
+    emulating oracle.  Against the oracle per layer a few codes in a
+    thousand round the other way (the single-layer code-match test bounds
+    that at 2e-3) and six e4m3 layers compound them: measured up to 4.6e-3,
+    bar 2e-2, while a wrong tap, channel or scale gives errors of order one."""
     ny, nx = shape
     say(f"case e4m3 layer pairs {ny}x{nx} block={block}")
     K = 8
-    ch, ws, bs = W.denoiser_weights(K, 64, seed=17)
+    ch, ws, bs = W.denoiser_weights(K, 64, seed=17, bias_scale=0.05)
     x = W.synthetic_image(ny, nx, 41)
     fmt = W.layer_formats(K, P.PNPULA_FP8_E4M3)
     small = ny * nx <= 150 * 190
@@ -240,8 +241,8 @@ def test_fp8_layer_pairs_match_per_layer_path(shape, block):
         e_f = e_l = 0.0                                  # per-layer path checked above
     say(f"  fused {e_f:.2e}  per-layer {e_l:.2e}  fused vs per-layer {e_fl:.2e}")
     assert np.all(np.isfinite(G_fused))
-    assert e_fl <= 1e-2
-    assert e_f <= 0.125 and e_l <= 0.125
+    assert e_fl <= 1e-5
+    assert e_f <= 2e-2 and e_l <= 2e-2
 
 
 @pytest.mark.parametrize("K", [3, 4, 5, 6, 7])
