@@ -11,9 +11,11 @@
 //   2. gdat = K^T res / s2 on every pixel;
 // and the update reads gdat.  K x = corr(x, flip(k)), K^T res = corr(res, k).
 // Each workgroup computes one 32 x 64 output tile from an LDS window of
-// (32 + 2r) x (64 + 2r) pixels; each thread keeps a row of 8 outputs in
-// registers and walks the kernel in chunks of 8 taps (16 window values read
-// as four 16-byte LDS reads, 8 taps from scalar registers, 64 FMAs).
+// (32 + 2r) x (64 + 2r) pixels, on the matrix cores: for one kernel row a,
+// out[y][x0 + n] = sum_j win[y + a][x0 + j] k[a][j - n] is a GEMM whose B
+// operand is a band (Toeplitz) slice of that row, so v_mfma_f32_16x16x4f32
+// takes 16 output rows x 16 columns per block and 4 shifts j per K step
+// (L + 15 shifts per row: 1 + 15/L times the algorithmic work).
 #include <mutex>
 
 #include "device_common.h"
@@ -25,47 +27,92 @@ namespace {
 constexpr int kBThreads = 256;
 typedef float b_f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int blur_ww(int kpitch) { return kUpdTileW + kpitch + 8; }
+typedef float b_f32x4m __attribute__((ext_vector_type(4)));
 
-// acc[o] = sum_{a,b} kc[a][b] win(ti + a, c0 + o + b), o = 0..7, for the
-// thread's row ti = tid / 8 and columns c0 = 8 (tid % 8) of a 32 x 64 output
-// tile; the window (32 + 2r) x (64 + 2r) starts r rows / columns before the
-// tile and is filled by load(Y, X) (global coordinates), zero beyond it
+// K steps (4 shifts each) per kernel row, a multiple of four (steps past the
+// band meet zero weights), and the LDS layout: the window's
+// row pitch is at least the columns the K steps read (16 w + 4 NJ) and 4 mod
+// 64, so the 16 rows x 4 columns of an A fragment fall on 64 distinct banks;
+// two kernel-row buffers with 16 zeros on either side supply the band's
+// zero weights
+__host__ __device__ constexpr int blur_nj(int L) { return ((L + 15 + 3) / 4 + 3) / 4 * 4; }
+__host__ __device__ constexpr int blur_wwm(int r) {
+  const int need = 48 + 4 * blur_nj(2 * r + 1);
+  return (need + 59) / 64 * 64 + 4;
+}
+__host__ __device__ constexpr int blur_kb(int r) { return 4 * blur_nj(2 * r + 1) + 32; }
+
+// acc[mb] (mb = 0, 1) = the 16 x 16 output block at rows 16 mb .. 16 mb + 15
+// and columns 16 w .. 16 w + 15 of a 32 x 64 output tile (w = the wave):
+// lane l holds rows 16 mb + 4 (l / 16) + i (i = 0..3), column 16 w + l % 16,
+// of sum_{a,b} kc[a][b] win(row + a, col + b).  The window (32 + 2r) x
+// (64 + 2r) starts r rows / columns before the tile and is filled by
+// load(Y, X) (global coordinates), zero beyond it; kernel row a goes through
+// an LDS buffer (row a + 1 is loaded into a register while row a is used and
+// stored into the other buffer before the row's barrier).
 template <class Load>
 __device__ __forceinline__ void corr_tile(float *sw, const PNP_CONST TileRef &tl, int r, int Lp,
-                                          const PNP_CONST float *kc, Load load, float acc[8]) {
+                                          const PNP_CONST float *kc, Load load, b_f32x4m acc[2]) {
   constexpr int TH = kUpdTileH, TW = kUpdTileW;
-  const int L = 2 * r + 1;
-  const int WH = TH + 2 * r, WWp = blur_ww(Lp), WV = TW + 2 * r;
-  const int tid = threadIdx.x;
-  for (int q = tid; q < WH * WWp; q += kBThreads) {
-    const int i = q / WWp, c = q % WWp;
+  static_assert(TH == 32 && TW == 64 && kBThreads == 256, "two 16-row blocks per wave");
+  const int L = 2 * r + 1, NJ = blur_nj(L), KB = blur_kb(r);
+  const int WH = TH + 2 * r, WW = blur_wwm(r), WV = TW + 2 * r;
+  float *kb = sw + WH * WW;                      // two rows of KB floats
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 15, k = lane >> 4;
+  for (int q = tid; q < WH * WW; q += kBThreads) {
+    const int i = q / WW, c = q % WW;
     sw[q] = c < WV ? load(tl.y0 - r + i, tl.x0 - r + c) : 0.0f;
   }
+  for (int q = tid; q < 2 * KB; q += kBThreads) {
+    const int t = q % KB - 16;
+    kb[q] = (q < KB && t >= 0 && t < L) ? kc[t] : 0.0f;
+  }
   __syncthreads();
-  const int ti = tid >> 3, c0 = 8 * (tid & 7);
+  acc[0] = b_f32x4m{0.f, 0.f, 0.f, 0.f};
+  acc[1] = b_f32x4m{0.f, 0.f, 0.f, 0.f};
+  // A: window row (16 mb + m + a), column 16 w + 4 js + k; B: the band entry
+  // k[a][4 js + k - n] for this lane's n = m
+  const float *wa = sw + m * WW + 16 * w + k;
+  const int bo = 16 + k - m;
+  for (int a = 0; a < L; ++a) {
+    // the next kernel row: loaded now, stored after this row's MFMAs
+    const bool nk = a + 1 < L && tid < L;
+    const float kn = nk ? kc[(int64_t)(a + 1) * Lp + tid] : 0.0f;
+    const float *kr = kb + (a & 1) * KB + bo;
+    const float *w0 = wa + a * WW, *w1 = w0 + 16 * WW;
+    // K steps in batches of four, the next batch's operands read from LDS
+    // before this batch's MFMAs
+    float ca[2][4], cb[4];
 #pragma unroll
-  for (int o = 0; o < 8; ++o) acc[o] = 0.0f;
-  for (int ka = 0; ka < L; ++ka) {
-    const float *row = sw + (ti + ka) * WWp + c0;
-    const PNP_CONST float *kr = kc + ka * Lp;
-    for (int b0 = 0; b0 < Lp; b0 += 8) {
-      float xv[16];
+    for (int u = 0; u < 4; ++u) {
+      cb[u] = kr[4 * u];
+      ca[0][u] = w0[4 * u];
+      ca[1][u] = w1[4 * u];
+    }
+    for (int jb = 0; jb < NJ; jb += 4) {
+      float na[2][4], nb[4];
+      if (jb + 4 < NJ) {
 #pragma unroll
-      for (int v4 = 0; v4 < 4; ++v4) {
-        const b_f32x4 u = *reinterpret_cast<const b_f32x4 *>(row + b0 + 4 * v4);
-        xv[4 * v4] = u.x;
-        xv[4 * v4 + 1] = u.y;
-        xv[4 * v4 + 2] = u.z;
-        xv[4 * v4 + 3] = u.w;
+        for (int u = 0; u < 4; ++u) {
+          nb[u] = kr[4 * (jb + 4 + u)];
+          na[0][u] = w0[4 * (jb + 4 + u)];
+          na[1][u] = w1[4 * (jb + 4 + u)];
+        }
       }
 #pragma unroll
-      for (int bb = 0; bb < 8; ++bb) {
-        const float wv = kr[b0 + bb];
+      for (int u = 0; u < 4; ++u) {
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[0][u], cb[u], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[1][u], cb[u], acc[1], 0, 0, 0);
+      }
 #pragma unroll
-        for (int o = 0; o < 8; ++o) acc[o] = fmaf(wv, xv[o + bb], acc[o]);
+      for (int u = 0; u < 4; ++u) {
+        cb[u] = nb[u];
+        ca[0][u] = na[0][u];
+        ca[1][u] = na[1][u];
       }
     }
+    if (nk) kb[((a + 1) & 1) * KB + 16 + tid] = kn;
+    __syncthreads();
   }
 }
 }  // namespace
@@ -77,7 +124,7 @@ __global__ __launch_bounds__(kBThreads) void blur_big_kernel(BlurArgs a) {
   const int64_t t = a.tick + j.t_offset;
   const int r = j.r;
   const int epi = a.epi;
-  float acc[8];
+  b_f32x4m acc[2];
   {
     // the sources carry a zero border: the residual of r, x of xborder
     const bool from_res = epi == EPI_GRAD;
@@ -87,23 +134,24 @@ __global__ __launch_bounds__(kBThreads) void blur_big_kernel(BlurArgs a) {
     corr_tile(sw, tl, r, j.kpitch, cp(j.kbig[from_res ? 1 : 0]),
               [&](int Y, int X) { return src[(int64_t)(Y + off) * pitch + (X + off)]; }, acc);
   }
-  const int ti = threadIdx.x >> 3, c0 = 8 * (threadIdx.x & 7);
-  if (ti >= tl.h) return;
-  const int Y = tl.y0 + ti;
+  const int lane = threadIdx.x & 63, col = 16 * (threadIdx.x >> 6) + (lane & 15);
+  if (col >= tl.w) return;
+  const int X = tl.x0 + col;
   const int B = j.xborder;
   const int64_t xpitch = j.xpitch;
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
-    const int X = tl.x0 + c0 + o;
-    if (c0 + o >= tl.w) break;
+    const int row = 16 * (o >> 2) + 4 * (lane >> 4) + (o & 3);
+    if (row >= tl.h) continue;
+    const int Y = tl.y0 + row;
+    const float kx = acc[o >> 2][o & 3];
     const int64_t pr = (int64_t)(Y + r) * j.rpitch + (X + r);
     if (epi == EPI_GRAD) {
-      gp(j.gdat)[(int64_t)Y * j.nx + X] = acc[o] * j.inv_s2;
+      gp(j.gdat)[(int64_t)Y * j.nx + X] = kx * j.inv_s2;
     } else if (epi == EPI_KX) {
-      gp(j.res)[pr] = acc[o];
+      gp(j.res)[pr] = kx;
     } else {
       const int64_t pp = (int64_t)(Y + B) * xpitch + (X + B);
-      const float kx = acc[o];
       const float mv = j.has_mask ? (float)gp(j.mask)[pp] : 1.0f;
       float res;
       if (j.zmode == 1) {
@@ -131,26 +179,28 @@ __global__ __launch_bounds__(kBThreads) void data_grad_kernel(GradArgs a) {
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int r = j.r, ny = j.ny, nx = j.nx;
   const PNP_GLOBAL float *src = gp(a.epi == 0 ? a.x : a.res);
-  float acc[8];
+  b_f32x4m acc[2];
   corr_tile(sw, tl, r, j.kpitch, cp(j.kbig[a.epi == 0 ? 0 : 1]),
             [&](int Y, int X) {
               return (Y >= 0 && Y < ny && X >= 0 && X < nx) ? src[(int64_t)Y * nx + X] : 0.0f;
             },
             acc);
-  const int ti = threadIdx.x >> 3, c0 = 8 * (threadIdx.x & 7);
-  if (ti >= tl.h) return;
-  const int Y = tl.y0 + ti;
+  const int lane = threadIdx.x & 63, col = 16 * (threadIdx.x >> 6) + (lane & 15);
+  if (col >= tl.w) return;
+  const int X = tl.x0 + col;
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
-    if (c0 + o >= tl.w) break;
-    const int X = tl.x0 + c0 + o;
+    const int row = 16 * (o >> 2) + 4 * (lane >> 4) + (o & 3);
+    if (row >= tl.h) continue;
+    const int Y = tl.y0 + row;
+    const float v = acc[o >> 2][o & 3];
     const int64_t p = (int64_t)Y * nx + X;
     if (a.epi == 0) {
       const int64_t pp = (int64_t)(Y + j.xborder) * j.xpitch + (X + j.xborder);
       const float mv = j.has_mask ? (float)gp(j.mask)[pp] : 1.0f;
-      gp(a.res)[p] = mv * (acc[o] - gp(j.y)[pp]);
+      gp(a.res)[p] = mv * (v - gp(j.y)[pp]);
     } else {
-      gp(a.g)[p] = acc[o] * j.inv_sig2;
+      gp(a.g)[p] = v * j.inv_sig2;
     }
   }
 }
@@ -169,7 +219,8 @@ hipError_t launch_data_grad(const GradArgs &a, int n_tiles, int r, int kpitch, h
 }
 
 size_t blur_big_lds_bytes(int r, int kpitch) {
-  return sizeof(float) * (size_t)(kUpdTileH + 2 * r) * (size_t)(kUpdTileW + kpitch + 8);
+  (void)kpitch;
+  return sizeof(float) * ((size_t)(kUpdTileH + 2 * r) * (size_t)blur_wwm(r) + 2 * (size_t)blur_kb(r));
 }
 
 hipError_t launch_blur_big(const BlurArgs &a, int n_tiles, int max_r, int kpitch, hipStream_t s) {
