@@ -250,7 +250,7 @@ def next_rows(a, stream):
             K, F = len(wl.ddfb_gamma), wl.ddfb_weights.shape[1]
             fl = 2.0 * 2 * K * 9 * F * npx        # K forward + K adjoint convolutions
             per_iter = prof[7][0] / a.next_steps / 1e3
-            r["roofline"] = {"bound": "alu", "kernel": "ddfb_stage_kernel (all K stages)",
+            r["roofline"] = {"bound": "mfma", "kernel": "ddfb_stage_kernel (all K stages, FP32 matrix cores)",
                              "achieved": round(fl / per_iter / 1e12, 2), "peak": 157.3,
                              "unit": "TFLOP/s", "frac": round(fl / per_iter / 1e12 / 157.3, 4),
                              "ms_per_iteration": round(per_iter * 1e3, 4),
@@ -258,7 +258,7 @@ def next_rows(a, stream):
         else:
             L = wl.kernel.shape[0]
             fl = 2.0 * L * L * npx                # one correlation pass
-            r["roofline"] = {"bound": "alu", "kernel": f"blur_big_kernel ({L}x{L})",
+            r["roofline"] = {"bound": "mfma", "kernel": f"blur_big_kernel ({L}x{L}, FP32 matrix cores)",
                              "achieved": round(fl / avg(9) / 1e12, 2), "peak": 157.3,
                              "unit": "TFLOP/s", "frac": round(fl / avg(9) / 1e12 / 157.3, 4),
                              "avg_launch_ms": round(avg(9) * 1e3, 4), "flops_per_launch": fl}

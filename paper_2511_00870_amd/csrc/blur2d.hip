@@ -27,8 +27,6 @@ namespace {
 constexpr int kBThreads = 256;
 typedef float b_f32x4 __attribute__((ext_vector_type(4)));
 
-typedef float b_f32x4m __attribute__((ext_vector_type(4)));
-
 // K steps (4 shifts each) per kernel row, a multiple of four (steps past the
 // band meet zero weights), and the LDS layout: the window's
 // row pitch is at least the columns the K steps read (16 w + 4 NJ) and 4 mod
@@ -52,7 +50,7 @@ __host__ __device__ constexpr int blur_kb(int r) { return 4 * blur_nj(2 * r + 1)
 // stored into the other buffer before the row's barrier).
 template <class Load>
 __device__ __forceinline__ void corr_tile(float *sw, const PNP_CONST TileRef &tl, int r, int Lp,
-                                          const PNP_CONST float *kc, Load load, b_f32x4m acc[2]) {
+                                          const PNP_CONST float *kc, Load load, b_f32x4 acc[2]) {
   constexpr int TH = kUpdTileH, TW = kUpdTileW;
   static_assert(TH == 32 && TW == 64 && kBThreads == 256, "two 16-row blocks per wave");
   const int L = 2 * r + 1, NJ = blur_nj(L), KB = blur_kb(r);
@@ -68,8 +66,8 @@ __device__ __forceinline__ void corr_tile(float *sw, const PNP_CONST TileRef &tl
     kb[q] = (q < KB && t >= 0 && t < L) ? kc[t] : 0.0f;
   }
   __syncthreads();
-  acc[0] = b_f32x4m{0.f, 0.f, 0.f, 0.f};
-  acc[1] = b_f32x4m{0.f, 0.f, 0.f, 0.f};
+  acc[0] = b_f32x4{0.f, 0.f, 0.f, 0.f};
+  acc[1] = b_f32x4{0.f, 0.f, 0.f, 0.f};
   // A: window row (16 mb + m + a), column 16 w + 4 js + k; B: the band entry
   // k[a][4 js + k - n] for this lane's n = m
   const float *wa = sw + m * WW + 16 * w + k;
@@ -124,7 +122,7 @@ __global__ __launch_bounds__(kBThreads) void blur_big_kernel(BlurArgs a) {
   const int64_t t = a.tick + j.t_offset;
   const int r = j.r;
   const int epi = a.epi;
-  b_f32x4m acc[2];
+  b_f32x4 acc[2];
   {
     // the sources carry a zero border: the residual of r, x of xborder
     const bool from_res = epi == EPI_GRAD;
@@ -179,7 +177,7 @@ __global__ __launch_bounds__(kBThreads) void data_grad_kernel(GradArgs a) {
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int r = j.r, ny = j.ny, nx = j.nx;
   const PNP_GLOBAL float *src = gp(a.epi == 0 ? a.x : a.res);
-  b_f32x4m acc[2];
+  b_f32x4 acc[2];
   corr_tile(sw, tl, r, j.kpitch, cp(j.kbig[a.epi == 0 ? 0 : 1]),
             [&](int Y, int X) {
               return (Y >= 0 && Y < ny && X >= 0 && X < nx) ? src[(int64_t)Y * nx + X] : 0.0f;
