@@ -41,6 +41,10 @@ __device__ __forceinline__ float prox_kl(float v, float y, float kappa) {
 // One workgroup per 32 x 64 tile: x^(t+1) on the core +- r into LDS, K x on
 // the core, then the z-steps of the core pixels.  Large blurs (JobDesc::big)
 // take K x from JobDesc::res, computed beforehand by the whole-image pass.
+// Every global read of the tile is issued before the first wait: the x window
+// into registers, then z1, y, the mask, z2 and (large blurs) K x of the
+// thread's eight core pixels; lanes past the tile read a valid address and
+// drop the value.
 __global__ __launch_bounds__(kZThreads) void zstep_psgla_kernel(UpdateArgs a) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
@@ -49,6 +53,8 @@ __global__ __launch_bounds__(kZThreads) void zstep_psgla_kernel(UpdateArgs a) {
   const bool big = j.big;
   const int r = big ? 0 : j.r, L = 2 * r + 1;
   constexpr int TH = kUpdTileH, TW = kUpdTileW, NT = kZThreads;
+  constexpr int XQ = ((TH + 2 * kMaxR) * (TW + 2 * kMaxR) + NT - 1) / NT;
+  constexpr int CQ = TH * TW / NT;
   const int WH = TH + 2 * r, WW = TW + 2 * r;
   float *sx = smem;                                  // WH x WW
   float *sh = sx + WH * WW;                          // WH x TW (row pass)
@@ -56,6 +62,36 @@ __global__ __launch_bounds__(kZThreads) void zstep_psgla_kernel(UpdateArgs a) {
   __shared__ float sku[2 * kMaxR + 1], skv[2 * kMaxR + 1], skern[KMAX];
   const int tid = threadIdx.x;
   const bool sep = !big && j.separable;
+  const PNP_GLOBAL float *xin = gp(j.x[t & 1]);
+  const int B = j.xborder;
+  const int64_t xpitch = j.xpitch;
+  const int wy = tl.y0 - r, wx = tl.x0 - r;
+  float xw[XQ];
+#pragma unroll
+  for (int k = 0; k < XQ; ++k) {
+    const int q0 = tid + NT * k, q = q0 < WH * WW ? q0 : 0;
+    const int i = q / WW, c = q % WW;
+    xw[k] = xin[(int64_t)(wy + i + B) * xpitch + (wx + c + B)];
+  }
+  const PNP_GLOBAL float *yb = gp(j.y);
+  PNP_GLOBAL float *z1 = gp(j.z1);
+  PNP_GLOBAL float *z2 = gp(j.has_z2 ? j.z2 : j.z1);
+  const PNP_GLOBAL uint8_t *mk = gp(j.has_mask ? j.mask : reinterpret_cast<const uint8_t *>(j.y));
+  const PNP_GLOBAL float *kxb = gp(big ? j.res : j.z1);
+  float zo[CQ], yv[CQ], wo[CQ], kxv[CQ];
+  uint32_t mraw[CQ];
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int q = tid + NT * k, i = q / TW, c = q % TW;
+    const int ii = i < tl.h ? i : 0, cc = c < tl.w ? c : 0;
+    const int Y = tl.y0 + ii, X = tl.x0 + cc;
+    const int64_t pp = (int64_t)(Y + B) * xpitch + (X + B);
+    zo[k] = z1[pp];
+    yv[k] = yb[pp];
+    mraw[k] = mk[pp];
+    wo[k] = z2[pp];
+    kxv[k] = big ? kxb[(int64_t)(Y + j.r) * j.rpitch + (X + j.r)] : 0.0f;
+  }
   if (sep) {
     if (tid < L) {
       sku[tid] = gp(j.ku)[tid];
@@ -64,13 +100,10 @@ __global__ __launch_bounds__(kZThreads) void zstep_psgla_kernel(UpdateArgs a) {
   } else if (!big) {
     for (int q = tid; q < L * L; q += NT) skern[q] = gp(j.kern)[q];
   }
-  const PNP_GLOBAL float *xin = gp(j.x[t & 1]);
-  const int B = j.xborder;
-  const int64_t xpitch = j.xpitch;
-  const int wy = tl.y0 - r, wx = tl.x0 - r;
-  for (int q = tid; q < WH * WW; q += NT) {
-    const int i = q / WW, c = q % WW;
-    sx[q] = xin[(int64_t)(wy + i + B) * xpitch + (wx + c + B)];
+#pragma unroll
+  for (int k = 0; k < XQ; ++k) {
+    const int q = tid + NT * k;
+    if (NT * k < WH * WW && q < WH * WW) sx[q] = xw[k];
   }
   __syncthreads();
   if (sep) {
@@ -83,38 +116,30 @@ __global__ __launch_bounds__(kZThreads) void zstep_psgla_kernel(UpdateArgs a) {
     }
     __syncthreads();
   }
-  const PNP_GLOBAL float *yb = gp(j.y);
-  const PNP_GLOBAL uint8_t *mk = gp(j.mask);
-  PNP_GLOBAL float *z1 = gp(j.z1);
-  PNP_GLOBAL float *z2 = gp(j.z2);
-  for (int q = tid; q < TH * TW; q += NT) {
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int q = tid + NT * k;
     const int i = q / TW, c = q % TW;
     if (i >= tl.h || c >= tl.w) continue;
-    float kx = 0.0f;
+    float kx = kxv[k];
     const int Y = tl.y0 + i, X = tl.x0 + c;
-    if (big) {
-      kx = gp(j.res)[(int64_t)(Y + j.r) * j.rpitch + (X + j.r)];
-    } else if (sep) {
-      for (int k = 0; k < L; ++k) kx = fmaf(sku[k], sh[(i + 2 * r - k) * TW + c], kx);
-    } else {
+    if (sep) {
+      for (int kk = 0; kk < L; ++kk) kx = fmaf(sku[kk], sh[(i + 2 * r - kk) * TW + c], kx);
+    } else if (!big) {
       for (int a2 = 0; a2 < L; ++a2)
-        for (int k = 0; k < L; ++k)
-          kx = fmaf(skern[a2 * L + k], sx[(i + 2 * r - a2) * WW + (c + 2 * r - k)], kx);
+        for (int kk = 0; kk < L; ++kk)
+          kx = fmaf(skern[a2 * L + kk], sx[(i + 2 * r - a2) * WW + (c + 2 * r - kk)], kx);
     }
     const int64_t pp = (int64_t)(Y + B) * xpitch + (X + B);
-    const float mv = j.has_mask ? (float)mk[pp] : 1.0f;
+    const float mv = j.has_mask ? (float)mraw[k] : 1.0f;
     float g0, g1, g2;
     gauss_triple(j.key0, j.key1, j.chain, (int64_t)Y * j.nx + X, t, g0, g1, g2);
-    const float zo = z1[pp];
-    float v = zo - j.za1 * (zo - j.eta * (mv * kx)) + j.zs1 * g1;
-    if (mv != 0.0f) {
-      const float yv = yb[pp];
-      v = j.poisson ? prox_kl(v, yv, j.zkappa) : (j.zsig2 * v + j.zkappa * yv) / (j.zsig2 + j.zkappa);
-    }
+    float v = zo[k] - j.za1 * (zo[k] - j.eta * (mv * kx)) + j.zs1 * g1;
+    if (mv != 0.0f)
+      v = j.poisson ? prox_kl(v, yv[k], j.zkappa) : (j.zsig2 * v + j.zkappa * yv[k]) / (j.zsig2 + j.zkappa);
     z1[pp] = v;
     if (j.has_z2) {
-      const float wo = z2[pp];
-      const float w = wo - j.za2 * (wo - sx[(i + r) * WW + (c + r)]) + j.zs2 * g2;
+      const float w = wo[k] - j.za2 * (wo[k] - sx[(i + r) * WW + (c + r)]) + j.zs2 * g2;
       z2[pp] = fmaxf(w, 0.0f);
     }
   }
@@ -123,7 +148,9 @@ __global__ __launch_bounds__(kZThreads) void zstep_psgla_kernel(UpdateArgs a) {
 // The TV prior term of the x-step on the tile's pixels:
 //   G = (1/rho) D^T (D x - z),
 //   (D^T w)_p = [j >= 1] w_h(p - 1) - [j < nx-1] w_h(p) + [i >= 1] w_v(p - nx) - [i < ny-1] w_v(p)
-// with w = D x - z (D x zero in the last column / row).
+// with w = D x - z (D x zero in the last column / row).  x, zh and zv carry a
+// zero border of at least two pixels, so every neighbour's address is valid:
+// the thread's eight pixels issue all their reads before the first use.
 __global__ __launch_bounds__(kZThreads) void tv_prior_kernel(UpdateArgs a) {
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
@@ -133,22 +160,38 @@ __global__ __launch_bounds__(kZThreads) void tv_prior_kernel(UpdateArgs a) {
   const PNP_GLOBAL float *zv = gp(j.z2);
   const int B = j.xborder;
   const int64_t P = j.xpitch;
-  for (int q = threadIdx.x; q < kUpdTileH * kUpdTileW; q += kZThreads) {
-    const int i = q / kUpdTileW, c = q % kUpdTileW;
+  constexpr int CQ = kUpdTileH * kUpdTileW / kZThreads;
+  float xc[CQ], xl[CQ], xr[CQ], xu[CQ], xd[CQ], hl[CQ], hc[CQ], vu[CQ], vc[CQ];
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int q = threadIdx.x + kZThreads * k, i = q / kUpdTileW, c = q % kUpdTileW;
+    const int ii = i < tl.h ? i : 0, cc = c < tl.w ? c : 0;
+    const int64_t pp = (int64_t)(tl.y0 + ii + B) * P + (tl.x0 + cc + B);
+    xc[k] = x[pp];
+    xl[k] = x[pp - 1];
+    xr[k] = x[pp + 1];
+    xu[k] = x[pp - P];
+    xd[k] = x[pp + P];
+    hl[k] = zh[pp - 1];
+    hc[k] = zh[pp];
+    vu[k] = zv[pp - P];
+    vc[k] = zv[pp];
+  }
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int q = threadIdx.x + kZThreads * k, i = q / kUpdTileW, c = q % kUpdTileW;
     if (i >= tl.h || c >= tl.w) continue;
     const int Y = tl.y0 + i, X = tl.x0 + c;
-    const int64_t pp = (int64_t)(Y + B) * P + (X + B);
-    const float xc = x[pp];
     float v = 0.0f;
-    if (X >= 1) v += (xc - x[pp - 1]) - zh[pp - 1];
-    if (X + 1 < j.nx) v -= (x[pp + 1] - xc) - zh[pp];
-    if (Y >= 1) v += (xc - x[pp - P]) - zv[pp - P];
-    if (Y + 1 < j.ny) v -= (x[pp + P] - xc) - zv[pp];
+    if (X >= 1) v += (xc[k] - xl[k]) - hl[k];
+    if (X + 1 < j.nx) v -= (xr[k] - xc[k]) - hc[k];
+    if (Y >= 1) v += (xc[k] - xu[k]) - vu[k];
+    if (Y + 1 < j.ny) v -= (xd[k] - xc[k]) - vc[k];
     gp(j.G)[(int64_t)Y * j.nx + X] = v * j.inv_rho;
   }
 }
 
-// TV z-step from x^(t+1) (x^(t) for the new t)
+// TV z-step from x^(t+1) (x^(t) for the new t); reads first, as above
 __global__ __launch_bounds__(kZThreads) void zstep_tv_kernel(UpdateArgs a) {
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
@@ -158,19 +201,31 @@ __global__ __launch_bounds__(kZThreads) void zstep_tv_kernel(UpdateArgs a) {
   PNP_GLOBAL float *zv = gp(j.z2);
   const int B = j.xborder;
   const int64_t P = j.xpitch;
-  for (int q = threadIdx.x; q < kUpdTileH * kUpdTileW; q += kZThreads) {
-    const int i = q / kUpdTileW, c = q % kUpdTileW;
+  constexpr int CQ = kUpdTileH * kUpdTileW / kZThreads;
+  float xc[CQ], xr[CQ], xd[CQ], ho[CQ], vo[CQ];
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int q = threadIdx.x + kZThreads * k, i = q / kUpdTileW, c = q % kUpdTileW;
+    const int ii = i < tl.h ? i : 0, cc = c < tl.w ? c : 0;
+    const int64_t pp = (int64_t)(tl.y0 + ii + B) * P + (tl.x0 + cc + B);
+    xc[k] = x[pp];
+    xr[k] = x[pp + 1];
+    xd[k] = x[pp + P];
+    ho[k] = zh[pp];
+    vo[k] = zv[pp];
+  }
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int q = threadIdx.x + kZThreads * k, i = q / kUpdTileW, c = q % kUpdTileW;
     if (i >= tl.h || c >= tl.w) continue;
     const int Y = tl.y0 + i, X = tl.x0 + c;
     const int64_t pp = (int64_t)(Y + B) * P + (X + B);
-    const float xc = x[pp];
-    const float dh = X + 1 < j.nx ? x[pp + 1] - xc : 0.0f;
-    const float dv = Y + 1 < j.ny ? x[pp + P] - xc : 0.0f;
+    const float dh = X + 1 < j.nx ? xr[k] - xc[k] : 0.0f;
+    const float dv = Y + 1 < j.ny ? xd[k] - xc[k] : 0.0f;
     float g0, g1, g2;
     gauss_triple(j.key0, j.key1, j.chain, (int64_t)Y * j.nx + X, t, g0, g1, g2);
-    const float ho = zh[pp], vo = zv[pp];
-    float vh = ho - j.za1 * (ho - dh) + j.zs1 * g1;
-    float vv = vo - j.za1 * (vo - dv) + j.zs1 * g2;
+    float vh = ho[k] - j.za1 * (ho[k] - dh) + j.zs1 * g1;
+    float vv = vo[k] - j.za1 * (vo[k] - dv) + j.zs1 * g2;
     const float nrm = __builtin_sqrtf(vh * vh + vv * vv);
     const float f = nrm > j.zkappa ? 1.0f - j.zkappa / nrm : 0.0f;
     zh[pp] = vh * f;
