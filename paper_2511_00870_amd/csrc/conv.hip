@@ -2276,9 +2276,11 @@ void conv_pair8_ws_kernel(ConvArgs a) {
 // tap's partial at the neighbour the tap reads, + bias.  The records' zero
 // border supplies the zero padding at the image edge.  A tile's records (its
 // rows and columns plus one on each side) are contiguous per row, so they
-// are staged in LDS with 16-byte loads and the taps are summed from there.
+// are staged in LDS with 16-byte loads, all issued before the first is
+// stored, and the taps are summed from there.
 __global__ __launch_bounds__(256) void g_from_s_kernel(ConvArgs a) {
   constexpr int RW = kConvTileW + 2, RREC = 12, NCH = RW * RREC / 4;   // 16-byte chunks per row
+  constexpr int NQ = (18 * NCH + 255) / 256;
   __shared__ __attribute__((aligned(16))) float srec[18 * RW * RREC];
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
@@ -2286,12 +2288,23 @@ __global__ __launch_bounds__(256) void g_from_s_kernel(ConvArgs a) {
   const int64_t spitch = j.nx + 2;
   const int rows = tl.h + 2, nch = (tl.w + 2) * RREC / 4;
   // record (y0 + r, x0 + c) of the bordered record grid holds pixel
-  // (y0 + r - 1, x0 + c - 1); rows y0 .. y0+h+1, columns x0 .. x0+w+1
-  for (int q = threadIdx.x; q < rows * NCH; q += 256) {
+  // (y0 + r - 1, x0 + c - 1); rows y0 .. y0+h+1, columns x0 .. x0+w+1.
+  // Chunks past the tile read chunk 0 of its first row and drop it.
+  f32x4 v[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q0 = threadIdx.x + 256 * i;
+    const int r0 = q0 / NCH, k0 = q0 % NCH;
+    const bool in = r0 < rows && k0 < nch;
+    const int r = in ? r0 : 0, k = in ? k0 : 0;
+    v[i] = *reinterpret_cast<const PNP_GLOBAL f32x4 *>(
+        S + ((int64_t)(tl.y0 + r) * spitch + tl.x0) * RREC + 4 * k);
+  }
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q = threadIdx.x + 256 * i;
     const int r = q / NCH, k = q % NCH;
-    if (k < nch)
-      *reinterpret_cast<f32x4 *>(srec + r * RW * RREC + 4 * k) = *reinterpret_cast<
-          const PNP_GLOBAL f32x4 *>(S + ((int64_t)(tl.y0 + r) * spitch + tl.x0) * RREC + 4 * k);
+    if (r < rows && k < nch) *reinterpret_cast<f32x4 *>(srec + r * RW * RREC + 4 * k) = v[i];
   }
   __syncthreads();
   const float sc = a.oscale[0], bi = a.bias[0];
