@@ -52,7 +52,9 @@ static_assert(kDdReg * kDdReg == 4 * kDdThreads, "four region pixels per thread"
 template <int KM, int MB>
 __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
   __shared__ float smap[KM][kDdWin * kDdWin];
-  __shared__ float spart[9][kDdReg * kDdReg];
+  // tap (dy, dx)'s partial sums on the 30 x 30 block of region positions the
+  // core's adjoint reads: rows 2 - dy .. 31 - dy, columns 2 - dx .. 31 - dx
+  __shared__ float spart[9][kDdTile * kDdTile];
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
   const int64_t t = a.tick + j.t_offset;
@@ -61,13 +63,29 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
   const int q4 = lane >> 4, l16 = lane & 15;
   const int B = j.xborder;
   const int64_t P = j.xpitch;
+  // the maps' windows: every load issued before the first is stored (the
+  // maps carry a zero border of two pixels; lanes past the window read its
+  // first element and drop it)
+  constexpr int NQ = (kDdWin * kDdWin + kDdThreads - 1) / kDdThreads;
+  float mv[KM][NQ];
 #pragma unroll
   for (int m = 0; m < KM; ++m) {
     if (m >= k) break;
     const PNP_GLOBAL float *src = gp(m == 0 ? j.x[t & 1] : j.dmaps + (int64_t)(m - 1) * j.dstride);
-    for (int q = tid; q < kDdWin * kDdWin; q += kDdThreads) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int q0 = tid + i * kDdThreads, q = q0 < kDdWin * kDdWin ? q0 : 0;
       const int Y = tl.y0 - 2 + q / kDdWin, X = tl.x0 - 2 + q % kDdWin;
-      smap[m][q] = src[(int64_t)(Y + B) * P + (X + B)];
+      mv[m][i] = src[(int64_t)(Y + B) * P + (X + B)];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < KM; ++m) {
+    if (m >= k) break;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int q = tid + i * kDdThreads;
+      if (q < kDdWin * kDdWin) smap[m][q] = mv[m][i];
     }
   }
   // A fragments: MB blocks of 16 channels (channels from F on have zero
@@ -162,9 +180,14 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
       f32x4 tot = sp[h][0];
 #pragma unroll
       for (int mb = 1; mb < MB; ++mb) tot += sp[h][mb];
+      const int col = 16 * h + l16;
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (4 * q4 + r < 9) spart[4 * q4 + r][ri * kDdReg + 16 * h + l16] = tot[r];
+      for (int r = 0; r < 4; ++r) {
+        const int tap = 4 * q4 + r, dy = tap / 3, dx = tap % 3;
+        const int pr = ri - 2 + dy, pc = col - 2 + dx;
+        if (tap < 9 && (unsigned)pr < (unsigned)kDdTile && (unsigned)pc < (unsigned)kDdTile)
+          spart[tap][pr * kDdTile + pc] = tot[r];
+      }
     }
   }
   __syncthreads();
@@ -174,8 +197,7 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
     if (ci >= tl.h || cc >= tl.w) continue;
     float out = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-      out += spart[i][(ci + 2 - i / 3) * kDdReg + (cc + 2 - i % 3)];
+    for (int i = 0; i < 9; ++i) out += spart[i][q];
     const float v = smap[0][(ci + 2) * kDdWin + cc + 2];
     const int Y = tl.y0 + ci, X = tl.x0 + cc;
     if (k < K) {
