@@ -26,6 +26,30 @@ namespace pnp {
 
 typedef float upd_f32x4 __attribute__((ext_vector_type(4)));
 
+// Position (i, c) in the (32 + 2r) x (64 + 2r) residual region of the q-th
+// residual pixel: the 32 x 64 core first, in the core's own row-major order
+// (so a thread's core pixels in the residual pass are its pixels in the
+// update and their noise stays in registers), then the ring: r rows above,
+// r rows below, then the r columns on either side of each core row.
+__device__ __forceinline__ void upd_res_pix(int q, int r, int RW, int &i, int &c) {
+  constexpr int TH = kUpdTileH, TW = kUpdTileW;
+  if (q < TH * TW) {
+    i = q / TW + r;
+    c = q % TW + r;
+    return;
+  }
+  const int u = q - TH * TW, band = r * RW;
+  if (u < 2 * band) {
+    const int v = u < band ? u : u - band;
+    i = (u < band ? 0 : TH + r) + v / RW;
+    c = v % RW;
+  } else {
+    const int v = u - 2 * band, cc = v % (2 * r);
+    i = r + v / (2 * r);
+    c = cc < r ? cc : cc + TW;
+  }
+}
+
 // RT > 0: every tile's blur half-width is RT (window sizes, divisions and
 // tap loops become compile-time constants); RT = 0: read per job.
 // MODE 0: the residual uses y (rho = 0) or the exact z draw (rho > 0);
@@ -33,7 +57,8 @@ typedef float upd_f32x4 __attribute__((ext_vector_type(4)));
 // residual is m (eta m K x - z1), read in place of y, and the data gradient
 // gains (x - z2)/rho2 on the core.
 template <int RT, int MODE>
-__global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a) {
+__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void fused_update_kernel(UpdateArgs a) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
   const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
@@ -54,7 +79,6 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
   float *sx = smem;                                  // WH x WW
   float *sh = sx + WH * WW;                          // WH x RW  (row pass of x)
   float *sres = sh + WH * RW;                        // RH x RW
-  float *sxi = sres + RH * RW;                       // TH x TW
   // RH x TW (row pass of the residual): reuses the row pass of x, whose last
   // reader (the residual pass) ends at the barrier before it is written
   float *shr = sh;
@@ -70,9 +94,12 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
     merge = nw == j.wwin;
   }
 
-  // blur taps, staged in LDS once per workgroup: their loads go first
-  constexpr int KMAX = (2 * kMaxR + 1) * (2 * kMaxR + 1);
-  __shared__ float sku[2 * kMaxR + 1], skv[2 * kMaxR + 1], skern[KMAX];
+  // blur taps, staged in LDS once per workgroup: their loads go first.  A
+  // non-separable kernel (at most 17 x 17 = 289 taps, fewer than the row
+  // pass buffer's 32 x 64 floats) lives in the row pass buffer, which only
+  // the separable passes use.
+  __shared__ float sku[2 * kMaxR + 1], skv[2 * kMaxR + 1];
+  float *skern = sh;
   const bool sep = j.separable;
   const int nk = sep ? L : L * L;
   float tap0, tap1;
@@ -123,7 +150,9 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
 #pragma unroll
   for (int k = 0; k < RQ; ++k) {
     const int q0 = tid + NT * k, q = q0 < RH * RW ? q0 : 0;
-    const int Y = tl.y0 - r + q / RW, X = tl.x0 - r + q % RW;
+    int ri, rc;
+    upd_res_pix(q, r, RW, ri, rc);
+    const int Y = tl.y0 - r + ri, X = tl.x0 - r + rc;
     const int64_t pidx = (Y + B) * xpitch + (X + B);   // inside the padded buffer
     yv[k] = yb[pidx];
     mraw[k] = mk[pidx];
@@ -186,14 +215,18 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
     }
     __syncthreads();
   }
-  // 3. residual (zero outside the image)
+  // 3. residual (zero outside the image); the noise xi of the thread's core
+  //    pixels (residual pixels k < CQ) is kept for the update
   const int split = j.split;
   const bool draw = split && t >= 1;
+  static_assert(NT * CQ == TH * TW, "the core's residual pixels come first, CQ per thread");
+  float xir[CQ];
 #pragma unroll
   for (int k = 0; k < RQ; ++k) {
     const int q = tid + NT * k;
     if (q >= RH * RW) break;
-    const int i = q / RW, c = q % RW;
+    int i, c;
+    upd_res_pix(q, r, RW, i, c);
     float kx = 0.0f;
     if (j.separable) {
       for (int kk = 0; kk < L; ++kk) kx = fmaf(sku[kk], sh[(i + 2 * r - kk) * RW + c], kx);
@@ -216,11 +249,10 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
         float xi, zeta;
         gauss_pair(j.key0, j.key1, j.chain, (int64_t)Y * j.nx + X, t, xi, zeta);
         res = mv * (j.zmix * (kx - yv[k]) - j.zsd * zeta);
-        const int ci = i - r, cc = c - r;
-        if (ci >= 0 && ci < TH && cc >= 0 && cc < TW) sxi[ci * TW + cc] = xi;
+        if (k < CQ) xir[k] = xi;
       }
     }
-    sres[q] = res;
+    sres[i * RW + c] = res;
   }
   __syncthreads();
 
@@ -259,7 +291,7 @@ __global__ __launch_bounds__(kUpdThreads) void fused_update_kernel(UpdateArgs a)
     const int64_t p = (int64_t)Y * j.nx + X;
     float xi;
     if (draw) {
-      xi = sxi[q];
+      xi = xir[k];
     } else {
       float zeta_unused;
       gauss_pair(j.key0, j.key1, j.chain, p, t, xi, zeta_unused);
@@ -414,9 +446,9 @@ hipError_t launch_amax(const float *p, size_t n, uint32_t *out, hipStream_t s) {
 size_t update_lds_bytes(int r) {
   const int TH = kUpdTileH, TW = kUpdTileW;
   const int WH = TH + 4 * r, WW = TW + 4 * r, RH = TH + 2 * r, RW = TW + 2 * r;
-  // the residual's row pass shares the x row pass's buffer (RH x TW <= WH x RW)
-  return sizeof(float) * ((size_t)WH * WW + (size_t)WH * RW + (size_t)RH * RW +
-                          (size_t)TH * TW);
+  // the residual's row pass shares the x row pass's buffer (RH x TW <= WH x RW),
+  // which also holds a non-separable kernel's taps
+  return sizeof(float) * ((size_t)WH * WW + (size_t)WH * RW + (size_t)RH * RW);
 }
 
 template <int RT, int MODE>
