@@ -11,8 +11,8 @@
 //   2. gdat = K^T res / s2 on every pixel;
 // and the update reads gdat.  K x = corr(x, flip(k)), K^T res = corr(res, k).
 // Each workgroup computes one 32 x 64 output tile from a window of
-// (32 + 2r) x (64 + 2r) pixels, of which LDS holds the 33 rows in use (53 KB
-// at r = 64, three workgroups per CU), on the matrix cores: for one kernel row a,
+// (32 + 2r) x (64 + 2r) pixels, of which LDS holds a ring of 48 rows (39 KB
+// at r = 64, four workgroups per CU), on the matrix cores: for one kernel row a,
 // out[y][x0 + n] = sum_j win[y + a][x0 + j] k[a][j - n] is a GEMM whose B
 // operand is a band (Toeplitz) slice of that row, so v_mfma_f32_16x16x4f32
 // takes 16 output rows x 16 columns per block and 4 shifts j per K step
@@ -40,10 +40,12 @@ __host__ __device__ constexpr int blur_wwm(int r) {
   return (need + 59) / 64 * 64 + 4;
 }
 __host__ __device__ constexpr int blur_kb(int r) { return 4 * blur_nj(2 * r + 1) + 32; }
-// window rows in the ring: the 32 rows one kernel row reads and the one
-// being stored; every row sits at ring slots s and s + kRing, so the 32 rows
-// read for kernel row a are the contiguous slots a % kRing .. a % kRing + 31
-constexpr int kRing = kUpdTileH + 1;
+// window rows in the ring: window row y sits at slot y % kRing.  Kernel row a
+// reads rows a .. a + 31 while row a + 32 is stored into the slot of row
+// a - 16; with a row pitch of 4 mod 64 floats, any 16 cyclically consecutive
+// slots of a ring whose length is a multiple of 16 fall on distinct banks
+constexpr int kRing = 48;
+static_assert(kRing % 16 == 0 && kRing >= kUpdTileH + 1, "ring length");
 static_assert(blur_wwm(kMaxRBig) <= kBThreads, "one window column per thread");
 
 // acc[mb] (mb = 0, 1) = the 16 x 16 output block at rows 16 mb .. 16 mb + 15
@@ -54,8 +56,8 @@ static_assert(blur_wwm(kMaxRBig) <= kBThreads, "one window column per thread");
 // coordinates) gives its values, zero beyond it.  Its rows pass through the
 // ring: kernel row a reads window rows a .. a + 31, and window row a + 32 and
 // kernel row a + 1 are loaded into registers while row a runs and stored
-// (the window row at its two slots, the kernel row into the other of two
-// buffers) before the row's barrier.
+// (the window row at its slot, the kernel row into the other of two buffers)
+// before the row's barrier.
 template <class Load>
 __device__ __forceinline__ void corr_tile(float *sw, const PNP_CONST TileRef &tl, int r, int Lp,
                                           const PNP_CONST float *kc, Load load, b_f32x4 acc[2]) {
@@ -63,13 +65,11 @@ __device__ __forceinline__ void corr_tile(float *sw, const PNP_CONST TileRef &tl
   static_assert(TH == 32 && TW == 64 && kBThreads == 256, "two 16-row blocks per wave");
   const int L = 2 * r + 1, NJ = blur_nj(L), KB = blur_kb(r);
   const int WH = TH + 2 * r, WW = blur_wwm(r), WV = TW + 2 * r;
-  float *kb = sw + 2 * kRing * WW;               // two rows of KB floats
+  float *kb = sw + kRing * WW;                   // two rows of KB floats
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 15, k = lane >> 4;
   for (int q = tid; q < TH * WW; q += kBThreads) {
     const int i = q / WW, c = q % WW;
-    const float v = c < WV ? load(tl.y0 - r + i, tl.x0 - r + c) : 0.0f;
-    sw[q] = v;
-    sw[q + kRing * WW] = v;
+    sw[q] = c < WV ? load(tl.y0 - r + i, tl.x0 - r + c) : 0.0f;
   }
   for (int q = tid; q < 2 * KB; q += kBThreads) {
     const int t = q % KB - 16;
@@ -91,7 +91,10 @@ __device__ __forceinline__ void corr_tile(float *sw, const PNP_CONST TileRef &tl
     const bool nw = a + TH < WH && wcol;
     const float wn = (nw && tid < WV) ? load(tl.y0 - r + a + TH, tl.x0 - r + tid) : 0.0f;
     const float *kr = kb + (a & 1) * KB + bo;
-    const float *w0 = sw + (slot + m) * WW + 16 * w + k, *w1 = w0 + 16 * WW;
+    int s0 = slot + m, s1 = s0 + 16;               // slots of rows a + m, a + m + 16
+    s0 = s0 >= kRing ? s0 - kRing : s0;
+    s1 = s1 >= kRing ? s1 - kRing : s1;
+    const float *w0 = sw + s0 * WW + 16 * w + k, *w1 = sw + s1 * WW + 16 * w + k;
     // K steps in batches of four, the next batch's operands read from LDS
     // before this batch's MFMAs
     float ca[2][4], cb[4];
@@ -123,14 +126,10 @@ __device__ __forceinline__ void corr_tile(float *sw, const PNP_CONST TileRef &tl
         ca[1][u] = na[1][u];
       }
     }
-    // window row a + 32 goes to the slot of row a - 1 (free since the last
-    // barrier) and its copy kRing further; neither lies in this row's slots
-    // slot .. slot + 31
-    const int ns = slot == 0 ? kRing - 1 : slot - 1;
-    if (nw) {
-      sw[ns * WW + tid] = wn;
-      sw[(ns + kRing) * WW + tid] = wn;
-    }
+    // window row a + 32 goes to the slot of row a + 32 - kRing, last read
+    // before an earlier barrier and not among this row's slots
+    const int ns = slot + TH >= kRing ? slot + TH - kRing : slot + TH;
+    if (nw) sw[ns * WW + tid] = wn;
     if (nk) kb[((a + 1) & 1) * KB + 16 + tid] = kn;
     __syncthreads();
     slot = slot + 1 == kRing ? 0 : slot + 1;
@@ -241,7 +240,7 @@ hipError_t launch_data_grad(const GradArgs &a, int n_tiles, int r, int kpitch, h
 
 size_t blur_big_lds_bytes(int r, int kpitch) {
   (void)kpitch;
-  return sizeof(float) * (2 * (size_t)kRing * (size_t)blur_wwm(r) + 2 * (size_t)blur_kb(r));
+  return sizeof(float) * ((size_t)kRing * (size_t)blur_wwm(r) + 2 * (size_t)blur_kb(r));
 }
 
 hipError_t launch_blur_big(const BlurArgs &a, int n_tiles, int max_r, int kpitch, hipStream_t s) {
