@@ -170,8 +170,9 @@ def test_ddfb_step_parity():
 
 
 # ------------------------------------------------------------ large blurs
+# 19 x 19 is the smallest blur routed to the whole-image correlation passes
 @pytest.mark.parametrize("L,split,mask_p", [(65, True, 0.5), (129, False, None),
-                                            (33, True, None)])
+                                            (33, True, None), (19, False, 0.5)])
 def test_large_blur_step_parity(L, split, mask_p):
     ny, nx = (150, 170) if L < 129 else (140, 150)
     wl = W.make_workload("b", ny, nx, L=5, sigma_k=1.0, sigma=0.02, block=max(ny, nx),
