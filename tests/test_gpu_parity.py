@@ -314,6 +314,21 @@ def test_step_parity_wide_blur_split_mask():
     _parity_run(wl, 20, label="L=9 mask")
 
 
+@pytest.mark.parametrize("L,separable", [(17, True), (13, False)])
+def test_step_parity_generic_radius(L, separable):
+    """Half-widths 5..8 run the generic fused update (tap counts read per job):
+    the longest ring of residual pixels around the tile's core, and for a
+    non-separable kernel up to 17 x 17 taps staged in the row-pass buffer."""
+    wl = W.config(1, ny=70, nx=83, block=35, halo=2 * (L // 2) + 2, L=L, sigma_k=L / 4.5,
+                  mask_p=0.4, bias_scale=0.05)
+    if not separable:
+        rng = np.random.default_rng(L)
+        wl.kernel = rng.random((L, L))
+        wl.kernel /= wl.kernel.sum()
+        wl.y = W.observe(wl.xbar, wl.kernel, wl.sigma, wl.mask, 21)
+    _parity_run(wl, 12, label=f"L={L} {'separable' if separable else '2-D'} mask")
+
+
 def test_step_parity_identity_blur():
     wl = W.config(1, ny=33, nx=47, block=33, halo=4, L=1, sigma_k=1.0)
     wl.kernel = np.ones((1, 1))
