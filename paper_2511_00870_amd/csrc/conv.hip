@@ -853,6 +853,16 @@ void conv_mid_rr_kernel(ConvArgs a) {
   // + bias, ReLU, bf16, written into the layer input window; window pixels
   // outside the image are the next layer's zero padding.
   auto layer0 = [&](const MidTile &c) {
+    // the A fragments and biases of the four channel blocks, read once per
+    // tile (the window stores below would otherwise make the compiler read
+    // them again for every block)
+    i16x4 A0s[MB];
+    f32x4 bias_s[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      bias_s[mb] = *reinterpret_cast<const f32x4 *>(lds_bias0 + mb * 16 + 4 * g);
+      A0s[mb] = *reinterpret_cast<const i16x4 *>(lds_a0 + (mb * 64 + lane) * 16);
+    }
 #pragma unroll
     for (int u = 0; u < BPW0; ++u) {
       const int blk = wave + 4 * u;
@@ -871,9 +881,7 @@ void conv_mid_rr_kernel(ConvArgs a) {
       const bool inside = Y >= 0 && Y < c.ny && X >= 0 && X < c.nx;
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        const f32x4 bia = *reinterpret_cast<const f32x4 *>(lds_bias0 + mb * 16 + 4 * g);
-        const i16x4 A0 = *reinterpret_cast<const i16x4 *>(lds_a0 + (mb * 64 + lane) * 16);
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, Bx, bia, 0, 0, 0);
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0s[mb], Bx, bias_s[mb], 0, 0, 0);
         u32x2 w;
         w.x = inside ? relu_bf16x2(pack_bf16x2(d[0], d[1])) : 0u;
         w.y = inside ? relu_bf16x2(pack_bf16x2(d[2], d[3])) : 0u;
