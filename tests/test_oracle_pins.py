@@ -105,12 +105,16 @@ def test_box_muller_moments_and_ks():
 
 
 # ----------------------------------------------------------- blur, mask
-@pytest.mark.parametrize("L", [1, 3, 5, 9])
+# 19 .. 129: the large motion blurs (Sec. III-A2); 65 and 129 exceed the
+# image, so most taps meet the zero boundary
+@pytest.mark.parametrize("L", [1, 3, 5, 9, 19, 65, 129])
 def test_blur_matches_fft_convolution(L):
     from scipy.signal import fftconvolve
     rng = np.random.default_rng(L)
     x = rng.random((37, 53))
     k = rng.random((L, L))            # non-symmetric: the flip matters
+    if L >= 19:
+        k = W.motion_blur_kernel(L, seed=L) + 0.01 * k   # sparse trajectory, no symmetry
     ref = fftconvolve(x, k, mode="same")
     assert np.abs(O.blur(x, k) - ref).max() <= 1e-12 * np.abs(ref).max()
     # adjoint = correlation = convolution with the flipped kernel
