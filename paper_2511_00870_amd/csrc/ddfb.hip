@@ -46,11 +46,13 @@ static_assert(kDdReg * kDdReg == 4 * kDdThreads, "four region pixels per thread"
 //                         channel block mb holds, in lane group q, channel
 //                         16 mb + 4 q + r, which is exactly a B operand whose
 //                         K index q stands for that channel, so u never moves.
+// u_0 carries no hard-tanh, so u_1 = HT(W_K v + gamma_1 W_1 b_1) is one sum over
+// 18 taps (v's nine, then b_1's nine): 5 K steps instead of 3 + 3.
 // Lane layout of the 16x16x4 f32 MFMA: A lane l = (row l % 16, k l / 16),
 // B lane l = (k l / 16, column l % 16), D lane l register r = (row 4 (l / 16)
 // + r, column l % 16).
 template <int KM, int MB>
-__global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
+__global__ __launch_bounds__(kDdThreads, KM <= 4 ? 3 : 2) void ddfb_stage_kernel(DdfbArgs a) {
   __shared__ float smap[KM][kDdWin * kDdWin];
   // tap (dy, dx)'s partial sums on the 30 x 30 block of region positions the
   // core's adjoint reads: rows 2 - dy .. 31 - dy, columns 2 - dx .. 31 - dx
@@ -89,10 +91,29 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
     }
   }
   // A fragments: MB blocks of 16 channels (channels from F on have zero
-  // weights, so their u stays zero and adds nothing)
+  // weights, so their u stays zero and adds nothing).  A01: the 18-tap
+  // chain of u_0 and the first update (K step s, lane group q4: slot
+  // 4 s + q4, v's tap for slots 0..8, b_1's for 9..17, zero weights beyond
+  // and for b_1 when k = 1); AJ[m - 2]: the updates m = 2 .. k - 1.  A slot
+  // with a zero weight reads tap (0, 0) of v, a finite value, so it adds an
+  // exact zero and needs no select.
   const PNP_GLOBAL float *w = gp(a.w);
-  float AK[MB][3], AJ[KM > 1 ? KM - 1 : 1][MB][3], AP[MB][4];
-  int toff[3];
+  float A01[MB][5], AJ[KM > 2 ? KM - 2 : 1][MB][3], AP[MB][4];
+  int toff[3], toff01[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const int t = 4 * s + q4, tp = t < 9 ? t : t - 9;
+    const bool used = t < 18 && (t < 9 || k >= 2);
+    toff01[s] = used ? (t < 9 ? 0 : kDdWin * kDdWin) + (tp / 3) * kDdWin + tp % 3 : 0;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int c = 16 * mb + l16;
+      const bool ok = used && c < F;
+      A01[mb][s] = !ok ? 0.0f
+                   : t < 9 ? w[((int64_t)(K - 1) * F + c) * 9 + tp]
+                           : a.gamma[0] * w[(int64_t)c * 9 + tp];
+    }
+  }
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int tp = 4 * s + q4;
@@ -101,10 +122,9 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
     for (int mb = 0; mb < MB; ++mb) {
       const int c = 16 * mb + l16;
       const bool ok = tp < 9 && c < F;
-      AK[mb][s] = ok ? w[((int64_t)(K - 1) * F + c) * 9 + tp] : 0.0f;
 #pragma unroll
-      for (int m = 1; m < KM; ++m)
-        AJ[m - 1][mb][s] = (m < k && ok) ? a.gamma[m - 1] * w[((int64_t)(m - 1) * F + c) * 9 + tp]
+      for (int m = 2; m < KM; ++m)
+        AJ[m - 2][mb][s] = (m < k && ok) ? a.gamma[m - 1] * w[((int64_t)(m - 1) * F + c) * 9 + tp]
                                          : 0.0f;
     }
   }
@@ -128,27 +148,38 @@ __global__ __launch_bounds__(kDdThreads) void ddfb_stage_kernel(DdfbArgs a) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) acc[h][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int base = ri * kDdWin + l16;            // window position of tap (0, 0), half 0
+    // u_0 (k = 1: three K steps), or u_0 + gamma_1 W_1 b_1 and its clip
+    const int ns01 = k >= 2 ? 5 : 3;
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < 5; ++s) {
+      if (s >= ns01) break;                          // uniform
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const float bv = (4 * s + q4 < 9) ? smap[0][base + 16 * h + toff[s]] : 0.0f;
+        const float bv = (&smap[0][0])[base + 16 * h + toff01[s]];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
-          acc[h][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(AK[mb][s], bv, acc[h][mb], 0, 0, 0);
+          acc[h][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A01[mb][s], bv, acc[h][mb], 0, 0, 0);
       }
     }
+    if (k >= 2) {
 #pragma unroll
-    for (int m = 1; m < KM; ++m) {
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[h][mb][r] = __builtin_amdgcn_fmed3f(acc[h][mb][r], -th, th);
+    }
+#pragma unroll
+    for (int m = 2; m < KM; ++m) {
       if (m >= k) break;
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const float bv = (4 * s + q4 < 9) ? smap[m][base + 16 * h + toff[s]] : 0.0f;
+          const float bv = smap[m][base + 16 * h + toff[s]];
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb)
-            acc[h][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(AJ[m - 1][mb][s], bv, acc[h][mb], 0, 0, 0);
+            acc[h][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(AJ[m - 2][mb][s], bv, acc[h][mb], 0, 0, 0);
         }
       }
 #pragma unroll
