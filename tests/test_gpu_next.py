@@ -141,7 +141,9 @@ def test_tv_prox_zeroes_pairs_on_gpu():
 
 
 # ------------------------------------------------------------------- DDFB
-@pytest.mark.parametrize("K,F,shape", [(4, 64, (61, 95)), (3, 6, (37, 29)), (8, 16, (64, 64))])
+# K = 1: u_0 alone; K = 2: one stage with u_1 from the 18-tap chain of v and b_1
+@pytest.mark.parametrize("K,F,shape", [(4, 64, (61, 95)), (3, 6, (37, 29)), (8, 16, (64, 64)),
+                                       (1, 32, (40, 50)), (2, 64, (47, 33))])
 def test_ddfb_denoiser_matches_oracle(K, F, shape):
     """G = x - D(x) of the DDFB stages against the oracle's D, FP32 bar."""
     ny, nx = shape
