@@ -314,11 +314,12 @@ def test_step_parity_wide_blur_split_mask():
     _parity_run(wl, 20, label="L=9 mask")
 
 
-@pytest.mark.parametrize("L,separable", [(17, True), (13, False)])
+@pytest.mark.parametrize("L,separable", [(17, True), (13, False), (3, True)])
 def test_step_parity_generic_radius(L, separable):
-    """Half-widths 5..8 run the generic fused update (tap counts read per job):
-    the longest ring of residual pixels around the tile's core, and for a
-    non-separable kernel up to 17 x 17 taps staged in the row-pass buffer."""
+    """Half-widths 1 and 5..8 run the generic fused update (tap counts read per
+    job): the thinnest and the longest rings of residual pixels around the
+    tile's core, and for a non-separable kernel up to 17 x 17 taps staged in
+    the row-pass buffer."""
     wl = W.config(1, ny=70, nx=83, block=35, halo=2 * (L // 2) + 2, L=L, sigma_k=L / 4.5,
                   mask_p=0.4, bias_scale=0.05)
     if not separable:
