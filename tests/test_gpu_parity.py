@@ -671,6 +671,44 @@ def test_serving_bf16_alone_equals_mix():
         assert np.array_equal(m, ma) and np.array_equal(v, va)
 
 
+def test_serving_e4m3_alone_equals_mix():
+    """The 8-layer 64-channel network with e4m3 middle layers (activation
+    scales shared by the server's jobs) serving three jobs of sides 256-512:
+    the first-layer, split-layer and last-layer e4m3 pair kernels run over
+    several jobs' tiles in one launch, and each job's statistics are bitwise
+    those of the same job run alone."""
+    K = 8
+    ch, ws, bs = W.denoiser_weights(K, 64, seed=7, bias_scale=0.05)
+    fmt = W.layer_formats(K, P.PNPULA_FP8_E4M3)
+    _, amax = O.denoiser_layers(O.Net(ch, ws, bs), W.synthetic_image(64, 64, 43))
+    scales = [float(2.0 ** np.ceil(np.log2(2 * a / 448))) if f == 2 else 1.0
+              for a, f in zip(amax, fmt)]
+    specs = [(256, 256, 5, False, 0.02, 2100, 10), (384, 320, 7, True, 0.01, 2200, 8),
+             (512, 512, 9, False, 0.03, 2300, 12)]
+    jobs = []
+    for ny, nx, L, masked, sigma, seed, iters in specs:
+        wl = W.make_workload(f"e{seed}", ny, nx, L=L, sigma_k=L / 4.5, sigma=sigma, block=256,
+                             halo=8, n_layers=K, features=64, precision=P.PNPULA_FP8_E4M3,
+                             iters=iters, burn_in=iters // 3, seed=seed,
+                             mask_p=0.5 if masked else None)
+        wl.channels, wl.weights, wl.biases = ch, ws, bs
+        jobs.append(wl)
+    say("case serving e4m3 8x64 alone vs mix")
+    srv = P.Server(ch, ws, bs, precision=P.PNPULA_FP8_E4M3, act_scales=scales, max_slots=3)
+    ids = [srv.submit(P.Config.from_workload(wl, act_scales=scales), wl.iters) for wl in jobs]
+    while srv.tick() > 0:
+        pass
+    for wl, i in zip(jobs, ids):
+        m, v, n = srv.result(i)
+        ctx = P.Context(P.Config.from_workload(wl, act_scales=scales))
+        ctx.step(wl.iters)
+        ma, va, na = ctx.stats()
+        say(f"  job {wl.ny}x{wl.nx}: n={n}, max |mean diff| {np.abs(m - ma).max():.1e}")
+        assert n == na == wl.iters - wl.burn_in
+        assert np.all(np.isfinite(m)) and np.all(np.isfinite(v))
+        assert np.array_equal(m, ma) and np.array_equal(v, va)
+
+
 def test_served_job_tracks_oracle():
     """A job served beside two others follows the FP64 oracle chain with the
     same noise: final state through the statistics, as the free-running
