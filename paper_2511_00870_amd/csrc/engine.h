@@ -137,6 +137,8 @@ class Engine {
                      bool first = false, bool last = false);
   bool pair_ok(int k) const;
   bool first_pair8_ok() const;
+  bool first8_ok() const;
+  Status launch_first8(int64_t tick, bool prof);
   Status launch_g_from_s(int64_t tick, bool prof);
   // called after each launch of the fused path that writes an activation
   // buffer: (index of the last layer it computed, buffer)

@@ -1051,6 +1051,39 @@ bool Engine::first_pair8_ok() const {
   return false;
 }
 
+// e4m3 networks whose first pair of middle layers goes to the split-layer
+// kernel: the first layer runs as a kernel of its own, since the split-layer
+// kernel has no place for it and carrying it in the one-group pair kernel
+// costs more than writing and re-reading its e4m3 output
+bool Engine::first8_ok() const {
+  if (net.K < 5 || net.K - 2 <= 2 || !pair_ok(1)) return false;
+  const LayerPlan &L0 = net.layers[0], &L1 = net.layers[1], &L2 = net.layers[2];
+  if (L1.in_fmt != FMT_E4M3 || L2.out_fmt != FMT_E4M3 || !L1.wblob_sl || !L2.wblob_sl) return false;
+  if (L0.out_buf != L1.in_buf) return false;
+  return first_pair8_fusable(L0.in_fmt, L0.out_fmt, L0.cin, L0.cout, L0.relu) &&
+         conv_th <= 16;
+}
+
+Status Engine::launch_first8(int64_t tick, bool prof) {
+  const LayerPlan &L0 = net.layers[0];
+  ConvArgs a{};
+  a.jobs = d_jobs;
+  a.tiles = d_conv;
+  a.n_tiles = n_conv;
+  a.tile_rows = conv_th;
+  a.tick = tick;
+  a.first_w = L0.wf32;
+  a.first_bias = L0.bias;
+  a.first_oscale = L0.oscale;
+  a.first_out_inv_scale = L0.out_inv_scale;
+  a.out_slot = L0.out_buf;
+  ProfileRec pr;
+  if (prof) prof_begin(1, &pr);
+  HIPOK(launch_conv_first8(a, n_conv, stream));
+  if (prof) prof_end(&pr);
+  return Status::ok();
+}
+
 Status Engine::launch_pair(int k, int in_slot, int out_slot, int64_t tick, bool prof,
                            bool first, bool last) {
   const LayerPlan &A = net.layers[k], &B = net.layers[k + 1];
@@ -1149,8 +1182,13 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof, const StageFn *on_sta
     TRY(launch_first_mid(tick, prof));
     TRY(stage(1, net.layers[1].out_buf));
     k = 2;
+  } else if (first8_ok()) {
+    TRY(launch_first8(tick, prof));
+    TRY(stage(0, net.layers[0].out_buf));
+    k = 1;
   } else if (first_pair8_ok()) {
-    // e4m3 networks: the first layer runs inside the first pair's kernel
+    // e4m3 networks whose first pair also feeds the last layer: the first
+    // layer runs inside that pair's kernel
     const int in = net.layers[1].in_buf;
     const int out = net.layers[2].out_fmt == net.buf_fmt[in] ? other(in) : net.layers[2].out_buf;
     const bool last = net.last_pair8 && K - 2 == 2;
