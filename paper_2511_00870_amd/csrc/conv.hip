@@ -198,28 +198,21 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
 // (channels 16 mb + 4g .. + 3 of pixel l16, mb = 0..3) go through one 32-lane
 // and one 16-lane swap per pair of registers, after which lane group g holds
 // channels 16g .. 16g + 15 of its pixel: one 16-byte store per lane, 1 KB
-// contiguous per wave and block.
+// contiguous per wave and block.  Each workgroup walks the tiles of its XCD's
+// contiguous range (the grid is a multiple of 8 and dispatched round-robin over
+// the XCDs), with the weights read once and the next tile's x window loaded
+// while the current tile is computed.
 __global__ __launch_bounds__(256) void conv_first8_kernel(ConvArgs a) {
   constexpr int TW = kConvTileW, XW = TW + 2, XH = 18;
   constexpr int XQ = (XH * XW + 255) / 256;
   static_assert(TW == 32, "two 16-pixel blocks per tile row");
   __shared__ uint16_t sx[XH * XW];
-  const PNP_CONST TileRef &tl = cp(a.tiles)[xcd_tile(blockIdx.x, a.n_tiles)];
-  const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
-  const int64_t t = a.tick + j.t_offset;
-  const PNP_GLOBAL float *xb = gp(j.x[t & 1]);
-  const int B = j.xborder;
-  const int64_t xpitch = j.xpitch;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
-  // the window's loads first (rows past the tile read the tile's first row)
-  float xv[XQ];
-#pragma unroll
-  for (int k = 0; k < XQ; ++k) {
-    const int q0 = tid + 256 * k, q = q0 < XH * XW ? q0 : 0;
-    const int i = q / XW, c = q % XW;
-    const int ii = i < tl.h + 2 ? i : 0;
-    xv[k] = xb[(int64_t)(tl.y0 - 1 + ii + B) * xpitch + (tl.x0 - 1 + c + B)];
-  }
+  const int n = a.n_tiles, xcd = blockIdx.x & 7, q8 = n >> 3, rem = n & 7;
+  const int cnt = q8 + (xcd < rem ? 1 : 0), base = xcd * q8 + (xcd < rem ? xcd : rem);
+  const int step = gridDim.x >> 3;
+  int i = blockIdx.x >> 3;
+  if (i >= cnt) return;                          // uniform over the workgroup
   // A fragments (rows: 16 channels of block mb; K slot 4g + e: tap (g, e)),
   // scale and bias of this lane's 4 channels per block
   i16x4 A0[4];
@@ -235,51 +228,78 @@ __global__ __launch_bounds__(256) void conv_first8_kernel(ConvArgs a) {
       bi[mb][e] = a.first_bias[c] * a.first_out_inv_scale;
     }
   }
+  // the x window of tile t into registers (rows past the tile read its first row)
+  float xv[XQ];
+  auto load_x = [&](int t) {
+    const PNP_CONST TileRef &tl = cp(a.tiles)[t];
+    const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+    const PNP_GLOBAL float *xb = gp(j.x[(a.tick + j.t_offset) & 1]);
+    const int B = j.xborder;
 #pragma unroll
-  for (int k = 0; k < XQ; ++k) {
-    const int q = tid + 256 * k;
-    if (q < XH * XW) sx[q] = f32_to_bf16(xv[k]);
-  }
-  __syncthreads();
-  PNP_GLOBAL uint8_t *out = gp(reinterpret_cast<uint8_t *>(j.act[a.out_slot]));
+    for (int k = 0; k < XQ; ++k) {
+      const int q0 = tid + 256 * k, q = q0 < XH * XW ? q0 : 0;
+      const int r = q / XW, c = q % XW;
+      const int rr = r < tl.h + 2 ? r : 0;
+      xv[k] = xb[(int64_t)(tl.y0 - 1 + rr + B) * j.xpitch + (tl.x0 - 1 + c + B)];
+    }
+  };
   const int gr = g < 3 ? g : 2;                  // lane group 3 reads a valid row (zero weights)
+  int t = base + i;
+  load_x(t);
+  for (;;) {
 #pragma unroll
-  for (int o = 0; o < 4; ++o) {
-    const int r = 4 * wave + o;
-    if (r >= tl.h) break;                          // uniform
+    for (int k = 0; k < XQ; ++k) {
+      const int q = tid + 256 * k;
+      if (q < XH * XW) sx[q] = f32_to_bf16(xv[k]);
+    }
+    __syncthreads();                             // window in place
+    const int inext = i + step;
+    if (inext < cnt) load_x(base + inext);       // uniform
+    const PNP_CONST TileRef &tl = cp(a.tiles)[t];
+    const PNP_CONST JobDesc &j = cp(a.jobs)[tl.job];
+    PNP_GLOBAL uint8_t *out = gp(reinterpret_cast<uint8_t *>(j.act[a.out_slot]));
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint16_t *xp = sx + (r + gr) * XW + 16 * h + l16;
-      i16x4 Bx;
-      Bx[0] = (short)xp[0];
-      Bx[1] = (short)xp[1];
-      Bx[2] = (short)xp[2];
-      Bx[3] = 0;
-      uint32_t v[4];
+    for (int o = 0; o < 4; ++o) {
+      const int r = 4 * wave + o;
+      if (r >= tl.h) break;                        // uniform
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0[mb], Bx, f32x4{0.f, 0.f, 0.f, 0.f},
-                                                                0, 0, 0);
-        v[mb] = pack_e4m3x4_relu(fmaf(d[0], sc[mb][0], bi[mb][0]), fmaf(d[1], sc[mb][1], bi[mb][1]),
-                                 fmaf(d[2], sc[mb][2], bi[mb][2]), fmaf(d[3], sc[mb][3], bi[mb][3]));
-      }
-      const auto s02 = __builtin_amdgcn_permlane32_swap(v[0], v[2], false, false);
-      const auto s13 = __builtin_amdgcn_permlane32_swap(v[1], v[3], false, false);
-      const auto t01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
-      const auto t23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
-      const int c = 16 * h + l16;
-      if (c < tl.w) {
-        PNP_GLOBAL uint8_t *dst =
-            out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * 64 + 16 * g;
-        *reinterpret_cast<PNP_GLOBAL u32x4 *>(dst) = u32x4{t01[0], t01[1], t23[0], t23[1]};
+      for (int h = 0; h < 2; ++h) {
+        const uint16_t *xp = sx + (r + gr) * XW + 16 * h + l16;
+        i16x4 Bx;
+        Bx[0] = (short)xp[0];
+        Bx[1] = (short)xp[1];
+        Bx[2] = (short)xp[2];
+        Bx[3] = 0;
+        uint32_t v[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0[mb], Bx, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                  0, 0, 0);
+          v[mb] = pack_e4m3x4_relu(fmaf(d[0], sc[mb][0], bi[mb][0]), fmaf(d[1], sc[mb][1], bi[mb][1]),
+                                   fmaf(d[2], sc[mb][2], bi[mb][2]), fmaf(d[3], sc[mb][3], bi[mb][3]));
+        }
+        const auto s02 = __builtin_amdgcn_permlane32_swap(v[0], v[2], false, false);
+        const auto s13 = __builtin_amdgcn_permlane32_swap(v[1], v[3], false, false);
+        const auto t01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+        const auto t23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+        const int c = 16 * h + l16;
+        if (c < tl.w) {
+          PNP_GLOBAL uint8_t *dst =
+              out + ((int64_t)(tl.y0 + r + 1) * j.apitch + (tl.x0 + c + 1)) * 64 + 16 * g;
+          *reinterpret_cast<PNP_GLOBAL u32x4 *>(dst) = u32x4{t01[0], t01[1], t23[0], t23[1]};
+        }
       }
     }
+    if (inext >= cnt) break;                     // uniform
+    __syncthreads();                             // window read before it is replaced
+    i = inext;
+    t = base + i;
   }
 }
 
-hipError_t launch_conv_first8(const ConvArgs &a, int n_tiles, hipStream_t s) {
-  if (a.tile_rows < 1 || a.tile_rows > 16) return hipErrorInvalidValue;   // 18-row window
-  hipLaunchKernelGGL(conv_first8_kernel, dim3(n_tiles), dim3(256), 0, s, a);
+hipError_t launch_conv_first8(const ConvArgs &a, int n_wg, hipStream_t s) {
+  if (a.tile_rows < 1 || a.tile_rows > 16 || n_wg < 8 || n_wg % 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(conv_first8_kernel, dim3(n_wg), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

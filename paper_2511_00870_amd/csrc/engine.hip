@@ -1079,7 +1079,8 @@ Status Engine::launch_first8(int64_t tick, bool prof) {
   a.out_slot = L0.out_buf;
   ProfileRec pr;
   if (prof) prof_begin(1, &pr);
-  HIPOK(launch_conv_first8(a, n_conv, stream));
+  const int need = ((n_conv + 7) / 8) * 8;
+  HIPOK(launch_conv_first8(a, std::max(8, std::min(6 * n_cu, need) / 8 * 8), stream));
   if (prof) prof_end(&pr);
   return Status::ok();
 }

@@ -125,8 +125,9 @@ hipError_t launch_conv_pair8_ws(const ConvArgs &a, int n_wg, hipStream_t s);
 // the network's first layer (1 -> 64, bf16 weights, e4m3 output into
 // j.act[out_slot]) on the matrix cores with the e4m3 first-layer pair's
 // arithmetic (first_w / first_bias / first_oscale / first_out_inv_scale);
-// one workgroup per convolution tile of at most 16 rows
-hipError_t launch_conv_first8(const ConvArgs &a, int n_tiles, hipStream_t s);
+// over convolution tiles of at most 16 rows; n_wg workgroups, a positive
+// multiple of 8, each walking tiles of its XCD's range
+hipError_t launch_conv_first8(const ConvArgs &a, int n_wg, hipStream_t s);
 bool last_pair8_fusable(int out_fmt2, int last_in_fmt, int last_cin, int last_cout);
 bool first_pair8_fusable(int in_fmt0, int out_fmt0, int cin0, int cout0, int relu0);
 bool pair8_fusable(int in_fmt, int out_fmt, int F, int relu, int in_fmt2, int out_fmt2,
