@@ -1722,22 +1722,21 @@ __device__ __forceinline__ constexpr int p8_off(int p, int col, int c) {
 // per output row each wave multiplies its 16 channels (rounded to bf16 after
 // ReLU) by the last layer's weights on the matrix core (M = 9 taps padded to
 // 16, K = 16 channels), the four waves' partials meet in LDS, and after a
-// barrier 96 lanes add them and store the records.  FIRST: the network's first
-// layer (1 -> 64, bf16 weights, e4m3 output) is computed per tile from x
-// into the input window instead of reading its output from memory: each
-// wave takes its 16 channels for every window pixel, one MFMA per 16 pixels
-// (K = the 9 taps padded to 16), then scale, bias, ReLU and e4m3 as the
-// standalone first-layer kernel does; window pixels outside the image are
-// set to zero (the next layer's padding).
+// barrier 96 lanes add them and store the records.  FIRST (only with LAST, in
+// the four-layer network whose one pair is both first and last): the
+// network's first layer (1 -> 64, bf16 weights, e4m3 output) is computed per
+// tile from x into the input window, as a phase before layer A, instead of
+// reading its output from memory: each wave takes its 16 channels for every
+// window pixel, one MFMA per 16 pixels (K = the 9 taps padded to 16), then
+// scale, bias, ReLU and e4m3 as conv_first8_kernel does; window pixels
+// outside the image are set to zero (the next layer's padding).
 template <int OUT2, bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPair8Wpe, kPair8Wpe)))
 void conv_pair8_kernel(ConvArgs a) {
   using Lo = Pair8Layout;
   constexpr int NT = Lo::NT, IW = Lo::IW, NL1 = Lo::NL1, NL2 = Lo::NL2;
   constexpr int NP = 2, PD = 2;                   // steps per input row; B reads ahead
-  // the next tile's first layer runs inside this tile's layer B (with the
-  // fused last layer its partial-sum ring occupies part of the window then)
-  constexpr bool L0_IN_B = FIRST && !LAST;
+  static_assert(!FIRST || LAST, "the first layer rides only in the pair that also feeds the last layer");
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   uint8_t *lds_in = lds;
   uint8_t *lds_mid = lds + Lo::IN_BYTES;
@@ -2016,15 +2015,8 @@ void conv_pair8_kernel(ConvArgs a) {
     auto pfA = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
       if constexpr (!FIRST && stg >= 4 && stg < 4 + NL1) pre[stg - 4] = load_chunk(nxt, stg - 4);
-      if constexpr (L0_IN_B && stg >= 1 && stg < 1 + Lo::XQ) prex[stg - 1] = load_x(nxt, stg - 1);
     };
     layer(base_in, WA, std::integral_constant<int, Lo::IH>{}, epA, pfA);
-    if constexpr (L0_IN_B) {
-      // the x window was last read by the first layer of this tile, during
-      // the previous tile's layer B
-#pragma unroll
-      for (int i = 0; i < Lo::XQ; ++i) put_x(i, prex[i]);
-    }
     __syncthreads();                             // intermediate written, window read
     if constexpr (!FIRST) {
 #pragma unroll
@@ -2095,14 +2087,9 @@ void conv_pair8_kernel(ConvArgs a) {
         *reinterpret_cast<PNP_GLOBAL u32x2 *>(cur.out + bo) = pack_row(oc, 1);
       }
     };
-    if constexpr (L0_IN_B) l0_reset();
     auto pfB = [&](auto stc) {
       constexpr int stg = decltype(stc)::value;
-      if constexpr (L0_IN_B) {
-        // the next tile's first layer, NB0 blocks spread over the stages
-        constexpr int NSB = Lo::MH * NP, b0 = NB0 * stg / NSB, b1 = NB0 * (stg + 1) / NSB;
-        static_for<b0, b1>([&](auto b) { l0_block(nxt, b); });
-      } else if constexpr (FIRST) {
+      if constexpr (FIRST) {
         if constexpr (stg >= 1 && stg < 1 + Lo::XQ) prex[stg - 1] = load_x(nxt, stg - 1);
       } else {
         if constexpr (stg >= 1 && stg < 1 + NL2) pre[stg - 1] = load_chunk(nxt, NL1 + stg - 1);
@@ -2110,7 +2097,7 @@ void conv_pair8_kernel(ConvArgs a) {
     };
     layer(base_mid, WB, std::integral_constant<int, Lo::MH>{}, epB, pfB);
     if constexpr (LAST) __syncthreads();         // the last row's partials are summed
-    if constexpr (FIRST && !L0_IN_B) {
+    if constexpr (FIRST) {
       // the x window is read by layer0 only, long done
 #pragma unroll
       for (int i = 0; i < Lo::XQ; ++i) put_x(i, prex[i]);
@@ -2123,7 +2110,7 @@ void conv_pair8_kernel(ConvArgs a) {
     cur = nxt;
     nxt = after;
     ti = tn;
-    if constexpr (FIRST && !L0_IN_B) {
+    if constexpr (FIRST) {
       layer0(cur);
       __syncthreads();
     }
@@ -2575,12 +2562,9 @@ hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, bool l
     return first ? launch_pair8_t<FMT_BF16, true, true>(a, n_wg, s)
                  : launch_pair8_t<FMT_BF16, false, true>(a, n_wg, s);
   }
-  if (out_fmt2 == FMT_E4M3)
-    return first ? launch_pair8_t<FMT_E4M3, true, false>(a, n_wg, s)
-                 : launch_pair8_t<FMT_E4M3, false, false>(a, n_wg, s);
-  if (out_fmt2 == FMT_BF16)
-    return first ? launch_pair8_t<FMT_BF16, true, false>(a, n_wg, s)
-                 : launch_pair8_t<FMT_BF16, false, false>(a, n_wg, s);
+  if (first) return hipErrorInvalidValue;        // the first layer rides only with the last
+  if (out_fmt2 == FMT_E4M3) return launch_pair8_t<FMT_E4M3, false, false>(a, n_wg, s);
+  if (out_fmt2 == FMT_BF16) return launch_pair8_t<FMT_BF16, false, false>(a, n_wg, s);
   return hipErrorInvalidValue;
 }
 

@@ -1041,7 +1041,9 @@ bool Engine::pair_ok(int k) const {
 
 // the first layer (bf16 -> e4m3) inside the kernel of the first e4m3 pair
 bool Engine::first_pair8_ok() const {
-  if (net.K < 4 || !pair_ok(1) || net.layers[1].in_fmt != FMT_E4M3) return false;
+  // only the pair that is both the first and the last (four layers)
+  if (net.K != 4 || !net.last_pair8 || !pair_ok(1) || net.layers[1].in_fmt != FMT_E4M3)
+    return false;
   if (net.last_fused && net.K - 2 == 2) return false;
   const LayerPlan &L0 = net.layers[0];
   if (!first_pair8_fusable(L0.in_fmt, L0.out_fmt, L0.cin, L0.cout, L0.relu)) return false;
@@ -1188,16 +1190,12 @@ Status Engine::run_fused_denoiser(int64_t tick, bool prof, const StageFn *on_sta
     TRY(stage(0, net.layers[0].out_buf));
     k = 1;
   } else if (first_pair8_ok()) {
-    // e4m3 networks whose first pair also feeds the last layer: the first
-    // layer runs inside that pair's kernel
+    // four-layer e4m3 networks: the one pair feeds the last layer and also
+    // carries the first layer
     const int in = net.layers[1].in_buf;
     const int out = net.layers[2].out_fmt == net.buf_fmt[in] ? other(in) : net.layers[2].out_buf;
-    const bool last = net.last_pair8 && K - 2 == 2;
-    TRY(launch_pair(1, in, out, tick, prof, true, last));
-    if (last) return launch_g_from_s(tick, prof);
-    TRY(stage(2, out));
-    cur = out;
-    k = 3;
+    TRY(launch_pair(1, in, out, tick, prof, true, true));
+    return launch_g_from_s(tick, prof);
   }
   for (; k < K; ++k) {
     const LayerPlan &L = net.layers[k];

@@ -110,8 +110,9 @@ bool pair_fusable(int in_fmt, int out_fmt, int F, int relu, int unit, int in_fmt
 // arguments with wblob_rr; wblob2 / bias2 / oscale2 / out_inv_scale2 the
 // second's); out_fmt2: the second layer's output format (e4m3 or bf16);
 // n_wg a positive multiple of 8, pair8_wg_per_cu() per CU
-// first: the network's first layer (bf16 -> e4m3) runs inside the kernel
-// from x (first_w / first_bias / first_oscale / first_out_inv_scale)
+// first (only together with last): the network's first layer (bf16 -> e4m3)
+// runs inside the kernel from x (first_w / first_bias / first_oscale /
+// first_out_inv_scale)
 // last: the second layer feeds the last layer, whose per-tap partials go to
 // JobDesc::S (last_w; out_fmt2 must be bf16)
 hipError_t launch_conv_pair8(const ConvArgs &a, int out_fmt2, bool first, bool last, int n_wg,
