@@ -187,12 +187,12 @@ __global__ __launch_bounds__(256) void conv_first_kernel(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------
-// First layer 1 -> 64 with e4m3 output on the matrix cores, as the e4m3
-// first-layer pair kernel computes it (so the codes are the same): x and the
-// weights rounded to bf16, one v_mfma_f32_16x16x16_bf16 per 16 pixels and 16
-// channels with K slot 4g + e holding tap (g, e) (zero weights for g or e = 3),
-// then fma with the scale and bias that already carry the output's inverse
-// activation scale, ReLU and saturation in one clamp, e4m3.  One workgroup per
+// First layer 1 -> 64 with e4m3 output on the matrix cores, as the e4m3 pair
+// kernel's fused first layer computes it (so the codes are the same): x and
+// the weights rounded to bf16, one v_mfma_f32_16x16x16_bf16 per 16 pixels and
+// 16 channels with K slot 4g + e holding tap (g, e) (zero weights for g or
+// e = 3), then fma with the scale and bias that already carry the output's
+// inverse activation scale, ReLU and saturation in one clamp, e4m3.  Per
 // 16 x 32 tile: the x window (18 x 34) as bf16 in LDS; wave w takes output
 // rows 4w .. 4w + 3, two 16-pixel blocks per row.  A lane's four results
 // (channels 16 mb + 4g .. + 3 of pixel l16, mb = 0..3) go through one 32-lane
